@@ -1,0 +1,218 @@
+"""Seeded synthetic light curves and search grids.
+
+Every workload here is an *input* to the transit search: observation times
+(FP64 days), flux offsets from baseline (FP32; 0 = baseline, 1 = star fully
+blocked, Sec. 2 units convention), per-point uncertainties (FP32), a dense
+template, trial durations and trial periods.  Normalised fluxes y are made in
+FP64 and converted once to offsets f = 1 - y, rounded to FP32, so every
+consumer of a workload sees exactly the same FP32 arrays.
+
+The workloads stand in for the paper's data (TESS/PLATO-like cadences and
+baselines, Sec. 3.2 and Sec. 4); none of the paper's data sets is used.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+from . import transit
+
+DAY_S = 86400.0
+HOUR = 1.0 / 24.0
+
+
+@dataclasses.dataclass
+class Injection:
+    period: float          # days (np.inf for a single event)
+    epoch: float           # mid-transit time of one transit (days)
+    duration: float        # first-to-last contact (days)
+    depth: float           # maximum flux offset
+    b: float = transit.DEFAULT_B
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    t: np.ndarray          # float64 [n_obs], ascending
+    f: np.ndarray          # float32 [n_obs], flux offset from baseline
+    sigma: np.ndarray      # float32 [n_obs]
+    cadence: float         # resample cadence (days)
+    durations: np.ndarray  # float64 [J], ascending (days)
+    periods: np.ndarray    # float64 [K], ascending (days)
+    dense: np.ndarray      # float64 dense template, max 1
+    n_model: int = 1024    # template samples M
+    t0_step_frac: float = 0.01
+    injections: List[Injection] = dataclasses.field(default_factory=list)
+    seed: int = 0
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.t.shape[0])
+
+
+def to_offset(y: np.ndarray) -> np.ndarray:
+    """FP64 normalised flux -> FP32 offset from baseline (single rounding)."""
+    return (1.0 - np.asarray(y, dtype=np.float64)).astype(np.float32)
+
+
+def inject(t: np.ndarray, inj: Injection, dense_cache: Optional[dict] = None) -> np.ndarray:
+    """Blocked-flux signal (>= 0) of a periodic transit at times t."""
+    key = round(inj.b, 6)
+    if dense_cache is not None and key in dense_cache:
+        dense = dense_cache[key]
+    else:
+        dense = transit.dense_template(b=inj.b)
+        if dense_cache is not None:
+            dense_cache[key] = dense
+    if np.isfinite(inj.period):
+        phase = np.mod(t - inj.epoch + 0.5 * inj.period, inj.period) - 0.5 * inj.period
+    else:
+        phase = t - inj.epoch
+    tau = phase / inj.duration + 0.5
+    return inj.depth * transit.shape_at(tau, dense)
+
+
+def random_gaps(rng, t_lo: float, t_hi: float, n_gaps: int, length: float,
+                max_tries: int = 10000):
+    """Start times of ``n_gaps`` non-overlapping gaps of fixed length."""
+    starts: List[float] = []
+    tries = 0
+    while len(starts) < n_gaps:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place gaps")
+        s = rng.uniform(t_lo, t_hi - length)
+        if all(abs(s - o) >= length for o in starts):
+            starts.append(s)
+    return sorted(starts)
+
+
+def uniform_frequency_periods(p_min: float, p_max: float, k: int) -> np.ndarray:
+    freq = np.linspace(1.0 / p_max, 1.0 / p_min, k)
+    return np.sort(1.0 / freq)
+
+
+def log_periods(p_min: float, p_max: float, k: int) -> np.ndarray:
+    return np.geomspace(p_min, p_max, k)
+
+
+def log_durations(d_min_h: float, d_max_h: float, j: int) -> np.ndarray:
+    return np.geomspace(d_min_h * HOUR, d_max_h * HOUR, j)
+
+
+def running_median(y: np.ndarray, window: int) -> np.ndarray:
+    """Centred running median (pandas' skip-list rolling median)."""
+    import pandas as pd
+    s = pd.Series(y)
+    return s.rolling(window, center=True, min_periods=1).median().to_numpy()
+
+
+def tiny_single(seed: int = 20250326) -> Workload:
+    """One 27.4-d light curve at 2-min cadence (about one TESS sector):
+    white noise 1000 ppm, two random 1-d gaps, one injected transit
+    P = 5.3 d, depth 2000 ppm, duration 3 h.  8 log-spaced durations
+    0.5-6 h; 1000 periods uniform in frequency over 1-13 d."""
+    rng = np.random.default_rng(seed)
+    c = 120.0 / DAY_S
+    n = int(round(27.4 / c))
+    t = np.arange(n, dtype=np.float64) * c
+    keep = np.ones(n, dtype=bool)
+    for s in random_gaps(rng, 0.0, t[-1], 2, 1.0):
+        keep &= ~((t >= s) & (t < s + 1.0))
+    t = t[keep]
+    sig = 1000e-6
+    inj = Injection(period=5.3, epoch=rng.uniform(0.0, 5.3), duration=3.0 * HOUR,
+                    depth=2000e-6)
+    y = 1.0 - inject(t, inj) + rng.normal(0.0, sig, t.shape[0])
+    return Workload(
+        name="single-lc 27.4d@120s (tiny)", t=t, f=to_offset(y),
+        sigma=np.full(t.shape[0], sig, dtype=np.float32), cadence=c,
+        durations=log_durations(0.5, 6.0, 8),
+        periods=uniform_frequency_periods(1.0, 13.0, 1000),
+        dense=transit.dense_template(), injections=[inj], seed=seed)
+
+
+def high_cadence(seed: int = 20250327) -> Workload:
+    """One 90-d light curve at 20-s cadence (TESS-20s-like): AR(1) red noise
+    (phi = 0.9, marginal 300 ppm) plus 500 ppm white noise, pre-whitened by a
+    centred 1-d running median over valid points; 5% of points masked as six
+    0.75-d gaps; per-point sigma = 1.4826 * MAD of the pre-whitened flux.
+    Transits P = 17.1 d / 400 ppm / 4 h and P = 3.2 d / 250 ppm / 1.5 h.
+    20 log-spaced durations 0.5-15 h; 50 000 log-spaced periods 0.5-45 d."""
+    rng = np.random.default_rng(seed)
+    c = 20.0 / DAY_S
+    n = int(round(90.0 / c))
+    t = np.arange(n, dtype=np.float64) * c
+    phi, marg = 0.9, 300e-6
+    innov = marg * np.sqrt(1.0 - phi * phi)
+    e = rng.normal(0.0, innov, n)
+    red = np.empty(n)
+    red[0] = rng.normal(0.0, marg)
+    # AR(1) recursion via a linear filter
+    from scipy.signal import lfilter
+    red[1:] = lfilter([1.0], [1.0, -phi], e[1:], zi=[phi * red[0]])[0]
+    white = rng.normal(0.0, 500e-6, n)
+    keep = np.ones(n, dtype=bool)
+    for s in random_gaps(rng, 0.0, t[-1], 6, 0.75):
+        keep &= ~((t >= s) & (t < s + 0.75))
+    injs = [Injection(17.1, rng.uniform(0.0, 17.1), 4.0 * HOUR, 400e-6),
+            Injection(3.2, rng.uniform(0.0, 3.2), 1.5 * HOUR, 250e-6)]
+    sig_blocked = sum(inject(t, inj) for inj in injs)
+    y = 1.0 - sig_blocked + red + white
+    t, y = t[keep], y[keep]
+    trend = running_median(y, int(round(1.0 / c)))
+    y = y - trend + 1.0
+    resid = y - 1.0
+    mad = np.median(np.abs(resid - np.median(resid)))
+    sig = 1.4826 * mad
+    return Workload(
+        name="single-lc 90d@20s (high cadence)", t=t, f=to_offset(y),
+        sigma=np.full(t.shape[0], sig, dtype=np.float32), cadence=c,
+        durations=log_durations(0.5, 15.0, 20),
+        periods=log_periods(0.5, 45.0, 50000),
+        dense=transit.dense_template(), injections=injs, seed=seed)
+
+
+def small_random(seed: int, n_obs: int = 600, cadence_s: float = 611.7,
+                 n_dur: int = 3, n_per: int = 12, jitter: float = 0.3,
+                 dup_frac: float = 0.1, gap_frac: float = 0.15,
+                 sigma_lognorm: float = 0.3, depth: float = 3e-3,
+                 p_range=(0.6, 2.5), dur_h=(1.0, 4.0)) -> Workload:
+    """Small irregular light curve for exhaustive checks: jittered cadence,
+    some co-located observations, gaps, lognormal per-point sigma and one
+    injected transit."""
+    rng = np.random.default_rng(seed)
+    c = cadence_s / DAY_S
+    t = np.arange(n_obs, dtype=np.float64) * c + rng.uniform(-jitter, jitter, n_obs) * c
+    n_dup = int(dup_frac * n_obs)
+    if n_dup:
+        extra = t[rng.integers(0, n_obs, n_dup)] + rng.uniform(-0.2, 0.2, n_dup) * c
+        t = np.concatenate([t, extra])
+    t = np.sort(t) + rng.uniform(0.0, 3.0)
+    n_tot = t.shape[0]
+    if gap_frac > 0:
+        g0 = rng.uniform(t[0], t[-1])
+        glen = gap_frac * (t[-1] - t[0])
+        keep = ~((t >= g0) & (t < g0 + glen))
+        t = t[keep]
+        n_tot = t.shape[0]
+    sig = (1e-3 * np.exp(sigma_lognorm * rng.normal(size=n_tot))).astype(np.float32)
+    per = rng.uniform(*p_range)
+    inj = Injection(per, t[0] + rng.uniform(0.0, per), rng.uniform(*dur_h) * HOUR, depth)
+    y = 1.0 - inject(t, inj) + rng.normal(size=n_tot) * sig.astype(np.float64)
+    # irregular factors keep window edges off exact grid coincidences
+    durs = log_durations(dur_h[0] * 0.7137, dur_h[1] * 1.2113, n_dur)
+    pers = np.sort(rng.uniform(p_range[0] * 0.8, p_range[1] * 1.5, n_per))
+    return Workload(name=f"small-random-{seed}", t=t, f=to_offset(y), sigma=sig,
+                    cadence=c, durations=durs, periods=pers,
+                    dense=transit.dense_template(), n_model=1024,
+                    injections=[inj], seed=seed)
+
+
+WORKLOADS = {
+    "tiny": tiny_single,
+    "high_cadence": high_cadence,
+}
