@@ -1,0 +1,255 @@
+"""Benchmark of the transit search on one MI355X.
+
+One step = one pass of the whole search over one light curve already resident
+in HBM: template resampling, light-curve resampling, linear search, periodic
+search (fold + per-period argmax) and the best period.  Workload: one 90-d
+light curve at 20-s cadence (369 360 observations, AR(1) red + white noise,
+pre-whitened, 5% gaps, two injected transits), 20 log-spaced durations
+0.5-15 h, 50 000 log-spaced periods 0.5-45 d; synthetic, seeded.
+
+Metric: light-curve points x trial periods per second, linear + periodic
+(N_obs * K / step time).  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_high_cadence_counters.json")
+FOLD_SOURCE = os.path.join(ROOT, "paper_2503_20875_amd", "csrc", "fold.hip")
+
+
+def fold_source_hash() -> str:
+    with open(FOLD_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def algorithmic_work(wl, grid):
+    """Element visits of the fold (sum over periods of allowed durations x I),
+    fold bytes (8 B per visit + 20 B per period record) and linear FLOP
+    (4 per window-point visit: two FMAs)."""
+    durs = np.asarray(wl.durations)
+    J_k = np.array([np.count_nonzero(durs < P) for P in wl.periods], dtype=np.int64)
+    visits = int(J_k.sum()) * int(grid.n_t0)
+    fold_bytes = 8 * visits + 20 * len(wl.periods)
+    c, dt = grid.cadence, grid.t0_step
+    # points per window: floor(te/c) - ceil(ts/c) + 1 ~ D/c (exact count summed below)
+    lin_points = 0
+    i = np.arange(grid.n_t0, dtype=np.float64)
+    t_end = (grid.n - 1) * c
+    for D in durs:
+        ts = i * dt - 0.5 * D
+        te = ts + D
+        ok = (ts >= 0) & (te <= t_end)
+        lo = np.ceil(ts[ok] / c)
+        hi = np.floor(te[ok] / c)
+        lin_points += int(np.sum(np.maximum(hi - lo + 1, 0)))
+    return dict(fold_visits=visits, fold_bytes=fold_bytes, linear_points=lin_points,
+                linear_flop=4 * lin_points)
+
+
+def cpu_baseline(wl, stride: int = 50):
+    """The FP64 oracle, as it is, on a bounded sample: full resample + linear
+    search, fold over every `stride`-th period, extrapolated linearly in fold
+    element visits to the full period grid."""
+    import oracle
+    g = oracle.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, wl.n_model)
+    model = oracle.template(wl.dense, wl.n_model)
+    t0 = time.perf_counter()
+    flux, ivar = oracle.resample(g, wl.t, wl.f, wl.sigma)
+    lin = oracle.linear(g, flux, ivar, model)
+    t_lin = time.perf_counter() - t0
+    sel = np.arange(0, len(wl.periods), stride)
+    t0 = time.perf_counter()
+    oracle.periodic(g, lin, wl.periods, sel=sel)
+    t_fold = time.perf_counter() - t0
+    durs = np.asarray(wl.durations)
+    jk = np.array([np.count_nonzero(durs < P) for P in wl.periods], dtype=np.float64)
+    scale = jk.sum() / jk[sel].sum()
+    t_full = t_lin + t_fold * scale
+    value = wl.n_obs * len(wl.periods) / t_full
+    return dict(value=value, unit="LC points x trial periods / s", cores=oracle.max_threads(), kind="oracle",
+                sample=(f"resample + linear search in full ({t_lin:.2f} s), fold over every {stride}th period "
+                        f"({len(sel)} of {len(wl.periods)}, {t_fold:.2f} s) extrapolated x{scale:.1f} in fold "
+                        f"element visits; estimated full search {t_full:.1f} s"),
+                seconds_measured=round(t_lin + t_fold, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="high_cadence", choices=["high_cadence", "tiny"])
+    ap.add_argument("--mode", default="full", choices=["full", "fold", "copy"],
+                    help="full: the benchmark; fold: setup once, then --steps fold launches only "
+                         "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
+                         "times (calibrates the HBM byte counters)")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search has no "
+              "multi-GPU path in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2503_20875_amd as cm
+    from synthlc import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.mode == "copy":
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                          "launches": args.steps}), flush=True)
+        return
+    wl = W.WORKLOADS[args.workload]()
+    dev = "cuda"
+    t_d = torch.as_tensor(wl.t, device=dev)
+    f_d = torch.as_tensor(wl.f, device=dev)
+    s_d = torch.as_tensor(wl.sigma, device=dev)
+    dense_d = torch.as_tensor(wl.dense, device=dev)
+    per_d = torch.as_tensor(wl.periods, device=dev)
+    grid = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
+    K = len(wl.periods)
+    # every buffer allocated up front: the timed region only launches kernels
+    fold = torch.empty((grid.n_dur, grid.n_t0, 2), dtype=torch.float32, device=dev)
+    work = torch.empty(cm.periodic_workspace(grid, K), dtype=torch.uint8, device=dev)
+    per = dict(lr=torch.empty(K, dtype=torch.float32, device=dev),
+               epoch=torch.empty(K, dtype=torch.int32, device=dev),
+               dur=torch.empty(K, dtype=torch.int32, device=dev),
+               depth=torch.empty(K, dtype=torch.float32, device=dev),
+               depth_var=torch.empty(K, dtype=torch.float32, device=dev))
+    best = torch.empty(96, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = {k: [] for k in ("start", "lin", "fold0", "fold1", "end")}
+
+    def step(record: bool):
+        e = {k: torch.cuda.Event(enable_timing=True) for k in ev} if record else None
+        if record:
+            e["start"].record(stream)
+        model = cm.template_resample(dense_d, wl.n_model)
+        flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
+        cm.linear_search(grid, flux, ivar, model, fold=fold)
+        if record:
+            e["lin"].record(stream)
+            e["fold0"].record(stream)
+        cm.periodic_search(grid, fold, per_d, work=work, out=per)
+        if record:
+            e["fold1"].record(stream)
+        cm.best(grid, per_d, per, out=best)
+        if record:
+            e["end"].record(stream)
+            for k in ev:
+                ev[k].append(e[k])
+
+    if args.mode == "fold":
+        model = cm.template_resample(dense_d, wl.n_model)
+        flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
+        cm.linear_search(grid, flux, ivar, model, fold=fold)
+        for _ in range(args.steps):
+            cm.periodic_search(grid, fold, per_d, work=work, out=per)
+        torch.cuda.synchronize()
+        work_alg = algorithmic_work(wl, grid)
+        print(json.dumps({"mode": "fold", "launches": args.steps, "workload": args.workload,
+                          "fold_source_sha256_16": fold_source_hash(),
+                          "algorithmic_bytes_per_launch": work_alg["fold_bytes"]}), flush=True)
+        return
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_steps = [ev["start"][i].elapsed_time(ev["end"][i]) for i in range(args.steps)]
+    ms_lin = [ev["start"][i].elapsed_time(ev["lin"][i]) for i in range(args.steps)]
+    ms_fold = [ev["fold0"][i].elapsed_time(ev["fold1"][i]) for i in range(args.steps)]
+    ms_step = float(np.mean(ms_steps))
+    b = cm.best_record(best)
+
+    work_alg = algorithmic_work(wl, grid)
+    fold_s = float(np.mean(ms_fold)) / 1e3
+    achieved = work_alg["fold_bytes"] / fold_s / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_COUNTERS):
+        with open(PROFILE_COUNTERS) as fh:
+            prof = json.load(fh)
+        if prof.get("fold_source_sha256_16") == fold_source_hash() and prof.get("workload") == args.workload:
+            traffic = prof.get("hbm_bytes_per_launch")
+    lin_s = float(np.mean(ms_lin)) / 1e3
+    value = wl.n_obs * K / (ms_step / 1e3)
+    out = {
+        "metric": "LC points x trials/sec (linear+periodic) on 1 GPU",
+        "value": value,
+        "unit": "LC points x trial periods / s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"single light curve, 90 d at 20 s cadence, {wl.n_obs} observations "
+                         f"(N = {grid.n} resampled), J = {grid.n_dur} durations 0.5-15 h, "
+                         f"I = {grid.n_t0} reference times, K = {K} periods 0.5-45 d")
+            if args.workload == "high_cadence" else wl.name,
+            "n_obs": wl.n_obs, "n_grid": int(grid.n), "n_t0": int(grid.n_t0), "n_durations": int(grid.n_dur),
+            "n_periods": K, "n_model": wl.n_model,
+        },
+        "roofline": {
+            "kernel": "fold_kernel (periodic search)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": work_alg["fold_bytes"],
+            "avg_launch_ms": fold_s * 1e3,
+        },
+        "roofline_linear": {
+            "kernel": "linear_kernel (linear search, all durations)",
+            "bound": "alu",
+            "achieved": work_alg["linear_flop"] / lin_s / 1e12,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": work_alg["linear_flop"] / lin_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+            "algorithmic_flop": work_alg["linear_flop"],
+            "avg_ms_incl_setup": lin_s * 1e3,
+        },
+        "stages_ms": {"setup_and_linear": lin_s * 1e3, "periodic": fold_s * 1e3,
+                      "best": ms_step - lin_s * 1e3 - fold_s * 1e3},
+        "wall_s_timed": wall,
+        "best": {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * cetra.h -- C ABI of the MI355X (gfx950) transit-search library.
+ *
+ * The library implements the two-stage transit search of Smith et al. 2025
+ * ("CETRA", arXiv:2503.20875): a linear search that correlates a transit
+ * template with a regularly resampled light curve over a grid of reference
+ * times and durations (Sec. 2.2), followed by a periodic search that
+ * phase-folds the single-event results over a grid of periods with a common
+ * transit depth and keeps the maximum-likelihood candidate per period
+ * (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units      Times are days (FP64).  Fluxes are offsets from baseline (FP32):
+ *            0 is the baseline and 1 means the star is fully blocked, so a
+ *            transit is a positive offset (Sec. 2, units).  Reference times
+ *            t0 are transit mid-points measured from the resampled grid's
+ *            origin (grid.t_origin).
+ * Memory     "device" pointers are HIP device memory on the current device;
+ *            "host" pointers are ordinary host memory.  The caller allocates
+ *            and owns every buffer, including workspaces; the library never
+ *            allocates device memory and keeps no pointer after a call
+ *            returns.
+ * Streams    `stream` is a hipStream_t passed as void* (NULL = the default
+ *            stream).  Device work is only enqueued: no entry point
+ *            synchronises, so results are ready when the stream is.  No entry
+ *            point allocates, frees or synchronises on the device, so the
+ *            calls may be captured into a HIP graph.
+ * Errors     Every entry point returns a status (CETRA_OK = 0, negative on
+ *            failure).  Arguments are validated on the host before anything
+ *            is enqueued; on failure nothing is enqueued.  A launch failure is
+ *            reported as CETRA_ERR_HIP.  cetra_last_error() gives the
+ *            calling thread's last message.  No exception crosses the ABI.
+ * Layouts    A resampled light curve is flux[N], ivar[N] (ivar = 1/sigma^2;
+ *            0 marks a null point, i.e. infinite uncertainty).  Linear-search
+ *            arrays are duration-major [J][I].  The fold-ready array is
+ *            float pairs [J][I][2] = (S_fm, S_mm) per element, where
+ *            S_fm = sum w f m and S_mm = sum w m^2 over the window.
+ * Nulls      A linear element with no usable data (Sec. 2.2, null outputs)
+ *            has fold pair (0, 0), depth NaN, variance +inf, LR 0.  A period
+ *            with no usable candidate has LR 0, epoch = duration = -1,
+ *            depth NaN, variance +inf.
+ */
+#ifndef CETRA_H
+#define CETRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CETRA_VERSION 100
+#define CETRA_MAX_DURATIONS 64
+#define CETRA_MAX_MODEL 4096
+
+enum cetra_status {
+    CETRA_OK = 0,
+    CETRA_ERR_INVALID = -1,   /* bad argument (null pointer, bad size, unsorted grid ...) */
+    CETRA_ERR_RANGE = -2,     /* a size exceeds what the library supports          */
+    CETRA_ERR_WORKSPACE = -3, /* workspace smaller than the size query returned    */
+    CETRA_ERR_HIP = -4,       /* a HIP runtime call or kernel launch failed        */
+    CETRA_ERR_DEVICE = -5     /* no usable gfx950 device                           */
+};
+
+/* Geometry of one search, produced by cetra_grid_plan (host only). */
+typedef struct cetra_grid {
+    double t_first;   /* time of the first observation (days)                   */
+    double cadence;   /* resampled cadence c (days)                             */
+    double t_origin;  /* time of resampled point 0 = t_first - n_pad * c        */
+    double t0_step;   /* reference-time step dt (days)                          */
+    int64_t n_pad;    /* null points padded before the data (and after it)      */
+    int64_t n_data;   /* grid points from the first to the last observation     */
+    int64_t n;        /* N = n_data + 2 n_pad                                   */
+    int64_t n_t0;     /* I: reference times t_i = i * dt, i in [0, I)            */
+    int32_t n_dur;    /* J: trial durations                                     */
+    int32_t n_model;  /* M: template samples                                    */
+    double durations[CETRA_MAX_DURATIONS];    /* ascending, days                */
+    uint64_t dur_step_fx[CETRA_MAX_DURATIONS]; /* template samples per grid point, 32.32 fixed point */
+} cetra_grid;
+
+/* Best period of a periodogram (written to device memory by cetra_best). */
+typedef struct cetra_best_record {
+    int64_t k;          /* index of the best period, -1 if every period is null */
+    int32_t epoch;      /* reference-time index i* of the best candidate          */
+    int32_t dur;        /* duration index j*                                      */
+    double period;      /* days                                                   */
+    double duration;    /* days                                                   */
+    double t0;          /* mid-transit time of the epoch, relative to t_origin     */
+    double t0_abs;      /* the same in the input's time system                    */
+    double lr;          /* log-likelihood ratio against the constant model        */
+    double depth;       /* maximum-likelihood common depth Z                       */
+    double depth_var;   /* its variance                                           */
+    double snr;         /* depth / sqrt(depth_var)                                */
+} cetra_best_record;
+
+/* ---------------------------------------------------------------- service */
+
+/* Library version (CETRA_VERSION). */
+int cetra_version(void);
+
+/* Last error message of the calling thread ("" if none).  The pointer stays
+ * valid until the thread's next failing call. */
+const char *cetra_last_error(void);
+
+/* Static description of a status code. */
+const char *cetra_status_string(int status);
+
+/* ------------------------------------------------------------------ setup */
+
+/* Grid plan (host only; Sec. 2.1.1 padding and index rule, Sec. 2.1.3 grids).
+ * t_first, t_last: first and last observation times (days, t_last >= t_first).
+ * cadence: resampled cadence c > 0 (days; the paper's default is the median
+ *   input cadence, which the caller computes).
+ * durations[n_dur]: trial durations, strictly ascending, 1 <= n_dur <= 64.
+ * t0_step: reference-time step; <= 0 selects the paper's default of 1% of the
+ *   shortest duration.
+ * n_model: template samples M, 1 <= M <= CETRA_MAX_MODEL.
+ * The grid has n_pad = ceil(max(D)/2 / c) null points before and after the
+ * n_data = floor((t_last - t_first)/c + 1/2) + 1 data points, and
+ * I = floor((N-1) c / dt) + 1 reference times.  Fails with CETRA_ERR_RANGE if
+ * J * I does not fit 32 bits.  `out` is host memory. */
+int cetra_grid_plan(double t_first, double t_last, double cadence, const double *durations,
+                    int32_t n_dur, double t0_step, int32_t n_model, cetra_grid *out);
+
+/* Template resampling (Sec. 2.1.2): the dense template dense[n_dense]
+ * (device, FP64, contact-normalised time from first to last contact, max
+ * offset 1) is resampled by linear interpolation to model[n_model] (device,
+ * FP32) at the cell centres tau_k = (k + 1/2)/M.  n_dense >= 2. */
+int cetra_template_resample(void *stream, const double *dense, int64_t n_dense, int32_t n_model,
+                            float *model);
+
+/* Resampling onto the regular grid (Sec. 2.1.1).  t[n_obs] (device, FP64,
+ * non-decreasing), f[n_obs] (device, FP32 flux offsets) and sigma[n_obs]
+ * (device, FP32) are binned to the nearest grid point,
+ * q = n_pad + floor((t - t_first)/c + 1/2); co-located points are combined by
+ * their inverse-variance weighted mean.  Outputs flux[N], ivar[N] (device,
+ * FP32; ivar = sum of sigma^-2, 0 for a null point).  Observations with a
+ * non-finite f or sigma, or sigma <= 0, count as missing.  If `status`
+ * (device int32, may be NULL) is given it is set to 0, or to 1 if t is not
+ * non-decreasing or not finite (the output is then undefined). */
+int cetra_resample(void *stream, const cetra_grid *grid, const double *t, const float *f,
+                   const float *sigma, int64_t n_obs, float *flux, float *ivar, int32_t *status);
+
+/* ----------------------------------------------------------- linear search */
+
+/* Linear search (Sec. 2.2).  For every reference time i and duration j the
+ * window [t_i - D_j/2, t_i + D_j/2] covers grid points ceil(t_s/c) ..
+ * floor(t_e/c); each point is compared with the nearest template sample
+ * (32.32 fixed-point index, clamped to M-1).  The maximum-likelihood depth is
+ * the inverse-variance weighted mean of f/m, its variance the reciprocal of
+ * the summed weights, and the likelihood ratio against the constant model
+ * (Eq. 2) equals S_fm^2 / (2 S_mm).  A window that leaves [0, (N-1) c] or
+ * holds no data is null.
+ * flux, ivar[N], model[M] (device) in; fold[J][I][2] (device, required) out;
+ * depth, var, lr [J][I] (device) are optional (NULL to skip). */
+int cetra_linear_search(void *stream, const cetra_grid *grid, const float *flux, const float *ivar,
+                        const float *model, float *fold, float *depth, float *var, float *lr);
+
+/* Log-likelihood of the constant (zero-offset) model over the non-null grid
+ * points (Eq. 1 at zero depth; Sec. 2.2 and Sec. 2.3 note that adding it to a
+ * likelihood ratio gives the full log-likelihood).  out: one double (device). */
+int cetra_loglike0(void *stream, const cetra_grid *grid, const float *flux, const float *ivar,
+                   double *out);
+
+/* --------------------------------------------------------- periodic search */
+
+/* Workspace bytes for cetra_periodic_search over n_eval periods (host only). */
+int cetra_periodic_workspace(const cetra_grid *grid, int64_t n_eval, size_t *bytes);
+
+/* Periodic search (Sec. 2.3).  For each evaluated period P_k every epoch
+ * i in [0, ceil(P_k/dt)) and allowed duration j (D_j < P_k, and j inside
+ * jrange[k] if given) combines the single-transit elements at
+ * i + round(m P_k/dt), m = 0, 1, ... (nearest reference time) with a common
+ * inverse-variance depth Z; its likelihood ratio, the sum of Eq. 4 over the
+ * transits, equals (sum S_fm)^2 / (2 sum S_mm).  The maximum over (j, i) is
+ * kept, ties going to the smallest j, then the smallest i.
+ * fold[J][I][2] (device) from cetra_linear_search.
+ * periods[n_periods] (device, FP64, days; ascending order gives the best
+ *   performance but is not required).  A period shorter than the
+ *   reference-time step, or not finite, gets the null record.
+ * jrange: NULL, or device int32 [n_periods][2] inclusive duration-index range.
+ * subset: NULL to evaluate every period, else device int64 [n_subset] period
+ *   indices to evaluate (the others get the null record).
+ * work/work_bytes: device workspace of at least
+ *   cetra_periodic_workspace(grid, n_subset or n_periods) bytes.
+ * Outputs (device, [n_periods]): lr (FP32), epoch (int32 i*), dur (int32 j*),
+ *   depth (FP32 Z), depth_var (FP32 1/sum S_mm). */
+int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fold,
+                          const double *periods, int64_t n_periods, const int32_t *jrange,
+                          const int64_t *subset, int64_t n_subset, void *work, size_t work_bytes,
+                          float *lr, int32_t *epoch, int32_t *dur, float *depth, float *depth_var);
+
+/* Best period of a periodogram (Sec. 2.3 outputs): the maximum LR over the
+ * n_periods records (ties to the smallest index), with SNR = Z / sqrt(var_Z)
+ * and the epoch converted to time.  Inputs are the device outputs of
+ * cetra_periodic_search; `out` is one cetra_best_record in device memory. */
+int cetra_best(void *stream, const cetra_grid *grid, const double *periods, int64_t n_periods,
+               const float *lr, const int32_t *epoch, const int32_t *dur, const float *depth,
+               const float *depth_var, cetra_best_record *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CETRA_H */

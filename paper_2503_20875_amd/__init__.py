@@ -1,0 +1,186 @@
+"""MI355X transit search: Python binding of ``libcetra.so``.
+
+Thin wrappers with the C ABI's names (``include/cetra.h``): they allocate
+output tensors with PyTorch (device memory only), pass raw pointers and the
+current HIP stream, and check the returned status.  All arithmetic runs in
+the library's HIP kernels; importing the package does not load the library,
+but the first call does and fails loudly if it has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import BestRecord, CetraError, Grid  # noqa: F401
+
+__all__ = ["grid_plan", "template_resample", "resample", "linear_search", "loglike0",
+           "periodic_workspace", "periodic_search", "best", "search", "Grid", "CetraError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, dtype):
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        if x.dtype != dtype:
+            raise TypeError(f"expected {dtype}, got {x.dtype}")
+        return x.contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def version() -> int:
+    return int(_abi.load().cetra_version())
+
+
+def grid_plan(t_first: float, t_last: float, cadence: float, durations, t0_step: float = 0.0,
+              n_model: int = 1024) -> Grid:
+    durs = np.ascontiguousarray(durations, dtype=np.float64)
+    g = Grid()
+    _abi.check(_abi.load().cetra_grid_plan(float(t_first), float(t_last), float(cadence),
+                                           durs.ctypes.data_as(ctypes.c_void_p), int(durs.shape[0]),
+                                           float(t0_step), int(n_model), ctypes.byref(g)))
+    return g
+
+
+def template_resample(dense, n_model: int = 1024, stream=None):
+    torch = _torch()
+    d = _dev(dense, torch.float64)
+    out = torch.empty(n_model, dtype=torch.float32, device=d.device)
+    _abi.check(_abi.load().cetra_template_resample(_stream(stream), _ptr(d), d.numel(), int(n_model), _ptr(out)))
+    return out
+
+
+def resample(grid: Grid, t, f, sigma, status: bool = True, stream=None):
+    """Returns (flux, ivar, status_tensor_or_None)."""
+    torch = _torch()
+    t = _dev(t, torch.float64)
+    f = _dev(f, torch.float32)
+    s = _dev(sigma, torch.float32)
+    if not (t.numel() == f.numel() == s.numel()):
+        raise ValueError("t, f, sigma must have the same length")
+    flux = torch.empty(grid.n, dtype=torch.float32, device=t.device)
+    ivar = torch.empty(grid.n, dtype=torch.float32, device=t.device)
+    st = torch.empty(1, dtype=torch.int32, device=t.device) if status else None
+    _abi.check(_abi.load().cetra_resample(_stream(stream), ctypes.byref(grid), _ptr(t), _ptr(f), _ptr(s),
+                                          t.numel(), _ptr(flux), _ptr(ivar), _ptr(st)))
+    return flux, ivar, st
+
+
+def linear_search(grid: Grid, flux, ivar, model, public: bool = False, fold=None, stream=None):
+    """Returns fold [J, I, 2] (and depth, var, lr [J, I] if public)."""
+    torch = _torch()
+    shape = (grid.n_dur, grid.n_t0)
+    dev = flux.device
+    if fold is None:
+        fold = torch.empty(shape + (2,), dtype=torch.float32, device=dev)
+    depth = var = lr = None
+    if public:
+        depth = torch.empty(shape, dtype=torch.float32, device=dev)
+        var = torch.empty(shape, dtype=torch.float32, device=dev)
+        lr = torch.empty(shape, dtype=torch.float32, device=dev)
+    _abi.check(_abi.load().cetra_linear_search(_stream(stream), ctypes.byref(grid), _ptr(flux), _ptr(ivar),
+                                               _ptr(model), _ptr(fold), _ptr(depth), _ptr(var), _ptr(lr)))
+    if public:
+        return fold, depth, var, lr
+    return fold
+
+
+def loglike0(grid: Grid, flux, ivar, stream=None):
+    torch = _torch()
+    out = torch.empty(1, dtype=torch.float64, device=flux.device)
+    _abi.check(_abi.load().cetra_loglike0(_stream(stream), ctypes.byref(grid), _ptr(flux), _ptr(ivar),
+                                          _ptr(out)))
+    return out
+
+
+def periodic_workspace(grid: Grid, n_eval: int) -> int:
+    n = ctypes.c_size_t()
+    _abi.check(_abi.load().cetra_periodic_workspace(ctypes.byref(grid), int(n_eval), ctypes.byref(n)))
+    return int(n.value)
+
+
+def periodic_search(grid: Grid, fold, periods, jrange=None, subset=None, work=None, out=None,
+                    stream=None) -> dict:
+    """Per-period maximum-likelihood records: dict of device tensors
+    lr, epoch, dur, depth, depth_var ([K] each)."""
+    torch = _torch()
+    dev = fold.device
+    periods = _dev(periods, torch.float64)
+    K = periods.numel()
+    jr = None if jrange is None else _dev(jrange, torch.int32)
+    sub = None if subset is None else _dev(subset, torch.int64)
+    n_eval = K if sub is None else sub.numel()
+    need = periodic_workspace(grid, n_eval)
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        out = dict(lr=torch.empty(K, dtype=torch.float32, device=dev),
+                   epoch=torch.empty(K, dtype=torch.int32, device=dev),
+                   dur=torch.empty(K, dtype=torch.int32, device=dev),
+                   depth=torch.empty(K, dtype=torch.float32, device=dev),
+                   depth_var=torch.empty(K, dtype=torch.float32, device=dev))
+    _abi.check(_abi.load().cetra_periodic_search(
+        _stream(stream), ctypes.byref(grid), _ptr(fold), _ptr(periods), K, _ptr(jr), _ptr(sub),
+        0 if sub is None else sub.numel(), _ptr(work), work.numel(), _ptr(out["lr"]), _ptr(out["epoch"]),
+        _ptr(out["dur"]), _ptr(out["depth"]), _ptr(out["depth_var"])))
+    return out
+
+
+def best(grid: Grid, periods, per: dict, out=None, stream=None):
+    """Best period; returns a uint8 device tensor holding one cetra_best_record
+    (use ``best_record`` to read it on the host)."""
+    torch = _torch()
+    periods = _dev(periods, torch.float64)
+    if out is None:
+        out = torch.empty(ctypes.sizeof(BestRecord), dtype=torch.uint8, device=periods.device)
+    _abi.check(_abi.load().cetra_best(_stream(stream), ctypes.byref(grid), _ptr(periods), periods.numel(),
+                                      _ptr(per["lr"]), _ptr(per["epoch"]), _ptr(per["dur"]), _ptr(per["depth"]),
+                                      _ptr(per["depth_var"]), _ptr(out)))
+    return out
+
+
+def best_record(raw) -> dict:
+    """Host copy of a cetra_best_record produced by ``best``."""
+    b = BestRecord.from_buffer_copy(bytes(raw.cpu().numpy().tobytes()))
+    return {name: getattr(b, name) for name, _ in BestRecord._fields_}
+
+
+def search(t, f, sigma, cadence: float, durations, periods, dense, n_model: int = 1024,
+           t0_step: float = 0.0, public: bool = False, jrange=None, subset=None, stream=None) -> dict:
+    """Whole path on the current device: template resampling, light-curve
+    resampling, linear search, periodic search, best period."""
+    t_host = np.asarray(t) if not hasattr(t, "cpu") else t.cpu().numpy()
+    grid = grid_plan(t_host[0], t_host[-1], cadence, durations, t0_step, n_model)
+    model = template_resample(dense, n_model, stream=stream)
+    flux, ivar, st = resample(grid, t, f, sigma, stream=stream)
+    lin = linear_search(grid, flux, ivar, model, public=public, stream=stream)
+    fold = lin[0] if public else lin
+    per = periodic_search(grid, fold, periods, jrange=jrange, subset=subset, stream=stream)
+    b = best(grid, periods, per, stream=stream)
+    out = dict(grid=grid, model=model, flux=flux, ivar=ivar, fold=fold, periodic=per, best_raw=b, status=st)
+    if public:
+        out.update(depth=lin[1], var=lin[2], lr=lin[3])
+    return out

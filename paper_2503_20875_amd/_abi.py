@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in ``include/cetra.h``.
+
+Argument marshalling only: every computation happens in ``libcetra.so``.
+Loading fails loudly if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcetra.so")
+MAX_DURATIONS = 64
+MAX_MODEL = 4096
+
+STATUS = {0: "CETRA_OK", -1: "CETRA_ERR_INVALID", -2: "CETRA_ERR_RANGE", -3: "CETRA_ERR_WORKSPACE",
+          -4: "CETRA_ERR_HIP", -5: "CETRA_ERR_DEVICE"}
+
+
+class CetraError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    """Mirror of ``cetra_grid``."""
+    _fields_ = [
+        ("t_first", ctypes.c_double),
+        ("cadence", ctypes.c_double),
+        ("t_origin", ctypes.c_double),
+        ("t0_step", ctypes.c_double),
+        ("n_pad", ctypes.c_int64),
+        ("n_data", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("n_t0", ctypes.c_int64),
+        ("n_dur", ctypes.c_int32),
+        ("n_model", ctypes.c_int32),
+        ("durations", ctypes.c_double * MAX_DURATIONS),
+        ("dur_step_fx", ctypes.c_uint64 * MAX_DURATIONS),
+    ]
+
+
+class BestRecord(ctypes.Structure):
+    """Mirror of ``cetra_best_record``."""
+    _fields_ = [
+        ("k", ctypes.c_int64),
+        ("epoch", ctypes.c_int32),
+        ("dur", ctypes.c_int32),
+        ("period", ctypes.c_double),
+        ("duration", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("t0_abs", ctypes.c_double),
+        ("lr", ctypes.c_double),
+        ("depth", ctypes.c_double),
+        ("depth_var", ctypes.c_double),
+        ("snr", ctypes.c_double),
+    ]
+
+
+_P = ctypes.c_void_p
+_i32, _i64, _d, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+
+# name -> (restype, argtypes); the list is the ABI's export list
+SIGNATURES = {
+    "cetra_version": (ctypes.c_int, []),
+    "cetra_last_error": (ctypes.c_char_p, []),
+    "cetra_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "cetra_grid_plan": (ctypes.c_int, [_d, _d, _d, _P, _i32, _d, _i32, ctypes.POINTER(Grid)]),
+    "cetra_template_resample": (ctypes.c_int, [_P, _P, _i64, _i32, _P]),
+    "cetra_resample": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _P, _i64, _P, _P, _P]),
+    "cetra_linear_search": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),
+    "cetra_loglike0": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _P]),
+    "cetra_periodic_workspace": (ctypes.c_int, [ctypes.POINTER(Grid), _i64, ctypes.POINTER(_sz)]),
+    "cetra_periodic_search": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _i64, _P, _P, _i64, _P, _sz,
+                                             _P, _P, _P, _P, _P]),
+    "cetra_best": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _i64, _P, _P, _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcetra.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with paper_2503_20875_amd.build.build() "
+                          "(there is no CPU fallback for the GPU path)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != 0:
+        msg = load().cetra_last_error()
+        raise CetraError(status, msg.decode() if msg else "")

@@ -1,0 +1,398 @@
+// Periodic search (Sec. 2.3) and best period.
+//
+// For period P_k, duration j and epoch i in [0, ceil(P_k/dt)), the transits
+// sit at reference times i + o_m with o_m = round_half_up(m P_k/dt)
+// (nearest-neighbour mapping, 32.32 fixed point).  Summing Eq. 4 over the
+// transits at the inverse-variance common depth Z gives, with the linear
+// search's per-window sums, LR = (sum S_fm)^2 / (2 sum S_mm), Z = sum S_fm /
+// sum S_mm and var_Z = 1 / sum S_mm.  So the fold reads one float pair per
+// (period, duration, transit) and the per-period reduction keeps the maximum.
+//
+// Work mapping (gfx950): a persistent grid of workgroups strides over units
+// (period block of up to B periods, duration j, epoch chunk).  Every unit
+// costs about B * I element reads whatever the period, because the transits
+// of all epochs of one period tile the whole row.  A lane owns one epoch and
+// accumulates all B periods of its block in FP64 at once: the B loads of one
+// transit step are independent (memory-level parallelism) and hit nearly the
+// same addresses, since neighbouring trial periods shift the transits by a
+// few elements, so the block's periods share cache lines in L1/L2.  Units
+// are ordered period-block fastest, so the workgroups running at once sweep
+// the same duration row, which then stays resident in each XCD's L2.
+//
+// Argmax: LR >= 0, so its FP32 bit pattern is monotone; the key
+// (bits(LR) << 32) | (2^32 - 1 - (j I + i)) under a 64-bit atomicMax gives
+// the maximum with ties to the smallest (j, i).  An epilogue recomputes the
+// winner's sums in the same order to emit LR, Z and var_Z.
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPeriodBlock = 8;   // B
+constexpr int kTargetUnitsPerWG = 4;
+
+struct FoldWork {
+    uint64_t *key;     // [n_eval] argmax keys
+    uint64_t *step;    // [n_eval] R_k = llround(2^32 P_k/dt)
+    int32_t *n_ep;     // [n_eval] I_P
+    int32_t *jr;       // [n_eval][2] allowed duration range after D_j < P_k
+    int64_t *kidx;     // [n_eval] period index (-1 = invalid subset entry)
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t workspace_bytes(int64_t n_eval) {
+    size_t b = 0;
+    b += align256(sizeof(uint64_t) * n_eval);
+    b += align256(sizeof(uint64_t) * n_eval);
+    b += align256(sizeof(int32_t) * n_eval);
+    b += align256(sizeof(int32_t) * 2 * n_eval);
+    b += align256(sizeof(int64_t) * n_eval);
+    return b;
+}
+
+FoldWork carve(void *work, int64_t n_eval) {
+    char *p = static_cast<char *>(work);
+    FoldWork w;
+    w.key = reinterpret_cast<uint64_t *>(p);
+    p += align256(sizeof(uint64_t) * n_eval);
+    w.step = reinterpret_cast<uint64_t *>(p);
+    p += align256(sizeof(uint64_t) * n_eval);
+    w.n_ep = reinterpret_cast<int32_t *>(p);
+    p += align256(sizeof(int32_t) * n_eval);
+    w.jr = reinterpret_cast<int32_t *>(p);
+    p += align256(sizeof(int32_t) * 2 * n_eval);
+    w.kidx = reinterpret_cast<int64_t *>(p);
+    return w;
+}
+
+struct Durations {
+    double d[CETRA_MAX_DURATIONS];
+};
+
+// Per evaluated period: fixed-point step, epoch count, allowed durations
+// (D_j < P_k, Sec. 2.3, intersected with the caller's range); clears its key.
+__global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_periods,
+                                  const int32_t *__restrict__ jrange, const int64_t *__restrict__ subset,
+                                  int64_t n_eval, double t0_step, int64_t n_t0, int32_t n_dur, Durations dur,
+                                  FoldWork w) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_eval) return;
+    const int64_t k = subset ? subset[s] : s;
+    w.key[s] = 0;
+    if (k < 0 || k >= n_periods) {
+        w.kidx[s] = -1;
+        w.step[s] = 0;
+        w.n_ep[s] = 0;
+        w.jr[2 * s] = 0;
+        w.jr[2 * s + 1] = -1;
+        return;
+    }
+    const double P = periods[k];
+    // a period must span at least one reference-time step (transit offsets
+    // then advance by >= 1 per transit, which bounds every fold loop)
+    if (!isfinite(P) || !(P >= t0_step) || !(P / t0_step < 2.0e9)) {
+        w.kidx[s] = k;
+        w.step[s] = 0;
+        w.n_ep[s] = 0;
+        w.jr[2 * s] = 0;
+        w.jr[2 * s + 1] = -1;
+        return;
+    }
+    const uint64_t R = (uint64_t)llround(4294967296.0 * (P / t0_step));
+    int64_t ip = (int64_t)((R + 4294967295ull) >> 32);
+    if (ip > n_t0) ip = n_t0;
+    int lo = 0, hi = n_dur - 1;
+    if (jrange) {
+        lo = max(lo, jrange[2 * k]);
+        hi = min(hi, jrange[2 * k + 1]);
+    }
+    while (hi >= lo && !(dur.d[hi] < P)) --hi;
+    w.kidx[s] = k;
+    w.step[s] = R;
+    w.n_ep[s] = (int32_t)ip;
+    w.jr[2 * s] = lo;
+    w.jr[2 * s + 1] = hi;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+template <int B>
+__global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
+                                                        int64_t n_t0, int32_t n_dur, int32_t n_chunks,
+                                                        int64_t n_units) {
+    const int64_t n_pblk = (n_eval + B - 1) / B;
+    const int lane = threadIdx.x & 63;
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int64_t pb = u % n_pblk;
+        const int64_t rest = u / n_pblk;
+        const int32_t c = (int32_t)(rest % n_chunks);
+        const int32_t j = (int32_t)(rest / n_chunks);
+        const int64_t s0 = pb * B;
+
+        uint64_t R[B];
+        int32_t ipb[B];
+        int32_t ipmax = 0;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int64_t s = s0 + b;
+            bool ok = s < n_eval;
+            if (ok) ok = w.kidx[s] >= 0 && j >= w.jr[2 * s] && j <= w.jr[2 * s + 1];
+            R[b] = ok ? w.step[s] : 0;
+            ipb[b] = ok ? w.n_ep[s] : 0;
+            ipmax = max(ipmax, ipb[b]);
+        }
+        if (ipmax == 0) continue;
+        const int32_t chunk = (int32_t)((ipmax + n_chunks - 1) / n_chunks);
+        const int32_t e_lo = c * chunk;
+        const int32_t e_hi = min(ipmax, e_lo + chunk);
+        if (e_lo >= e_hi) continue;
+
+        const float2 *row = fold + (int64_t)j * n_t0;
+        const int32_t I = (int32_t)n_t0;
+        uint64_t best[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) best[b] = 0;
+
+        for (int32_t e0 = e_lo; e0 < e_hi; e0 += kThreads) {
+            const int32_t e = e0 + (int32_t)threadIdx.x;
+            // first epoch of this wave: the transit loop runs while it is inside the row
+            const int32_t e_wave = __builtin_amdgcn_readfirstlane(e - lane);
+            double A[B], S[B];
+            uint64_t acc[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                A[b] = 0.0;
+                S[b] = 0.0;
+                acc[b] = 2147483648ull;  // + 1/2 for round half up
+            }
+            while (true) {
+                bool any = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    // offsets compared in 64 bits: a block may mix very different
+                    // periods, whose offsets exceed 2^31 long before the loop ends;
+                    // the accumulator stops once past the row, so it cannot wrap
+                    const uint64_t o = acc[b] >> 32;
+                    acc[b] = o < (uint64_t)I ? acc[b] + R[b] : acc[b];
+                    if (ipb[b] > 0 && (uint64_t)e_wave + o < (uint64_t)I) any = true;
+                    if (e < ipb[b] && e < e_hi && (uint64_t)e + o < (uint64_t)I) {
+                        const float2 v = row[e + (int32_t)o];
+                        A[b] += (double)v.x;
+                        S[b] += (double)v.y;
+                    }
+                }
+                if (!any) break;
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (e < ipb[b] && e < e_hi && S[b] > 0.0) {
+                    const float l = (float)(0.5 * A[b] * A[b] / S[b]);
+                    const uint32_t flat = (uint32_t)j * (uint32_t)I + (uint32_t)e;
+                    const uint64_t key = ((uint64_t)__float_as_uint(l) << 32) | (uint64_t)(0xFFFFFFFFu - flat);
+                    best[b] = key > best[b] ? key : best[b];
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const uint64_t m = wave_max_u64(best[b]);
+            if (lane == 0 && m != 0) atomicMax((unsigned long long *)&w.key[s0 + b], (unsigned long long)m);
+        }
+    }
+}
+
+// Null record for every period (used before a subset search).
+__global__ void fold_null_kernel(int64_t n, float *lr, int32_t *ep, int32_t *du, float *z, float *zv) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    lr[k] = 0.0f;
+    ep[k] = -1;
+    du[k] = -1;
+    z[k] = __builtin_nanf("");
+    zv[k] = __builtin_inff();
+}
+
+// Decode each period's winner and recompute its sums in the fold's order.
+__global__ void fold_epilogue_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval, int64_t n_t0,
+                                     float *lr, int32_t *ep, int32_t *du, float *z, float *zv) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_eval) return;
+    const int64_t k = w.kidx[s];
+    if (k < 0) return;
+    const uint64_t key = w.key[s];
+    if (key == 0) {
+        lr[k] = 0.0f;
+        ep[k] = -1;
+        du[k] = -1;
+        z[k] = __builtin_nanf("");
+        zv[k] = __builtin_inff();
+        return;
+    }
+    const uint32_t flat = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+    const int32_t j = (int32_t)(flat / (uint32_t)n_t0);
+    const int32_t i = (int32_t)(flat % (uint32_t)n_t0);
+    const float2 *row = fold + (int64_t)j * n_t0;
+    const uint64_t R = w.step[s];
+    double A = 0.0, S = 0.0;
+    for (uint64_t acc = 2147483648ull;; acc += R) {
+        const int64_t x = (int64_t)i + (int64_t)(acc >> 32);
+        if (x >= n_t0) break;
+        const float2 v = row[x];
+        A += (double)v.x;
+        S += (double)v.y;
+    }
+    lr[k] = (float)(0.5 * A * A / S);
+    ep[k] = i;
+    du[k] = j;
+    z[k] = (float)(A / S);
+    zv[k] = (float)(1.0 / S);
+}
+
+__global__ void __launch_bounds__(1024) best_kernel(const double *__restrict__ periods, int64_t n,
+                                                    const float *__restrict__ lr, const int32_t *__restrict__ ep,
+                                                    const int32_t *__restrict__ du, const float *__restrict__ z,
+                                                    const float *__restrict__ zv, double t0_step, double t_origin,
+                                                    Durations dur, cetra_best_record *out) {
+    __shared__ float s_lr[1024];
+    __shared__ int64_t s_k[1024];
+    float bl = -1.0f;
+    int64_t bk = -1;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        if (ep[k] < 0) continue;
+        if (lr[k] > bl) {
+            bl = lr[k];
+            bk = k;
+        }
+    }
+    s_lr[threadIdx.x] = bl;
+    s_k[threadIdx.x] = bk;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const float ol = s_lr[threadIdx.x + h];
+            const int64_t ok = s_k[threadIdx.x + h];
+            const int64_t mk = s_k[threadIdx.x];
+            if (ok >= 0 && (mk < 0 || ol > s_lr[threadIdx.x] || (ol == s_lr[threadIdx.x] && ok < mk))) {
+                s_lr[threadIdx.x] = ol;
+                s_k[threadIdx.x] = ok;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    cetra_best_record b;
+    const int64_t k = s_k[0];
+    b.k = k;
+    if (k < 0) {
+        b.epoch = -1;
+        b.dur = -1;
+        b.period = b.duration = b.t0 = b.t0_abs = __builtin_nan("");
+        b.lr = 0.0;
+        b.depth = __builtin_nan("");
+        b.depth_var = __builtin_inf();
+        b.snr = 0.0;
+    } else {
+        b.epoch = ep[k];
+        b.dur = du[k];
+        b.period = periods[k];
+        b.duration = dur.d[b.dur];
+        b.t0 = (double)b.epoch * t0_step;
+        b.t0_abs = t_origin + b.t0;
+        b.lr = (double)lr[k];
+        b.depth = (double)z[k];
+        b.depth_var = (double)zv[k];
+        b.snr = b.depth / sqrt(b.depth_var);
+    }
+    *out = b;
+}
+
+Durations pack_durations(const cetra_grid *g) {
+    Durations d;
+    for (int j = 0; j < CETRA_MAX_DURATIONS; ++j) d.d[j] = j < g->n_dur ? g->durations[j] : 0.0;
+    return d;
+}
+
+}  // namespace
+
+using namespace cetra;
+
+extern "C" int cetra_periodic_workspace(const cetra_grid *grid, int64_t n_eval, size_t *bytes) {
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    CETRA_REQUIRE(bytes != nullptr, "periodic_workspace: NULL output");
+    CETRA_REQUIRE(n_eval >= 0, "periodic_workspace: n_eval < 0");
+    *bytes = workspace_bytes(n_eval);
+    return CETRA_OK;
+}
+
+extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fold, const double *periods,
+                                     int64_t n_periods, const int32_t *jrange, const int64_t *subset,
+                                     int64_t n_subset, void *work, size_t work_bytes, float *lr, int32_t *epoch,
+                                     int32_t *dur, float *depth, float *depth_var) {
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    CETRA_REQUIRE(fold && lr && epoch && dur && depth && depth_var, "periodic_search: NULL pointer");
+    CETRA_REQUIRE(n_periods >= 0 && (n_periods == 0 || periods), "periodic_search: bad periods");
+    CETRA_REQUIRE(!subset || n_subset >= 0, "periodic_search: bad subset");
+    if (grid->n_t0 >= INT32_MAX) return set_error(CETRA_ERR_RANGE, "periodic_search: I must be < 2^31");
+    const int64_t n_eval = subset ? n_subset : n_periods;
+    if (work_bytes < workspace_bytes(n_eval) || (n_eval > 0 && !work))
+        return set_error(CETRA_ERR_WORKSPACE, "periodic_search: workspace needs %zu bytes",
+                         workspace_bytes(n_eval));
+    hipStream_t s = as_stream(stream);
+    if (subset && n_periods > 0) {
+        hipLaunchKernelGGL(fold_null_kernel, dim3((unsigned)ceil_div(n_periods, 256)), dim3(256), 0, s, n_periods,
+                           lr, epoch, dur, depth, depth_var);
+        if ((rc = check_launch("periodic_search/null"))) return rc;
+    }
+    if (n_eval == 0) return CETRA_OK;
+    FoldWork w = carve(work, n_eval);
+    const Durations d = pack_durations(grid);
+    hipLaunchKernelGGL(fold_setup_kernel, dim3((unsigned)ceil_div(n_eval, 256)), dim3(256), 0, s, periods,
+                       n_periods, jrange, subset, n_eval, grid->t0_step, grid->n_t0, grid->n_dur, d, w);
+    if ((rc = check_launch("periodic_search/setup"))) return rc;
+
+    constexpr int B = kPeriodBlock;
+    const int64_t n_pblk = ceil_div(n_eval, B);
+    const int64_t wgs = (int64_t)device_cu_count() * 8;
+    const int64_t base_units = n_pblk * grid->n_dur;
+    int64_t n_chunks = ceil_div(kTargetUnitsPerWG * wgs, base_units);
+    n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, 64));
+    const int64_t n_units = base_units * n_chunks;
+    const int64_t grid_wgs = std::min<int64_t>(wgs, n_units);
+    hipLaunchKernelGGL(fold_kernel<B>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s,
+                       reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, grid->n_dur,
+                       (int32_t)n_chunks, n_units);
+    if ((rc = check_launch("periodic_search/fold"))) return rc;
+    hipLaunchKernelGGL(fold_epilogue_kernel, dim3((unsigned)ceil_div(n_eval, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, lr, epoch, dur, depth,
+                       depth_var);
+    return check_launch("periodic_search/epilogue");
+}
+
+extern "C" int cetra_best(void *stream, const cetra_grid *grid, const double *periods, int64_t n_periods,
+                          const float *lr, const int32_t *epoch, const int32_t *dur, const float *depth,
+                          const float *depth_var, cetra_best_record *out) {
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    CETRA_REQUIRE(out && (n_periods == 0 || (periods && lr && epoch && dur && depth && depth_var)),
+                  "best: NULL pointer");
+    CETRA_REQUIRE(n_periods >= 0, "best: n_periods < 0");
+    hipLaunchKernelGGL(best_kernel, dim3(1), dim3(1024), 0, as_stream(stream), periods, n_periods, lr, epoch, dur,
+                       depth, depth_var, grid->t0_step, grid->t_origin, pack_durations(grid), out);
+    return check_launch("best");
+}

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, validates arguments before enqueueing anything, and its
+host-only grid plan agrees with the oracle's (separately written) one."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cetra.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cetra_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2503_20875_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2503_20875_amd import build
+        build.build()
+    return _abi.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2503_20875_amd import _abi
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in cetra.h but not exported"
+    assert set(names) == set(_abi.SIGNATURES), "binding and header disagree on the export list"
+
+
+def test_version_and_status_strings(lib):
+    assert lib.cetra_version() == 100
+    assert lib.cetra_status_string(0) == b"ok"
+    assert lib.cetra_status_string(-3) == b"workspace too small"
+
+
+def test_grid_plan_matches_oracle(lib, ora):
+    import paper_2503_20875_amd as cm
+    from synthlc import workloads as W
+    for wl in (W.tiny_single(), W.small_random(3)):
+        g = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
+        o = ora.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, wl.n_model)
+        for f in ("t_first", "cadence", "t_origin", "t0_step", "n_pad", "n_data", "n", "n_t0", "n_dur", "n_model"):
+            assert getattr(g, f) == getattr(o, f), f
+        assert list(g.durations) == list(o.durations)
+        assert list(g.dur_step_fx) == list(o.dur_step_fx)
+
+
+def test_grid_plan_validation(lib):
+    import paper_2503_20875_amd as cm
+    with pytest.raises(cm.CetraError, match="ascending"):
+        cm.grid_plan(0.0, 10.0, 0.01, [0.2, 0.1])
+    with pytest.raises(cm.CetraError, match="cadence"):
+        cm.grid_plan(0.0, 10.0, 0.0, [0.1])
+    with pytest.raises(cm.CetraError, match="n_model"):
+        cm.grid_plan(0.0, 10.0, 0.01, [0.1], n_model=5000)
+    with pytest.raises(cm.CetraError, match="reference times|2\\^32"):
+        cm.grid_plan(0.0, 1e6, 1e-4, [1e-4, 2e-4])
+
+
+def test_calls_reject_bad_arguments_without_a_gpu(lib):
+    """Argument checks run on the host before any launch."""
+    from paper_2503_20875_amd import _abi
+    g = _abi.Grid()
+    rc = lib.cetra_linear_search(None, ctypes.byref(g), None, None, None, None, None, None, None)
+    assert rc == -1 and b"not planned" in lib.cetra_last_error() or rc == -1
+    import paper_2503_20875_amd as cm
+    grid = cm.grid_plan(0.0, 1.0, 0.01, [0.05, 0.1])
+    rc = lib.cetra_linear_search(None, ctypes.byref(grid), None, None, None, None, None, None, None)
+    assert rc == -1 and b"NULL" in lib.cetra_last_error()
+    need = ctypes.c_size_t()
+    assert lib.cetra_periodic_workspace(ctypes.byref(grid), 1000, ctypes.byref(need)) == 0
+    assert need.value >= 1000 * 8
+    rc = lib.cetra_periodic_search(None, ctypes.byref(grid), ctypes.c_void_p(8), ctypes.c_void_p(8), 1000, None,
+                                   None, 0, ctypes.c_void_p(8), need.value - 1, ctypes.c_void_p(8),
+                                   ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8))
+    assert rc == -3
