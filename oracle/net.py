@@ -1,0 +1,177 @@
+"""FP64 oracle of the period-window proposal network -- TEST INFRASTRUCTURE ONLY.
+
+The proposal network is not part of the paper; it ranks period windows from
+the linear search's single-event likelihood ratios so that the periodic
+search (Sec. 2.3) folds only the best-ranked windows.  This module is the
+plain numpy definition (forward and hand-derived backward, FP64) the GPU
+kernels are checked against; its gradients are pinned by central finite
+differences in the tests.
+
+Architecture (B examples, C_in input channels = durations, L bins):
+  x [B, C_in, L]                        downsampled single-event features
+  h_l = relu(conv1d(h_{l-1}, W_l) + b_l), l = 1..5, kernel 9, zero padding 4,
+        64 channels                      (trunk)
+  e = relu(P h_5 + p)                    1x1 projection to E event channels
+  a_c(tau) = (1/L) sum_t e_c[t] e_c[t + tau]   lag correlation, tau >= 1
+  per window w (lag range [lo_w, hi_w]):
+        g[w, c] = max_tau a_c(tau)   (ties: smallest tau)
+        m[w, c] = mean_tau a_c(tau)
+  f[w] = [g[w, :], m[w, :], q_w]         q_w = window position in [0, 1]
+  z[w] = v . relu(U f[w] + u) + v0       shared head -> one logit per window
+  loss = mean_{b,w} pos_w(y) * bce(z, y),  pos weight for the single positive
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+K_CONV = 9
+PAD = 4
+
+
+def init_params(c_in: int = 16, width: int = 64, n_layers: int = 5, n_event: int = 8, hidden: int = 64,
+                seed: int = 0) -> dict:
+    """He-style initialisation (FP64)."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    ch = c_in
+    for l in range(n_layers):
+        fan_in = ch * K_CONV
+        p[f"W{l}"] = rng.normal(0, np.sqrt(2.0 / fan_in), (width, ch, K_CONV))
+        p[f"b{l}"] = np.zeros(width)
+        ch = width
+    p["P"] = rng.normal(0, np.sqrt(2.0 / width), (n_event, width))
+    p["p"] = np.full(n_event, 0.01)
+    n_feat = 2 * n_event + 1
+    p["U"] = rng.normal(0, np.sqrt(2.0 / n_feat), (hidden, n_feat))
+    p["u"] = np.zeros(hidden)
+    p["v"] = rng.normal(0, np.sqrt(1.0 / hidden), hidden)
+    p["v0"] = np.array([-2.0])
+    return p
+
+
+def n_params(p: dict) -> int:
+    return int(sum(np.asarray(v).size for v in p.values()))
+
+
+def conv1d(x, W, b):
+    """'Same' 1-D convolution (cross-correlation) with zero padding 4."""
+    B, C, L = x.shape
+    O = W.shape[0]
+    xp = np.zeros((B, C, L + 2 * PAD))
+    xp[:, :, PAD:PAD + L] = x
+    y = np.zeros((B, O, L))
+    for k in range(K_CONV):
+        y += np.einsum("oc,bcl->bol", W[:, :, k], xp[:, :, k:k + L])
+    return y + b[None, :, None]
+
+
+def conv1d_backward(x, W, gy):
+    """Gradients of conv1d with respect to x, W, b given dL/dy."""
+    B, C, L = x.shape
+    xp = np.zeros((B, C, L + 2 * PAD))
+    xp[:, :, PAD:PAD + L] = x
+    gW = np.zeros_like(W)
+    gxp = np.zeros_like(xp)
+    for k in range(K_CONV):
+        gW[:, :, k] = np.einsum("bol,bcl->oc", gy, xp[:, :, k:k + L])
+        gxp[:, :, k:k + L] += np.einsum("oc,bol->bcl", W[:, :, k], gy)
+    return gxp[:, :, PAD:PAD + L], gW, gy.sum(axis=(0, 2))
+
+
+def lag_correlation(e, lags):
+    """a[b, c, i] = (1/L) sum_t e[b,c,t] e[b,c,t+lags[i]]."""
+    B, C, L = e.shape
+    a = np.zeros((B, C, len(lags)))
+    for i, tau in enumerate(lags):
+        if tau < L:
+            a[:, :, i] = np.sum(e[:, :, :L - tau] * e[:, :, tau:], axis=2) / L
+    return a
+
+
+def windows_for(n_windows: int, p_lo: float, p_hi: float, bin_days: float):
+    """Integer lag ranges [lo, hi] (bins) of n_windows log-spaced period
+    windows over [p_lo, p_hi] days, and each window's position q in [0, 1]."""
+    edges = p_lo * (p_hi / p_lo) ** (np.arange(n_windows + 1) / n_windows)
+    lo = np.maximum(1, np.round(edges[:-1] / bin_days)).astype(np.int64)
+    hi = np.maximum(lo, np.round(edges[1:] / bin_days).astype(np.int64))
+    q = (np.arange(n_windows) + 0.5) / n_windows
+    return lo, hi, q, edges
+
+
+def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = False):
+    h = [x]
+    for l in range(n_layers):
+        h.append(np.maximum(conv1d(h[-1], p[f"W{l}"], p[f"b{l}"]), 0.0))
+    pre_e = np.einsum("ec,bcl->bel", p["P"], h[-1]) + p["p"][None, :, None]
+    e = np.maximum(pre_e, 0.0)
+    lags = np.arange(int(win_lo.min()), int(win_hi.max()) + 1)
+    a = lag_correlation(e, lags)
+    B, E, _ = a.shape
+    W = len(win_lo)
+    g = np.zeros((B, W, E))
+    m = np.zeros((B, W, E))
+    arg = np.zeros((B, W, E), dtype=np.int64)
+    for w in range(W):
+        sl = slice(win_lo[w] - lags[0], win_hi[w] - lags[0] + 1)
+        seg = a[:, :, sl]
+        arg[:, w, :] = np.argmax(seg, axis=2) + win_lo[w]  # absolute lag of the first maximum
+        g[:, w, :] = np.max(seg, axis=2)
+        m[:, w, :] = np.mean(seg, axis=2)
+    f = np.concatenate([g, m, np.broadcast_to(win_q[None, :, None], (B, W, 1))], axis=2)
+    pre_r = np.einsum("hf,bwf->bwh", p["U"], f) + p["u"]
+    r = np.maximum(pre_r, 0.0)
+    z = np.einsum("h,bwh->bw", p["v"], r) + p["v0"][0]
+    if not keep:
+        return z
+    cache = dict(h=h, pre_e=pre_e, e=e, lags=lags, a=a, arg=arg, f=f, pre_r=pre_r, r=r)
+    return z, cache
+
+
+def bce_loss(z, y, pos_weight: float = 1.0):
+    """Mean over (b, w) of the weighted binary cross-entropy with logits."""
+    w = np.where(y > 0.5, pos_weight, 1.0)
+    l = np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z)))
+    loss = np.sum(w * l) / z.size
+    gz = w * (1.0 / (1.0 + np.exp(-z)) - y) / z.size
+    return loss, gz
+
+
+def backward(p: dict, cache: dict, gz, win_lo, win_hi, n_layers: int = 5) -> dict:
+    g = {}
+    r, pre_r, f = cache["r"], cache["pre_r"], cache["f"]
+    g["v0"] = np.array([gz.sum()])
+    g["v"] = np.einsum("bw,bwh->h", gz, r)
+    gr = gz[:, :, None] * p["v"][None, None, :]
+    gpre_r = gr * (pre_r > 0)
+    g["U"] = np.einsum("bwh,bwf->hf", gpre_r, f)
+    g["u"] = gpre_r.sum(axis=(0, 1))
+    gf = np.einsum("bwh,hf->bwf", gpre_r, p["U"])
+    E = p["P"].shape[0]
+    gg, gm = gf[:, :, :E], gf[:, :, E:2 * E]
+    a, lags, arg, e = cache["a"], cache["lags"], cache["arg"], cache["e"]
+    B, _, L = e.shape
+    ga = np.zeros_like(a)
+    for w in range(len(win_lo)):
+        lo, hi = win_lo[w] - lags[0], win_hi[w] - lags[0] + 1
+        ga[:, :, lo:hi] += gm[:, w, :, None] / (hi - lo)
+        for b in range(B):
+            for c in range(E):
+                ga[b, c, arg[b, w, c] - lags[0]] += gg[b, w, c]
+    ge = np.zeros_like(e)
+    for i, tau in enumerate(lags):
+        if tau < L:
+            coef = ga[:, :, i:i + 1] / L
+            ge[:, :, :L - tau] += coef * e[:, :, tau:]
+            ge[:, :, tau:] += coef * e[:, :, :L - tau]
+    gpre_e = ge * (cache["pre_e"] > 0)
+    h = cache["h"]
+    g["P"] = np.einsum("bel,bcl->ec", gpre_e, h[-1])
+    g["p"] = gpre_e.sum(axis=(0, 2))
+    gh = np.einsum("ec,bel->bcl", p["P"], gpre_e)
+    for l in reversed(range(n_layers)):
+        gh = gh * (h[l + 1] > 0)
+        gx, g[f"W{l}"], g[f"b{l}"] = conv1d_backward(h[l], p[f"W{l}"], gh)
+        gh = gx
+    g["x"] = gh
+    return g

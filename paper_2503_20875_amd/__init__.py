@@ -15,9 +15,9 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import BestRecord, CetraError, Grid  # noqa: F401
+from ._abi import BestRecord, CetraError, Grid, Tuning  # noqa: F401
 
-__all__ = ["grid_plan", "template_resample", "resample", "linear_search", "loglike0",
+__all__ = ["BatchPlan", "batch_plan", "batch_search", "get_tuning", "set_tuning", "reset_tuning", "grid_plan", "template_resample", "resample", "linear_search", "loglike0",
            "periodic_workspace", "periodic_search", "best", "search", "Grid", "CetraError"]
 
 
@@ -53,6 +53,22 @@ def _dev(x, dtype):
 
 def version() -> int:
     return int(_abi.load().cetra_version())
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _abi.check(_abi.load().cetra_get_tuning(ctypes.byref(t)))
+    return dict(fold_period_block=t.fold_period_block, fold_wgs_per_cu=t.fold_wgs_per_cu,
+                fold_units_per_wg=t.fold_units_per_wg)
+
+
+def set_tuning(fold_period_block: int = 8, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4) -> None:
+    t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg)
+    _abi.check(_abi.load().cetra_set_tuning(ctypes.byref(t)))
+
+
+def reset_tuning() -> None:
+    _abi.check(_abi.load().cetra_set_tuning(None))
 
 
 def grid_plan(t_first: float, t_last: float, cadence: float, durations, t0_step: float = 0.0,
@@ -184,3 +200,97 @@ def search(t, f, sigma, cadence: float, durations, periods, dense, n_model: int 
     if public:
         out.update(depth=lin[1], var=lin[2], lr=lin[3])
     return out
+
+
+# ------------------------------------------------------------------- batches
+class BatchPlan:
+    """Host-side plan of a batch (owns the C plan object)."""
+
+    def __init__(self, handle, info, tables: bytes, n_curves: int, period_offsets):
+        self._h = handle
+        self.info = {name: getattr(info, name) for name, _ in _abi.BatchInfo._fields_}
+        self.tables = tables
+        self.n_curves = n_curves
+        self.period_offsets = np.asarray(period_offsets, dtype=np.int64)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            try:
+                _abi.load().cetra_batch_plan_destroy(h)
+            except Exception:
+                pass
+
+
+def batch_plan(grids, obs_offsets, period_offsets, arena_bytes: int = 0, period_block: int = 0) -> BatchPlan:
+    """Plan a batch from per-curve grid plans and CSR offsets (host arrays)."""
+    n = len(grids)
+    garr = (Grid * n)(*grids)
+    oo = np.ascontiguousarray(obs_offsets, dtype=np.int64)
+    po = np.ascontiguousarray(period_offsets, dtype=np.int64)
+    if oo.shape[0] != n + 1 or po.shape[0] != n + 1:
+        raise ValueError("offsets must have n_curves + 1 entries")
+    d = _abi.BatchDesc(n, int(period_block), ctypes.cast(garr, ctypes.c_void_p),
+                       oo.ctypes.data_as(ctypes.c_void_p), po.ctypes.data_as(ctypes.c_void_p), int(arena_bytes))
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    _abi.check(lib.cetra_batch_plan_create(ctypes.byref(d), ctypes.byref(h)))
+    info = _abi.BatchInfo()
+    _abi.check(lib.cetra_batch_plan_info(h, ctypes.byref(info)))
+    buf = (ctypes.c_char * info.tables_bytes)()
+    _abi.check(lib.cetra_batch_tables(h, buf, info.tables_bytes))
+    return BatchPlan(h, info, bytes(buf), n, po)
+
+
+def batch_workspace(plan: BatchPlan, device="cuda"):
+    """Device workspace with the plan's tables copied to its start."""
+    torch = _torch()
+    work = torch.empty(plan.info["workspace_bytes"], dtype=torch.uint8, device=device)
+    tbl = torch.frombuffer(bytearray(plan.tables), dtype=torch.uint8)
+    work[: tbl.numel()].copy_(tbl.to(device))
+    return work
+
+
+def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, cancel=None, out=None,
+                 stream=None) -> dict:
+    """Search every curve of the batch (a short sequence of persistent
+    work-queue launches on one stream).  Returns
+    device tensors: per-period lr, epoch, dur, depth, depth_var (CSR), best
+    records (uint8 [n_curves, sizeof(cetra_best_record)]) and status."""
+    torch = _torch()
+    t = _dev(t, torch.float64)
+    f = _dev(f, torch.float32)
+    s = _dev(sigma, torch.float32)
+    periods = _dev(periods, torch.float64)
+    dev = t.device
+    if work is None:
+        work = batch_workspace(plan, dev)
+    K = int(plan.period_offsets[-1])
+    if out is None:
+        out = dict(lr=torch.empty(max(K, 1), dtype=torch.float32, device=dev),
+                   epoch=torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+                   dur=torch.empty(max(K, 1), dtype=torch.int32, device=dev),
+                   depth=torch.empty(max(K, 1), dtype=torch.float32, device=dev),
+                   depth_var=torch.empty(max(K, 1), dtype=torch.float32, device=dev),
+                   best=torch.empty((plan.n_curves, ctypes.sizeof(BestRecord)), dtype=torch.uint8, device=dev),
+                   status=torch.empty(1, dtype=torch.int32, device=dev))
+    _abi.check(_abi.load().cetra_batch_search(
+        plan.handle, _stream(stream), _ptr(t), _ptr(f), _ptr(s), _ptr(model), _ptr(periods), _ptr(work),
+        work.numel(), _ptr(cancel), _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]),
+        _ptr(out["depth"]), _ptr(out["depth_var"]), _ptr(out["best"]), _ptr(out["status"])))
+    return out
+
+
+def best_records(raw) -> list:
+    """Host copies of a [n, sizeof(cetra_best_record)] device tensor."""
+    data = raw.cpu().numpy()
+    return [best_record_bytes(bytes(row.tobytes())) for row in data]
+
+
+def best_record_bytes(b: bytes) -> dict:
+    r = BestRecord.from_buffer_copy(b)
+    return {name: getattr(r, name) for name, _ in BestRecord._fields_}

@@ -59,6 +59,43 @@ class BestRecord(ctypes.Structure):
     ]
 
 
+class Tuning(ctypes.Structure):
+    """Mirror of ``cetra_tuning``."""
+    _fields_ = [
+        ("fold_period_block", ctypes.c_int32),
+        ("fold_wgs_per_cu", ctypes.c_int32),
+        ("fold_units_per_wg", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class BatchDesc(ctypes.Structure):
+    """Mirror of ``cetra_batch_desc``."""
+    _fields_ = [
+        ("n_curves", ctypes.c_int32),
+        ("fold_period_block", ctypes.c_int32),
+        ("grids", ctypes.c_void_p),
+        ("obs_offsets", ctypes.c_void_p),
+        ("period_offsets", ctypes.c_void_p),
+        ("arena_bytes", ctypes.c_int64),
+    ]
+
+
+class BatchInfo(ctypes.Structure):
+    """Mirror of ``cetra_batch_info``."""
+    _fields_ = [
+        ("workspace_bytes", ctypes.c_size_t),
+        ("tables_bytes", ctypes.c_size_t),
+        ("arena_bytes", ctypes.c_size_t),
+        ("n_items", ctypes.c_int64),
+        ("n_generations", ctypes.c_int64),
+        ("n_launches", ctypes.c_int64),
+        ("total_periods", ctypes.c_int64),
+        ("period_block", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+    ]
+
+
 _P = ctypes.c_void_p
 _i32, _i64, _d, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 
@@ -67,6 +104,8 @@ SIGNATURES = {
     "cetra_version": (ctypes.c_int, []),
     "cetra_last_error": (ctypes.c_char_p, []),
     "cetra_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "cetra_get_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
+    "cetra_set_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "cetra_grid_plan": (ctypes.c_int, [_d, _d, _d, _P, _i32, _d, _i32, ctypes.POINTER(Grid)]),
     "cetra_template_resample": (ctypes.c_int, [_P, _P, _i64, _i32, _P]),
     "cetra_resample": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _P, _i64, _P, _P, _P]),
@@ -76,6 +115,12 @@ SIGNATURES = {
     "cetra_periodic_search": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _i64, _P, _P, _i64, _P, _sz,
                                              _P, _P, _P, _P, _P]),
     "cetra_best": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _i64, _P, _P, _P, _P, _P, _P]),
+    "cetra_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P)]),
+    "cetra_batch_plan_destroy": (ctypes.c_int, [_P]),
+    "cetra_batch_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(BatchInfo)]),
+    "cetra_batch_tables": (ctypes.c_int, [_P, _P, _sz]),
+    "cetra_batch_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P, _P, _P, _P, _P, _P,
+                                          _P]),
 }
 
 _lib = None

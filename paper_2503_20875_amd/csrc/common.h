@@ -25,6 +25,13 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Launch tuning currently in force (process-wide).
+cetra_tuning current_tuning();
+
+// LDS bytes of the linear tile for duration j and its staged span.
+constexpr int kMaxLinearLdsBytes = 64 * 1024;
+size_t linear_lds_bytes(const cetra_grid *g, int j, int32_t *span_cap);
+
 // Validates the parts of a grid plan that kernels rely on.
 int check_grid(const cetra_grid *g);
 

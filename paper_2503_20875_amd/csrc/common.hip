@@ -45,6 +45,14 @@ int check_launch(const char *what) {
     return CETRA_OK;
 }
 
+static std::mutex g_tuning_mu;
+static cetra_tuning g_tuning = {8, 8, 4, {0, 0, 0, 0, 0}};
+
+cetra_tuning current_tuning() {
+    std::lock_guard<std::mutex> lock(g_tuning_mu);
+    return g_tuning;
+}
+
 int check_grid(const cetra_grid *g) {
     CETRA_REQUIRE(g != nullptr, "grid is NULL");
     CETRA_REQUIRE(g->n_dur >= 1 && g->n_dur <= CETRA_MAX_DURATIONS, "grid: bad n_dur %d", g->n_dur);
@@ -74,6 +82,29 @@ extern "C" const char *cetra_status_string(int status) {
         case CETRA_ERR_DEVICE: return "no usable device";
         default: return "unknown status";
     }
+}
+
+extern "C" int cetra_get_tuning(cetra_tuning *out) {
+    clear_error();
+    CETRA_REQUIRE(out != nullptr, "get_tuning: NULL pointer");
+    *out = current_tuning();
+    return CETRA_OK;
+}
+
+extern "C" int cetra_set_tuning(const cetra_tuning *in) {
+    clear_error();
+    cetra_tuning t = {8, 8, 4, {0, 0, 0, 0, 0}};
+    if (in) {
+        CETRA_REQUIRE(in->fold_period_block == 4 || in->fold_period_block == 8 || in->fold_period_block == 16,
+                      "set_tuning: fold_period_block must be 4, 8 or 16");
+        CETRA_REQUIRE(in->fold_wgs_per_cu >= 1 && in->fold_wgs_per_cu <= 32, "set_tuning: fold_wgs_per_cu in [1, 32]");
+        CETRA_REQUIRE(in->fold_units_per_wg >= 1 && in->fold_units_per_wg <= 64,
+                      "set_tuning: fold_units_per_wg in [1, 64]");
+        t = *in;
+    }
+    std::lock_guard<std::mutex> lock(g_tuning_mu);
+    g_tuning = t;
+    return CETRA_OK;
 }
 
 // Grid plan: padding of half the longest duration at both ends (Sec. 2.1.1),

@@ -23,15 +23,15 @@
 // (bits(LR) << 32) | (2^32 - 1 - (j I + i)) under a 64-bit atomicMax gives
 // the maximum with ties to the smallest (j, i).  An epilogue recomputes the
 // winner's sums in the same order to emit LR, Z and var_Z.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
+#include "stages.h"
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPeriodBlock = 8;   // B
-constexpr int kTargetUnitsPerWG = 4;
+using cetra::dev::kThreads;
 
 struct FoldWork {
     uint64_t *key;     // [n_eval] argmax keys
@@ -90,56 +90,28 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
         w.jr[2 * s + 1] = -1;
         return;
     }
-    const double P = periods[k];
-    // a period must span at least one reference-time step (transit offsets
-    // then advance by >= 1 per transit, which bounds every fold loop)
-    if (!isfinite(P) || !(P >= t0_step) || !(P / t0_step < 2.0e9)) {
-        w.kidx[s] = k;
-        w.step[s] = 0;
-        w.n_ep[s] = 0;
-        w.jr[2 * s] = 0;
-        w.jr[2 * s + 1] = -1;
-        return;
-    }
-    const uint64_t R = (uint64_t)llround(4294967296.0 * (P / t0_step));
-    int64_t ip = (int64_t)((R + 4294967295ull) >> 32);
-    if (ip > n_t0) ip = n_t0;
-    int lo = 0, hi = n_dur - 1;
-    if (jrange) {
-        lo = max(lo, jrange[2 * k]);
-        hi = min(hi, jrange[2 * k + 1]);
-    }
-    while (hi >= lo && !(dur.d[hi] < P)) --hi;
+    const cetra::dev::PeriodInfo pi = cetra::dev::period_info(
+        periods[k], t0_step, n_t0, n_dur, dur.d, jrange ? jrange[2 * k] : 0,
+        jrange ? jrange[2 * k + 1] : n_dur - 1);
     w.kidx[s] = k;
-    w.step[s] = R;
-    w.n_ep[s] = (int32_t)ip;
-    w.jr[2 * s] = lo;
-    w.jr[2 * s + 1] = hi;
+    w.step[s] = pi.step;
+    w.n_ep[s] = pi.n_ep;
+    w.jr[2 * s] = pi.jlo;
+    w.jr[2 * s + 1] = pi.jhi;
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
-        const uint64_t o = ((uint64_t)hi << 32) | lo;
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
+// Persistent grid over units (period block of B periods, duration j, epoch
+// chunk), ordered block-fastest; each unit is one dev::fold_unit.
 template <int B>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
-                                                        int64_t n_t0, int32_t n_dur, int32_t n_chunks,
-                                                        int64_t n_units) {
+                                                        int32_t I, int32_t n_chunks, int64_t n_units) {
     const int64_t n_pblk = (n_eval + B - 1) / B;
-    const int lane = threadIdx.x & 63;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pb = u % n_pblk;
         const int64_t rest = u / n_pblk;
         const int32_t c = (int32_t)(rest % n_chunks);
         const int32_t j = (int32_t)(rest / n_chunks);
         const int64_t s0 = pb * B;
-
         uint64_t R[B];
         int32_t ipb[B];
         int32_t ipmax = 0;
@@ -153,62 +125,11 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
             ipmax = max(ipmax, ipb[b]);
         }
         if (ipmax == 0) continue;
-        const int32_t chunk = (int32_t)((ipmax + n_chunks - 1) / n_chunks);
+        const int32_t chunk = (ipmax + n_chunks - 1) / n_chunks;
         const int32_t e_lo = c * chunk;
         const int32_t e_hi = min(ipmax, e_lo + chunk);
         if (e_lo >= e_hi) continue;
-
-        const float2 *row = fold + (int64_t)j * n_t0;
-        const int32_t I = (int32_t)n_t0;
-        uint64_t best[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) best[b] = 0;
-
-        for (int32_t e0 = e_lo; e0 < e_hi; e0 += kThreads) {
-            const int32_t e = e0 + (int32_t)threadIdx.x;
-            // first epoch of this wave: the transit loop runs while it is inside the row
-            const int32_t e_wave = __builtin_amdgcn_readfirstlane(e - lane);
-            double A[B], S[B];
-            uint64_t acc[B];
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                A[b] = 0.0;
-                S[b] = 0.0;
-                acc[b] = 2147483648ull;  // + 1/2 for round half up
-            }
-            while (true) {
-                bool any = false;
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    // offsets compared in 64 bits: a block may mix very different
-                    // periods, whose offsets exceed 2^31 long before the loop ends;
-                    // the accumulator stops once past the row, so it cannot wrap
-                    const uint64_t o = acc[b] >> 32;
-                    acc[b] = o < (uint64_t)I ? acc[b] + R[b] : acc[b];
-                    if (ipb[b] > 0 && (uint64_t)e_wave + o < (uint64_t)I) any = true;
-                    if (e < ipb[b] && e < e_hi && (uint64_t)e + o < (uint64_t)I) {
-                        const float2 v = row[e + (int32_t)o];
-                        A[b] += (double)v.x;
-                        S[b] += (double)v.y;
-                    }
-                }
-                if (!any) break;
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                if (e < ipb[b] && e < e_hi && S[b] > 0.0) {
-                    const float l = (float)(0.5 * A[b] * A[b] / S[b]);
-                    const uint32_t flat = (uint32_t)j * (uint32_t)I + (uint32_t)e;
-                    const uint64_t key = ((uint64_t)__float_as_uint(l) << 32) | (uint64_t)(0xFFFFFFFFu - flat);
-                    best[b] = key > best[b] ? key : best[b];
-                }
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const uint64_t m = wave_max_u64(best[b]);
-            if (lane == 0 && m != 0) atomicMax((unsigned long long *)&w.key[s0 + b], (unsigned long long)m);
-        }
+        cetra::dev::fold_unit<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
     }
 }
 
@@ -225,38 +146,12 @@ __global__ void fold_null_kernel(int64_t n, float *lr, int32_t *ep, int32_t *du,
 
 // Decode each period's winner and recompute its sums in the fold's order.
 __global__ void fold_epilogue_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval, int64_t n_t0,
-                                     float *lr, int32_t *ep, int32_t *du, float *z, float *zv) {
+                                     int32_t n_dur, float *lr, int32_t *ep, int32_t *du, float *z, float *zv) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n_eval) return;
     const int64_t k = w.kidx[s];
     if (k < 0) return;
-    const uint64_t key = w.key[s];
-    if (key == 0) {
-        lr[k] = 0.0f;
-        ep[k] = -1;
-        du[k] = -1;
-        z[k] = __builtin_nanf("");
-        zv[k] = __builtin_inff();
-        return;
-    }
-    const uint32_t flat = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
-    const int32_t j = (int32_t)(flat / (uint32_t)n_t0);
-    const int32_t i = (int32_t)(flat % (uint32_t)n_t0);
-    const float2 *row = fold + (int64_t)j * n_t0;
-    const uint64_t R = w.step[s];
-    double A = 0.0, S = 0.0;
-    for (uint64_t acc = 2147483648ull;; acc += R) {
-        const int64_t x = (int64_t)i + (int64_t)(acc >> 32);
-        if (x >= n_t0) break;
-        const float2 v = row[x];
-        A += (double)v.x;
-        S += (double)v.y;
-    }
-    lr[k] = (float)(0.5 * A * A / S);
-    ep[k] = i;
-    du[k] = j;
-    z[k] = (float)(A / S);
-    zv[k] = (float)(1.0 / S);
+    cetra::dev::fold_decode(fold, n_t0, n_dur, w.step[s], w.key[s], lr + k, ep + k, du + k, z + k, zv + k);
 }
 
 __global__ void __launch_bounds__(1024) best_kernel(const double *__restrict__ periods, int64_t n,
@@ -347,7 +242,9 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
     CETRA_REQUIRE(fold && lr && epoch && dur && depth && depth_var, "periodic_search: NULL pointer");
     CETRA_REQUIRE(n_periods >= 0 && (n_periods == 0 || periods), "periodic_search: bad periods");
     CETRA_REQUIRE(!subset || n_subset >= 0, "periodic_search: bad subset");
-    if (grid->n_t0 >= INT32_MAX) return set_error(CETRA_ERR_RANGE, "periodic_search: I must be < 2^31");
+    // buffer byte offsets (element index + saturated transit offset) * 8 must fit 32 bits
+    if (grid->n_t0 >= (int64_t)1 << 28)
+        return set_error(CETRA_ERR_RANGE, "periodic_search: I must be < 2^28");
     const int64_t n_eval = subset ? n_subset : n_periods;
     if (work_bytes < workspace_bytes(n_eval) || (n_eval > 0 && !work))
         return set_error(CETRA_ERR_WORKSPACE, "periodic_search: workspace needs %zu bytes",
@@ -365,21 +262,36 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
                        n_periods, jrange, subset, n_eval, grid->t0_step, grid->n_t0, grid->n_dur, d, w);
     if ((rc = check_launch("periodic_search/setup"))) return rc;
 
-    constexpr int B = kPeriodBlock;
+    const cetra_tuning tu = current_tuning();
+    const int B = tu.fold_period_block;
     const int64_t n_pblk = ceil_div(n_eval, B);
-    const int64_t wgs = (int64_t)device_cu_count() * 8;
+    // persistent grid: no more workgroups than can be resident at once
+    int occ = 0;
+    hipError_t oe = B == 4    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fold_kernel<4>, kThreads, 0)
+                    : B == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fold_kernel<16>, kThreads, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fold_kernel<8>, kThreads, 0);
+    if (oe != hipSuccess || occ <= 0) occ = 1;
+    const int64_t wgs = (int64_t)device_cu_count() * std::min(tu.fold_wgs_per_cu, occ);
     const int64_t base_units = n_pblk * grid->n_dur;
-    int64_t n_chunks = ceil_div(kTargetUnitsPerWG * wgs, base_units);
+    int64_t n_chunks = ceil_div((int64_t)tu.fold_units_per_wg * wgs, base_units);
     n_chunks = std::max<int64_t>(1, std::min<int64_t>(n_chunks, 64));
     const int64_t n_units = base_units * n_chunks;
     const int64_t grid_wgs = std::min<int64_t>(wgs, n_units);
-    hipLaunchKernelGGL(fold_kernel<B>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s,
-                       reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, grid->n_dur,
-                       (int32_t)n_chunks, n_units);
+    const auto *f2 = reinterpret_cast<const float2 *>(fold);
+    const int32_t I = (int32_t)grid->n_t0;
+    if (B == 4)
+        hipLaunchKernelGGL(fold_kernel<4>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s, f2, w, n_eval, I,
+                           (int32_t)n_chunks, n_units);
+    else if (B == 16)
+        hipLaunchKernelGGL(fold_kernel<16>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s, f2, w, n_eval, I,
+                           (int32_t)n_chunks, n_units);
+    else
+        hipLaunchKernelGGL(fold_kernel<8>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s, f2, w, n_eval, I,
+                           (int32_t)n_chunks, n_units);
     if ((rc = check_launch("periodic_search/fold"))) return rc;
     hipLaunchKernelGGL(fold_epilogue_kernel, dim3((unsigned)ceil_div(n_eval, 256)), dim3(256), 0, s,
-                       reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, lr, epoch, dur, depth,
-                       depth_var);
+                       reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, grid->n_dur, lr, epoch, dur,
+                       depth, depth_var);
     return check_launch("periodic_search/epilogue");
 }
 

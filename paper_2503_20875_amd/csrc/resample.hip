@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "stages.h"
 
 namespace {
 
@@ -19,11 +20,6 @@ __global__ void template_kernel(const double *__restrict__ dense, int64_t n_dens
     if (a < 0) a = 0;
     const double fr = x - (double)a;
     model[k] = (float)(dense[a] + fr * (dense[a + 1] - dense[a]));
-}
-
-// Nearest grid point of an observation (round half up), FP64.
-__device__ __forceinline__ int64_t obs_bin(double t, double t_first, double c, int64_t n_pad) {
-    return n_pad + (int64_t)floor((t - t_first) / c + 0.5);
 }
 
 // --- input check: times finite and non-decreasing.  One workgroup, so the
@@ -45,38 +41,14 @@ __global__ void __launch_bounds__(1024) check_sorted_kernel(const double *__rest
 }
 
 // --- resampling: one thread per grid point gathers the (sorted) observations
-// whose nearest grid point it is, in input order, and forms the
-// inverse-variance weighted mean and total weight in FP64.
+// whose nearest grid point it is (dev::resample_point).
 __global__ void resample_kernel(const double *__restrict__ t, const float *__restrict__ f,
                                 const float *__restrict__ sigma, int64_t n_obs, double t_first, double c,
                                 int64_t n_pad, int64_t n_grid, float *__restrict__ flux,
                                 float *__restrict__ ivar) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_grid) return;
-    int64_t lo = 0, hi = n_obs;
-    while (lo < hi) {  // first observation whose bin is >= q
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (obs_bin(t[mid], t_first, c, n_pad) < q)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    double wsum = 0.0, fsum = 0.0;
-    for (int64_t n = lo; n < n_obs && obs_bin(t[n], t_first, c, n_pad) == q; ++n) {
-        const double fn = (double)f[n];
-        const double sn = (double)sigma[n];
-        if (!isfinite(fn) || !isfinite(sn) || !(sn > 0.0)) continue;
-        const double w = 1.0 / (sn * sn);
-        wsum += w;
-        fsum += w * fn;
-    }
-    if (wsum > 0.0) {
-        flux[q] = (float)(fsum / wsum);
-        ivar[q] = (float)wsum;
-    } else {
-        flux[q] = 0.0f;
-        ivar[q] = 0.0f;
-    }
+    cetra::dev::resample_point(t, f, sigma, n_obs, t_first, c, n_pad, q, flux, ivar);
 }
 
 // --- constant-model log-likelihood: one workgroup, fixed reduction order.

@@ -1,0 +1,400 @@
+// Per-item device code of the search stages, shared by the single-curve
+// kernels and the batched persistent kernel (so both produce bit-identical
+// results).  Internal header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "cetra.h"
+
+namespace cetra {
+namespace dev {
+
+constexpr int kThreads = 256;          // lanes per workgroup in every stage
+constexpr int kLinearChunk = 32;       // FP32 partial-sum length of the linear search
+constexpr int kFoldChunk = 32;         // FP32 partial-sum length of the fold
+constexpr int kFoldWaveEpochs = 128;   // epochs per wave in the fold
+constexpr int kFoldTileEpochs = kFoldWaveEpochs * (kThreads / 64);
+
+// ------------------------------------------------------------- resampling
+// Nearest grid point of an observation, round half up (Sec. 2.1.1), FP64.
+__device__ __forceinline__ int64_t obs_bin(double t, double t_first, double c, int64_t n_pad) {
+    return n_pad + (int64_t)floor((t - t_first) / c + 0.5);
+}
+
+// Grid point q: inverse-variance weighted mean of the (time-sorted)
+// observations whose nearest grid point it is, in input order, FP64.
+__device__ __forceinline__ void resample_point(const double *__restrict__ t, const float *__restrict__ f,
+                                               const float *__restrict__ sigma, int64_t n_obs, double t_first,
+                                               double c, int64_t n_pad, int64_t q, float *__restrict__ flux,
+                                               float *__restrict__ ivar) {
+    int64_t lo = 0, hi = n_obs;
+    while (lo < hi) {  // first observation whose bin is >= q
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (obs_bin(t[mid], t_first, c, n_pad) < q)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    double wsum = 0.0, fsum = 0.0;
+    for (int64_t n = lo; n < n_obs && obs_bin(t[n], t_first, c, n_pad) == q; ++n) {
+        const double fn = (double)f[n];
+        const double sn = (double)sigma[n];
+        if (!isfinite(fn) || !isfinite(sn) || !(sn > 0.0)) continue;
+        const double w = 1.0 / (sn * sn);
+        wsum += w;
+        fsum += w * fn;
+    }
+    if (wsum > 0.0) {
+        flux[q] = (float)(fsum / wsum);
+        ivar[q] = (float)wsum;
+    } else {
+        flux[q] = 0.0f;
+        ivar[q] = 0.0f;
+    }
+}
+
+// ----------------------------------------------------------- linear search
+struct LinearParams {
+    double cadence, t0_step, duration, t_end;  // t_end = (N-1) c
+    int64_t n_t0;
+    uint64_t step_fx;                           // G_j
+    int32_t n_model;
+    int32_t span_cap;                           // staged points (0 = not staged)
+};
+
+struct Window {
+    int64_t lo, hi;
+    uint64_t phase;
+    bool ok;
+};
+
+// Points covered by 256 consecutive windows of one duration, with a margin of
+// three for rounding: (255 dt + D)/c + 1 at most.
+__host__ __device__ inline double linear_span(double t0_step, double duration, double cadence) {
+    return ((double)(kThreads - 1) * t0_step + duration) / cadence + 4.0;
+}
+
+__host__ __device__ inline LinearParams linear_params(const cetra_grid &g, int j) {
+    LinearParams p;
+    p.cadence = g.cadence;
+    p.t0_step = g.t0_step;
+    p.duration = g.durations[j];
+    p.t_end = (double)(g.n - 1) * g.cadence;
+    p.n_t0 = g.n_t0;
+    p.step_fx = g.dur_step_fx[j];
+    p.n_model = g.n_model;
+    p.span_cap = 0;
+    return p;
+}
+
+// Window of reference time i: [t_i - D/2, t_i + D/2], null if it leaves
+// [0, (N-1) c]; first/last grid points ceil(t_s/c), floor(t_e/c); template
+// phase of the first point in 32.32 fixed point (plain FP64 operations).
+__device__ __forceinline__ Window make_window(const LinearParams &p, int64_t i) {
+    Window w;
+    const double ts = (double)i * p.t0_step - 0.5 * p.duration;
+    const double te = ts + p.duration;
+    w.ok = !(ts < 0.0 || te > p.t_end);
+    w.lo = 0;
+    w.hi = -1;
+    w.phase = 0;
+    if (!w.ok) return w;
+    w.lo = (int64_t)ceil(ts / p.cadence);
+    w.hi = (int64_t)floor(te / p.cadence);
+    if (w.lo > w.hi) {
+        w.ok = false;
+        return w;
+    }
+    const long long ph =
+        llround(4294967296.0 * ((((double)w.lo * p.cadence - ts) / p.duration) * (double)p.n_model));
+    w.phase = ph < 0 ? 0ull : (uint64_t)ph;
+    return w;
+}
+
+// One workgroup computes reference times i0 .. i0+255 of one duration.  The
+// template and (if p.span_cap > 0) the light-curve span of the 256 windows,
+// as (w f, w) pairs, are staged in LDS.  Template indices advance in 32.32
+// fixed point; FP32 partial sums over 32 points are folded into FP64.  Must
+// be called by all lanes of the workgroup (it synchronises).
+__device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, const float *__restrict__ flux,
+                                            const float *__restrict__ ivar, const float *__restrict__ model,
+                                            float2 *__restrict__ fold_row, float *__restrict__ depth_row,
+                                            float *__restrict__ var_row, float *__restrict__ lr_row, float *lds,
+                                            int *s_bounds) {
+    float *s_model = lds;                                                        // [M]
+    float2 *s_data = reinterpret_cast<float2 *>(lds + ((p.n_model + 1) & ~1));  // [span_cap]
+    const bool staged = p.span_cap > 0;
+
+    const int64_t i = i0 + threadIdx.x;
+    const bool in_range = i < p.n_t0;
+    Window w = make_window(p, in_range ? i : 0);
+    w.ok = w.ok && in_range;
+
+    for (int k = threadIdx.x; k < p.n_model; k += kThreads) s_model[k] = model[k];
+    int64_t base = 0;
+    if (staged) {
+        if (threadIdx.x == 0) {
+            s_bounds[0] = INT_MAX;
+            s_bounds[1] = -1;
+        }
+        __syncthreads();
+        if (w.ok) {
+            atomicMin(&s_bounds[0], (int)w.lo);
+            atomicMax(&s_bounds[1], (int)w.hi);
+        }
+        __syncthreads();
+        base = s_bounds[0];
+        const int64_t count = min((int64_t)s_bounds[1] - (int64_t)s_bounds[0] + 1, (int64_t)p.span_cap);
+        for (int64_t q = threadIdx.x; q < count; q += kThreads) {
+            const float wq = ivar[base + q];
+            s_data[q] = make_float2(flux[base + q] * wq, wq);
+        }
+    }
+    __syncthreads();
+
+    double dfm = 0.0, dmm = 0.0;
+    if (w.ok) {
+        const uint32_t last = (uint32_t)(p.n_model - 1);
+        uint64_t ph = w.phase;
+        int64_t n = w.lo;
+        while (n <= w.hi) {
+            const int64_t stop = min(w.hi + 1, n + kLinearChunk);
+            float sfm = 0.0f, smm = 0.0f;
+            for (; n < stop; ++n) {
+                const uint32_t k = min((uint32_t)(ph >> 32), last);
+                const float mk = s_model[k];
+                float wf, wq;
+                if (staged) {
+                    const float2 d = s_data[n - base];
+                    wf = d.x;
+                    wq = d.y;
+                } else {
+                    wq = ivar[n];
+                    wf = flux[n] * wq;
+                }
+                sfm = fmaf(wf, mk, sfm);
+                smm = fmaf(wq * mk, mk, smm);
+                ph += p.step_fx;
+            }
+            dfm += (double)sfm;
+            dmm += (double)smm;
+        }
+    }
+    __syncthreads();  // LDS may be reused by the caller's next item
+    if (!in_range) return;
+    if (w.ok && dmm > 0.0) {
+        fold_row[i] = make_float2((float)dfm, (float)dmm);
+        if (depth_row) depth_row[i] = (float)(dfm / dmm);
+        if (var_row) var_row[i] = (float)(1.0 / dmm);
+        if (lr_row) lr_row[i] = (float)(0.5 * dfm * dfm / dmm);
+    } else {
+        fold_row[i] = make_float2(0.0f, 0.0f);
+        if (depth_row) depth_row[i] = __builtin_nanf("");
+        if (var_row) var_row[i] = __builtin_inff();
+        if (lr_row) lr_row[i] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------- periodic search
+struct PeriodInfo {
+    uint64_t step;   // R = llround(2^32 P/dt); 0 = period not evaluated
+    int32_t n_ep;    // I_P = min(I, ceil(R / 2^32))
+    int32_t jlo, jhi;
+};
+
+// Fixed-point step, epoch count and allowed duration range of a period:
+// D_j < P (Sec. 2.3) intersected with [jlo_cap, jhi_cap].  A period shorter
+// than the reference-time step (or not finite) is not evaluated: transit
+// offsets then advance by >= 1 per transit, which bounds every fold loop.
+__device__ __forceinline__ PeriodInfo period_info(double P, double t0_step, int64_t n_t0, int32_t n_dur,
+                                                  const double *durations, int32_t jlo_cap, int32_t jhi_cap) {
+    PeriodInfo pi;
+    pi.step = 0;
+    pi.n_ep = 0;
+    pi.jlo = 0;
+    pi.jhi = -1;
+    if (!isfinite(P) || !(P >= t0_step) || !(P / t0_step < 2.0e9)) return pi;
+    const uint64_t R = (uint64_t)llround(4294967296.0 * (P / t0_step));
+    int64_t ip = (int64_t)((R + 4294967295ull) >> 32);
+    if (ip > n_t0) ip = n_t0;
+    int lo = max(0, jlo_cap), hi = min(n_dur - 1, jhi_cap);
+    while (hi >= lo && !(durations[hi] < P)) --hi;
+    pi.step = R;
+    pi.n_ep = (int32_t)ip;
+    pi.jlo = lo;
+    pi.jhi = hi;
+    return pi;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Raw buffer resource over one row: loads at byte offsets >= the row size
+// return zero (hardware range check), so the transit loop needs no per-lane
+// bounds test and every load can be issued unconditionally.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_resource(const float2 *row, int32_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2 *>(row), (short)0, n * 8, 0x00020000);
+}
+
+// One float pair at a byte offset (two dword loads; the compiler merges them
+// into one 8-byte load, which never straddles the row end because elements
+// and the row size are multiples of 8 bytes).
+__device__ __forceinline__ float2 load_pair(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, int imm) {
+    const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off + imm, 0, 0));
+    const float y = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off + imm + 4, 0, 0));
+    return make_float2(x, y);
+}
+
+// Argmax key of a candidate: LR >= 0 makes its FP32 bits monotone; ties go to
+// the smallest flat index j I + i.
+__device__ __forceinline__ uint64_t fold_key(float lr, uint32_t flat) {
+    return ((uint64_t)__float_as_uint(lr) << 32) | (uint64_t)(0xFFFFFFFFu - flat);
+}
+
+// One fold unit: B periods (R[b], ipb[b]; ipb = 0 means "skip"), duration row
+// `row` (index j), epochs [e_lo, e_hi).  Each wave owns 128 consecutive
+// epochs, lane l the epochs e_wave + l and e_wave + 64 + l (so a wave's loads
+// stay contiguous and a lane's two loads are never adjacent).  Per transit
+// step and period: two 8-byte buffer loads and four FP32 adds; offsets and the
+// loop exit are wave-uniform (scalar registers).  FP32 chunks of 32 transits
+// fold into FP32 totals (error below (31 + n/32) u of the absolute sum); the
+// sums only rank candidates -- the epilogue recomputes the winner in FP64.
+// The per-period maxima go to keys[b] by 64-bit atomicMax.
+template <int B>
+__device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
+                                          const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    uint64_t best[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) best[b] = 0;
+
+    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
+        const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
+        if (e_wave >= e_hi) break;
+        const int32_t e = e_wave + lane;  // epochs e and e + 64
+        const uint32_t e_bytes = (uint32_t)e * 8u;
+        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
+        uint64_t acc[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
+            acc[b] = 2147483648ull;  // + 1/2: round half up
+        }
+        bool done = false;
+        while (!done) {
+            for (int mm = 0; mm < kFoldChunk; ++mm) {
+                uint32_t o[B];
+                bool any = false;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    // saturate at I: finished periods read past the row
+                    // (zeros) and the byte offset stays below 2^32
+                    const uint32_t hi = (uint32_t)(acc[b] >> 32);
+                    const bool live = hi < (uint32_t)I;
+                    o[b] = live ? hi : (uint32_t)I;
+                    acc[b] += live ? R[b] : 0ull;
+                    any |= ipb[b] > 0 && (uint32_t)e_wave + o[b] < (uint32_t)I;
+                }
+                if (!any) {
+                    done = true;
+                    break;
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const uint32_t off = e_bytes + o[b] * 8u;
+                    const float2 v0 = load_pair(rsrc, off, 0);
+                    const float2 v1 = load_pair(rsrc, off, 64 * 8);
+                    a0[b] += v0.x;
+                    s0[b] += v0.y;
+                    a1[b] += v1.x;
+                    s1[b] += v1.y;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ta0[b] += a0[b];
+                ts0[b] += s0[b];
+                ta1[b] += a1[b];
+                ts1[b] += s1[b];
+                a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int32_t eh = e + 64 * h;
+                const float A = h ? ta1[b] : ta0[b];
+                const float S = h ? ts1[b] : ts0[b];
+                if (eh < ipb[b] && eh < e_hi && S > 0.0f) {
+                    const uint64_t key = fold_key(0.5f * A * (A / S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
+                    best[b] = key > best[b] ? key : best[b];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t m = wave_max_u64(best[b]);
+        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
+    }
+}
+
+// FP64 sums of one candidate (epoch i of row `row`, period step R), in
+// transit order.
+__device__ __forceinline__ void fold_sums(const float2 *row, int64_t I, uint64_t R, int64_t i, double &A, double &S) {
+    A = 0.0;
+    S = 0.0;
+    if (R < 4294967296ull) return;  // not a valid period step (offsets would not advance)
+    for (uint64_t acc = 2147483648ull;; acc += R) {
+        const int64_t x = i + (int64_t)(acc >> 32);
+        if (x >= I) break;
+        const float2 v = row[x];
+        A += (double)v.x;
+        S += (double)v.y;
+    }
+}
+
+// Decode a period's key into (lr, epoch, dur, depth, depth_var); a zero key
+// is the null record.  Returns the LR as written (0 for null).
+__device__ __forceinline__ float fold_decode(const float2 *fold, int64_t I, int32_t n_dur, uint64_t R, uint64_t key,
+                                             float *lr, int32_t *ep, int32_t *du, float *z, float *zv) {
+    const uint32_t flat_ = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+    if (key == 0 || R < 4294967296ull || flat_ / (uint32_t)I >= (uint32_t)n_dur) {
+        *lr = 0.0f;
+        *ep = -1;
+        *du = -1;
+        *z = __builtin_nanf("");
+        *zv = __builtin_inff();
+        return 0.0f;
+    }
+    const uint32_t flat = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+    const int32_t j = (int32_t)(flat / (uint32_t)I);
+    const int32_t i = (int32_t)(flat % (uint32_t)I);
+    double A, S;
+    fold_sums(fold + (int64_t)j * I, I, R, i, A, S);
+    const float l = (float)(0.5 * A * A / S);
+    *lr = l;
+    *ep = i;
+    *du = j;
+    *z = (float)(A / S);
+    *zv = (float)(1.0 / S);
+    return l;
+}
+
+}  // namespace dev
+}  // namespace cetra

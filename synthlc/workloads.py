@@ -212,6 +212,68 @@ def small_random(seed: int, n_obs: int = 600, cadence_s: float = 611.7,
                     injections=[inj], seed=seed)
 
 
+def duty_cycle_periods(p_min: float, p_max: float, span: float, d_min: float, alpha: float = 0.389):
+    """Period grid with relative step dP/P = alpha * D_min / T (the phase
+    shift of the last transit stays a fixed fraction of the shortest
+    duration)."""
+    step = alpha * d_min / span
+    k = int(np.floor(np.log(p_max / p_min) / np.log1p(step))) + 1
+    return p_min * (1.0 + step) ** np.arange(k)
+
+
+def survey_curve(rng, n_points: int, cadence_s: float = 120.0, sigma_ppm: float = 800.0,
+                 planet_frac: float = 0.3, durations=None, p_range=(0.5, 40.0)):
+    """One light curve of a batched survey: regular cadence, Poisson(1.5)
+    gaps of U(0.2, 2) d, per-point sigma log-normal (log-sd 0.25) around
+    sigma_ppm, and with probability planet_frac one transit with P log-uniform
+    over p_range, depth log-uniform 100-5000 ppm, b uniform 0-0.9 and the
+    duration of a circular orbit around a Sun-density star."""
+    c = cadence_s / DAY_S
+    t = np.arange(n_points, dtype=np.float64) * c
+    span = t[-1]
+    keep = np.ones(n_points, dtype=bool)
+    for _ in range(rng.poisson(1.5)):
+        glen = rng.uniform(0.2, 2.0)
+        g0 = rng.uniform(0.0, max(span - glen, 1e-9))
+        keep &= ~((t >= g0) & (t < g0 + glen))
+    if keep.sum() < 2:
+        keep[:2] = True
+    t = t[keep]
+    sig = sigma_ppm * 1e-6 * np.exp(0.25 * rng.normal(size=t.shape[0]))
+    injs = []
+    y = 1.0 + rng.normal(size=t.shape[0]) * sig
+    if rng.uniform() < planet_frac:
+        P = float(np.exp(rng.uniform(np.log(p_range[0]), np.log(p_range[1]))))
+        b = float(rng.uniform(0.0, 0.9))
+        dur = transit.transit_duration_days(P, b)
+        inj = Injection(P, rng.uniform(0.0, P), dur,
+                        float(np.exp(rng.uniform(np.log(100e-6), np.log(5000e-6)))), b)
+        y = y - inject(t, inj)
+        injs.append(inj)
+    return t, to_offset(y), sig.astype(np.float32), injs
+
+
+def batched_survey(n_curves: int, seed: int = 20250328, n_min: int = 5000, n_max: int = 120000,
+                   n_dur: int = 16, d_min_h: float = 0.5, d_max_h: float = 10.0, alpha: float = 0.389,
+                   p_min: float = 0.5, p_max: float = 40.0):
+    """A batch of survey light curves of uneven length (uniform n_min-n_max
+    points at 2-min cadence), shared durations, and per-curve duty-cycle
+    period grids over [p_min, min(p_max, T/2)]."""
+    rng = np.random.default_rng(seed)
+    durs = log_durations(d_min_h, d_max_h, n_dur)
+    curves = []
+    for _ in range(n_curves):
+        n = int(rng.integers(n_min, n_max + 1))
+        t, f, s, injs = survey_curve(rng, n, durations=durs, p_range=(p_min, p_max))
+        span = t[-1] - t[0]
+        hi = min(p_max, span / 2.0)
+        periods = duty_cycle_periods(p_min, hi, span, durs[0], alpha) if hi > p_min else np.zeros(0)
+        curves.append(Workload(name=f"survey-{len(curves)}", t=t, f=f, sigma=s, cadence=120.0 / DAY_S,
+                               durations=durs, periods=periods, dense=transit.dense_template(),
+                               injections=injs, seed=seed))
+    return curves
+
+
 WORKLOADS = {
     "tiny": tiny_single,
     "high_cadence": high_cadence,

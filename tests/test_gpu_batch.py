@@ -1,0 +1,162 @@
+"""Batched search: results bit-identical to single-curve calls, across arena
+generations, period blocks and graph replays; a host-set cancel flag ends
+the launches early and the same workspace then completes normally."""
+
+import numpy as np
+import pytest
+
+from synthlc import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2503_20875_amd as cm
+    cm._abi.load()
+    return cm
+
+
+def make_batch(n=10, seed=7, thin=25):
+    curves = W.batched_survey(n, seed=seed, n_min=2000, n_max=15000)
+    for c in curves:
+        c.periods = c.periods[::thin].copy()
+    # edge cases: a 2-point curve, an all-missing curve, a curve with no periods
+    tiny = curves[1]
+    tiny.t, tiny.f, tiny.sigma = tiny.t[:2].copy(), tiny.f[:2].copy(), tiny.sigma[:2].copy()
+    curves[2].sigma = np.full_like(curves[2].sigma, np.nan)
+    curves[3].periods = np.zeros(0)
+    return curves
+
+
+def pack(cm, curves):
+    grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations, 0.0, c.n_model) for c in curves]
+    obs_off = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
+    per_off = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
+    t = np.concatenate([c.t for c in curves])
+    f = np.concatenate([c.f for c in curves])
+    s = np.concatenate([c.sigma for c in curves])
+    p = np.concatenate([c.periods for c in curves]) if per_off[-1] else np.zeros(1)
+    return grids, obs_off, per_off, t, f, s, p
+
+
+def single_results(cm, curves, model):
+    import torch
+    out = []
+    print(f"[single] {len(curves)} curves", flush=True)
+    for c in curves:
+        r = {}
+        if len(c.periods):
+            res = cm.search(c.t, c.f, c.sigma, c.cadence, c.durations, c.periods, c.dense, n_model=c.n_model)
+            torch.cuda.synchronize()
+            r = {k: v.cpu().numpy() for k, v in res["periodic"].items()}
+            r["best"] = cm.best_record(res["best_raw"])
+        out.append(r)
+    return out
+
+
+def batch_results(cm, plan, curves, packed, model, **kw):
+    import torch
+    grids, obs_off, per_off, t, f, s, p = packed
+    print(f"[batch] curves={plan.n_curves} items={plan.info['n_items']} gens={plan.info['n_generations']} "
+          f"block={plan.info['period_block']} kw={sorted(kw)}", flush=True)
+    o = cm.batch_search(plan, t, f, s, model, p, **kw)
+    torch.cuda.synchronize()
+    print(f"[batch] done status={int(o['status'].item())}", flush=True)
+    return o
+
+
+def compare(cm, o, single, per_off):
+    h = {k: v.cpu().numpy() for k, v in o.items() if k not in ("best", "status")}
+    bests = cm.best_records(o["best"])
+    for ci, r in enumerate(single):
+        sl = slice(per_off[ci], per_off[ci + 1])
+        if not r:
+            assert bests[ci]["k"] == -1
+            continue
+        for k in ("lr", "epoch", "dur", "depth", "depth_var"):
+            assert np.array_equal(h[k][sl], r[k], equal_nan=True), (ci, k)
+        b, sb = bests[ci], r["best"]
+        for k in ("k", "epoch", "dur", "lr", "depth", "depth_var", "snr", "t0", "t0_abs", "period"):
+            assert (b[k] == sb[k]) or (np.isnan(b[k]) and np.isnan(sb[k])), (ci, k, b[k], sb[k])
+
+
+@pytest.fixture(scope="module")
+def setup(cm):
+    import torch
+    curves = make_batch()
+    model = cm.template_resample(torch.as_tensor(curves[0].dense, device="cuda"), curves[0].n_model)
+    packed = pack(cm, curves)
+    single = single_results(cm, curves, model)
+    return curves, model, packed, single
+
+
+def test_batch_equals_single_bitwise(cm, setup):
+    curves, model, packed, single = setup
+    grids, obs_off, per_off = packed[:3]
+    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=1 << 30)
+    assert plan.info["n_generations"] == 1
+    o = batch_results(cm, plan, curves, packed, model)
+    assert int(o["status"].item()) == 0
+    compare(cm, o, single, per_off)
+
+
+@pytest.mark.parametrize("block", [4, 8])
+def test_batch_generations_and_period_blocks(cm, setup, block):
+    """Smallest arena (two longest curves): many generations and launches,
+    arena halves reused; identical results."""
+    curves, model, packed, single = setup
+    grids, obs_off, per_off = packed[:3]
+    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=0, period_block=block)
+    assert plan.info["n_generations"] >= 4
+    o = batch_results(cm, plan, curves, packed, model)
+    assert int(o["status"].item()) == 0
+    compare(cm, o, single, per_off)
+
+
+def test_batch_graph_replay(cm, setup):
+    """Capture the whole launch sequence in a HIP graph; every replay, with
+    eager work in between, equals the single-curve results."""
+    import torch
+    curves, model, packed, single = setup
+    grids, obs_off, per_off, t, f, s, p = packed
+    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=0)
+    td, fd, sd, pd = (torch.as_tensor(x, device="cuda") for x in (t, f, s, p))
+    work = cm.batch_workspace(plan)
+    o = cm.batch_search(plan, td, fd, sd, model, pd, work=work)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            cm.batch_search(plan, td, fd, sd, model, pd, work=work, out=o)
+    torch.cuda.current_stream().wait_stream(side)
+    for rep in range(3):
+        for k in ("lr", "depth"):
+            o[k].fill_(-7.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(o["status"].item()) == 0
+        compare(cm, o, single, per_off)
+        _ = (torch.randn(1000, device="cuda") ** 2).sum().item()  # eager work between replays
+
+
+def test_batch_cancel_flag_stops_queue(cm, setup):
+    import torch
+    curves, model, packed, single = setup
+    grids, obs_off, per_off, t, f, s_, p = packed
+    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=0)
+    work = cm.batch_workspace(plan)
+    cancel = torch.ones(1, dtype=torch.int32, device="cuda")
+    o = batch_results(cm, plan, curves, packed, model, cancel=cancel, work=work)
+    assert int(o["status"].item()) & 1
+    # the same workspace then completes normally
+    cancel.zero_()
+    o = batch_results(cm, plan, curves, packed, model, cancel=cancel, work=work)
+    assert int(o["status"].item()) == 0
+    compare(cm, o, single, per_off)

@@ -1,0 +1,81 @@
+"""Pins of the FP64 proposal-network oracle: gradients against central finite
+differences, and the lag correlation against a direct double loop."""
+
+import numpy as np
+import pytest
+
+from oracle import net
+
+
+def small_case(seed=0, B=2, C=3, L=48, width=5, n_event=2, hidden=6):
+    rng = np.random.default_rng(seed)
+    p = net.init_params(c_in=C, width=width, n_layers=5, n_event=n_event, hidden=hidden, seed=seed)
+    for k in p:  # non-zero biases so every term is exercised
+        if k.startswith("b") or k in ("p", "u"):
+            p[k] = rng.normal(0, 0.1, p[k].shape)
+    x = rng.uniform(0, 1, (B, C, L))
+    lo = np.array([2, 3, 5, 9, 14])
+    hi = np.array([2, 4, 8, 13, 21])
+    q = (np.arange(5) + 0.5) / 5
+    y = np.zeros((B, 5))
+    y[0, 2] = 1
+    return p, x, lo, hi, q, y
+
+
+def total_loss(p, x, lo, hi, q, y):
+    z = net.forward(p, x, lo, hi, q)
+    return net.bce_loss(z, y, pos_weight=4.0)[0]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradients_match_central_differences(seed):
+    p, x, lo, hi, q, y = small_case(seed)
+    z, cache = net.forward(p, x, lo, hi, q, keep=True)
+    _, gz = net.bce_loss(z, y, pos_weight=4.0)
+    g = net.backward(p, cache, gz, lo, hi)
+    rng = np.random.default_rng(seed + 10)
+    h = 1e-6
+    for name in list(p.keys()) + ["x"]:
+        arr = x if name == "x" else p[name]
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = total_loss(p, x, lo, hi, q, y)
+            flat[idx] = old - h
+            lm = total_loss(p, x, lo, hi, q, y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[idx]
+            # relu kinks and max ties are measure-zero with random inputs
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (name, idx, fd, an)
+
+
+def test_lag_correlation_direct():
+    rng = np.random.default_rng(3)
+    e = rng.uniform(0, 1, (2, 3, 40))
+    lags = np.array([1, 4, 7, 39, 40])
+    a = net.lag_correlation(e, lags)
+    for b in range(2):
+        for c in range(3):
+            for i, tau in enumerate(lags):
+                ref = sum(e[b, c, t] * e[b, c, t + tau] for t in range(40 - tau)) / 40 if tau < 40 else 0.0
+                assert a[b, c, i] == pytest.approx(ref, abs=1e-14)
+
+
+def test_periodic_events_peak_at_their_spacing():
+    """A train of events every 37 bins correlates most at lag 37."""
+    e = np.zeros((1, 1, 400))
+    e[0, 0, 5::37] = 1.0
+    lags = np.arange(1, 120)
+    a = net.lag_correlation(e, lags)[0, 0]
+    assert lags[np.argmax(a)] == 37
+    assert a[lags == 74][0] > 0 and a[lags == 20][0] == 0
+
+
+def test_windows_cover_the_lag_axis():
+    lo, hi, q, edges = net.windows_for(512, 1.0, 100.0, 111.5 / 8192)
+    assert lo.shape == (512,) and np.all(hi >= lo) and np.all(np.diff(lo) >= 0)
+    assert lo[0] == round(1.0 / (111.5 / 8192)) and hi[-1] == round(100.0 / (111.5 / 8192))
+    p = net.init_params()
+    assert 150_000 < net.n_params(p) < 260_000
