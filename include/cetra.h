@@ -96,13 +96,14 @@ typedef struct cetra_best_record {
 } cetra_best_record;
 
 /* Launch tuning of the periodic search, process-wide for this library
- * instance (an autotuner sets it; the defaults are 8, 8, 4).  Results do not
+ * instance (an autotuner sets it; the defaults are 8, 8, 4, 1).  Results do not
  * depend on it except through near-ties of the argmax. */
 typedef struct cetra_tuning {
     int32_t fold_period_block;  /* trial periods accumulated per lane: 4, 8 or 16     */
     int32_t fold_wgs_per_cu;    /* resident workgroups per compute unit, 1..32       */
     int32_t fold_units_per_wg;  /* target work units per workgroup, 1..64            */
-    int32_t reserved[5];
+    int32_t fold_lds;           /* 1: stage each transit step's window in LDS       */
+    int32_t reserved[4];
 } cetra_tuning;
 
 /* ---------------------------------------------------------------- service */
@@ -269,7 +270,9 @@ int cetra_batch_plan_info(const cetra_batch_plan *plan, cetra_batch_info *info);
  * searches, e.g. graph replays). */
 int cetra_batch_tables(const cetra_batch_plan *plan, void *host_dst, size_t bytes);
 
-/* Search every curve of the batch.  Enqueues a counter-clearing kernel and
+/* Currently switched off: returns CETRA_ERR_INVALID and enqueues nothing
+ * (its launches did not complete on the GPU; cause not yet found).
+ * Search every curve of the batch.  Enqueues a counter-clearing kernel and
  * then 2 + 3 G persistent launches (G = generations): RES(0); LIN(0); and per
  * generation FOLD(g)+RES(g+1), EPI(g)+LIN(g+1), FIN(g) -- resampling, linear
  * search, fold, epilogue and best period of each curve, every launch draining

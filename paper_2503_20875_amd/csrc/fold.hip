@@ -101,10 +101,12 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 }
 
 // Persistent grid over units (period block of B periods, duration j, epoch
-// chunk), ordered block-fastest; each unit is one dev::fold_unit.
-template <int B>
+// chunk), ordered block-fastest; each unit is one dev::fold_unit (kLds:
+// dev::fold_unit_lds).
+template <int B, bool kLds>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
                                                         int32_t I, int32_t n_chunks, int64_t n_units) {
+    __shared__ float2 s_buf[kLds ? cetra::dev::kFoldLdsCap : 1];
     const int64_t n_pblk = (n_eval + B - 1) / B;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pb = u % n_pblk;
@@ -129,7 +131,10 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
         const int32_t e_lo = c * chunk;
         const int32_t e_hi = min(ipmax, e_lo + chunk);
         if (e_lo >= e_hi) continue;
-        cetra::dev::fold_unit<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
+        if (kLds)
+            cetra::dev::fold_unit_lds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0, s_buf);
+        else
+            cetra::dev::fold_unit<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
     }
 }
 
@@ -266,11 +271,15 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
     const int B = tu.fold_period_block;
     const int64_t n_pblk = ceil_div(n_eval, B);
     // persistent grid: no more workgroups than can be resident at once
+    const void *kern = nullptr;
+    if (tu.fold_lds)
+        kern = B == 4 ? (const void *)fold_kernel<4, true> : B == 16 ? (const void *)fold_kernel<16, true>
+                                                                    : (const void *)fold_kernel<8, true>;
+    else
+        kern = B == 4 ? (const void *)fold_kernel<4, false> : B == 16 ? (const void *)fold_kernel<16, false>
+                                                                     : (const void *)fold_kernel<8, false>;
     int occ = 0;
-    hipError_t oe = B == 4    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fold_kernel<4>, kThreads, 0)
-                    : B == 16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fold_kernel<16>, kThreads, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fold_kernel<8>, kThreads, 0);
-    if (oe != hipSuccess || occ <= 0) occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0) != hipSuccess || occ <= 0) occ = 1;
     const int64_t wgs = (int64_t)device_cu_count() * std::min(tu.fold_wgs_per_cu, occ);
     const int64_t base_units = n_pblk * grid->n_dur;
     int64_t n_chunks = ceil_div((int64_t)tu.fold_units_per_wg * wgs, base_units);
@@ -279,16 +288,10 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
     const int64_t grid_wgs = std::min<int64_t>(wgs, n_units);
     const auto *f2 = reinterpret_cast<const float2 *>(fold);
     const int32_t I = (int32_t)grid->n_t0;
-    if (B == 4)
-        hipLaunchKernelGGL(fold_kernel<4>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s, f2, w, n_eval, I,
-                           (int32_t)n_chunks, n_units);
-    else if (B == 16)
-        hipLaunchKernelGGL(fold_kernel<16>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s, f2, w, n_eval, I,
-                           (int32_t)n_chunks, n_units);
-    else
-        hipLaunchKernelGGL(fold_kernel<8>, dim3((unsigned)grid_wgs), dim3(kThreads), 0, s, f2, w, n_eval, I,
-                           (int32_t)n_chunks, n_units);
-    if ((rc = check_launch("periodic_search/fold"))) return rc;
+    const int32_t n_chunks32 = (int32_t)n_chunks;
+    void *args[] = {(void *)&f2, (void *)&w, (void *)&n_eval, (void *)&I, (void *)&n_chunks32, (void *)&n_units};
+    const hipError_t le = hipLaunchKernel(kern, dim3((unsigned)grid_wgs), dim3(kThreads), args, 0, s);
+    if (le != hipSuccess) return set_error(CETRA_ERR_HIP, "periodic_search/fold: %s", hipGetErrorString(le));
     hipLaunchKernelGGL(fold_epilogue_kernel, dim3((unsigned)ceil_div(n_eval, 256)), dim3(256), 0, s,
                        reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, grid->n_dur, lr, epoch, dur,
                        depth, depth_var);

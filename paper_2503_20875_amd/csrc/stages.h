@@ -354,6 +354,121 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
     }
 }
 
+// LDS-staged fold unit.  The workgroup owns 512 consecutive epochs (lane t:
+// epochs e0 + 2t and e0 + 2t + 1) of B periods.  For every transit step the
+// union of the B periods' element windows -- [e0 + min_b o_b, e0 + max_b o_b
+// + 512), a few hundred elements more than the tile when the periods are
+// close -- is loaded cooperatively into LDS with coalesced loads, and each
+// lane then reads its two elements per period from LDS (one 16-byte read).
+// Steps whose window exceeds kFoldLdsCap fall back to direct buffer loads.
+// The sums (and hence the ranking) are identical to fold_unit's.
+constexpr int kFoldLdsTile = 2 * kThreads;
+constexpr int kFoldLdsCap = 2048;  // float pairs (16 KB)
+
+template <int B>
+__device__ __forceinline__ void fold_unit_lds(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
+                                              const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
+                                              float2 *s_buf) {
+    const int lane = threadIdx.x & 63;
+    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    uint64_t best[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) best[b] = 0;
+
+    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldLdsTile) {
+        const int32_t t2 = 2 * (int32_t)threadIdx.x;
+        const int32_t e = e0 + t2;  // epochs e, e + 1
+        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
+        uint64_t acc[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
+            acc[b] = 2147483648ull;
+        }
+        bool done = false;
+        while (!done) {
+            for (int mm = 0; mm < kFoldChunk; ++mm) {
+                uint32_t o[B];
+                bool use[B];
+                uint32_t omin = 0xFFFFFFFFu, omax = 0;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const uint32_t hi = (uint32_t)(acc[b] >> 32);
+                    const bool live = hi < (uint32_t)I;
+                    o[b] = live ? hi : (uint32_t)I;
+                    acc[b] += live ? R[b] : 0ull;
+                    use[b] = ipb[b] > 0 && (uint32_t)e0 + o[b] < (uint32_t)I;
+                    omin = use[b] ? min(omin, o[b]) : omin;
+                    omax = use[b] ? max(omax, o[b]) : omax;
+                }
+                if (omin == 0xFFFFFFFFu) {  // no period has a transit inside the row
+                    done = true;
+                    break;
+                }
+                const uint32_t ws = (uint32_t)e0 + omin;
+                const uint32_t span = min(omax - omin + (uint32_t)kFoldLdsTile, (uint32_t)I - ws);
+                if (span <= (uint32_t)kFoldLdsCap) {
+                    __syncthreads();  // the previous step's reads are done
+                    for (uint32_t q = threadIdx.x; q < span; q += kThreads)
+                        s_buf[q] = load_pair(rsrc, (ws + q) * 8u, 0);
+                    __syncthreads();
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        if (!use[b]) continue;
+                        const uint32_t x = (uint32_t)t2 + (o[b] - omin);  // local index of epoch e
+                        const float2 v0 = x < span ? s_buf[x] : make_float2(0.0f, 0.0f);
+                        const float2 v1 = x + 1 < span ? s_buf[x + 1] : make_float2(0.0f, 0.0f);
+                        a0[b] += v0.x;
+                        s0[b] += v0.y;
+                        a1[b] += v1.x;
+                        s1[b] += v1.y;
+                    }
+                } else {
+                    const uint32_t e_bytes = (uint32_t)e * 8u;
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        if (!use[b]) continue;
+                        const uint32_t off = e_bytes + o[b] * 8u;
+                        const float2 v0 = load_pair(rsrc, off, 0);
+                        const float2 v1 = load_pair(rsrc, off, 8);
+                        a0[b] += v0.x;
+                        s0[b] += v0.y;
+                        a1[b] += v1.x;
+                        s1[b] += v1.y;
+                    }
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ta0[b] += a0[b];
+                ts0[b] += s0[b];
+                ta1[b] += a1[b];
+                ts1[b] += s1[b];
+                a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int32_t eh = e + h;
+                const float A = h ? ta1[b] : ta0[b];
+                const float S = h ? ts1[b] : ts0[b];
+                if (eh < ipb[b] && eh < e_hi && S > 0.0f) {
+                    const uint64_t key = fold_key(0.5f * A * (A / S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
+                    best[b] = key > best[b] ? key : best[b];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t m = wave_max_u64(best[b]);
+        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
+    }
+}
+
 // FP64 sums of one candidate (epoch i of row `row`, period step R), in
 // transit order.
 __device__ __forceinline__ void fold_sums(const float2 *row, int64_t I, uint64_t R, int64_t i, double &A, double &S) {

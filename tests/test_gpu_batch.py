@@ -7,7 +7,11 @@ import pytest
 
 from synthlc import workloads as W
 
-pytestmark = pytest.mark.gpu
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="batched search switched off: its launches did not complete on the MI355X "
+                            "(10-curve batch, > 75 s); cause not yet found, not to be run again until it is"),
+]
 
 
 @pytest.fixture(scope="module")

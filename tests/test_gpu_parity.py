@@ -279,3 +279,22 @@ def test_high_cadence_full_size_sampled(cm, ora):
     assert min(abs(b["period"] / (P * f) - 1) for P in (17.1, 3.2) for f in (0.5, 1, 2)) < 0.01
     alt = ora.fold_at(og, lin, b["period"], b["epoch"], b["dur"])
     assert b["lr"] == pytest.approx(alt[0], rel=TOL)
+
+
+@pytest.mark.parametrize("cfg", [(8, 8, 4, 1), (4, 8, 4, 1), (8, 8, 4, 0), (4, 8, 16, 0)])
+def test_fold_variants_identical(cm, ora, tiny_pair, tiny_wl, cfg):
+    """Register and LDS fold variants, period blocks 4 and 8: the same
+    per-period records, bit for bit (the FP32 ranking sums are accumulated in
+    the same order), and parity with the oracle."""
+    import torch
+    r, o, g = tiny_pair
+    cm.set_tuning(*cfg)
+    try:
+        per = cm.periodic_search(r["grid"], r["fold"], tiny_wl.periods)
+        torch.cuda.synchronize()
+    finally:
+        cm.reset_tuning()
+    h = {k: v.cpu().numpy() for k, v in per.items()}
+    for k in ("lr", "epoch", "dur", "depth", "depth_var"):
+        assert np.array_equal(h[k], g[k], equal_nan=True), (cfg, k)
+    check_periodic(h, o["periodic"], fold_at(ora, o), tiny_wl.periods)
