@@ -96,7 +96,7 @@ typedef struct cetra_best_record {
 } cetra_best_record;
 
 /* Launch tuning of the periodic search, process-wide for this library
- * instance (an autotuner sets it; the defaults are 8, 8, 4, 1).  Results do not
+ * instance (an autotuner sets it; the defaults are 8, 8, 4, 0).  Results do not
  * depend on it except through near-ties of the argmax. */
 typedef struct cetra_tuning {
     int32_t fold_period_block;  /* trial periods accumulated per lane: 4, 8 or 16     */
@@ -292,6 +292,116 @@ int cetra_batch_search(const cetra_batch_plan *plan, void *stream, const double 
                        const float *sigma, const float *model, const double *periods, void *work,
                        size_t work_bytes, const int32_t *cancel, float *lr, int32_t *epoch, int32_t *dur,
                        float *depth, float *depth_var, cetra_best_record *best, int32_t *status);
+
+/* ------------------------------------------------------------------------
+ * Period-window proposal network (an addition, not part of the paper).
+ *
+ * A small 1-D convolutional network reads the linear search's single-event
+ * statistics (Sec. 2.2), downsampled to L bins, and scores W period windows;
+ * the periodic search (Sec. 2.3) then folds only the periods of the K
+ * best-scored windows (cetra_periodic_search's subset argument).  The calls
+ * below are the network's forward and backward stages and its optimiser, so
+ * that training and inference run on the device; the host only sequences
+ * them.  Conventions:
+ *   bf16   device buffers of IEEE bfloat16 values (passed as void*)
+ *   x      input [batch][L][16] bf16 (channel-last; channels = durations)
+ *   h      trunk activations [batch][L][64] bf16 (after ReLU)
+ *   conv weights, packed: [64][k32] bf16, element (co, tap*cin + ci) is
+ *          W[co][ci][tap] of the cross-correlation y[t] = sum W x[t+tap-4]
+ *          (zero padding 4), k32 = 9*cin rounded up to a multiple of 32,
+ *          padding columns zero (tap-major, channel-minor; FP32 masters and
+ *          weight gradients use the same [64][k32] layout)
+ *   e      event channels [batch][L][E] FP32, E <= 16
+ *   a      lag correlation [batch][E][n_tau] FP32, lags tau_lo .. tau_lo+n_tau-1
+ *   windows  win_lo/win_hi: device int32[W] inclusive lag ranges (absolute
+ *          lags), win_q: device float[W] window position in [0, 1]
+ *   f      window features [batch][W][2E+1] FP32 = (max_c, mean_c, q)
+ *   z      logits [batch][W] FP32
+ * Gradient outputs named d* / g* that are parameters accumulate (+=): the
+ * caller clears them before each step; activation gradients are overwritten.
+ * Every call only enqueues work on `stream`; errors as for the other calls.
+ * ---------------------------------------------------------------------- */
+
+/* One v_mfma_f32_16x16x32_bf16: c[16][16] (FP32) = a[16][32] b[32][16]
+ * (bf16, row-major); pins the operand layout the convolutions assume. */
+int cetra_net_mfma_probe(void *stream, const void *a, const void *b, float *c);
+
+/* x[bin][j] (bf16) = min(sqrt(max over the bin's reference times of
+ * S_fm^2 / S_mm), 30) / 8 from a fold-ready array [n_dur][n_t0][2] (device);
+ * bins split the reference times evenly (bin b covers i in
+ * [b n_t0 / n_bins, (b+1) n_t0 / n_bins)).  x is [n_bins][n_dur]. */
+int cetra_net_downsample(void *stream, const float *fold, int32_t n_dur, int64_t n_t0, int32_t n_bins, void *x);
+
+/* y = relu(conv(x, w) + bias): x [batch][L][cin] bf16 (cin 16 or 64),
+ * w packed bf16, bias[64] FP32, y [batch][L][64] bf16.  MFMA implicit GEMM. */
+int cetra_conv1d_fwd(void *stream, const void *x, int32_t cin, int32_t L, int32_t batch, const void *w,
+                     int32_t k32, const float *bias, void *y);
+
+/* Backward of cetra_conv1d_fwd given dy [batch][L][64] FP32 (gradient of the
+ * post-ReLU output y): dw [64][k32] FP32 and db[64] accumulate; dx
+ * [batch][L][cin] FP32 is overwritten (dx = NULL skips it).  Scratch:
+ * g_scratch batch*L*64 bf16, wt_scratch 64*9*cin bf16 (device). */
+int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, const void *x, int32_t cin, int32_t L,
+                     int32_t batch, const void *w, int32_t k32, void *g_scratch, void *wt_scratch, float *dx,
+                     float *dw, float *db);
+
+/* e[pos][c] = relu(P[c][:] . h[pos][:] + p[c]) over n_pos = batch*L
+ * positions; P [E][64], p[E] FP32. */
+int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p, int32_t E,
+                          float *e);
+/* Backward of the projection given ge [n_pos][E]: dh [n_pos][64] FP32
+ * (overwritten), dP [E][64] and dp[E] accumulate. */
+int cetra_net_project_bwd(void *stream, const void *h, const float *e, const float *ge, int64_t n_pos,
+                          const float *P, int32_t E, float *dh, float *dP, float *dp);
+
+/* a[b][c][i] = (1/L) sum_t e[b][t][c] e[b][t+tau][c], tau = tau_lo + i
+ * (terms past the end are zero).  L <= 8192, tau_lo >= 1. */
+int cetra_net_lag_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E, int32_t tau_lo,
+                      int32_t n_tau, float *a);
+/* Window max / mean of a over each window's lags (clipped to the computed
+ * lags) plus q; arg[b][w][c] = index into a's lag axis of the first maximum
+ * (-1 for an empty window, whose features are 0). */
+int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
+                       const int32_t *win_lo, const int32_t *win_hi, const float *win_q, int32_t W, float *f,
+                       int32_t *arg);
+/* z = v . relu(U f + u) + v0 per (example, window); U [H][nf], H <= 128,
+ * nf = 2E+1. */
+int cetra_net_head_fwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U, const float *u,
+                       const float *v, const float *v0, int32_t H, float *z);
+/* Weighted binary cross-entropy with logits, mean over the n logits:
+ * loss[0] += value (device), gz = d loss / d z (overwritten); labels y in
+ * {0, 1}, positives weighted by pos_weight. */
+int cetra_net_bce(void *stream, const float *z, const float *y, int64_t n, float pos_weight, float *gz,
+                  float *loss);
+/* Head backward: gU, gu, gv, gv0 accumulate; gf [n_bw][nf] overwritten. */
+int cetra_net_head_bwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U, const float *u,
+                       const float *v, int32_t H, const float *gz, float *gU, float *gu, float *gv, float *gv0,
+                       float *gf);
+/* Pool backward: ga [B][E][n_tau] accumulates (the caller zeroes it). */
+int cetra_net_pool_bwd(void *stream, const float *gf, const int32_t *arg, int32_t B, int32_t E, int32_t n_tau,
+                       int32_t tau_lo, const int32_t *win_lo, const int32_t *win_hi, int32_t W, float *ga);
+/* Lag-correlation backward: ge [B][L][E] (overwritten). n_tau <= 8192. */
+int cetra_net_lag_bwd(void *stream, const float *e, const float *ga, int32_t B, int32_t L, int32_t E,
+                      int32_t tau_lo, int32_t n_tau, float *ge);
+
+/* One Adam step (bias-corrected, step >= 1) on n FP32 parameters p with
+ * gradient g and moments m, v (device, updated in place). */
+int cetra_adam_step(void *stream, float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1,
+                    float beta2, float eps, int64_t step);
+/* Packed bf16 conv weights (layout above) from FP32 masters w [64][k32] in
+ * the same layout (padding columns are written as zero whatever w holds). */
+int cetra_net_pack_conv_w(void *stream, const float *w, int32_t cin, int32_t k32, void *out);
+
+/* out[b][r] = index of the window with the r-th largest score of example b
+ * (ties: smaller index first); 1 <= K <= W <= 1024. */
+int cetra_topk_windows(void *stream, const float *scores, int32_t B, int32_t W, int32_t K, int32_t *out);
+/* Ascending indices k of the periods[K] (device, ascending) that fall in a
+ * selected window, edges[w] <= P < edges[w+1] (edges: device double[W+1],
+ * ascending; W <= 4096); sel[n_sel] device window indices (out-of-range
+ * entries ignored).  subset must hold K entries; *n_out (device) = count.
+ * The result is cetra_periodic_search's subset argument. */
+int cetra_windows_to_periods(void *stream, const double *periods, int64_t K, const double *edges, int32_t W,
+                             const int32_t *sel, int32_t n_sel, int64_t *subset, int64_t *n_out);
 
 #ifdef __cplusplus
 }

@@ -99,10 +99,25 @@ def windows_for(n_windows: int, p_lo: float, p_hi: float, bin_days: float):
     return lo, hi, q, edges
 
 
-def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = False):
-    h = [x]
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    a = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    a = (a + 0x7FFF + ((a >> 16) & 1)) & 0xFFFF0000
+    return a.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _q(x, on):
+    return bf16(x) if on else x
+
+
+def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = False, bf16_trunk: bool = False):
+    """bf16_trunk: round the convolution inputs, weights and outputs to
+    bfloat16 (the storage precision of the device trunk); the arithmetic
+    stays FP64."""
+    h = [_q(x, bf16_trunk)]
     for l in range(n_layers):
-        h.append(np.maximum(conv1d(h[-1], p[f"W{l}"], p[f"b{l}"]), 0.0))
+        y = np.maximum(conv1d(h[-1], _q(p[f"W{l}"], bf16_trunk), p[f"b{l}"]), 0.0)
+        h.append(_q(y, bf16_trunk))
     pre_e = np.einsum("ec,bcl->bel", p["P"], h[-1]) + p["p"][None, :, None]
     e = np.maximum(pre_e, 0.0)
     lags = np.arange(int(win_lo.min()), int(win_hi.max()) + 1)
@@ -124,7 +139,7 @@ def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = F
     z = np.einsum("h,bwh->bw", p["v"], r) + p["v0"][0]
     if not keep:
         return z
-    cache = dict(h=h, pre_e=pre_e, e=e, lags=lags, a=a, arg=arg, f=f, pre_r=pre_r, r=r)
+    cache = dict(h=h, pre_e=pre_e, e=e, lags=lags, a=a, arg=arg, f=f, pre_r=pre_r, r=r, bf16_trunk=bf16_trunk)
     return z, cache
 
 
@@ -169,9 +184,10 @@ def backward(p: dict, cache: dict, gz, win_lo, win_hi, n_layers: int = 5) -> dic
     g["P"] = np.einsum("bel,bcl->ec", gpre_e, h[-1])
     g["p"] = gpre_e.sum(axis=(0, 2))
     gh = np.einsum("ec,bel->bcl", p["P"], gpre_e)
+    rq = cache.get("bf16_trunk", False)
     for l in reversed(range(n_layers)):
-        gh = gh * (h[l + 1] > 0)
-        gx, g[f"W{l}"], g[f"b{l}"] = conv1d_backward(h[l], p[f"W{l}"], gh)
+        gh = _q(gh * (h[l + 1] > 0), rq)
+        gx, g[f"W{l}"], g[f"b{l}"] = conv1d_backward(h[l], _q(p[f"W{l}"], rq), gh)
         gh = gx
     g["x"] = gh
     return g

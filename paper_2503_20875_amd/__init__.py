@@ -63,7 +63,7 @@ def get_tuning() -> dict:
 
 
 def set_tuning(fold_period_block: int = 8, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
-               fold_lds: int = 1) -> None:
+               fold_lds: int = 0) -> None:
     t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_lds)
     _abi.check(_abi.load().cetra_set_tuning(ctypes.byref(t)))
 

@@ -98,7 +98,7 @@ class BatchInfo(ctypes.Structure):
 
 
 _P = ctypes.c_void_p
-_i32, _i64, _d, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_i32, _i64, _d, _sz, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_float
 
 # name -> (restype, argtypes); the list is the ABI's export list
 SIGNATURES = {
@@ -122,6 +122,23 @@ SIGNATURES = {
     "cetra_batch_tables": (ctypes.c_int, [_P, _P, _sz]),
     "cetra_batch_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P, _P, _P, _P, _P, _P,
                                           _P]),
+    "cetra_net_mfma_probe": (ctypes.c_int, [_P, _P, _P, _P]),
+    "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
+    "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),
+    "cetra_conv1d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _P, _i32, _P, _P, _P, _P, _P]),
+    "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _P]),
+    "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _P, _i32, _P, _P, _P]),
+    "cetra_net_lag_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
+    "cetra_net_pool_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _P, _P, _P, _i32, _P, _P]),
+    "cetra_net_head_fwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P, _P, _P, _i32, _P]),
+    "cetra_net_bce": (ctypes.c_int, [_P, _P, _P, _i64, _f32, _P, _P]),
+    "cetra_net_head_bwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P, _P, _i32, _P, _P, _P, _P, _P, _P]),
+    "cetra_net_pool_bwd": (ctypes.c_int, [_P, _P, _P, _i32, _i32, _i32, _i32, _P, _P, _i32, _P]),
+    "cetra_net_lag_bwd": (ctypes.c_int, [_P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
+    "cetra_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _i64, _f32, _f32, _f32, _f32, _i64]),
+    "cetra_net_pack_conv_w": (ctypes.c_int, [_P, _P, _i32, _i32, _P]),
+    "cetra_topk_windows": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P]),
+    "cetra_windows_to_periods": (ctypes.c_int, [_P, _P, _i64, _P, _i32, _P, _i32, _P, _P]),
 }
 
 _lib = None

@@ -1,0 +1,489 @@
+// Proposal network, after the convolutional trunk: 1x1 event projection, lag
+// correlation pooled over period windows, a shared MLP head per window, the
+// weighted binary cross-entropy, the Adam step, and the top-K window
+// selection that restricts the periodic search (Sec. 2.3) to the proposed
+// period windows.  VALU kernels (the work here is small next to the
+// convolutions).
+//
+// Shapes: B examples, L bins, E event channels (<= 16), W windows; e is
+// [B][L][E] FP32, lag correlation a is [B][E][n_tau] (lags tau_lo ..
+// tau_lo + n_tau - 1), window features f are [B][W][2E + 1] = (max, mean,
+// window position), logits z are [B][W].
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kWidth = 64;
+constexpr int kMaxE = 16;
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// e[b][t][c] = relu(sum_ci P[c][ci] h[b][t][ci] + p[c])
+__global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, const float *__restrict__ P,
+                                   const float *__restrict__ p, int32_t E, float *__restrict__ e) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n_pos) return;
+    float hv[kWidth];
+#pragma unroll
+    for (int ci = 0; ci < kWidth; ++ci) hv[ci] = (float)h[pos * kWidth + ci];
+    for (int c = 0; c < E; ++c) {
+        float s = p[c];
+#pragma unroll
+        for (int ci = 0; ci < kWidth; ++ci) s = fmaf(P[c * kWidth + ci], hv[ci], s);
+        e[pos * E + c] = fmaxf(s, 0.0f);
+    }
+}
+
+// gpre = ge * (e > 0); dh[pos][ci] = sum_c P[c][ci] gpre[c];
+// dP[c][ci] += sum_pos gpre[c] h[pos][ci]; dp[c] += sum_pos gpre[c]
+// (wave-level reductions, one atomic per wave and parameter).
+__global__ void __launch_bounds__(kT) project_bwd_kernel(const __bf16 *__restrict__ h, const float *__restrict__ e,
+                                                         const float *__restrict__ ge, int64_t n_pos,
+                                                         const float *__restrict__ P, int32_t E,
+                                                         float *__restrict__ dh, float *__restrict__ dP,
+                                                         float *__restrict__ dp) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = pos < n_pos;
+    const int lane = threadIdx.x & 63;
+    float g[kMaxE];
+    for (int c = 0; c < E; ++c) g[c] = (ok && e[pos * E + c] > 0.0f) ? ge[pos * E + c] : 0.0f;
+    for (int ci = 0; ci < kWidth; ++ci) {
+        const float hv = ok ? (float)h[pos * kWidth + ci] : 0.0f;
+        float s = 0.0f;
+        for (int c = 0; c < E; ++c) {
+            s = fmaf(P[c * kWidth + ci], g[c], s);
+            const float r = wave_sum(g[c] * hv);
+            if (lane == 0) atomicAdd(&dP[c * kWidth + ci], r);
+        }
+        if (ok) dh[pos * kWidth + ci] = s;
+    }
+    for (int c = 0; c < E; ++c) {
+        const float r = wave_sum(g[c]);
+        if (lane == 0) atomicAdd(&dp[c], r);
+    }
+}
+
+// a[b][c][i] = (1/L) sum_t e[b][t][c] e[b][t + tau][c], tau = tau_lo + i.
+// Workgroup: (block of 1024 lags, channel, example); e of the channel is
+// staged in LDS; each lane computes four consecutive lags.
+constexpr int kLagsPerLane = 4;
+constexpr int kMaxL = 8192;
+__global__ void __launch_bounds__(kT) lag_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
+                                                     int32_t tau_lo, int32_t n_tau, float *__restrict__ a) {
+    __shared__ float s_e[kMaxL];
+    const int32_t c = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
+    __syncthreads();
+    const int32_t i0 = (blockIdx.x * kT + threadIdx.x) * kLagsPerLane;
+    if (i0 >= n_tau) return;
+    const int32_t tau0 = tau_lo + i0;
+    float acc[kLagsPerLane] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int32_t t = 0; t + tau0 < L; ++t) {
+        const float x = s_e[t];
+#pragma unroll
+        for (int q = 0; q < kLagsPerLane; ++q) {
+            const int32_t u = t + tau0 + q;
+            acc[q] = fmaf(x, u < L ? s_e[u] : 0.0f, acc[q]);
+        }
+    }
+    const float inv = 1.0f / (float)L;
+#pragma unroll
+    for (int q = 0; q < kLagsPerLane; ++q)
+        if (i0 + q < n_tau) a[(b * E + c) * n_tau + i0 + q] = acc[q] * inv;
+}
+
+// Window features: f[b][w] = (max_tau a, mean_tau a over the window's lags,
+// q_w); arg[b][w][c] = lag index of the first maximum.
+__global__ void pool_fwd_kernel(const float *__restrict__ a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
+                                const int32_t *__restrict__ win_lo, const int32_t *__restrict__ win_hi,
+                                const float *__restrict__ win_q, int32_t W, float *__restrict__ f,
+                                int32_t *__restrict__ arg) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)B * W * E) return;
+    const int32_t c = (int32_t)(id % E);
+    const int64_t bw = id / E;
+    const int32_t w = (int32_t)(bw % W);
+    const int64_t b = bw / W;
+    const float *ac = a + (b * E + c) * n_tau;
+    // lag range clipped to the computed lags; an empty range gives zero
+    // features and no argmax (-1)
+    const int32_t lo = max(win_lo[w] - tau_lo, 0), hi = min(win_hi[w] - tau_lo, n_tau - 1);
+    float mx = -INFINITY, s = 0.0f;
+    int32_t am = -1;
+    for (int32_t i = lo; i <= hi; ++i) {
+        const float v = ac[i];
+        if (v > mx) {
+            mx = v;
+            am = i;
+        }
+        s += v;
+    }
+    const int32_t nf = 2 * E + 1;
+    f[bw * nf + c] = am >= 0 ? mx : 0.0f;
+    f[bw * nf + E + c] = am >= 0 ? s / (float)(hi - lo + 1) : 0.0f;
+    arg[id] = am;
+    if (c == 0) f[bw * nf + 2 * E] = win_q[w];
+}
+
+// z[b][w] = v . relu(U f + u) + v0 (hidden width <= 128)
+constexpr int kMaxHidden = 128;
+__global__ void head_fwd_kernel(const float *__restrict__ f, int64_t n_bw, int32_t nf, const float *__restrict__ U,
+                                const float *__restrict__ u, const float *__restrict__ v, const float *__restrict__ v0,
+                                int32_t H, float *__restrict__ z) {
+    const int64_t bw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bw >= n_bw) return;
+    float s = v0[0];
+    for (int hh = 0; hh < H; ++hh) {
+        float r = u[hh];
+        for (int k = 0; k < nf; ++k) r = fmaf(U[hh * nf + k], f[bw * nf + k], r);
+        s = fmaf(v[hh], fmaxf(r, 0.0f), s);
+    }
+    z[bw] = s;
+}
+
+// Weighted BCE with logits, mean over (b, w): loss (atomic sum) and dz.
+__global__ void bce_kernel(const float *__restrict__ z, const float *__restrict__ y, int64_t n, float pos_weight,
+                           float *__restrict__ gz, float *__restrict__ loss) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.0f;
+    if (i < n) {
+        const float zz = z[i], yy = y[i];
+        const float wt = yy > 0.5f ? pos_weight : 1.0f;
+        l = wt * (fmaxf(zz, 0.0f) - zz * yy + log1pf(expf(-fabsf(zz)))) / (float)n;
+        gz[i] = wt * (1.0f / (1.0f + expf(-zz)) - yy) / (float)n;
+    }
+    l = wave_sum(l);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
+}
+
+// Head backward: gradients of U, u, v, v0 (wave reductions + atomics) and of
+// the window features gf[b][w][k].
+__global__ void __launch_bounds__(kT) head_bwd_kernel(const float *__restrict__ f, int64_t n_bw, int32_t nf,
+                                                      const float *__restrict__ U, const float *__restrict__ u,
+                                                      const float *__restrict__ v, int32_t H,
+                                                      const float *__restrict__ gz, float *__restrict__ gU,
+                                                      float *__restrict__ gu, float *__restrict__ gv,
+                                                      float *__restrict__ gv0, float *__restrict__ gf) {
+    const int64_t bw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = bw < n_bw;
+    const int lane = threadIdx.x & 63;
+    const float g = ok ? gz[bw] : 0.0f;
+    float fv[2 * kMaxE + 1];
+    for (int k = 0; k < nf; ++k) fv[k] = ok ? f[bw * nf + k] : 0.0f;
+    float gfv[2 * kMaxE + 1];
+    for (int k = 0; k < nf; ++k) gfv[k] = 0.0f;
+    for (int hh = 0; hh < H; ++hh) {
+        float r = u[hh];
+        for (int k = 0; k < nf; ++k) r = fmaf(U[hh * nf + k], fv[k], r);
+        const float rr = fmaxf(r, 0.0f);
+        const float t1 = wave_sum(g * rr);
+        if (lane == 0) atomicAdd(&gv[hh], t1);
+        const float gp = r > 0.0f ? g * v[hh] : 0.0f;
+        const float t2 = wave_sum(gp);
+        if (lane == 0) atomicAdd(&gu[hh], t2);
+        for (int k = 0; k < nf; ++k) {
+            const float t3 = wave_sum(gp * fv[k]);
+            if (lane == 0) atomicAdd(&gU[hh * nf + k], t3);
+            gfv[k] = fmaf(U[hh * nf + k], gp, gfv[k]);
+        }
+    }
+    const float t4 = wave_sum(g);
+    if (lane == 0) atomicAdd(gv0, t4);
+    if (ok)
+        for (int k = 0; k < nf; ++k) gf[bw * nf + k] = gfv[k];
+}
+
+// Pool backward: ga[b][c][i] += gmax at the argmax lag and gmean / n over
+// the window's lags (windows may share lags: atomics).
+__global__ void pool_bwd_kernel(const float *__restrict__ gf, const int32_t *__restrict__ arg, int32_t B, int32_t E,
+                                int32_t n_tau, int32_t tau_lo, const int32_t *__restrict__ win_lo,
+                                const int32_t *__restrict__ win_hi, int32_t W, float *__restrict__ ga) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)B * W * E) return;
+    const int32_t c = (int32_t)(id % E);
+    const int64_t bw = id / E;
+    const int32_t w = (int32_t)(bw % W);
+    const int64_t b = bw / W;
+    const int32_t nf = 2 * E + 1;
+    float *gac = ga + (b * E + c) * n_tau;
+    const int32_t am = arg[id];
+    if (am < 0 || am >= n_tau) return;
+    atomicAdd(&gac[am], gf[bw * nf + c]);
+    const int32_t lo = max(win_lo[w] - tau_lo, 0), hi = min(win_hi[w] - tau_lo, n_tau - 1);
+    const float gm = gf[bw * nf + E + c] / (float)(hi - lo + 1);
+    for (int32_t i = lo; i <= hi; ++i) atomicAdd(&gac[i], gm);
+}
+
+// ge[b][t][c] = (1/L) sum_i ga[i] (e[t + tau_i] + e[t - tau_i]); e and ga of
+// the channel staged in LDS.
+__global__ void __launch_bounds__(kT) lag_bwd_kernel(const float *__restrict__ e, const float *__restrict__ ga,
+                                                     int32_t L, int32_t E, int32_t tau_lo, int32_t n_tau,
+                                                     float *__restrict__ ge) {
+    __shared__ float s_e[kMaxL];
+    __shared__ float s_g[kMaxL];
+    const int32_t c = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
+    for (int i = threadIdx.x; i < n_tau; i += kT) s_g[i] = ga[(b * E + c) * n_tau + i];
+    __syncthreads();
+    const int32_t t = blockIdx.x * kT + threadIdx.x;
+    if (t >= L) return;
+    float s = 0.0f;
+    for (int32_t i = 0; i < n_tau; ++i) {
+        const int32_t tau = tau_lo + i;
+        const float up = t + tau < L ? s_e[t + tau] : 0.0f;
+        const float dn = t - tau >= 0 ? s_e[t - tau] : 0.0f;
+        s = fmaf(s_g[i], up + dn, s);
+    }
+    ge[(b * L + t) * E + c] = s / (float)L;
+}
+
+// Adam on FP32 master parameters.
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                            float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// BF16 copy of FP32 conv weights [co][k32] (k = tap * cin + ci), padding
+// columns k >= 9 cin forced to zero.
+__global__ void pack_conv_w_kernel(const float *__restrict__ w, int32_t cin, int32_t k32, __bf16 *__restrict__ out) {
+    const int32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= kWidth * k32) return;
+    const int32_t k = id % k32;
+    out[id] = k < 9 * cin ? (__bf16)w[id] : (__bf16)0.0f;
+}
+
+// Top-K windows per example by score (bitonic sort of W <= 1024 in LDS;
+// ties to the smaller window index); out[b][r] = window of rank r.
+__global__ void __launch_bounds__(1024) topk_kernel(const float *__restrict__ z, int32_t W, int32_t K,
+                                                    int32_t *__restrict__ out) {
+    __shared__ float s_v[1024];
+    __shared__ int32_t s_i[1024];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x;
+    s_v[tid] = tid < W ? z[b * W + tid] : -INFINITY;
+    s_i[tid] = tid < W ? tid : 0x7fffffff;
+    __syncthreads();
+    // descending by value, ascending index on ties
+    for (int size = 2; size <= 1024; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int partner = tid ^ stride;
+            if (partner > tid) {
+                const bool desc = (tid & size) == 0;
+                const float va = s_v[tid], vb = s_v[partner];
+                const int32_t ia = s_i[tid], ib = s_i[partner];
+                const bool a_first = va > vb || (va == vb && ia < ib);
+                if (a_first != desc) {
+                    s_v[tid] = vb;
+                    s_v[partner] = va;
+                    s_i[tid] = ib;
+                    s_i[partner] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid < K) out[b * K + tid] = s_i[tid];
+}
+
+// Period subset of the selected windows: periods (ascending) whose value lies
+// in [edges[w], edges[w+1]) for a selected window w, as ascending indices.
+// One workgroup; returns the count in *n_out.
+__global__ void __launch_bounds__(1024) windows_to_periods_kernel(const double *__restrict__ periods, int64_t K,
+                                                                  const double *__restrict__ edges, int32_t W,
+                                                                  const int32_t *__restrict__ sel, int32_t n_sel,
+                                                                  int64_t *__restrict__ subset,
+                                                                  int64_t *__restrict__ n_out) {
+    __shared__ uint8_t s_on[4096];
+    __shared__ int64_t s_base;
+    __shared__ int32_t s_cnt[1024];
+    for (int i = threadIdx.x; i < W; i += blockDim.x) s_on[i] = 0;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_sel; i += blockDim.x)
+        if (sel[i] >= 0 && sel[i] < W) s_on[sel[i]] = 1;
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < K; k0 += blockDim.x) {
+        const int64_t k = k0 + threadIdx.x;
+        int32_t on = 0;
+        if (k < K) {
+            const double P = periods[k];
+            int lo = 0, hi = W;  // window w with edges[w] <= P < edges[w+1]
+            if (P >= edges[0] && P < edges[W]) {
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (edges[mid] <= P)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                on = s_on[lo];
+            }
+        }
+        s_cnt[threadIdx.x] = on;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {  // inclusive scan
+            const int32_t add = threadIdx.x >= (unsigned)off ? s_cnt[threadIdx.x - off] : 0;
+            __syncthreads();
+            s_cnt[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (on) subset[s_base + s_cnt[threadIdx.x] - 1] = k;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) s_base += s_cnt[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_out = s_base;
+}
+
+}  // namespace
+
+using namespace cetra;
+
+extern "C" int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p,
+                                     int32_t E, float *e) {
+    clear_error();
+    CETRA_REQUIRE(h && P && p && e, "net_project_fwd: NULL pointer");
+    CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_fwd: bad sizes");
+    hipLaunchKernelGGL(project_fwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), (const __bf16 *)h, n_pos, P, p, E, e);
+    return check_launch("net_project_fwd");
+}
+
+extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *e, const float *ge, int64_t n_pos,
+                                     const float *P, int32_t E, float *dh, float *dP, float *dp) {
+    clear_error();
+    CETRA_REQUIRE(h && e && ge && P && dh && dP && dp, "net_project_bwd: NULL pointer");
+    CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_bwd: bad sizes");
+    hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), (const __bf16 *)h, e, ge, n_pos, P, E, dh, dP, dp);
+    return check_launch("net_project_bwd");
+}
+
+extern "C" int cetra_net_lag_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E, int32_t tau_lo,
+                                 int32_t n_tau, float *a) {
+    clear_error();
+    CETRA_REQUIRE(e && a, "net_lag_fwd: NULL pointer");
+    CETRA_REQUIRE(L >= 1 && L <= kMaxL && E >= 1 && E <= kMaxE && B >= 1 && tau_lo >= 1 && n_tau >= 1,
+                  "net_lag_fwd: bad sizes");
+    hipLaunchKernelGGL(lag_fwd_kernel, dim3((unsigned)ceil_div(n_tau, kT * kLagsPerLane), E, B), dim3(kT), 0,
+                       as_stream(stream), e, L, E, tau_lo, n_tau, a);
+    return check_launch("net_lag_fwd");
+}
+
+extern "C" int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
+                                  const int32_t *win_lo, const int32_t *win_hi, const float *win_q, int32_t W,
+                                  float *f, int32_t *arg) {
+    clear_error();
+    CETRA_REQUIRE(a && win_lo && win_hi && win_q && f && arg, "net_pool_fwd: NULL pointer");
+    const int64_t n = (int64_t)B * W * E;
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), a, B, E, n_tau, tau_lo, win_lo, win_hi, win_q, W, f, arg);
+    return check_launch("net_pool_fwd");
+}
+
+extern "C" int cetra_net_head_fwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U,
+                                  const float *u, const float *v, const float *v0, int32_t H, float *z) {
+    clear_error();
+    CETRA_REQUIRE(f && U && u && v && v0 && z, "net_head_fwd: NULL pointer");
+    CETRA_REQUIRE(nf >= 1 && nf <= 2 * kMaxE + 1 && H >= 1 && H <= kMaxHidden, "net_head_fwd: bad sizes");
+    hipLaunchKernelGGL(head_fwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_bw, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), f, n_bw, nf, U, u, v, v0, H, z);
+    return check_launch("net_head_fwd");
+}
+
+extern "C" int cetra_net_bce(void *stream, const float *z, const float *y, int64_t n, float pos_weight, float *gz,
+                             float *loss) {
+    clear_error();
+    CETRA_REQUIRE(z && y && gz && loss, "net_bce: NULL pointer");
+    hipLaunchKernelGGL(bce_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), z, y, n, pos_weight, gz, loss);
+    return check_launch("net_bce");
+}
+
+extern "C" int cetra_net_head_bwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U,
+                                  const float *u, const float *v, int32_t H, const float *gz, float *gU, float *gu,
+                                  float *gv, float *gv0, float *gf) {
+    clear_error();
+    CETRA_REQUIRE(f && U && u && v && gz && gU && gu && gv && gv0 && gf, "net_head_bwd: NULL pointer");
+    CETRA_REQUIRE(nf >= 1 && nf <= 2 * kMaxE + 1 && H >= 1 && H <= kMaxHidden, "net_head_bwd: bad sizes");
+    hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_bw, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), f, n_bw, nf, U, u, v, H, gz, gU, gu, gv, gv0, gf);
+    return check_launch("net_head_bwd");
+}
+
+extern "C" int cetra_net_pool_bwd(void *stream, const float *gf, const int32_t *arg, int32_t B, int32_t E,
+                                  int32_t n_tau, int32_t tau_lo, const int32_t *win_lo, const int32_t *win_hi,
+                                  int32_t W, float *ga) {
+    clear_error();
+    CETRA_REQUIRE(gf && arg && win_lo && win_hi && ga, "net_pool_bwd: NULL pointer");
+    const int64_t n = (int64_t)B * W * E;
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), gf, arg, B, E, n_tau, tau_lo, win_lo, win_hi, W, ga);
+    return check_launch("net_pool_bwd");
+}
+
+extern "C" int cetra_net_lag_bwd(void *stream, const float *e, const float *ga, int32_t B, int32_t L, int32_t E,
+                                 int32_t tau_lo, int32_t n_tau, float *ge) {
+    clear_error();
+    CETRA_REQUIRE(e && ga && ge, "net_lag_bwd: NULL pointer");
+    CETRA_REQUIRE(L >= 1 && L <= kMaxL && n_tau >= 1 && n_tau <= kMaxL && E >= 1 && E <= kMaxE && B >= 1,
+                  "net_lag_bwd: bad sizes");
+    hipLaunchKernelGGL(lag_bwd_kernel, dim3((unsigned)ceil_div(L, kT), E, B), dim3(kT), 0, as_stream(stream), e, ga,
+                       L, E, tau_lo, n_tau, ge);
+    return check_launch("net_lag_bwd");
+}
+
+extern "C" int cetra_adam_step(void *stream, float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                               float beta1, float beta2, float eps, int64_t step) {
+    clear_error();
+    CETRA_REQUIRE(p && g && m && v && n >= 0 && step >= 1, "adam_step: bad arguments");
+    const float bc1 = 1.0f - powf(beta1, (float)step), bc2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), kT)), dim3(kT), 0,
+                       as_stream(stream), p, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2);
+    return check_launch("adam_step");
+}
+
+extern "C" int cetra_net_pack_conv_w(void *stream, const float *w, int32_t cin, int32_t k32, void *out) {
+    clear_error();
+    CETRA_REQUIRE(w && out && (cin == 16 || cin == 64) && k32 == (9 * cin + 31) / 32 * 32,
+                  "net_pack_conv_w: cin must be 16 or 64 and k32 = 9 cin rounded up to 32");
+    hipLaunchKernelGGL(pack_conv_w_kernel, dim3((unsigned)ceil_div(kWidth * k32, kT)), dim3(kT), 0,
+                       as_stream(stream), w, cin, k32, (__bf16 *)out);
+    return check_launch("net_pack_conv_w");
+}
+
+extern "C" int cetra_topk_windows(void *stream, const float *scores, int32_t B, int32_t W, int32_t K,
+                                  int32_t *out) {
+    clear_error();
+    CETRA_REQUIRE(scores && out, "topk_windows: NULL pointer");
+    CETRA_REQUIRE(W >= 1 && W <= 1024 && K >= 1 && K <= W && B >= 1, "topk_windows: need 1 <= K <= W <= 1024");
+    hipLaunchKernelGGL(topk_kernel, dim3(B), dim3(1024), 0, as_stream(stream), scores, W, K, out);
+    return check_launch("topk_windows");
+}
+
+extern "C" int cetra_windows_to_periods(void *stream, const double *periods, int64_t K, const double *edges,
+                                        int32_t W, const int32_t *sel, int32_t n_sel, int64_t *subset,
+                                        int64_t *n_out) {
+    clear_error();
+    CETRA_REQUIRE(periods && edges && sel && subset && n_out, "windows_to_periods: NULL pointer");
+    CETRA_REQUIRE(W >= 1 && W <= 4096 && n_sel >= 0 && K >= 0, "windows_to_periods: bad sizes");
+    hipLaunchKernelGGL(windows_to_periods_kernel, dim3(1), dim3(1024), 0, as_stream(stream), periods, K, edges, W, sel,
+                       n_sel, subset, n_out);
+    return check_launch("windows_to_periods");
+}

@@ -1,0 +1,241 @@
+"""Proposal network on the GPU against the FP64 net oracle.
+
+Tolerances follow from the device arithmetic: the trunk stores activations,
+weights and the back-propagated ReLU-masked gradients in bfloat16 (the oracle
+rounds at the same points with bf16_trunk=True), every sum accumulates in
+FP32.  Left over are FP32-vs-FP64 accumulation differences (relative ~1e-6)
+and, where such a difference moves a value across a bfloat16 rounding
+boundary, one bfloat16 unit (2^-8 relative) on a small fraction of the
+elements -- so norm-relative errors of a few 1e-4 are expected and 3e-3 is
+the bar.  Outputs rounded to bfloat16 by the kernel itself are compared to
+2^-8 relative.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import net as onet
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pn(torch):
+    import paper_2503_20875_amd as cm
+    from paper_2503_20875_amd import proposal
+    cm._abi.load()
+    return proposal
+
+
+def bf16_exact(rng, shape, lo=-1.0, hi=1.0):
+    return onet.bf16(rng.uniform(lo, hi, shape))
+
+
+def to_dev(torch, a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda").to(dtype)
+
+
+def rel_norm(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_mfma_probe_layout(torch, pn):
+    """One MFMA on small integers (exact in FP32) equals A @ B."""
+    rng = np.random.default_rng(1)
+    A = rng.integers(-8, 9, (16, 32)).astype(np.float64)
+    B = rng.integers(-8, 9, (32, 16)).astype(np.float64)
+    print("[net] mfma probe", flush=True)
+    C = pn.mfma_probe(to_dev(torch, A, torch.bfloat16), to_dev(torch, B, torch.bfloat16))
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy().astype(np.float64), A @ B)
+
+
+def packed_w(W):
+    """[64][cin][9] -> [64][k32] with k = tap * cin + ci (the test's own
+    restatement of the documented layout)."""
+    o, cin, taps = W.shape
+    k32 = (taps * cin + 31) // 32 * 32
+    out = np.zeros((o, k32))
+    out[:, :taps * cin] = W.transpose(0, 2, 1).reshape(o, taps * cin)
+    return out
+
+
+@pytest.mark.parametrize("cin,L,B", [(16, 300, 2), (64, 131, 3), (16, 1, 1), (64, 64, 1)])
+def test_conv_forward(torch, pn, cin, L, B):
+    rng = np.random.default_rng(cin + L)
+    x = bf16_exact(rng, (B, cin, L), 0.0, 1.0)
+    W = onet.bf16(rng.normal(0, np.sqrt(2.0 / (9 * cin)), (64, cin, 9)))
+    b = rng.normal(0, 0.1, 64).astype(np.float32).astype(np.float64)
+    ref = np.maximum(onet.conv1d(x, W, b), 0.0).transpose(0, 2, 1)  # [B][L][64]
+    print(f"[net] conv fwd cin={cin} L={L} B={B}", flush=True)
+    y = pn.conv1d_fwd(to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16), to_dev(torch, packed_w(W), torch.bfloat16),
+                      to_dev(torch, b, torch.float32))
+    torch.cuda.synchronize()
+    got = y.float().cpu().numpy().astype(np.float64)
+    scale = max(np.abs(ref).max(), 1e-30)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * scale)
+
+
+@pytest.mark.parametrize("cin,L,B", [(16, 300, 2), (64, 517, 2), (64, 5, 1)])
+def test_conv_backward(torch, pn, cin, L, B):
+    rng = np.random.default_rng(7 * cin + L)
+    x = bf16_exact(rng, (B, cin, L), 0.0, 1.0)
+    W = onet.bf16(rng.normal(0, np.sqrt(2.0 / (9 * cin)), (64, cin, 9)))
+    b = rng.normal(0, 0.1, 64)
+    y = onet.bf16(np.maximum(onet.conv1d(x, W, b), 0.0))  # post-ReLU output as the device stores it
+    dy = bf16_exact(rng, (B, 64, L))
+    G = dy * (y > 0)
+    gx, gW, gb = onet.conv1d_backward(x, W, G)
+    print(f"[net] conv bwd cin={cin} L={L} B={B}", flush=True)
+    dx, dw, db = pn.conv1d_bwd(to_dev(torch, dy.transpose(0, 2, 1), torch.float32),
+                               to_dev(torch, y.transpose(0, 2, 1), torch.bfloat16),
+                               to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16),
+                               to_dev(torch, packed_w(W), torch.bfloat16))
+    torch.cuda.synchronize()
+    k32 = (9 * cin + 31) // 32 * 32
+    dw = dw.cpu().numpy().astype(np.float64)
+    assert np.all(dw[:, 9 * cin:] == 0.0) and dw.shape == (64, k32)
+    dw = dw[:, :9 * cin].reshape(64, 9, cin).transpose(0, 2, 1)
+    for got, ref in ((dx.cpu().numpy().transpose(0, 2, 1), gx), (dw, gW), (db.cpu().numpy(), gb)):
+        scale = max(np.abs(ref).max(), 1e-30)
+        assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-5 * scale)
+
+
+def net_case(seed=0, B=2, L=700, n_win=48):
+    rng = np.random.default_rng(seed)
+    p = onet.init_params(c_in=16, width=64, n_layers=5, n_event=8, hidden=64, seed=seed)
+    for k in p:
+        if k.startswith("b") or k in ("p", "u"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    for k in p:  # FP32-exact parameters (the device masters are FP32)
+        p[k] = p[k].astype(np.float32).astype(np.float64)
+    x = bf16_exact(rng, (B, 16, L), 0.0, 1.0)
+    lo, hi, q, edges = onet.windows_for(n_win, 0.1, 5.0, 0.02)
+    q = q.astype(np.float32).astype(np.float64)
+    y = np.zeros((B, n_win))
+    for b in range(B):
+        y[b, rng.integers(n_win)] = 1.0
+    return p, x, (lo, hi, q, edges), y
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_network_forward_backward(torch, pn, seed):
+    p, x, (lo, hi, q, edges), y = net_case(seed)
+    z_ref, cache = onet.forward(p, x, lo, hi, q, keep=True, bf16_trunk=True)
+    loss_ref, gz = onet.bce_loss(z_ref, y, pos_weight=4.0)
+    g_ref = onet.backward(p, cache, gz, lo, hi)
+
+    win = pn.Windows.log_spaced(len(lo), 0.1, 5.0, 0.02)
+    assert np.array_equal(win.lo, lo) and np.array_equal(win.hi, hi)
+    model = pn.ProposalNet(n_event=8, hidden=64)
+    model.load_arrays(p)
+    print(f"[net] forward/backward seed={seed} B={x.shape[0]} L={x.shape[2]} W={len(lo)}", flush=True)
+    z = model.forward(to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16), win)
+    loss, dx = model.backward(to_dev(torch, y, torch.float32), pos_weight=4.0, want_dx=True)
+    torch.cuda.synchronize()
+    zg = z.cpu().numpy()
+    assert np.all(np.abs(zg - z_ref) <= 3e-3 * max(1.0, np.abs(z_ref).max()))
+    assert abs(float(loss.item()) - loss_ref) <= 3e-3 * abs(loss_ref)
+    g = model.grad_arrays()
+    for name, ref in g_ref.items():
+        got = dx.cpu().numpy().transpose(0, 2, 1) if name == "x" else g[name]
+        assert rel_norm(got, ref) < 3e-3, (name, rel_norm(got, ref))
+
+
+def test_adam_step(torch, pn):
+    """Adam on the flat parameter buffer against the update rule in FP64."""
+    model = pn.ProposalNet()
+    rng = np.random.default_rng(3)
+    p0 = model.flat.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(p0)
+    v = np.zeros_like(p0)
+    pcur = p0.copy()
+    for step in (1, 2):
+        g = rng.normal(0, 1e-2, p0.shape).astype(np.float32).astype(np.float64)
+        model.grad.copy_(torch.as_tensor(g, dtype=torch.float32))
+        model.adam(lr=1e-3)
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        pcur = pcur - 1e-3 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
+    torch.cuda.synchronize()
+    got = model.flat.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - pcur) <= 1e-6 * np.abs(pcur) + 1e-8)
+    # packed bf16 weights follow the masters, padding zero
+    w0 = model.packed[0].float().cpu().numpy()
+    assert np.array_equal(w0[:, :144], onet.bf16(model.view("W0").cpu().numpy())[:, :144]) and np.all(w0[:, 144:] == 0)
+
+
+def test_training_reduces_loss(torch, pn):
+    """A few Adam steps on a fixed batch lower the loss (periodic spikes in
+    the input, label = the window of their spacing)."""
+    B, L = 4, 512
+    win = pn.Windows.log_spaced(32, 0.1, 5.0, 0.02)
+    x = np.zeros((B, L, 16), dtype=np.float32)
+    y = np.zeros((B, win.n), dtype=np.float32)
+    rng = np.random.default_rng(5)
+    for b in range(B):
+        spacing = int(rng.integers(20, 200))
+        x[b, int(rng.integers(spacing))::spacing, :] = 1.0
+        y[b] = win.labels([spacing * 0.02])[0]
+    model = pn.ProposalNet(seed=2)
+    xd = torch.as_tensor(x, device="cuda").to(torch.bfloat16)
+    yd = torch.as_tensor(y, device="cuda")
+    losses = []
+    print("[net] training steps", flush=True)
+    for _ in range(60):
+        model.forward(xd, win)
+        losses.append(float(model.backward(yd, pos_weight=8.0).item()))
+        model.adam(lr=3e-3)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.7 * losses[0], losses
+
+
+def test_topk_windows(torch, pn):
+    rng = np.random.default_rng(9)
+    B, W = 3, 700
+    s = rng.normal(size=(B, W)).astype(np.float32)
+    s[0, 10] = s[0, 20] = s[0, 30] = 5.0  # ties: smaller index first
+    for K in (1, 64, W):
+        out = pn.topk_windows(torch.as_tensor(s, device="cuda"), K).cpu().numpy()
+        for b in range(B):
+            ref = np.lexsort((np.arange(W), -s[b]))[:K]
+            assert np.array_equal(out[b], ref), (K, b)
+
+
+def test_windows_to_periods(torch, pn):
+    win = pn.Windows.log_spaced(512, 0.5, 45.0, 0.01)
+    periods = np.geomspace(0.3, 60.0, 20011)  # partly outside the windows
+    sel = np.array([0, 3, 511, 250, 250, -1, 600], dtype=np.int32)  # duplicates and out-of-range ignored
+    subset, n = pn.windows_to_periods(torch.as_tensor(periods, device="cuda"), win,
+                                      torch.as_tensor(sel, device="cuda"))
+    torch.cuda.synchronize()
+    w = np.searchsorted(win.edges, periods, side="right") - 1
+    keep = np.isin(w, sel[(sel >= 0) & (sel < 512)]) & (w >= 0) & (w < 512)
+    ref = np.nonzero(keep)[0]
+    assert int(n.item()) == ref.size
+    assert np.array_equal(subset.cpu().numpy()[:ref.size], ref)
+
+
+def test_downsample(torch, pn):
+    rng = np.random.default_rng(11)
+    J, I, nb = 16, 10007, 257
+    fold = np.stack([rng.normal(0, 1, (J, I)), rng.uniform(0, 2, (J, I))], axis=2).astype(np.float32)
+    fold[:, ::7, 1] = 0.0  # null elements
+    fold[3, :, 0] = 1e4  # saturates at 30
+    out = pn.downsample(torch.as_tensor(fold, device="cuda"), nb).float().cpu().numpy()
+    x, w = fold[..., 0], fold[..., 1]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lr2 = np.where(w > 0, x * (x / w), np.float32(0.0)).astype(np.float32)
+    ref = np.zeros((nb, J))
+    for b in range(nb):
+        i0, i1 = b * I // nb, (b + 1) * I // nb
+        ref[b] = np.minimum(np.sqrt(np.maximum(lr2[:, i0:i1].max(axis=1), 0.0)), 30.0) / 8.0
+    assert np.all(np.abs(out - ref) <= 2.0 ** -8 * ref + 1e-7)
+    assert np.all(out[:, 3] == 3.75)

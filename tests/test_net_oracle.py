@@ -79,3 +79,42 @@ def test_windows_cover_the_lag_axis():
     assert lo[0] == round(1.0 / (111.5 / 8192)) and hi[-1] == round(100.0 / (111.5 / 8192))
     p = net.init_params()
     assert 150_000 < net.n_params(p) < 260_000
+
+
+def test_bf16_rounding_known_values():
+    """Round-to-nearest-even onto the 8-bit significand: exact values pass,
+    halfway cases go to the even neighbour."""
+    one_ulp = 2.0 ** -7  # spacing of bfloat16 in [1, 2)
+    vals = np.array([1.0, 1.0 + one_ulp, 1.0 + one_ulp / 2, 1.0 + 3 * one_ulp / 2, -2.5, 3.0e38, 1.0e-30])
+    got = net.bf16(vals)
+    assert got[0] == 1.0 and got[1] == 1.0 + one_ulp
+    assert got[2] == 1.0  # tie -> even (1.0)
+    assert got[3] == 1.0 + 2 * one_ulp  # tie -> even
+    assert got[4] == -2.5
+    assert abs(got[5] - 3.0e38) / 3.0e38 < 2 ** -8 and abs(got[6] - 1e-30) / 1e-30 < 2 ** -8
+    x = np.random.default_rng(0).normal(size=1000)
+    r = net.bf16(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
+    assert np.array_equal(net.bf16(r), r)
+
+
+def test_bf16_trunk_gradients_consistent():
+    """With the trunk rounded to bfloat16, the head and projection gradients
+    still match central differences (rounding is piecewise constant, so only
+    the parameters after the trunk are differentiated here)."""
+    p, x, lo, hi, q, y = small_case(4)
+    z, cache = net.forward(p, x, lo, hi, q, keep=True, bf16_trunk=True)
+    _, gz = net.bce_loss(z, y, pos_weight=4.0)
+    g = net.backward(p, cache, gz, lo, hi)
+    h = 1e-6
+    for name in ("P", "p", "U", "u", "v", "v0"):
+        flat = p[name].reshape(-1)
+        for idx in range(min(4, flat.size)):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = net.bce_loss(net.forward(p, x, lo, hi, q, bf16_trunk=True), y, 4.0)[0]
+            flat[idx] = old - h
+            lm = net.bce_loss(net.forward(p, x, lo, hi, q, bf16_trunk=True), y, 4.0)[0]
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (name, idx)
