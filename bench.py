@@ -8,7 +8,9 @@ pre-whitened, 5% gaps, two injected transits), 20 log-spaced durations
 0.5-15 h, 50 000 log-spaced periods 0.5-45 d; synthetic, seeded.
 
 Metric: light-curve points x trial periods per second, linear + periodic
-(N_obs * K / step time).  Prints one JSON line.
+(N_obs * K / step time), and the learned proposal's recall of the plain
+search's detections above SNR 7 with its speedup (held-out curves of the
+learned-proposal workload).  Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -28,12 +30,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_high_cadence_counters.json")
-FOLD_SOURCE = os.path.join(ROOT, "paper_2503_20875_amd", "csrc", "fold.hip")
+FOLD_SOURCES = [os.path.join(ROOT, "paper_2503_20875_amd", "csrc", name) for name in ("fold.hip", "stages.h")]
+PROPOSAL_WEIGHTS = os.path.join(ROOT, "paper_2503_20875_amd", "weights", "proposal.npz")
 
 
 def fold_source_hash() -> str:
-    with open(FOLD_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources the fold kernel is compiled from (counter figures
+    are only reported for the kernel they were taken on)."""
+    h = hashlib.sha256()
+    for path in FOLD_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_work(wl, grid):
@@ -87,6 +95,33 @@ def cpu_baseline(wl, stride: int = 50):
                 seconds_measured=round(t_lin + t_fold, 2))
 
 
+def learned_block(n_curves: int, seed: int = 20250402) -> dict:
+    """Learned proposal versus the plain periodic search on held-out curves of
+    the learned-proposal workload (80 000 points at 2-min cadence, half with
+    one planet; seeds disjoint from the training set): recall of the plain
+    detections above SNR 7 and the device-time speedup of proposal +
+    restricted fold over the full fold."""
+    if not os.path.exists(PROPOSAL_WEIGHTS):
+        return {"status": "no trained proposal weights in the tree"}
+    from paper_2503_20875_amd.learned import evaluate, load_weights
+    from paper_2503_20875_amd.train_proposal import make_pipeline
+    from synthlc import workloads as W
+    net, meta = load_weights(PROPOSAL_WEIGHTS)
+    pipe = make_pipeline()
+    rng = np.random.default_rng(seed)
+    curves = [W.learned_curve(rng) for _ in range(n_curves)]
+    r = evaluate(pipe, net, curves)
+    return {
+        "workload": (f"{n_curves} held-out curves, {W.LEARNED_N_POINTS} points at 120 s, 16 durations "
+                     f"0.5-10 h, K = {pipe.K} periods 1-100 d; top {pipe.cfg.top_k} of {pipe.cfg.n_windows} "
+                     f"log windows"),
+        "recall_at_snr7": r["recall"], "n_detections": r["n_detections"], "n_recalled": r["n_recalled"],
+        "plain_ms_per_curve": r["plain_ms_per_curve"], "learned_ms_per_curve": r["learned_ms_per_curve"],
+        "speedup": r["speedup"], "periods_folded_fraction": r["periods_folded_fraction"],
+        "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "batch", "lr", "seed")},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +134,8 @@ def main():
                          "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
                          "times (calibrates the HBM byte counters)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--learned-curves", type=int, default=32,
+                    help="held-out curves for the learned-versus-plain comparison (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the search has no "
@@ -246,6 +283,8 @@ def main():
         "wall_s_timed": wall,
         "best": {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"]},
     }
+    if args.learned_curves > 0 and args.workload == "high_cadence":
+        out["learned"] = learned_block(args.learned_curves)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -187,6 +187,7 @@ def backward(p: dict, cache: dict, gz, win_lo, win_hi, n_layers: int = 5) -> dic
     rq = cache.get("bf16_trunk", False)
     for l in reversed(range(n_layers)):
         gh = _q(gh * (h[l + 1] > 0), rq)
+        cache[f"G{l}"] = gh  # masked gradient entering layer l's convolution
         gx, g[f"W{l}"], g[f"b{l}"] = conv1d_backward(h[l], _q(p[f"W{l}"], rq), gh)
         gh = gx
     g["x"] = gh

@@ -62,7 +62,7 @@ def get_tuning() -> dict:
                 fold_units_per_wg=t.fold_units_per_wg, fold_lds=t.fold_lds)
 
 
-def set_tuning(fold_period_block: int = 8, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
+def set_tuning(fold_period_block: int = 4, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
                fold_lds: int = 0) -> None:
     t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_lds)
     _abi.check(_abi.load().cetra_set_tuning(ctypes.byref(t)))

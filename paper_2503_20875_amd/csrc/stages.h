@@ -313,15 +313,21 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
                     done = true;
                     break;
                 }
+                // all 2B loads of the step are issued before the first add
+                // consumes one, so a wave keeps 2B loads in flight
+                float2 v0[B], v1[B];
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const uint32_t off = e_bytes + o[b] * 8u;
-                    const float2 v0 = load_pair(rsrc, off, 0);
-                    const float2 v1 = load_pair(rsrc, off, 64 * 8);
-                    a0[b] += v0.x;
-                    s0[b] += v0.y;
-                    a1[b] += v1.x;
-                    s1[b] += v1.y;
+                    v0[b] = load_pair(rsrc, off, 0);
+                    v1[b] = load_pair(rsrc, off, 64 * 8);
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    a0[b] += v0[b].x;
+                    s0[b] += v0[b].y;
+                    a1[b] += v1[b].x;
+                    s1[b] += v1[b].y;
                 }
             }
 #pragma unroll

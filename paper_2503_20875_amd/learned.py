@@ -1,0 +1,182 @@
+"""Learned proposal around the plain search: features, training, proposal.
+
+The single-event statistics of the linear search (Sec. 2.2) are turned into
+network inputs on the device (cetra_net_downsample: per duration, the
+maximum single-event SNR in each of n_bins time bins), the proposal network
+scores log-spaced period windows, and the periodic search (Sec. 2.3) runs
+on the periods of the top-K windows only.  The plain search over every
+period stays available and is what the proposal's recall is measured
+against.
+"""
+
+from __future__ import annotations
+
+import io
+import json
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import best, best_record, grid_plan, linear_search, periodic_search, periodic_workspace, resample, \
+    template_resample
+from .proposal import C_IN, ProposalNet, Windows, downsample, topk_windows, windows_to_periods
+
+
+@dataclass
+class LearnedConfig:
+    n_bins: int = 8192
+    n_windows: int = 512
+    top_k: int = 64
+    p_lo: float = 1.0
+    p_hi: float = 100.0
+    n_event: int = 8
+    hidden: int = 64
+
+
+class Pipeline:
+    """Search of light curves that share one time grid (same cadence and
+    span), the same durations and the same period grid."""
+
+    def __init__(self, t_first: float, t_last: float, cadence: float, durations, periods, dense,
+                 cfg: LearnedConfig = LearnedConfig(), n_model: int = 1024):
+        import torch
+        if len(durations) != C_IN:
+            raise ValueError(f"the proposal network reads {C_IN} durations")
+        self.cfg = cfg
+        self.grid = grid_plan(t_first, t_last, cadence, durations, 0.0, n_model)
+        self.model = template_resample(torch.as_tensor(np.asarray(dense, np.float64), device="cuda"), n_model)
+        self.periods_host = np.ascontiguousarray(periods, dtype=np.float64)
+        if np.any(np.diff(self.periods_host) <= 0):
+            raise ValueError("periods must be ascending")
+        self.periods = torch.as_tensor(self.periods_host, device="cuda")
+        self.K = int(self.periods.numel())
+        bin_days = self.grid.n_t0 * self.grid.t0_step / cfg.n_bins
+        self.windows = Windows.log_spaced(cfg.n_windows, cfg.p_lo, cfg.p_hi, bin_days)
+        self.work = torch.empty(max(periodic_workspace(self.grid, self.K), 1), dtype=torch.uint8, device="cuda")
+        self.per = None
+
+    # ------------------------------------------------------------ features
+    def linear(self, t, f, sigma):
+        """Resample + linear search: fold-ready [J][I][2] (device)."""
+        flux, ivar, _ = resample(self.grid, t, f, sigma, status=False)
+        return linear_search(self.grid, flux, ivar, self.model)
+
+    def features(self, fold, out=None):
+        """bf16 [n_bins][J] network input from a fold-ready array."""
+        return downsample(fold, self.cfg.n_bins, out=out)
+
+    # -------------------------------------------------------------- search
+    def plain(self, fold):
+        """Periodic search over every period; host best record."""
+        self.per = periodic_search(self.grid, fold, self.periods, work=self.work, out=self.per)
+        return best_record(best(self.grid, self.periods, self.per))
+
+    def propose(self, net: ProposalNet, x):
+        """Top-K window indices [B][K] (device) for inputs x [B][n_bins][J]."""
+        z = net.forward(x, self.windows)
+        return topk_windows(z, self.cfg.top_k)
+
+    def restricted(self, fold, sel):
+        """Periodic search over the periods of the selected windows only
+        (one curve); host best record and the number of periods folded."""
+        subset, n = windows_to_periods(self.periods, self.windows, sel)
+        n_sub = int(n.item())
+        if n_sub == 0:
+            return None, 0
+        self.per = periodic_search(self.grid, fold, self.periods, subset=subset[:n_sub], work=self.work,
+                                   out=self.per)
+        return best_record(best(self.grid, self.periods, self.per)), n_sub
+
+    def window_of(self, period: float) -> int:
+        w = int(np.searchsorted(self.windows.edges, period, side="right") - 1)
+        return w if 0 <= w < self.windows.n else -1
+
+
+# ------------------------------------------------------------------ training
+def train(net: ProposalNet, x, y, windows: Windows, epochs: int, batch: int = 32, lr: float = 1e-3,
+          pos_weight: float = 32.0, seed: int = 0, log=None):
+    """Adam on (x [N][n_bins][J] bf16, y [N][W] FP32) device tensors, in
+    shuffled mini-batches; returns the per-epoch mean losses."""
+    import torch
+    N = int(x.shape[0])
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(N, generator=g).to(x.device)
+        tot, nb, t0 = torch.zeros((), device=x.device), 0, time.time()
+        for s in range(0, N - batch + 1, batch):
+            idx = perm[s:s + batch]
+            net.forward(x.index_select(0, idx), windows)
+            tot += net.backward(y.index_select(0, idx), pos_weight=pos_weight)[0]
+            net.adam(lr=lr)
+            nb += 1
+        losses.append(float(tot.item()) / max(nb, 1))
+        if log:
+            log(f"epoch {ep} loss {losses[-1]:.5f} ({time.time() - t0:.1f} s)")
+    return losses
+
+
+def save_weights(net: ProposalNet, path: str, meta: dict) -> None:
+    """Parameters (FP32) and metadata in a NumPy archive (no pickled objects)."""
+    arrays = {name: net.view(name).cpu().numpy() for name in net.offsets}
+    arrays["__meta__"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
+    with open(path, "wb") as fh:
+        np.savez(fh, **arrays)
+
+
+def load_weights(path: str) -> tuple:
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(bytes(z["__meta__"]).decode())
+        net = ProposalNet(n_event=meta["n_event"], hidden=meta["hidden"])
+        import torch
+        for name in net.offsets:
+            net.view(name).copy_(torch.as_tensor(z[name]))
+        net.pack()
+    return net, meta
+
+
+# ---------------------------------------------------------------- evaluation
+def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, log=None) -> dict:
+    """Plain search versus proposal + restricted search on each curve
+    (t, f, sigma, injections).  A plain detection is a best period with
+    SNR > snr_min; it is recalled when the restricted search returns the
+    same best period (its window was among the top-K).  Times are device
+    times per curve (events on the current stream): the plain periodic
+    search + best, and downsample + network + top-K + subset + restricted
+    search + best."""
+    import torch
+    n_det = n_hit = 0
+    t_plain = t_learned = 0.0
+    n_folded = 0
+    rows = []
+    for ci, (t, f, s, injs) in enumerate(curves):
+        fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
+                           torch.as_tensor(s, device="cuda"))
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        bp = pipe.plain(fold)
+        e[1].record()
+        e[2].record()
+        x = pipe.features(fold)
+        sel = pipe.propose(net, x.unsqueeze(0))
+        bl, n_sub = pipe.restricted(fold, sel[0])
+        e[3].record()
+        torch.cuda.synchronize()
+        t_plain += e[0].elapsed_time(e[1])
+        t_learned += e[2].elapsed_time(e[3])
+        n_folded += n_sub
+        det = bool(bp["k"] >= 0 and bp["snr"] > snr_min)
+        hit = bool(det and bl is not None and bl["k"] == bp["k"])
+        n_det += det
+        n_hit += hit
+        rows.append(dict(curve=ci, plain_k=int(bp["k"]), plain_period=float(bp["period"]), plain_snr=float(bp["snr"]),
+                         learned_k=-1 if bl is None else int(bl["k"]), detected=det, recalled=hit,
+                         injected=[float(i.period) for i in injs]))
+        if log and (ci + 1) % 16 == 0:
+            log(f"eval {ci + 1}/{len(curves)}: detections {n_det}, recalled {n_hit}")
+    n = max(len(curves), 1)
+    return dict(n_curves=len(curves), n_detections=n_det, n_recalled=n_hit,
+                recall=(n_hit / n_det) if n_det else None, plain_ms_per_curve=t_plain / n,
+                learned_ms_per_curve=t_learned / n, speedup=(t_plain / t_learned) if t_learned > 0 else None,
+                periods_folded_fraction=n_folded / (n * pipe.K), rows=rows)

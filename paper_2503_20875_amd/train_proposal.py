@@ -1,0 +1,104 @@
+"""Train the period-window proposal network on method-generated data.
+
+Synthetic light curves of the learned-proposal workload (80 000 points at
+2-min cadence, half with one injected planet) go through the library's own
+linear search on the GPU; the downsampled single-event statistics are the
+inputs and the windows of the injected period (and of its half and double,
+the aliases a fold can prefer) are the labels.  Training runs the library's
+forward, backward and Adam kernels.  The weights are written as a NumPy
+archive together with the settings they were trained with.
+
+    python -m paper_2503_20875_amd.train_proposal --n-train 4000 --epochs 20 --out weights.npz
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg: str) -> None:
+    print(f"[train] {msg}", flush=True)
+
+
+def make_pipeline(cfg=None):
+    from synthlc import transit
+    from synthlc import workloads as W
+    from .learned import LearnedConfig, Pipeline
+    durations, periods = W.learned_grid()
+    cad = 120.0 / 86400.0
+    return Pipeline(0.0, (W.LEARNED_N_POINTS - 1) * cad, cad, durations, periods, transit.dense_template(),
+                    cfg or LearnedConfig())
+
+
+def labels_for(pipe, injections) -> np.ndarray:
+    y = np.zeros(pipe.windows.n, dtype=np.float32)
+    for inj in injections:
+        for mult in (1.0, 0.5, 2.0):
+            w = pipe.window_of(inj.period * mult)
+            if w >= 0:
+                y[w] = 1.0
+    return y
+
+
+def build_dataset(pipe, n: int, seed: int):
+    """Device features [n][n_bins][J] (bf16) and labels [n][W], plus the
+    injections of every curve."""
+    import torch
+    from synthlc import workloads as W
+    rng = np.random.default_rng(seed)
+    x = torch.empty((n, pipe.cfg.n_bins, pipe.grid.n_dur), dtype=torch.bfloat16,
+                    device="cuda")
+    y = np.zeros((n, pipe.windows.n), dtype=np.float32)
+    injs = []
+    t0 = time.time()
+    for i in range(n):
+        t, f, s, inj = W.learned_curve(rng)
+        fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
+                           torch.as_tensor(s, device="cuda"))
+        pipe.features(fold, out=x[i])
+        y[i] = labels_for(pipe, inj)
+        injs.append(inj)
+        if (i + 1) % 500 == 0:
+            log(f"features {i + 1}/{n} ({time.time() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return x, torch.as_tensor(y, device="cuda"), injs
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--n-train", type=int, default=4000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--pos-weight", type=float, default=32.0)
+    ap.add_argument("--seed", type=int, default=20250401)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("train_proposal: no GPU", file=sys.stderr)
+        return 2
+    from .learned import save_weights, train
+    from .proposal import ProposalNet
+    pipe = make_pipeline()
+    log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
+        f"lags {pipe.windows.tau_lo}..{pipe.windows.tau_lo + pipe.windows.n_tau - 1}")
+    x, y, _ = build_dataset(pipe, a.n_train, a.seed)
+    net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed)
+    losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)
+    meta = dict(n_event=net.E, hidden=net.H, n_train=a.n_train, epochs=a.epochs, batch=a.batch, lr=a.lr,
+                pos_weight=a.pos_weight, seed=a.seed, losses=losses, n_bins=pipe.cfg.n_bins,
+                n_windows=pipe.cfg.n_windows, p_lo=pipe.cfg.p_lo, p_hi=pipe.cfg.p_hi)
+    save_weights(net, a.out, meta)
+    log(f"wrote {a.out}: {json.dumps({k: v for k, v in meta.items() if k != 'losses'})}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -131,7 +131,7 @@ def chord_separation(tau, p: float, b: float):
     return np.sqrt(x * x + b * b)
 
 
-@functools.lru_cache(maxsize=64)
+@functools.lru_cache(maxsize=128)
 def _dense_shape_cached(n: int, p: float, b: float, u1: float, u2: float):
     tau = np.linspace(0.0, 1.0, n)
     z = chord_separation(tau, p, b)

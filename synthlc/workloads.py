@@ -222,12 +222,15 @@ def duty_cycle_periods(p_min: float, p_max: float, span: float, d_min: float, al
 
 
 def survey_curve(rng, n_points: int, cadence_s: float = 120.0, sigma_ppm: float = 800.0,
-                 planet_frac: float = 0.3, durations=None, p_range=(0.5, 40.0)):
+                 planet_frac: float = 0.3, durations=None, p_range=(0.5, 40.0), depth_range=(100e-6, 5000e-6),
+                 b_step: float = 0.0):
     """One light curve of a batched survey: regular cadence, Poisson(1.5)
     gaps of U(0.2, 2) d, per-point sigma log-normal (log-sd 0.25) around
     sigma_ppm, and with probability planet_frac one transit with P log-uniform
-    over p_range, depth log-uniform 100-5000 ppm, b uniform 0-0.9 and the
-    duration of a circular orbit around a Sun-density star."""
+    over p_range, depth log-uniform over depth_range (default 100-5000 ppm),
+    b uniform 0-0.9 and the duration of a circular orbit around a
+    Sun-density star.  b_step > 0 rounds b to that step (so the transit
+    shapes of many curves come from a small cache)."""
     c = cadence_s / DAY_S
     t = np.arange(n_points, dtype=np.float64) * c
     span = t[-1]
@@ -245,9 +248,11 @@ def survey_curve(rng, n_points: int, cadence_s: float = 120.0, sigma_ppm: float 
     if rng.uniform() < planet_frac:
         P = float(np.exp(rng.uniform(np.log(p_range[0]), np.log(p_range[1]))))
         b = float(rng.uniform(0.0, 0.9))
+        if b_step > 0:
+            b = round(round(b / b_step) * b_step, 6)
         dur = transit.transit_duration_days(P, b)
         inj = Injection(P, rng.uniform(0.0, P), dur,
-                        float(np.exp(rng.uniform(np.log(100e-6), np.log(5000e-6)))), b)
+                        float(np.exp(rng.uniform(np.log(depth_range[0]), np.log(depth_range[1])))), b)
         y = y - inject(t, inj)
         injs.append(inj)
     return t, to_offset(y), sig.astype(np.float32), injs
@@ -278,3 +283,26 @@ WORKLOADS = {
     "tiny": tiny_single,
     "high_cadence": high_cadence,
 }
+
+
+# Learned-proposal workload: 80 000 points at 2-min cadence (111.1 d), noise
+# and gaps as the batched survey, half the curves with one planet (P
+# log-uniform 1-100 d, depth log-uniform 50-3000 ppm), 16 durations 0.5-10 h,
+# plain period grid alpha = 0.389 over 1-100 d.
+LEARNED_N_POINTS = 80000
+LEARNED_DURATIONS_H = (0.5, 10.0, 16)
+LEARNED_P_RANGE = (1.0, 100.0)
+
+
+def learned_curve(rng):
+    """One curve of the learned-proposal workload: (t, f, sigma, injections)."""
+    return survey_curve(rng, LEARNED_N_POINTS, planet_frac=0.5, p_range=LEARNED_P_RANGE,
+                        depth_range=(50e-6, 3000e-6), b_step=0.01)
+
+
+def learned_grid():
+    """Durations (days) and the plain period grid of the learned workload."""
+    durations = log_durations(*LEARNED_DURATIONS_H)
+    span = (LEARNED_N_POINTS - 1) * 120.0 / DAY_S
+    periods = duty_cycle_periods(LEARNED_P_RANGE[0], LEARNED_P_RANGE[1], span, durations[0])
+    return durations, periods

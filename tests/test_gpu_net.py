@@ -6,9 +6,14 @@ rounds at the same points with bf16_trunk=True), every sum accumulates in
 FP32.  Left over are FP32-vs-FP64 accumulation differences (relative ~1e-6)
 and, where such a difference moves a value across a bfloat16 rounding
 boundary, one bfloat16 unit (2^-8 relative) on a small fraction of the
-elements -- so norm-relative errors of a few 1e-4 are expected and 3e-3 is
-the bar.  Outputs rounded to bfloat16 by the kernel itself are compared to
-2^-8 relative.
+elements.  Parameter gradients are sums of many same-signed-magnitude
+terms and are compared norm-relative to 3e-3.  The input gradient is a sum
+of 576 terms of both signs per element that largely cancel, so a one-unit
+difference of the rounded masked gradient G0 shows up relative to the size
+of the terms, not of the sum: it is bounded elementwise by 2^-6 (four
+bfloat16 units, for the flips and the upstream differences) times the same
+sum taken over absolute values, sum |W0| |G0|.  Outputs rounded to bfloat16
+by the kernel itself are compared to 2^-8 relative.
 """
 
 import numpy as np
@@ -146,8 +151,13 @@ def test_network_forward_backward(torch, pn, seed):
     assert abs(float(loss.item()) - loss_ref) <= 3e-3 * abs(loss_ref)
     g = model.grad_arrays()
     for name, ref in g_ref.items():
-        got = dx.cpu().numpy().transpose(0, 2, 1) if name == "x" else g[name]
-        assert rel_norm(got, ref) < 3e-3, (name, rel_norm(got, ref))
+        if name == "x":
+            continue
+        assert rel_norm(g[name], ref) < 3e-3, (name, rel_norm(g[name], ref))
+    gx = dx.cpu().numpy().transpose(0, 2, 1).astype(np.float64)
+    mag = onet.conv1d_backward(x, np.abs(onet.bf16(p["W0"])), np.abs(cache["G0"]))[0]
+    assert np.all(np.abs(gx - g_ref["x"]) <= 2.0 ** -6 * mag + 1e-12), \
+        float(np.max(np.abs(gx - g_ref["x"]) / (mag + 1e-30)))
 
 
 def test_adam_step(torch, pn):

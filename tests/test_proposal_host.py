@@ -1,0 +1,35 @@
+"""Host-side logic of the learned proposal (no GPU): the period windows and
+their labels, against the oracle's definition of the windows."""
+
+import numpy as np
+
+from oracle import net as onet
+from paper_2503_20875_amd.proposal import Windows
+
+
+def test_windows_match_oracle_definition():
+    for n, lo_p, hi_p, bin_days in ((512, 1.0, 100.0, 111.1 / 8192), (48, 0.1, 5.0, 0.02), (7, 0.5, 45.0, 0.3)):
+        w = Windows.log_spaced(n, lo_p, hi_p, bin_days)
+        lo, hi, q, edges = onet.windows_for(n, lo_p, hi_p, bin_days)
+        assert np.array_equal(w.lo, lo) and np.array_equal(w.hi, hi)
+        assert np.allclose(w.q, q) and np.allclose(w.edges, edges, rtol=1e-15)
+        assert w.tau_lo == lo.min() and w.n_tau == hi.max() - lo.min() + 1
+
+
+def test_labels_one_window_per_period():
+    w = Windows.log_spaced(512, 1.0, 100.0, 0.01)
+    periods = np.array([1.0, 3.3, 99.999, 0.5, 150.0])
+    y = w.labels(periods)
+    assert y.shape == (5, 512)
+    assert y[0, 0] == 1 and y[0].sum() == 1  # left edge belongs to window 0
+    k = int(np.argmax(y[1]))
+    assert w.edges[k] <= 3.3 < w.edges[k + 1]
+    assert y[2, 511] == 1
+    assert y[3].sum() == 0 and y[4].sum() == 0  # outside the windows
+
+
+def test_windows_rejects_bad_arguments():
+    import pytest
+    for args in ((0, 1.0, 2.0, 0.1), (4, 2.0, 1.0, 0.1), (4, 1.0, 2.0, 0.0)):
+        with pytest.raises(ValueError):
+            Windows.log_spaced(*args)
