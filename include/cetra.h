@@ -221,77 +221,61 @@ int cetra_best(void *stream, const cetra_grid *grid, const double *periods, int6
 
 /* ---------------------------------------------------------- batched search */
 
-/* A batch of light curves searched by a short sequence of persistent
- * work-queue launches (the per-curve method is Sec. 2.1-2.3 unchanged;
- * batching is this library's addition).  Curves share the durations and
- * template size; each has its own grid plan, observations and period grid,
- * concatenated (CSR) in device arrays. */
+/* A batch of light curves searched with one call (the per-curve method is
+ * Sec. 2.1-2.3 unchanged; batching is this library's addition).  Curves share
+ * the durations and template size; each has its own grid plan, observations
+ * and period grid, concatenated (CSR) in device arrays. */
 typedef struct cetra_batch_desc {
     int32_t n_curves;              /* >= 1                                           */
-    int32_t fold_period_block;     /* periods per lane in the fold: 4 or 8 (0: the
-                                      current tuning)                                  */
+    int32_t reserved0;             /* must be 0                                      */
     const cetra_grid *grids;       /* host [n_curves]: cetra_grid_plan of each curve;
                                       all with the same n_dur, durations and n_model    */
     const int64_t *obs_offsets;    /* host [n_curves + 1]: curve c's observations are
                                       t/f/sigma[obs_offsets[c] .. obs_offsets[c+1])     */
     const int64_t *period_offsets; /* host [n_curves + 1]: the same for periods and for
                                       the per-period outputs                            */
-    int64_t arena_bytes;           /* device scratch for resampled curves and fold-ready
-                                      arrays in flight; 0 = twice the longest curve's
-                                      need (curves then run two at a time)              */
+    int64_t reserved1;             /* must be 0                                      */
 } cetra_batch_desc;
 
 typedef struct cetra_batch_info {
-    size_t workspace_bytes;  /* device workspace cetra_batch_search needs         */
-    size_t tables_bytes;     /* leading bytes of the workspace: the plan's tables */
-    size_t arena_bytes;
-    int64_t n_items;         /* work-queue items                                  */
-    int64_t n_generations;   /* arena generations                                 */
-    int64_t n_launches;      /* persistent launches enqueued per search           */
+    size_t workspace_bytes;  /* device workspace cetra_batch_search needs          */
+    int64_t n_curves;
     int64_t total_periods;
-    int32_t period_block;
-    int32_t lds_bytes;       /* dynamic LDS of the persistent kernel              */
+    int64_t n_launches;      /* kernel launches one cetra_batch_search enqueues    */
 } cetra_batch_info;
 
-/* Opaque host-side plan (curve order, arena placement, work-queue layout). */
+/* Opaque host-side plan. */
 typedef struct cetra_batch_plan cetra_batch_plan;
 
-/* Plan a batch (host only).  Curves are ordered longest first and packed into
- * generations that fit half the arena; CETRA_ERR_WORKSPACE if the arena cannot
- * hold the longest curve twice.  The plan owns host memory only; free it with
+/* Plan a batch (host only): validates the grids and offsets, orders the
+ * curves by descending fold cost (sum over periods of allowed durations times
+ * reference times) and sizes the device workspace for the largest curve
+ * (resampled curve, fold-ready array and fold workspace).  The plan copies
+ * what it needs from desc and owns host memory only; free it with
  * cetra_batch_plan_destroy. */
 int cetra_batch_plan_create(const cetra_batch_desc *desc, cetra_batch_plan **out);
 int cetra_batch_plan_destroy(cetra_batch_plan *plan);
 int cetra_batch_plan_info(const cetra_batch_plan *plan, cetra_batch_info *info);
+/* The processing order (host int32 [n], n = number of curves). */
+int cetra_batch_plan_order(const cetra_batch_plan *plan, int32_t *order, int32_t n);
 
-/* Copy the plan's tables (info.tables_bytes) to host memory host_dst; the
- * caller then copies them to the start of the device workspace before the
- * first cetra_batch_search with that workspace (they stay valid for repeated
- * searches, e.g. graph replays). */
-int cetra_batch_tables(const cetra_batch_plan *plan, void *host_dst, size_t bytes);
-
-/* Currently switched off: returns CETRA_ERR_INVALID and enqueues nothing
- * (its launches did not complete on the GPU; cause not yet found).
- * Search every curve of the batch.  Enqueues a counter-clearing kernel and
- * then 2 + 3 G persistent launches (G = generations): RES(0); LIN(0); and per
- * generation FOLD(g)+RES(g+1), EPI(g)+LIN(g+1), FIN(g) -- resampling, linear
- * search, fold, epilogue and best period of each curve, every launch draining
- * its own range of work items through an atomic counter.  Stream order carries
- * all dependencies, so no workgroup waits on another; the sequence allocates
- * nothing and can be captured in one HIP graph.  Results are identical to
- * per-curve calls of the single-curve entry points.
+/* Search every curve of the batch: for each curve in plan order, enqueue on
+ * `stream` the single-curve stages (cetra_resample, cetra_linear_search,
+ * cetra_periodic_search, cetra_best) with the curve's slice of the inputs and
+ * outputs; the resampled curve and fold-ready array live in `work`, reused
+ * curve after curve in stream order.  Results are identical to separate
+ * single-curve calls.  Nothing is allocated and nothing synchronises, so the
+ * whole batch can be captured in one HIP graph and replayed.
  * t, f, sigma: device CSR observations (as cetra_resample, each curve sorted).
  * model[M]: device template (cetra_template_resample).  periods: device CSR.
- * work: device workspace (info.workspace_bytes) starting with the tables.
- * cancel: NULL, or a device-visible int32 polled before each item; non-zero
- *   ends every remaining launch early (status |= 1; unfinished curves keep
- *   stale outputs).
+ * work: device workspace of info.workspace_bytes.
  * Outputs: per-period lr, epoch, dur, depth, depth_var (device, CSR like the
- * periods), best[n_curves] (device), status (device int32, 0 = complete). */
+ * periods), best[n_curves] (device; a curve without periods gets the null
+ * record), status (device int32, set to 0 after the last curve). */
 int cetra_batch_search(const cetra_batch_plan *plan, void *stream, const double *t, const float *f,
                        const float *sigma, const float *model, const double *periods, void *work,
-                       size_t work_bytes, const int32_t *cancel, float *lr, int32_t *epoch, int32_t *dur,
-                       float *depth, float *depth_var, cetra_best_record *best, int32_t *status);
+                       size_t work_bytes, float *lr, int32_t *epoch, int32_t *dur, float *depth, float *depth_var,
+                       cetra_best_record *best, int32_t *status);
 
 /* ------------------------------------------------------------------------
  * Period-window proposal network (an addition, not part of the paper).

@@ -207,16 +207,20 @@ def search(t, f, sigma, cadence: float, durations, periods, dense, n_model: int 
 class BatchPlan:
     """Host-side plan of a batch (owns the C plan object)."""
 
-    def __init__(self, handle, info, tables: bytes, n_curves: int, period_offsets):
+    def __init__(self, handle, info, n_curves: int, period_offsets):
         self._h = handle
         self.info = {name: getattr(info, name) for name, _ in _abi.BatchInfo._fields_}
-        self.tables = tables
         self.n_curves = n_curves
         self.period_offsets = np.asarray(period_offsets, dtype=np.int64)
 
     @property
     def handle(self):
         return self._h
+
+    def order(self) -> np.ndarray:
+        o = np.zeros(self.n_curves, dtype=np.int32)
+        _abi.check(_abi.load().cetra_batch_plan_order(self._h, o.ctypes.data_as(ctypes.c_void_p), self.n_curves))
+        return o
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
@@ -227,7 +231,7 @@ class BatchPlan:
                 pass
 
 
-def batch_plan(grids, obs_offsets, period_offsets, arena_bytes: int = 0, period_block: int = 0) -> BatchPlan:
+def batch_plan(grids, obs_offsets, period_offsets) -> BatchPlan:
     """Plan a batch from per-curve grid plans and CSR offsets (host arrays)."""
     n = len(grids)
     garr = (Grid * n)(*grids)
@@ -235,33 +239,26 @@ def batch_plan(grids, obs_offsets, period_offsets, arena_bytes: int = 0, period_
     po = np.ascontiguousarray(period_offsets, dtype=np.int64)
     if oo.shape[0] != n + 1 or po.shape[0] != n + 1:
         raise ValueError("offsets must have n_curves + 1 entries")
-    d = _abi.BatchDesc(n, int(period_block), ctypes.cast(garr, ctypes.c_void_p),
-                       oo.ctypes.data_as(ctypes.c_void_p), po.ctypes.data_as(ctypes.c_void_p), int(arena_bytes))
+    d = _abi.BatchDesc(n, 0, ctypes.cast(garr, ctypes.c_void_p), oo.ctypes.data_as(ctypes.c_void_p),
+                       po.ctypes.data_as(ctypes.c_void_p), 0)
     lib = _abi.load()
     h = ctypes.c_void_p()
     _abi.check(lib.cetra_batch_plan_create(ctypes.byref(d), ctypes.byref(h)))
     info = _abi.BatchInfo()
     _abi.check(lib.cetra_batch_plan_info(h, ctypes.byref(info)))
-    buf = (ctypes.c_char * info.tables_bytes)()
-    _abi.check(lib.cetra_batch_tables(h, buf, info.tables_bytes))
-    return BatchPlan(h, info, bytes(buf), n, po)
+    return BatchPlan(h, info, n, po)
 
 
 def batch_workspace(plan: BatchPlan, device="cuda"):
-    """Device workspace with the plan's tables copied to its start."""
+    """Device workspace of the plan's size."""
     torch = _torch()
-    work = torch.empty(plan.info["workspace_bytes"], dtype=torch.uint8, device=device)
-    tbl = torch.frombuffer(bytearray(plan.tables), dtype=torch.uint8)
-    work[: tbl.numel()].copy_(tbl.to(device))
-    return work
+    return torch.empty(max(plan.info["workspace_bytes"], 1), dtype=torch.uint8, device=device)
 
 
-def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, cancel=None, out=None,
-                 stream=None) -> dict:
-    """Search every curve of the batch (a short sequence of persistent
-    work-queue launches on one stream).  Returns
-    device tensors: per-period lr, epoch, dur, depth, depth_var (CSR), best
-    records (uint8 [n_curves, sizeof(cetra_best_record)]) and status."""
+def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, out=None, stream=None) -> dict:
+    """Search every curve of the batch on one stream.  Returns device
+    tensors: per-period lr, epoch, dur, depth, depth_var (CSR), best records
+    (uint8 [n_curves, sizeof(cetra_best_record)]) and status."""
     torch = _torch()
     t = _dev(t, torch.float64)
     f = _dev(f, torch.float32)
@@ -281,8 +278,8 @@ def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, cancel
                    status=torch.empty(1, dtype=torch.int32, device=dev))
     _abi.check(_abi.load().cetra_batch_search(
         plan.handle, _stream(stream), _ptr(t), _ptr(f), _ptr(s), _ptr(model), _ptr(periods), _ptr(work),
-        work.numel(), _ptr(cancel), _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]),
-        _ptr(out["depth"]), _ptr(out["depth_var"]), _ptr(out["best"]), _ptr(out["status"])))
+        work.numel(), _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]), _ptr(out["depth"]),
+        _ptr(out["depth_var"]), _ptr(out["best"]), _ptr(out["status"])))
     return out
 
 

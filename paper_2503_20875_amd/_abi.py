@@ -74,11 +74,11 @@ class BatchDesc(ctypes.Structure):
     """Mirror of ``cetra_batch_desc``."""
     _fields_ = [
         ("n_curves", ctypes.c_int32),
-        ("fold_period_block", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
         ("grids", ctypes.c_void_p),
         ("obs_offsets", ctypes.c_void_p),
         ("period_offsets", ctypes.c_void_p),
-        ("arena_bytes", ctypes.c_int64),
+        ("reserved1", ctypes.c_int64),
     ]
 
 
@@ -86,14 +86,9 @@ class BatchInfo(ctypes.Structure):
     """Mirror of ``cetra_batch_info``."""
     _fields_ = [
         ("workspace_bytes", ctypes.c_size_t),
-        ("tables_bytes", ctypes.c_size_t),
-        ("arena_bytes", ctypes.c_size_t),
-        ("n_items", ctypes.c_int64),
-        ("n_generations", ctypes.c_int64),
-        ("n_launches", ctypes.c_int64),
+        ("n_curves", ctypes.c_int64),
         ("total_periods", ctypes.c_int64),
-        ("period_block", ctypes.c_int32),
-        ("lds_bytes", ctypes.c_int32),
+        ("n_launches", ctypes.c_int64),
     ]
 
 
@@ -119,9 +114,8 @@ SIGNATURES = {
     "cetra_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P)]),
     "cetra_batch_plan_destroy": (ctypes.c_int, [_P]),
     "cetra_batch_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(BatchInfo)]),
-    "cetra_batch_tables": (ctypes.c_int, [_P, _P, _sz]),
-    "cetra_batch_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P, _P, _P, _P, _P, _P,
-                                          _P]),
+    "cetra_batch_plan_order": (ctypes.c_int, [_P, _P, _i32]),
+    "cetra_batch_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P, _P, _P, _P, _P, _P]),
     "cetra_net_mfma_probe": (ctypes.c_int, [_P, _P, _P, _P]),
     "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),

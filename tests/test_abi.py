@@ -99,95 +99,37 @@ def test_tuning_roundtrip_and_validation(lib):
     assert cm.get_tuning()["fold_period_block"] == 4
 
 
-def test_batch_plan_host_only(lib):
-    """Planning is host-only: generations, queue size and argument checks."""
-    import paper_2503_20875_amd as cm
+def _survey_batch(cm, n, seed, n_min, n_max):
     from synthlc import workloads as W
-    curves = W.batched_survey(6, seed=3, n_min=2000, n_max=9000)
+    curves = W.batched_survey(n, seed=seed, n_min=n_min, n_max=n_max)
     grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations) for c in curves]
     oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
     po = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
-    big = cm.batch_plan(grids, oo, po, arena_bytes=1 << 32)
-    assert big.info["n_generations"] == 1 and big.info["n_items"] > 0
-    assert big.info["workspace_bytes"] > big.info["tables_bytes"] > 0
-    assert len(big.tables) == big.info["tables_bytes"]
-    small = cm.batch_plan(grids, oo, po, arena_bytes=0)
-    assert small.info["n_generations"] >= 3
-    assert small.info["n_items"] == big.info["n_items"]
-    with pytest.raises(cm.CetraError, match="arena"):
-        cm.batch_plan(grids, oo, po, arena_bytes=1024)
+    return curves, grids, oo, po
+
+
+def test_batch_plan_host_only(lib):
+    """Planning is host-only: workspace sized for the largest curve, order by
+    descending fold cost, argument checks."""
+    import paper_2503_20875_amd as cm
+    curves, grids, oo, po = _survey_batch(cm, 6, 3, 2000, 9000)
+    plan = cm.batch_plan(grids, oo, po)
+    info = plan.info
+    assert info["n_curves"] == 6 and info["total_periods"] == po[-1]
+    J = grids[0].n_dur
+    need = max(8 * J * g.n_t0 for g in grids) + 2 * 4 * max(g.n for g in grids)
+    assert need <= info["workspace_bytes"] <= need + 4 * 256 + max(
+        cm.periodic_workspace(g, int(po[c + 1] - po[c])) for c, g in enumerate(grids))
+    cost = [(po[c + 1] - po[c]) * J * g.n_t0 for c, g in enumerate(grids)]
+    order = plan.order()
+    assert sorted(order.tolist()) == list(range(6))
+    assert all(cost[a] >= cost[b] for a, b in zip(order, order[1:]))
+    # launches: status + per curve resample, J linear, fold (3) if periods, best
+    assert info["n_launches"] == 1 + sum(1 + J + (3 if po[c + 1] > po[c] else 0) + 1 for c in range(6))
     other = cm.grid_plan(curves[0].t[0], curves[0].t[-1], curves[0].cadence, curves[0].durations * 1.01)
     with pytest.raises(cm.CetraError, match="durations"):
         cm.batch_plan([other] + grids[1:], oo, po)
-    with pytest.raises(cm.CetraError, match="fold_period_block"):
-        cm.batch_plan(grids, oo, po, period_block=16)
-
-
-HEADER_DT = np.dtype([(n, "<i8") for n in ("n_curves", "n_segments", "n_items", "n_gens", "n_launches",
-                                           "off_curves", "off_grids", "off_segments", "off_launches",
-                                           "tables_bytes", "off_counters", "off_keys", "off_best_keys",
-                                           "off_arena", "workspace_bytes", "total_periods")]
-                     + [("period_block", "<i4"), ("lds_bytes", "<i4")])
-CURVE_DT = np.dtype([("obs_off", "<i8"), ("n_obs", "<i8"), ("per_off", "<i8"), ("n_per", "<i8"),
-                     ("arena_off", "<i8"), ("n_items", "<i8", 5), ("gen", "<i4"), ("n_lin_per_dur", "<i4"),
-                     ("n_pblk", "<i4"), ("pad", "<i4")])
-SEG_DT = np.dtype([("first", "<i8"), ("count", "<i8"), ("curve", "<i4"), ("stage", "<i4")])
-LAUNCH_DT = np.dtype([("first", "<i8"), ("end", "<i8")])
-
-
-def parse_tables(blob: bytes):
-    h = np.frombuffer(blob, HEADER_DT, count=1)[0]
-    curves = np.frombuffer(blob, CURVE_DT, count=int(h["n_curves"]), offset=int(h["off_curves"]))
-    segs = np.frombuffer(blob, SEG_DT, count=int(h["n_segments"]), offset=int(h["off_segments"]))
-    launches = np.frombuffer(blob, LAUNCH_DT, count=int(h["n_launches"]), offset=int(h["off_launches"]))
-    return h, curves, segs, launches
-
-
-@pytest.mark.parametrize("arena", [0, 1 << 26, 1 << 32])
-def test_batch_launches_respect_dependencies(lib, arena):
-    """Stage s-1 of every curve is in an earlier launch than stage s, a
-    generation's arena half is reused only after the epilogue of the
-    generation two before it, the launches tile the queue, and arena
-    placements of one generation do not overlap."""
-    import paper_2503_20875_amd as cm
-    from synthlc import workloads as W
-    curves = W.batched_survey(9, seed=5, n_min=2000, n_max=20000)
-    grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations) for c in curves]
-    oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
-    po = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
-    plan = cm.batch_plan(grids, oo, po, arena_bytes=arena)
-    h, cds, segs, launches = parse_tables(plan.tables)
-    G = int(h["n_gens"])
-    assert h["n_items"] == plan.info["n_items"] and len(cds) == 9
-    assert plan.info["n_launches"] == len(launches) == 2 + 3 * G
-    # segments and launches tile [0, n_items)
-    assert segs["first"][0] == 0 and launches["first"][0] == 0
-    assert np.all(segs["first"][1:] == segs["first"][:-1] + segs["count"][:-1])
-    assert np.all(launches["first"][1:] == launches["end"][:-1]) and launches["end"][-1] == h["n_items"]
-    launch_of = {}
-    for sg in segs:
-        key = (int(sg["curve"]), int(sg["stage"]))
-        assert key not in launch_of
-        assert sg["count"] == cds[sg["curve"]]["n_items"][sg["stage"]]
-        li = int(np.searchsorted(launches["end"], sg["first"], side="right"))
-        assert launches["first"][li] <= sg["first"] and sg["first"] + sg["count"] <= launches["end"][li]
-        launch_of[key] = li
-    assert len(launch_of) == 9 * 5
-    for c in range(9):
-        for st in range(1, 5):
-            assert launch_of[(c, st - 1)] < launch_of[(c, st)]
-        g = cds[c]["gen"]
-        for d in range(9):  # reuse of the arena half of generation g - 2
-            if cds[d]["gen"] == g - 2:
-                assert launch_of[(d, 3)] < launch_of[(c, 0)]
-    half = plan.info["arena_bytes"] // 2
-    J = grids[0].n_dur
-    for g in range(G):
-        spans = []
-        for c in np.flatnonzero(cds["gen"] == g):
-            need = ((8 * grids[c].n + 255) // 256) * 256 + ((8 * J * grids[c].n_t0 + 255) // 256) * 256
-            lo = cds[c]["arena_off"]
-            assert (g % 2) * half <= lo and lo + need <= (g % 2 + 1) * half
-            spans.append((lo, lo + need))
-        spans.sort()
-        assert all(a[1] <= b[0] for a, b in zip(spans, spans[1:]))
+    with pytest.raises(cm.CetraError, match="offsets"):
+        cm.batch_plan(grids, oo[::-1].copy(), po)
+    with pytest.raises(ValueError):
+        cm.batch_plan(grids, oo[:-1], po)

@@ -1,17 +1,13 @@
-"""Batched search: results bit-identical to single-curve calls, across arena
-generations, period blocks and graph replays; a host-set cancel flag ends
-the launches early and the same workspace then completes normally."""
+"""Batched search: results bit-identical to single-curve calls, on a batch
+with edge cases (a two-point curve, a curve with every point missing, a
+curve without periods), and on every replay of a captured HIP graph."""
 
 import numpy as np
 import pytest
 
 from synthlc import workloads as W
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="batched search switched off: its launches did not complete on the MI355X "
-                            "(10-curve batch, > 75 s); cause not yet found, not to be run again until it is"),
-]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -65,8 +61,7 @@ def single_results(cm, curves, model):
 def batch_results(cm, plan, curves, packed, model, **kw):
     import torch
     grids, obs_off, per_off, t, f, s, p = packed
-    print(f"[batch] curves={plan.n_curves} items={plan.info['n_items']} gens={plan.info['n_generations']} "
-          f"block={plan.info['period_block']} kw={sorted(kw)}", flush=True)
+    print(f"[batch] curves={plan.n_curves} launches={plan.info['n_launches']} kw={sorted(kw)}", flush=True)
     o = cm.batch_search(plan, t, f, s, model, p, **kw)
     torch.cuda.synchronize()
     print(f"[batch] done status={int(o['status'].item())}", flush=True)
@@ -101,33 +96,19 @@ def setup(cm):
 def test_batch_equals_single_bitwise(cm, setup):
     curves, model, packed, single = setup
     grids, obs_off, per_off = packed[:3]
-    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=1 << 30)
-    assert plan.info["n_generations"] == 1
-    o = batch_results(cm, plan, curves, packed, model)
-    assert int(o["status"].item()) == 0
-    compare(cm, o, single, per_off)
-
-
-@pytest.mark.parametrize("block", [4, 8])
-def test_batch_generations_and_period_blocks(cm, setup, block):
-    """Smallest arena (two longest curves): many generations and launches,
-    arena halves reused; identical results."""
-    curves, model, packed, single = setup
-    grids, obs_off, per_off = packed[:3]
-    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=0, period_block=block)
-    assert plan.info["n_generations"] >= 4
+    plan = cm.batch_plan(grids, obs_off, per_off)
     o = batch_results(cm, plan, curves, packed, model)
     assert int(o["status"].item()) == 0
     compare(cm, o, single, per_off)
 
 
 def test_batch_graph_replay(cm, setup):
-    """Capture the whole launch sequence in a HIP graph; every replay, with
-    eager work in between, equals the single-curve results."""
+    """Capture the whole batch in a HIP graph; every replay, with eager work
+    in between, equals the single-curve results."""
     import torch
     curves, model, packed, single = setup
     grids, obs_off, per_off, t, f, s, p = packed
-    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=0)
+    plan = cm.batch_plan(grids, obs_off, per_off)
     td, fd, sd, pd = (torch.as_tensor(x, device="cuda") for x in (t, f, s, p))
     work = cm.batch_workspace(plan)
     o = cm.batch_search(plan, td, fd, sd, model, pd, work=work)
@@ -143,24 +124,10 @@ def test_batch_graph_replay(cm, setup):
     for rep in range(3):
         for k in ("lr", "depth"):
             o[k].fill_(-7.0)
+        o["status"].fill_(5)
+        print(f"[batch] graph replay {rep}", flush=True)
         g.replay()
         torch.cuda.synchronize()
         assert int(o["status"].item()) == 0
         compare(cm, o, single, per_off)
         _ = (torch.randn(1000, device="cuda") ** 2).sum().item()  # eager work between replays
-
-
-def test_batch_cancel_flag_stops_queue(cm, setup):
-    import torch
-    curves, model, packed, single = setup
-    grids, obs_off, per_off, t, f, s_, p = packed
-    plan = cm.batch_plan(grids, obs_off, per_off, arena_bytes=0)
-    work = cm.batch_workspace(plan)
-    cancel = torch.ones(1, dtype=torch.int32, device="cuda")
-    o = batch_results(cm, plan, curves, packed, model, cancel=cancel, work=work)
-    assert int(o["status"].item()) & 1
-    # the same workspace then completes normally
-    cancel.zero_()
-    o = batch_results(cm, plan, curves, packed, model, cancel=cancel, work=work)
-    assert int(o["status"].item()) == 0
-    compare(cm, o, single, per_off)
