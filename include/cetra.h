@@ -296,7 +296,8 @@ int cetra_batch_search(const cetra_batch_plan *plan, void *stream, const double 
  *          padding columns zero (tap-major, channel-minor; FP32 masters and
  *          weight gradients use the same [64][k32] layout)
  *   e      event channels [batch][L][E] FP32, E <= 16
- *   a      lag correlation [batch][E][n_tau] FP32, lags tau_lo .. tau_lo+n_tau-1
+ *   a      lag correlation [batch][E][n_tau] FP32, lags tau_lo .. tau_lo+n_tau-1,
+ *          standardised per row before the window pooling
  *   windows  win_lo/win_hi: device int32[W] inclusive lag ranges (absolute
  *          lags), win_q: device float[W] window position in [0, 1]
  *   f      window features [batch][W][2E+1] FP32 = (max_c, mean_c, q)
@@ -342,9 +343,18 @@ int cetra_net_project_bwd(void *stream, const void *h, const float *e, const flo
  * (terms past the end are zero).  L <= 8192, tau_lo >= 1. */
 int cetra_net_lag_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E, int32_t tau_lo,
                       int32_t n_tau, float *a);
-/* Window max / mean of a over each window's lags (clipped to the computed
- * lags) plus q; arg[b][w][c] = index into a's lag axis of the first maximum
- * (-1 for an empty window, whose features are 0). */
+/* Standardise each of the n_rows = B*E rows of a [n_rows][n_tau] over its
+ * lags: an = (a - mean) / sd, sd = sqrt(population variance + 1e-12);
+ * sd[n_rows] is kept for the backward pass (all device FP32). */
+int cetra_net_lag_norm_fwd(void *stream, const float *a, int64_t n_rows, int32_t n_tau, float *an, float *sd);
+/* Backward of the standardisation: ga = (gn - mean(gn) - an mean(gn an)) / sd
+ * per row (overwritten). */
+int cetra_net_lag_norm_bwd(void *stream, const float *gn, const float *an, const float *sd, int64_t n_rows,
+                           int32_t n_tau, float *ga);
+/* Window max / mean of the (standardised) correlation a over each window's
+ * lags (clipped to the computed lags) plus q; arg[b][w][c] = index into a's
+ * lag axis of the first maximum (-1 for an empty window, whose features are
+ * 0). */
 int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
                        const int32_t *win_lo, const int32_t *win_hi, const float *win_q, int32_t W, float *f,
                        int32_t *arg);

@@ -13,9 +13,11 @@ Architecture (B examples, C_in input channels = durations, L bins):
         64 channels                      (trunk)
   e = relu(P h_5 + p)                    1x1 projection to E event channels
   a_c(tau) = (1/L) sum_t e_c[t] e_c[t + tau]   lag correlation, tau >= 1
+  n_c(tau) = (a_c(tau) - mean_tau a_c) / sqrt(var_tau a_c + EPS)
+                                         standardised over the computed lags
   per window w (lag range [lo_w, hi_w]):
-        g[w, c] = max_tau a_c(tau)   (ties: smallest tau)
-        m[w, c] = mean_tau a_c(tau)
+        g[w, c] = max_tau n_c(tau)   (ties: smallest tau)
+        m[w, c] = mean_tau n_c(tau)
   f[w] = [g[w, :], m[w, :], q_w]         q_w = window position in [0, 1]
   z[w] = v . relu(U f[w] + u) + v0       shared head -> one logit per window
   loss = mean_{b,w} pos_w(y) * bce(z, y),  pos weight for the single positive
@@ -27,6 +29,7 @@ import numpy as np
 
 K_CONV = 9
 PAD = 4
+EPS = 1e-12  # variance floor of the lag standardisation
 
 
 def init_params(c_in: int = 16, width: int = 64, n_layers: int = 5, n_event: int = 8, hidden: int = 64,
@@ -89,6 +92,20 @@ def lag_correlation(e, lags):
     return a
 
 
+def standardise(a):
+    """Per (example, channel): subtract the mean over the lag axis and divide
+    by the standard deviation (population, floored by EPS)."""
+    mu = a.mean(axis=2, keepdims=True)
+    d = a - mu
+    sd = np.sqrt((d * d).mean(axis=2, keepdims=True) + EPS)
+    return d / sd, sd
+
+
+def standardise_backward(gn, n, sd):
+    """Gradient through standardise given dL/dn, the output n and the sd."""
+    return (gn - gn.mean(axis=2, keepdims=True) - n * (gn * n).mean(axis=2, keepdims=True)) / sd
+
+
 def windows_for(n_windows: int, p_lo: float, p_hi: float, bin_days: float):
     """Integer lag ranges [lo, hi] (bins) of n_windows log-spaced period
     windows over [p_lo, p_hi] days, and each window's position q in [0, 1]."""
@@ -122,6 +139,7 @@ def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = F
     e = np.maximum(pre_e, 0.0)
     lags = np.arange(int(win_lo.min()), int(win_hi.max()) + 1)
     a = lag_correlation(e, lags)
+    an, sd = standardise(a)
     B, E, _ = a.shape
     W = len(win_lo)
     g = np.zeros((B, W, E))
@@ -129,7 +147,7 @@ def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = F
     arg = np.zeros((B, W, E), dtype=np.int64)
     for w in range(W):
         sl = slice(win_lo[w] - lags[0], win_hi[w] - lags[0] + 1)
-        seg = a[:, :, sl]
+        seg = an[:, :, sl]
         arg[:, w, :] = np.argmax(seg, axis=2) + win_lo[w]  # absolute lag of the first maximum
         g[:, w, :] = np.max(seg, axis=2)
         m[:, w, :] = np.mean(seg, axis=2)
@@ -139,7 +157,8 @@ def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = F
     z = np.einsum("h,bwh->bw", p["v"], r) + p["v0"][0]
     if not keep:
         return z
-    cache = dict(h=h, pre_e=pre_e, e=e, lags=lags, a=a, arg=arg, f=f, pre_r=pre_r, r=r, bf16_trunk=bf16_trunk)
+    cache = dict(h=h, pre_e=pre_e, e=e, lags=lags, a=a, an=an, sd=sd, arg=arg, f=f, pre_r=pre_r, r=r,
+                 bf16_trunk=bf16_trunk)
     return z, cache
 
 
@@ -173,6 +192,7 @@ def backward(p: dict, cache: dict, gz, win_lo, win_hi, n_layers: int = 5) -> dic
         for b in range(B):
             for c in range(E):
                 ga[b, c, arg[b, w, c] - lags[0]] += gg[b, w, c]
+    ga = standardise_backward(ga, cache["an"], cache["sd"])
     ge = np.zeros_like(e)
     for i, tau in enumerate(lags):
         if tau < L:

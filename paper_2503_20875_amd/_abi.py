@@ -123,6 +123,8 @@ SIGNATURES = {
     "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _P]),
     "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _P, _i32, _P, _P, _P]),
     "cetra_net_lag_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
+    "cetra_net_lag_norm_fwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P]),
+    "cetra_net_lag_norm_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _i32, _P]),
     "cetra_net_pool_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _P, _P, _P, _i32, _P, _P]),
     "cetra_net_head_fwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P, _P, _P, _i32, _P]),
     "cetra_net_bce": (ctypes.c_int, [_P, _P, _P, _i64, _f32, _P, _P]),

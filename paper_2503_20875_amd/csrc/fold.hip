@@ -106,7 +106,7 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 template <int B, bool kLds>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
                                                         int32_t I, int32_t n_chunks, int64_t n_units) {
-    __shared__ float2 s_buf[kLds ? cetra::dev::kFoldLdsCap : 1];
+    __shared__ float2 s_buf[kLds ? 2 * cetra::dev::kFoldLdsCap : 1];
     const int64_t n_pblk = (n_eval + B - 1) / B;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pb = u % n_pblk;

@@ -99,6 +99,57 @@ __global__ void __launch_bounds__(kT) lag_fwd_kernel(const float *__restrict__ e
         if (i0 + q < n_tau) a[(b * E + c) * n_tau + i0 + q] = acc[q] * inv;
 }
 
+// Sum over the workgroup (256 lanes); every lane gets the total.
+__device__ __forceinline__ float block_sum(float v, float *s_red) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();  // s_red may still be read from a previous call
+    if ((threadIdx.x & 63) == 0) s_red[wave] = v;
+    __syncthreads();
+    return s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// Standardise each (example, channel) row of the lag correlation over its
+// n_tau lags: an = (a - mean) / sqrt(var + eps), population variance of the
+// centred values; sd[b][c] keeps the divisor for the backward pass.
+constexpr float kLagEps = 1e-12f;
+__global__ void __launch_bounds__(kT) lag_norm_fwd_kernel(const float *__restrict__ a, int32_t n_tau,
+                                                          float *__restrict__ an, float *__restrict__ sd) {
+    __shared__ float s_red[4];
+    const int64_t row = blockIdx.x;
+    const float *x = a + row * n_tau;
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n_tau; i += kT) s += x[i];
+    const float mu = block_sum(s, s_red) / (float)n_tau;
+    float q = 0.0f;
+    for (int i = threadIdx.x; i < n_tau; i += kT) {
+        const float d = x[i] - mu;
+        q = fmaf(d, d, q);
+    }
+    const float sdv = sqrtf(block_sum(q, s_red) / (float)n_tau + kLagEps);
+    for (int i = threadIdx.x; i < n_tau; i += kT) an[row * n_tau + i] = (x[i] - mu) / sdv;
+    if (threadIdx.x == 0) sd[row] = sdv;
+}
+
+// ga = (gn - mean(gn) - an * mean(gn * an)) / sd per row.
+__global__ void __launch_bounds__(kT) lag_norm_bwd_kernel(const float *__restrict__ gn, const float *__restrict__ an,
+                                                          const float *__restrict__ sd, int32_t n_tau,
+                                                          float *__restrict__ ga) {
+    __shared__ float s_red[4];
+    const int64_t row = blockIdx.x;
+    const float *g = gn + row * n_tau;
+    const float *z = an + row * n_tau;
+    float s1 = 0.0f, s2 = 0.0f;
+    for (int i = threadIdx.x; i < n_tau; i += kT) {
+        s1 += g[i];
+        s2 = fmaf(g[i], z[i], s2);
+    }
+    const float m1 = block_sum(s1, s_red) / (float)n_tau;
+    const float m2 = block_sum(s2, s_red) / (float)n_tau;
+    const float inv = 1.0f / sd[row];
+    for (int i = threadIdx.x; i < n_tau; i += kT) ga[row * n_tau + i] = (g[i] - m1 - z[i] * m2) * inv;
+}
+
 // Window features: f[b][w] = (max_tau a, mean_tau a over the window's lags,
 // q_w); arg[b][w][c] = lag index of the first maximum.
 __global__ void pool_fwd_kernel(const float *__restrict__ a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
@@ -384,6 +435,25 @@ extern "C" int cetra_net_lag_fwd(void *stream, const float *e, int32_t B, int32_
     hipLaunchKernelGGL(lag_fwd_kernel, dim3((unsigned)ceil_div(n_tau, kT * kLagsPerLane), E, B), dim3(kT), 0,
                        as_stream(stream), e, L, E, tau_lo, n_tau, a);
     return check_launch("net_lag_fwd");
+}
+
+extern "C" int cetra_net_lag_norm_fwd(void *stream, const float *a, int64_t n_rows, int32_t n_tau, float *an,
+                                      float *sd) {
+    clear_error();
+    CETRA_REQUIRE(a && an && sd, "net_lag_norm_fwd: NULL pointer");
+    CETRA_REQUIRE(n_rows >= 1 && n_rows <= INT32_MAX && n_tau >= 1, "net_lag_norm_fwd: bad sizes");
+    hipLaunchKernelGGL(lag_norm_fwd_kernel, dim3((unsigned)n_rows), dim3(kT), 0, as_stream(stream), a, n_tau, an, sd);
+    return check_launch("net_lag_norm_fwd");
+}
+
+extern "C" int cetra_net_lag_norm_bwd(void *stream, const float *gn, const float *an, const float *sd,
+                                      int64_t n_rows, int32_t n_tau, float *ga) {
+    clear_error();
+    CETRA_REQUIRE(gn && an && sd && ga, "net_lag_norm_bwd: NULL pointer");
+    CETRA_REQUIRE(n_rows >= 1 && n_rows <= INT32_MAX && n_tau >= 1, "net_lag_norm_bwd: bad sizes");
+    hipLaunchKernelGGL(lag_norm_bwd_kernel, dim3((unsigned)n_rows), dim3(kT), 0, as_stream(stream), gn, an, sd, n_tau,
+                       ga);
+    return check_launch("net_lag_norm_bwd");
 }
 
 extern "C" int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,

@@ -360,105 +360,164 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
     }
 }
 
-// LDS-staged fold unit.  The workgroup owns 512 consecutive epochs (lane t:
-// epochs e0 + 2t and e0 + 2t + 1) of B periods.  For every transit step the
-// union of the B periods' element windows -- [e0 + min_b o_b, e0 + max_b o_b
-// + 512), a few hundred elements more than the tile when the periods are
-// close -- is loaded cooperatively into LDS with coalesced loads, and each
-// lane then reads its two elements per period from LDS (one 16-byte read).
-// Steps whose window exceeds kFoldLdsCap fall back to direct buffer loads.
-// The sums (and hence the ranking) are identical to fold_unit's.
+// LDS-staged fold unit.  The workgroup owns 512 consecutive epochs of B
+// periods: lane t accumulates epochs e0 + t and e0 + t + 256.  For every
+// transit step the union of the B periods' element windows, [e0 + o_min,
+// e0 + o_max + 512), a few hundred elements more than the tile when the
+// periods are close, is loaded once with coalesced buffer loads (out-of-row
+// elements read as zero) and every lane then reads its 2B elements from LDS,
+// consecutive lanes on consecutive elements.  The loads are software
+// pipelined: step m + 1's window is loaded into registers while step m is
+// summed from the other half of the double buffer, so each step costs one
+// barrier and the load latency is hidden behind the sums.  A step whose
+// window exceeds kFoldLdsCap is summed with direct loads instead.  Partial
+// sums, their order and the argmax keys are those of fold_unit.
 constexpr int kFoldLdsTile = 2 * kThreads;
-constexpr int kFoldLdsCap = 2048;  // float pairs (16 KB)
+constexpr int kFoldLdsCap = 2048;                      // float pairs per buffer half (16 KB)
+constexpr int kFoldLdsPf = kFoldLdsCap / kThreads;     // prefetch registers (pairs) per lane
+
+template <int B>
+struct FoldStep {
+    uint32_t o[B];
+    uint32_t use;    // bit b: period b has a transit inside the row
+    uint32_t omin;   // window start offset (valid when use != 0)
+    uint32_t span;   // window length in pairs
+};
+
+template <int B>
+__device__ __forceinline__ FoldStep<B> fold_next_step(uint64_t (&acc)[B], const uint64_t (&R)[B],
+                                                      const int32_t (&ipb)[B], uint32_t e0, uint32_t I) {
+    FoldStep<B> st;
+    st.use = 0;
+    uint32_t omin = 0xFFFFFFFFu, omax = 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint32_t hi = (uint32_t)(acc[b] >> 32);
+        const bool live = hi < I;
+        st.o[b] = live ? hi : I;
+        acc[b] += live ? R[b] : 0ull;
+        const bool u = ipb[b] > 0 && e0 + st.o[b] < I;
+        st.use |= u ? (1u << b) : 0u;
+        omin = u ? min(omin, st.o[b]) : omin;
+        omax = u ? max(omax, st.o[b]) : omax;
+    }
+    st.omin = omin;
+    st.span = st.use ? omax - omin + (uint32_t)kFoldLdsTile : 0u;
+    return st;
+}
 
 template <int B>
 __device__ __forceinline__ void fold_unit_lds(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
                                               const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
                                               float2 *s_buf) {
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    const uint32_t uI = (uint32_t)I;
     uint64_t best[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) best[b] = 0;
 
     for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldLdsTile) {
-        const int32_t t2 = 2 * (int32_t)threadIdx.x;
-        const int32_t e = e0 + t2;  // epochs e, e + 1
         float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
         uint64_t acc[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
             ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
-            acc[b] = 2147483648ull;
+            acc[b] = 2147483648ull;  // + 1/2: round half up
         }
-        bool done = false;
-        while (!done) {
-            for (int mm = 0; mm < kFoldChunk; ++mm) {
-                uint32_t o[B];
-                bool use[B];
-                uint32_t omin = 0xFFFFFFFFu, omax = 0;
+        // prologue: stage step 0 into buffer half 0
+        FoldStep<B> cur = fold_next_step<B>(acc, R, ipb, (uint32_t)e0, uI);
+        if (cur.use && cur.span <= (uint32_t)kFoldLdsCap) {
+            const uint32_t ws = (uint32_t)e0 + cur.omin;
+            for (uint32_t q = tid; q < cur.span; q += kThreads) s_buf[q] = load_pair(rsrc, (ws + q) * 8u, 0);
+        }
+        __syncthreads();
+        int half = 0;
+        int n_in_chunk = 0;
+        while (cur.use) {
+            // issue the loads of the next step before summing this one
+            FoldStep<B> nxt = fold_next_step<B>(acc, R, ipb, (uint32_t)e0, uI);
+            const bool nxt_lds = nxt.use && nxt.span <= (uint32_t)kFoldLdsCap;
+            float2 pf[kFoldLdsPf];
+            if (nxt_lds) {
+                const uint32_t ws = (uint32_t)e0 + nxt.omin;
+#pragma unroll
+                for (int k = 0; k < kFoldLdsPf; ++k) {
+                    const uint32_t q = (uint32_t)tid + (uint32_t)(k * kThreads);
+                    if (q < nxt.span) pf[k] = load_pair(rsrc, (ws + q) * 8u, 0);
+                }
+            }
+            if (cur.span <= (uint32_t)kFoldLdsCap) {
+                // every period reads (an unused one at offset 0 and adds
+                // zero), so the 2B LDS reads issue back to back
+                const float2 *buf = s_buf + half * kFoldLdsCap;
+                float2 v0[B], v1[B];
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    const uint32_t hi = (uint32_t)(acc[b] >> 32);
-                    const bool live = hi < (uint32_t)I;
-                    o[b] = live ? hi : (uint32_t)I;
-                    acc[b] += live ? R[b] : 0ull;
-                    use[b] = ipb[b] > 0 && (uint32_t)e0 + o[b] < (uint32_t)I;
-                    omin = use[b] ? min(omin, o[b]) : omin;
-                    omax = use[b] ? max(omax, o[b]) : omax;
+                    const bool u = (cur.use >> b) & 1u;
+                    const uint32_t x = (uint32_t)tid + (u ? cur.o[b] - cur.omin : 0u);
+                    v0[b] = buf[x];
+                    v1[b] = buf[x + kThreads];
                 }
-                if (omin == 0xFFFFFFFFu) {  // no period has a transit inside the row
-                    done = true;
-                    break;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const bool u = (cur.use >> b) & 1u;
+                    a0[b] += u ? v0[b].x : 0.0f;
+                    s0[b] += u ? v0[b].y : 0.0f;
+                    a1[b] += u ? v1[b].x : 0.0f;
+                    s1[b] += u ? v1[b].y : 0.0f;
                 }
-                const uint32_t ws = (uint32_t)e0 + omin;
-                const uint32_t span = min(omax - omin + (uint32_t)kFoldLdsTile, (uint32_t)I - ws);
-                if (span <= (uint32_t)kFoldLdsCap) {
-                    __syncthreads();  // the previous step's reads are done
-                    for (uint32_t q = threadIdx.x; q < span; q += kThreads)
-                        s_buf[q] = load_pair(rsrc, (ws + q) * 8u, 0);
-                    __syncthreads();
+            } else {
+                const uint32_t e_bytes = ((uint32_t)e0 + (uint32_t)tid) * 8u;
 #pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        if (!use[b]) continue;
-                        const uint32_t x = (uint32_t)t2 + (o[b] - omin);  // local index of epoch e
-                        const float2 v0 = x < span ? s_buf[x] : make_float2(0.0f, 0.0f);
-                        const float2 v1 = x + 1 < span ? s_buf[x + 1] : make_float2(0.0f, 0.0f);
-                        a0[b] += v0.x;
-                        s0[b] += v0.y;
-                        a1[b] += v1.x;
-                        s1[b] += v1.y;
-                    }
-                } else {
-                    const uint32_t e_bytes = (uint32_t)e * 8u;
-#pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        if (!use[b]) continue;
-                        const uint32_t off = e_bytes + o[b] * 8u;
-                        const float2 v0 = load_pair(rsrc, off, 0);
-                        const float2 v1 = load_pair(rsrc, off, 8);
-                        a0[b] += v0.x;
-                        s0[b] += v0.y;
-                        a1[b] += v1.x;
-                        s1[b] += v1.y;
-                    }
+                for (int b = 0; b < B; ++b) {
+                    if (!(cur.use & (1u << b))) continue;
+                    const uint32_t off = e_bytes + cur.o[b] * 8u;
+                    const float2 v0 = load_pair(rsrc, off, 0);
+                    const float2 v1 = load_pair(rsrc, off, kThreads * 8);
+                    a0[b] += v0.x;
+                    s0[b] += v0.y;
+                    a1[b] += v1.x;
+                    s1[b] += v1.y;
                 }
             }
+            if (++n_in_chunk == kFoldChunk) {
+                n_in_chunk = 0;
 #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                ta0[b] += a0[b];
-                ts0[b] += s0[b];
-                ta1[b] += a1[b];
-                ts1[b] += s1[b];
-                a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                for (int b = 0; b < B; ++b) {
+                    ta0[b] += a0[b];
+                    ts0[b] += s0[b];
+                    ta1[b] += a1[b];
+                    ts1[b] += s1[b];
+                    a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                }
             }
+            if (nxt_lds) {
+                float2 *dst = s_buf + (half ^ 1) * kFoldLdsCap;
+#pragma unroll
+                for (int k = 0; k < kFoldLdsPf; ++k) {
+                    const uint32_t q = (uint32_t)tid + (uint32_t)(k * kThreads);
+                    if (q < nxt.span) dst[q] = pf[k];
+                }
+            }
+            __syncthreads();  // the next half is written; this half's reads are done
+            half ^= 1;
+            cur = nxt;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            ta0[b] += a0[b];
+            ts0[b] += s0[b];
+            ta1[b] += a1[b];
+            ts1[b] += s1[b];
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int32_t eh = e + h;
+                const int32_t eh = e0 + tid + kThreads * h;
                 const float A = h ? ta1[b] : ta0[b];
                 const float S = h ? ts1[b] : ts0[b];
                 if (eh < ipb[b] && eh < e_hi && S > 0.0f) {

@@ -95,9 +95,10 @@ class Windows:
 
 class ProposalNet:
     """Five 9-tap convolutions of 64 channels (ReLU), a 1x1 projection to E
-    event channels (ReLU), the lag correlation of each event channel, the
-    max and mean of the correlation over every window's lags, and a shared
-    MLP head (hidden width H) giving one logit per window."""
+    event channels (ReLU), the lag correlation of each event channel
+    standardised over its lags, the max and mean of it over every window's
+    lags, and a shared MLP head (hidden width H) giving one logit per
+    window."""
 
     def __init__(self, n_event: int = 8, hidden: int = 64, seed: int = 0):
         import torch
@@ -207,6 +208,9 @@ class ProposalNet:
             h=[None] + [torch.empty((B, L, WIDTH), dtype=bf, device=dev) for _ in range(N_LAYERS)],
             e=torch.empty((B, L, self.E), dtype=f32, device=dev),
             a=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
+            an=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
+            sd=torch.empty((B, self.E), dtype=f32, device=dev),
+            gan=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
             f=torch.empty((B, win.n, self.nf), dtype=f32, device=dev),
             arg=torch.empty((B, win.n, self.E), dtype=torch.int32, device=dev),
             z=torch.empty((B, win.n), dtype=f32, device=dev),
@@ -244,7 +248,9 @@ class ProposalNet:
         _abi.check(lib.cetra_net_project_fwd(s, _ptr(bufs["h"][N_LAYERS]), B * L, _ptr(self.view("P")),
                                              _ptr(self.view("p")), self.E, _ptr(bufs["e"])))
         _abi.check(lib.cetra_net_lag_fwd(s, _ptr(bufs["e"]), B, L, self.E, win.tau_lo, win.n_tau, _ptr(bufs["a"])))
-        _abi.check(lib.cetra_net_pool_fwd(s, _ptr(bufs["a"]), B, self.E, win.n_tau, win.tau_lo, _ptr(dw["lo"]),
+        _abi.check(lib.cetra_net_lag_norm_fwd(s, _ptr(bufs["a"]), B * self.E, win.n_tau, _ptr(bufs["an"]),
+                                              _ptr(bufs["sd"])))
+        _abi.check(lib.cetra_net_pool_fwd(s, _ptr(bufs["an"]), B, self.E, win.n_tau, win.tau_lo, _ptr(dw["lo"]),
                                           _ptr(dw["hi"]), _ptr(dw["q"]), win.n, _ptr(bufs["f"]), _ptr(bufs["arg"])))
         _abi.check(lib.cetra_net_head_fwd(s, _ptr(bufs["f"]), B * win.n, self.nf, _ptr(self.view("U")),
                                           _ptr(self.view("u")), _ptr(self.view("v")), _ptr(self.view("v0")), self.H,
@@ -264,7 +270,7 @@ class ProposalNet:
         dw = win.device()
         self.grad.zero_()
         bufs["loss"].zero_()
-        bufs["ga"].zero_()
+        bufs["gan"].zero_()
         n_bw = B * win.n
         _abi.check(lib.cetra_net_bce(s, _ptr(bufs["z"]), _ptr(y), n_bw, float(pos_weight), _ptr(bufs["gz"]),
                                      _ptr(bufs["loss"])))
@@ -274,7 +280,9 @@ class ProposalNet:
                                           _ptr(self.view("v", self.grad)), _ptr(self.view("v0", self.grad)),
                                           _ptr(bufs["gf"])))
         _abi.check(lib.cetra_net_pool_bwd(s, _ptr(bufs["gf"]), _ptr(bufs["arg"]), B, self.E, win.n_tau, win.tau_lo,
-                                          _ptr(dw["lo"]), _ptr(dw["hi"]), win.n, _ptr(bufs["ga"])))
+                                          _ptr(dw["lo"]), _ptr(dw["hi"]), win.n, _ptr(bufs["gan"])))
+        _abi.check(lib.cetra_net_lag_norm_bwd(s, _ptr(bufs["gan"]), _ptr(bufs["an"]), _ptr(bufs["sd"]), B * self.E,
+                                              win.n_tau, _ptr(bufs["ga"])))
         _abi.check(lib.cetra_net_lag_bwd(s, _ptr(bufs["e"]), _ptr(bufs["ga"]), B, L, self.E, win.tau_lo, win.n_tau,
                                          _ptr(bufs["ge"])))
         dh_in, dh_out = bufs["dh"]

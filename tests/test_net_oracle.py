@@ -118,3 +118,15 @@ def test_bf16_trunk_gradients_consistent():
             flat[idx] = old
             fd = (lp - lm) / (2 * h)
             assert abs(fd - g[name].reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (name, idx)
+
+
+def test_standardise_zero_mean_unit_variance_and_affine_invariant():
+    rng = np.random.default_rng(8)
+    a = rng.normal(size=(2, 3, 50)) * 1e-3 + 5e-3
+    n, sd = net.standardise(a)
+    assert np.allclose(n.mean(axis=2), 0, atol=1e-12) and np.allclose((n * n).mean(axis=2), 1, atol=1e-5)
+    n2, _ = net.standardise(7.0 * a - 3.0)
+    assert np.allclose(n2, n, atol=1e-5)
+    # constant input: no signal, output zero
+    n0, _ = net.standardise(np.full((1, 1, 10), 0.25))
+    assert np.all(n0 == 0)
