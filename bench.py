@@ -68,7 +68,7 @@ def algorithmic_work(wl, grid):
                 linear_flop=4 * lin_points)
 
 
-def cpu_baseline(wl, stride: int = 50):
+def cpu_baseline(wl, stride: int = 10):
     """The FP64 oracle, as it is, on a bounded sample: full resample + linear
     search, fold over every `stride`-th period, extrapolated linearly in fold
     element visits to the full period grid."""

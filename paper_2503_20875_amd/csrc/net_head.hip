@@ -84,24 +84,30 @@ __global__ void __launch_bounds__(kT) lag_fwd_kernel(const float *__restrict__ e
     const int32_t i0 = (blockIdx.x * kT + threadIdx.x) * kLagsPerLane;
     if (i0 >= n_tau) return;
     const int32_t tau0 = tau_lo + i0;
-    float acc[kLagsPerLane] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // FP64 sums: the correlation is standardised over the lags next, which
+    // subtracts its mean level and so magnifies relative summation error
+    double acc[kLagsPerLane] = {0.0, 0.0, 0.0, 0.0};
     for (int32_t t = 0; t + tau0 < L; ++t) {
-        const float x = s_e[t];
+        const double x = (double)s_e[t];
 #pragma unroll
         for (int q = 0; q < kLagsPerLane; ++q) {
             const int32_t u = t + tau0 + q;
-            acc[q] = fmaf(x, u < L ? s_e[u] : 0.0f, acc[q]);
+            acc[q] = fma(x, u < L ? (double)s_e[u] : 0.0, acc[q]);
         }
     }
-    const float inv = 1.0f / (float)L;
 #pragma unroll
     for (int q = 0; q < kLagsPerLane; ++q)
-        if (i0 + q < n_tau) a[(b * E + c) * n_tau + i0 + q] = acc[q] * inv;
+        if (i0 + q < n_tau) a[(b * E + c) * n_tau + i0 + q] = (float)(acc[q] / (double)L);
 }
 
-// Sum over the workgroup (256 lanes); every lane gets the total.
-__device__ __forceinline__ float block_sum(float v, float *s_red) {
-    v = wave_sum(v);
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup (256 lanes) in FP64; every lane gets the total.
+__device__ __forceinline__ double block_sum(double v, double *s_red) {
+    v = wave_sum_f64(v);
     const int wave = threadIdx.x >> 6;
     __syncthreads();  // s_red may still be read from a previous call
     if ((threadIdx.x & 63) == 0) s_red[wave] = v;
@@ -115,39 +121,40 @@ __device__ __forceinline__ float block_sum(float v, float *s_red) {
 constexpr float kLagEps = 1e-12f;
 __global__ void __launch_bounds__(kT) lag_norm_fwd_kernel(const float *__restrict__ a, int32_t n_tau,
                                                           float *__restrict__ an, float *__restrict__ sd) {
-    __shared__ float s_red[4];
+    __shared__ double s_red[4];
     const int64_t row = blockIdx.x;
     const float *x = a + row * n_tau;
-    float s = 0.0f;
-    for (int i = threadIdx.x; i < n_tau; i += kT) s += x[i];
-    const float mu = block_sum(s, s_red) / (float)n_tau;
-    float q = 0.0f;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_tau; i += kT) s += (double)x[i];
+    const double mu = block_sum(s, s_red) / (double)n_tau;
+    double q = 0.0;
     for (int i = threadIdx.x; i < n_tau; i += kT) {
-        const float d = x[i] - mu;
-        q = fmaf(d, d, q);
+        const double d = (double)x[i] - mu;
+        q = fma(d, d, q);
     }
-    const float sdv = sqrtf(block_sum(q, s_red) / (float)n_tau + kLagEps);
-    for (int i = threadIdx.x; i < n_tau; i += kT) an[row * n_tau + i] = (x[i] - mu) / sdv;
-    if (threadIdx.x == 0) sd[row] = sdv;
+    const double sdv = sqrt(block_sum(q, s_red) / (double)n_tau + (double)kLagEps);
+    for (int i = threadIdx.x; i < n_tau; i += kT) an[row * n_tau + i] = (float)(((double)x[i] - mu) / sdv);
+    if (threadIdx.x == 0) sd[row] = (float)sdv;
 }
 
 // ga = (gn - mean(gn) - an * mean(gn * an)) / sd per row.
 __global__ void __launch_bounds__(kT) lag_norm_bwd_kernel(const float *__restrict__ gn, const float *__restrict__ an,
                                                           const float *__restrict__ sd, int32_t n_tau,
                                                           float *__restrict__ ga) {
-    __shared__ float s_red[4];
+    __shared__ double s_red[4];
     const int64_t row = blockIdx.x;
     const float *g = gn + row * n_tau;
     const float *z = an + row * n_tau;
-    float s1 = 0.0f, s2 = 0.0f;
+    double s1 = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < n_tau; i += kT) {
-        s1 += g[i];
-        s2 = fmaf(g[i], z[i], s2);
+        s1 += (double)g[i];
+        s2 = fma((double)g[i], (double)z[i], s2);
     }
-    const float m1 = block_sum(s1, s_red) / (float)n_tau;
-    const float m2 = block_sum(s2, s_red) / (float)n_tau;
-    const float inv = 1.0f / sd[row];
-    for (int i = threadIdx.x; i < n_tau; i += kT) ga[row * n_tau + i] = (g[i] - m1 - z[i] * m2) * inv;
+    const double m1 = block_sum(s1, s_red) / (double)n_tau;
+    const double m2 = block_sum(s2, s_red) / (double)n_tau;
+    const double inv = 1.0 / (double)sd[row];
+    for (int i = threadIdx.x; i < n_tau; i += kT)
+        ga[row * n_tau + i] = (float)(((double)g[i] - m1 - (double)z[i] * m2) * inv);
 }
 
 // Window features: f[b][w] = (max_tau a, mean_tau a over the window's lags,
@@ -286,14 +293,16 @@ __global__ void __launch_bounds__(kT) lag_bwd_kernel(const float *__restrict__ e
     __syncthreads();
     const int32_t t = blockIdx.x * kT + threadIdx.x;
     if (t >= L) return;
-    float s = 0.0f;
+    // FP64 sums: ga is mean-free over the lags, so its products with the
+    // (non-negative) events cancel
+    double s = 0.0;
     for (int32_t i = 0; i < n_tau; ++i) {
         const int32_t tau = tau_lo + i;
         const float up = t + tau < L ? s_e[t + tau] : 0.0f;
         const float dn = t - tau >= 0 ? s_e[t - tau] : 0.0f;
-        s = fmaf(s_g[i], up + dn, s);
+        s = fma((double)s_g[i], (double)up + (double)dn, s);
     }
-    ge[(b * L + t) * E + c] = s / (float)L;
+    ge[(b * L + t) * E + c] = (float)(s / (double)L);
 }
 
 // Adam on FP32 master parameters.
