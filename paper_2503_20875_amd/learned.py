@@ -137,19 +137,22 @@ def load_weights(path: str) -> tuple:
 
 
 # ---------------------------------------------------------------- evaluation
-def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, log=None) -> dict:
+def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top_k: int = 0, log=None) -> dict:
     """Plain search versus proposal + restricted search on each curve
     (t, f, sigma, injections).  A plain detection is a best period with
-    SNR > snr_min; it is recalled when the restricted search returns the
-    same best period (its window was among the top-K).  Times are device
-    times per curve (events on the current stream): the plain periodic
-    search + best, and downsample + network + top-K + subset + restricted
-    search + best."""
+    SNR > snr_min; it is recalled when the restricted search over the top_k
+    windows (default: the pipeline's) returns the same best period.  Also
+    returned: for every detection, the rank of its window among the network's
+    scores (0 = best; ties to the smaller window), so recall at any K is the
+    fraction of ranks below K.  Times are device times per curve (events on
+    the current stream): the plain periodic search + best, and downsample +
+    network + top-K + subset + restricted search + best."""
     import torch
+    top_k = int(top_k or pipe.cfg.top_k)
     n_det = n_hit = 0
     t_plain = t_learned = 0.0
     n_folded = 0
-    rows = []
+    rows, ranks = [], []
     for ci, (t, f, s, injs) in enumerate(curves):
         fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
                            torch.as_tensor(s, device="cuda"))
@@ -159,7 +162,8 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, log
         e[1].record()
         e[2].record()
         x = pipe.features(fold)
-        sel = pipe.propose(net, x.unsqueeze(0))
+        z = net.forward(x.unsqueeze(0), pipe.windows)
+        sel = topk_windows(z, top_k)
         bl, n_sub = pipe.restricted(fold, sel[0])
         e[3].record()
         torch.cuda.synchronize()
@@ -168,15 +172,31 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, log
         n_folded += n_sub
         det = bool(bp["k"] >= 0 and bp["snr"] > snr_min)
         hit = bool(det and bl is not None and bl["k"] == bp["k"])
+        rank = -1
+        if det:
+            zs = z[0].float().cpu().numpy()
+            w = pipe.window_of(float(bp["period"]))
+            rank = int(np.count_nonzero(zs > zs[w]) + np.count_nonzero(zs[:w] == zs[w])) if w >= 0 else pipe.windows.n
+            ranks.append(rank)
         n_det += det
         n_hit += hit
         rows.append(dict(curve=ci, plain_k=int(bp["k"]), plain_period=float(bp["period"]), plain_snr=float(bp["snr"]),
-                         learned_k=-1 if bl is None else int(bl["k"]), detected=det, recalled=hit,
+                         learned_k=-1 if bl is None else int(bl["k"]), detected=det, recalled=hit, rank=rank,
                          injected=[float(i.period) for i in injs]))
         if log and (ci + 1) % 16 == 0:
             log(f"eval {ci + 1}/{len(curves)}: detections {n_det}, recalled {n_hit}")
     n = max(len(curves), 1)
-    return dict(n_curves=len(curves), n_detections=n_det, n_recalled=n_hit,
+    return dict(n_curves=len(curves), top_k=top_k, n_detections=n_det, n_recalled=n_hit,
                 recall=(n_hit / n_det) if n_det else None, plain_ms_per_curve=t_plain / n,
                 learned_ms_per_curve=t_learned / n, speedup=(t_plain / t_learned) if t_learned > 0 else None,
-                periods_folded_fraction=n_folded / (n * pipe.K), rows=rows)
+                periods_folded_fraction=n_folded / (n * pipe.K), ranks=ranks, rows=rows)
+
+
+def k_for_recall(ranks, target: float, n_windows: int) -> int:
+    """Smallest K whose top-K windows hold at least `target` of the
+    detections' windows (n_windows if none does)."""
+    if not ranks:
+        return 1
+    r = np.sort(np.asarray(ranks))
+    need = int(np.ceil(target * len(r)))
+    return int(min(n_windows, r[need - 1] + 1))
