@@ -330,14 +330,31 @@ int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, const void *x
                      int32_t batch, const void *w, int32_t k32, void *g_scratch, void *wt_scratch, float *dx,
                      float *dw, float *db);
 
-/* e[pos][c] = relu(P[c][:] . h[pos][:] + p[c]) over n_pos = batch*L
- * positions; P [E][64], p[E] FP32. */
+/* e[pos][c] = P[c][:] . h[pos][:] + p[c] over n_pos = batch*L positions,
+ * through a ReLU when relu != 0; P [E][64], p[E] FP32. */
 int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p, int32_t E,
-                          float *e);
+                          int32_t relu, float *e);
 /* Backward of the projection given ge [n_pos][E]: dh [n_pos][64] FP32
  * (overwritten), dP [E][64] and dp[E] accumulate. */
 int cetra_net_project_bwd(void *stream, const void *h, const float *e, const float *ge, int64_t n_pos,
-                          const float *P, int32_t E, float *dh, float *dP, float *dp);
+                          const float *P, int32_t E, int32_t relu, float *dh, float *dP, float *dp);
+
+/* Fold pooling: a coarse version of the periodic search on the event series.
+ * For window w and trial t < S, T = trials[w][t] bins (device FP64 [W][S];
+ * a trial that is not finite or shorter than one bin is skipped) has the
+ * 32.32 step R = floor(2^32 T + 1/2); each phase phi < min(L, ceil(R/2^32))
+ * sums e over the positions phi + ((k R + 2^31) >> 32) < L (the nearest-
+ * epoch rule of Sec. 2.3 at bin resolution) and scores sum / sqrt(count).
+ * f [B][W][E+1]: the maximum score over the window's trials and phases per
+ * channel (ties: first trial, then smallest phase), then win_q[w];
+ * arg [B][W][E] = trial * 65536 + phase (-1 if no trial is valid, feature 0).
+ * e [B][L][E] FP32 (channel-last), L <= 8192, E <= 16, S <= 32. */
+int cetra_net_foldpool_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E, const double *trials,
+                           int32_t W, int32_t S, const float *win_q, float *f, int32_t *arg);
+/* Backward of the fold pooling: ge [B][L][E] (overwritten) collects
+ * gf[b][w][c] / sqrt(count) at every position of each window's winner. */
+int cetra_net_foldpool_bwd(void *stream, const float *gf, const int32_t *arg, const double *trials, int32_t B,
+                           int32_t L, int32_t E, int32_t W, int32_t S, float *ge);
 
 /* a[b][c][i] = (1/L) sum_t e[b][t][c] e[b][t+tau][c], tau = tau_lo + i
  * (terms past the end are zero).  L <= 8192, tau_lo >= 1. */

@@ -33,7 +33,7 @@ EPS = 1e-12  # variance floor of the lag standardisation
 
 
 def init_params(c_in: int = 16, width: int = 64, n_layers: int = 5, n_event: int = 8, hidden: int = 64,
-                seed: int = 0) -> dict:
+                seed: int = 0, fold: bool = False) -> dict:
     """He-style initialisation (FP64)."""
     rng = np.random.default_rng(seed)
     p = {}
@@ -45,7 +45,7 @@ def init_params(c_in: int = 16, width: int = 64, n_layers: int = 5, n_event: int
         ch = width
     p["P"] = rng.normal(0, np.sqrt(2.0 / width), (n_event, width))
     p["p"] = np.full(n_event, 0.01)
-    n_feat = 2 * n_event + 1
+    n_feat = n_event + 1 if fold else 2 * n_event + 1
     p["U"] = rng.normal(0, np.sqrt(2.0 / n_feat), (hidden, n_feat))
     p["u"] = np.zeros(hidden)
     p["v"] = rng.normal(0, np.sqrt(1.0 / hidden), hidden)
@@ -106,6 +106,84 @@ def standardise_backward(gn, n, sd):
     return (gn - gn.mean(axis=2, keepdims=True) - n * (gn * n).mean(axis=2, keepdims=True)) / sd
 
 
+def fold_trials(edges, n_trial: int, bin_days: float):
+    """Trial periods (in bins) of every window: n_trial log-spaced points at
+    the centres of n_trial equal log-steps of [edges[w], edges[w+1])."""
+    edges = np.asarray(edges, dtype=np.float64)
+    frac = (np.arange(n_trial) + 0.5) / n_trial
+    return edges[:-1, None] * (edges[1:, None] / edges[:-1, None]) ** frac[None, :] / bin_days
+
+
+def fold_step(T: float) -> int:
+    """32.32 fixed-point step of a trial period of T bins (round half up)."""
+    return int(np.floor(4294967296.0 * float(T) + 0.5))
+
+
+def fold_pool(e, trials):
+    """Coarse fold of each event series at every trial period.  For trial T
+    (bins) with fixed-point step R, phase phi in [0, min(L, ceil(R/2^32)))
+    sums e over the transit positions phi + ((k R + 2^31) >> 32), k = 0, 1,
+    ..., inside the series; the score is that sum over sqrt(number of
+    terms).  Per window: the maximum score over its trials and phases (ties:
+    the first trial, then the smallest phase).  Returns g [B][W][E] and the
+    winning (trial, phase) [B][W][E][2]."""
+    B, E, L = e.shape
+    W, S = trials.shape
+    g = np.zeros((B, W, E))
+    arg = np.zeros((B, W, E, 2), dtype=np.int64)
+    for w in range(W):
+        best = np.full((B, E), -np.inf)
+        for s_ in range(S):
+            if not (1.0 <= trials[w, s_] < 1e9):
+                continue  # a trial shorter than one bin is skipped
+            R = fold_step(trials[w, s_])
+            n_ph = min(L, -(-R // 4294967296))
+            o = []
+            k = 0
+            while True:
+                ok = (k * R + 2147483648) >> 32
+                if ok >= L:
+                    break
+                o.append(ok)
+                k += 1
+            o = np.array(o, dtype=np.int64)
+            for ph in range(n_ph):
+                pos = ph + o
+                pos = pos[pos < L]
+                sc = e[:, :, pos].sum(axis=2) / np.sqrt(len(pos))
+                better = sc > best
+                best = np.where(better, sc, best)
+                arg[:, w, :, 0] = np.where(better, s_, arg[:, w, :, 0])
+                arg[:, w, :, 1] = np.where(better, ph, arg[:, w, :, 1])
+        g[:, w, :] = np.where(np.isfinite(best), best, 0.0)
+        arg[:, w, :, 0] = np.where(np.isfinite(best), arg[:, w, :, 0], -1)
+    return g, arg
+
+
+def fold_pool_backward(gg, arg, trials, L):
+    """Gradient of the window maxima w.r.t. e: each window's winning phase
+    passes gg / sqrt(n) to every one of its transit positions."""
+    B, W, E = gg.shape
+    ge = np.zeros((B, E, L))
+    for b in range(B):
+        for w in range(W):
+            for c in range(E):
+                s_, ph = arg[b, w, c]
+                if s_ < 0:
+                    continue
+                R = fold_step(trials[w, s_])
+                pos = []
+                k = 0
+                while True:
+                    x = ph + ((k * R + 2147483648) >> 32)
+                    if x >= L:
+                        break
+                    pos.append(x)
+                    k += 1
+                ge[b, c, pos] += gg[b, w, c] / np.sqrt(len(pos))
+    return ge
+
+
 def windows_for(n_windows: int, p_lo: float, p_hi: float, bin_days: float):
     """Integer lag ranges [lo, hi] (bins) of n_windows log-spaced period
     windows over [p_lo, p_hi] days, and each window's position q in [0, 1]."""
@@ -127,15 +205,30 @@ def _q(x, on):
     return bf16(x) if on else x
 
 
-def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = False, bf16_trunk: bool = False):
+def forward(p: dict, x, win_lo, win_hi, win_q, n_layers: int = 5, keep: bool = False, bf16_trunk: bool = False,
+            trials=None):
     """bf16_trunk: round the convolution inputs, weights and outputs to
     bfloat16 (the storage precision of the device trunk); the arithmetic
-    stays FP64."""
+    stays FP64.  trials: None for lag-correlation pooling over the windows'
+    lag ranges; else [W][S] trial periods in bins for fold pooling, with a
+    linear event projection and features (window max, q)."""
     h = [_q(x, bf16_trunk)]
     for l in range(n_layers):
         y = np.maximum(conv1d(h[-1], _q(p[f"W{l}"], bf16_trunk), p[f"b{l}"]), 0.0)
         h.append(_q(y, bf16_trunk))
     pre_e = np.einsum("ec,bcl->bel", p["P"], h[-1]) + p["p"][None, :, None]
+    if trials is not None:
+        e = pre_e
+        g, arg = fold_pool(e, np.asarray(trials, dtype=np.float64))
+        B, W = g.shape[:2]
+        f = np.concatenate([g, np.broadcast_to(win_q[None, :, None], (B, W, 1))], axis=2)
+        pre_r = np.einsum("hf,bwf->bwh", p["U"], f) + p["u"]
+        r = np.maximum(pre_r, 0.0)
+        z = np.einsum("h,bwh->bw", p["v"], r) + p["v0"][0]
+        if not keep:
+            return z
+        return z, dict(h=h, pre_e=pre_e, e=e, arg=arg, f=f, pre_r=pre_r, r=r, bf16_trunk=bf16_trunk,
+                       trials=np.asarray(trials, dtype=np.float64))
     e = np.maximum(pre_e, 0.0)
     lags = np.arange(int(win_lo.min()), int(win_hi.max()) + 1)
     a = lag_correlation(e, lags)
@@ -182,6 +275,11 @@ def backward(p: dict, cache: dict, gz, win_lo, win_hi, n_layers: int = 5) -> dic
     g["u"] = gpre_r.sum(axis=(0, 1))
     gf = np.einsum("bwh,hf->bwf", gpre_r, p["U"])
     E = p["P"].shape[0]
+    h = cache["h"]
+    if "trials" in cache:
+        L = cache["e"].shape[2]
+        gpre_e = fold_pool_backward(gf[:, :, :E], cache["arg"], cache["trials"], L)
+        return _trunk_backward(p, g, h, gpre_e, cache, n_layers)
     gg, gm = gf[:, :, :E], gf[:, :, E:2 * E]
     a, lags, arg, e = cache["a"], cache["lags"], cache["arg"], cache["e"]
     B, _, L = e.shape
@@ -200,7 +298,10 @@ def backward(p: dict, cache: dict, gz, win_lo, win_hi, n_layers: int = 5) -> dic
             ge[:, :, :L - tau] += coef * e[:, :, tau:]
             ge[:, :, tau:] += coef * e[:, :, :L - tau]
     gpre_e = ge * (cache["pre_e"] > 0)
-    h = cache["h"]
+    return _trunk_backward(p, g, h, gpre_e, cache, n_layers)
+
+
+def _trunk_backward(p, g, h, gpre_e, cache, n_layers):
     g["P"] = np.einsum("bel,bcl->ec", gpre_e, h[-1])
     g["p"] = gpre_e.sum(axis=(0, 2))
     gh = np.einsum("ec,bel->bcl", p["P"], gpre_e)

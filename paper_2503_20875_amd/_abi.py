@@ -120,8 +120,10 @@ SIGNATURES = {
     "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),
     "cetra_conv1d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _P, _i32, _P, _P, _P, _P, _P]),
-    "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _P]),
-    "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _P, _i32, _P, _P, _P]),
+    "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _i32, _P]),
+    "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _P, _i32, _i32, _P, _P, _P]),
+    "cetra_net_foldpool_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _i32, _P, _P, _P]),
+    "cetra_net_foldpool_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
     "cetra_net_lag_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
     "cetra_net_lag_norm_fwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P]),
     "cetra_net_lag_norm_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _i32, _P]),

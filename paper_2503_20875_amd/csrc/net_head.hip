@@ -24,9 +24,9 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// e[b][t][c] = relu(sum_ci P[c][ci] h[b][t][ci] + p[c])
+// e[b][t][c] = sum_ci P[c][ci] h[b][t][ci] + p[c], through a ReLU if relu
 __global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, const float *__restrict__ P,
-                                   const float *__restrict__ p, int32_t E, float *__restrict__ e) {
+                                   const float *__restrict__ p, int32_t E, int32_t relu, float *__restrict__ e) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= n_pos) return;
     float hv[kWidth];
@@ -36,23 +36,25 @@ __global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, 
         float s = p[c];
 #pragma unroll
         for (int ci = 0; ci < kWidth; ++ci) s = fmaf(P[c * kWidth + ci], hv[ci], s);
-        e[pos * E + c] = fmaxf(s, 0.0f);
+        e[pos * E + c] = relu ? fmaxf(s, 0.0f) : s;
     }
 }
 
-// gpre = ge * (e > 0); dh[pos][ci] = sum_c P[c][ci] gpre[c];
-// dP[c][ci] += sum_pos gpre[c] h[pos][ci]; dp[c] += sum_pos gpre[c]
-// (wave-level reductions, one atomic per wave and parameter).
+// gpre = ge * (e > 0) (ge itself without the ReLU); dh[pos][ci] =
+// sum_c P[c][ci] gpre[c]; dP[c][ci] += sum_pos gpre[c] h[pos][ci];
+// dp[c] += sum_pos gpre[c] (wave-level reductions, one atomic per wave and
+// parameter).
 __global__ void __launch_bounds__(kT) project_bwd_kernel(const __bf16 *__restrict__ h, const float *__restrict__ e,
                                                          const float *__restrict__ ge, int64_t n_pos,
-                                                         const float *__restrict__ P, int32_t E,
+                                                         const float *__restrict__ P, int32_t E, int32_t relu,
                                                          float *__restrict__ dh, float *__restrict__ dP,
                                                          float *__restrict__ dp) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = pos < n_pos;
     const int lane = threadIdx.x & 63;
     float g[kMaxE];
-    for (int c = 0; c < E; ++c) g[c] = (ok && e[pos * E + c] > 0.0f) ? ge[pos * E + c] : 0.0f;
+    for (int c = 0; c < E; ++c)
+        g[c] = (ok && (!relu || e[pos * E + c] > 0.0f)) ? ge[pos * E + c] : 0.0f;
     for (int ci = 0; ci < kWidth; ++ci) {
         const float hv = ok ? (float)h[pos * kWidth + ci] : 0.0f;
         float s = 0.0f;
@@ -155,6 +157,137 @@ __global__ void __launch_bounds__(kT) lag_norm_bwd_kernel(const float *__restric
     const double inv = 1.0 / (double)sd[row];
     for (int i = threadIdx.x; i < n_tau; i += kT)
         ga[row * n_tau + i] = (float)(((double)g[i] - m1 - (double)z[i] * m2) * inv);
+}
+
+// ---------------------------------------------------------- fold pooling
+// Coarse fold of each event series at every window's trial periods.  Trial
+// T (bins) has the 32.32 step R = floor(2^32 T + 1/2); phase phi in
+// [0, min(L, ceil(R / 2^32))) sums e over the positions phi + ((k R + 2^31)
+// >> 32) inside the series, and scores sum / sqrt(count).  Per (example,
+// window, channel) the maximum score over trials and phases is the feature
+// (ties: first trial, then smallest phase); arg keeps trial * 65536 + phase.
+// One workgroup per (channel, example) with the series staged in LDS; the
+// (trial, phase) items of a window are spread over the lanes.  Sums are FP32
+// (exact for the integer-valued inputs of the tests), scores FP64.
+// 0 for a trial that is not finite or shorter than one bin (such a trial is
+// skipped: its offsets would not advance)
+__device__ __forceinline__ uint64_t trial_step(double T) {
+    return (T >= 1.0 && T < 1.0e9) ? (uint64_t)floor(4294967296.0 * T + 0.5) : 0ull;
+}
+
+__device__ __forceinline__ void best_pair_reduce(double &v, int32_t &j, double *s_v, int32_t *s_j) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int32_t oj = __shfl_xor(j, off, 64);
+        if (ov > v || (ov == v && oj < j)) {
+            v = ov;
+            j = oj;
+        }
+    }
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        s_v[wave] = v;
+        s_j[wave] = j;
+    }
+    __syncthreads();
+    v = s_v[0];
+    j = s_j[0];
+    for (int q = 1; q < kT / 64; ++q)
+        if (s_v[q] > v || (s_v[q] == v && s_j[q] < j)) {
+            v = s_v[q];
+            j = s_j[q];
+        }
+}
+
+__global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
+                                                          const double *__restrict__ trials, int32_t W, int32_t S,
+                                                          const float *__restrict__ win_q, float *__restrict__ f,
+                                                          int32_t *__restrict__ arg) {
+    __shared__ float s_e[kMaxL];
+    __shared__ double s_v[kT / 64];
+    __shared__ int32_t s_j[kT / 64];
+    const int32_t c = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int32_t nf = E + 1;
+    for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
+    __syncthreads();
+    for (int32_t w = 0; w < W; ++w) {
+        int32_t n_ph_max = 0;
+        for (int32_t q = 0; q < S; ++q) {
+            const uint64_t R = trial_step(trials[w * S + q]);
+            n_ph_max = max(n_ph_max, (int32_t)min<uint64_t>((uint64_t)L, (R + 4294967295ull) >> 32));
+        }
+        if (n_ph_max == 0) {  // no valid trial: zero feature, no argmax
+            if (threadIdx.x == 0) {
+                f[(b * W + w) * nf + c] = 0.0f;
+                arg[(b * W + w) * E + c] = -1;
+                if (c == 0) f[(b * W + w) * nf + E] = win_q[w];
+            }
+            continue;
+        }
+        double best = -INFINITY;
+        int32_t bj = INT_MAX;
+        for (int32_t jj = threadIdx.x; jj < S * n_ph_max; jj += kT) {
+            const int32_t q = jj / n_ph_max, ph = jj % n_ph_max;
+            const uint64_t R = trial_step(trials[w * S + q]);
+            if (R == 0 || (uint64_t)ph >= ((R + 4294967295ull) >> 32)) continue;
+            float acc = 0.0f;
+            int32_t n = 0;
+            for (uint64_t o = 2147483648ull;; o += R) {
+                const uint64_t x = (uint64_t)ph + (o >> 32);
+                if (x >= (uint64_t)L) break;
+                acc += s_e[x];
+                ++n;
+            }
+            const double sc = (double)acc / sqrt((double)n);
+            if (sc > best || (sc == best && jj < bj)) {
+                best = sc;
+                bj = jj;
+            }
+        }
+        best_pair_reduce(best, bj, s_v, s_j);
+        if (threadIdx.x == 0) {
+            const int32_t q = bj / n_ph_max, ph = bj % n_ph_max;
+            f[(b * W + w) * nf + c] = (float)best;
+            arg[(b * W + w) * E + c] = q * 65536 + ph;
+            if (c == 0) f[(b * W + w) * nf + E] = win_q[w];
+        }
+    }
+}
+
+// ge[b][t][c] (overwritten) = sum over windows of gf[b][w][c] / sqrt(n) at
+// every transit position of the window's winning (trial, phase).
+__global__ void __launch_bounds__(kT) foldpool_bwd_kernel(const float *__restrict__ gf, const int32_t *__restrict__ arg,
+                                                          const double *__restrict__ trials, int32_t L, int32_t E,
+                                                          int32_t W, int32_t S, float *__restrict__ ge) {
+    __shared__ float s_g[kMaxL];
+    const int32_t c = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int32_t nf = E + 1;
+    for (int t = threadIdx.x; t < L; t += kT) s_g[t] = 0.0f;
+    __syncthreads();
+    for (int32_t w = threadIdx.x; w < W; w += kT) {
+        const int32_t a = arg[(b * W + w) * E + c];
+        const int32_t q = a >> 16, ph = a & 0xFFFF;
+        if (q < 0 || q >= S) continue;
+        const uint64_t R = trial_step(trials[w * S + q]);
+        if (R == 0) continue;
+        int32_t n = 0;
+        for (uint64_t o = 2147483648ull;; o += R) {
+            if ((uint64_t)ph + (o >> 32) >= (uint64_t)L) break;
+            ++n;
+        }
+        if (n == 0) continue;
+        const float gg = gf[(b * W + w) * nf + c] / sqrtf((float)n);
+        for (uint64_t o = 2147483648ull;; o += R) {
+            const uint64_t x = (uint64_t)ph + (o >> 32);
+            if (x >= (uint64_t)L) break;
+            atomicAdd(&s_g[x], gg);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < L; t += kT) ge[(b * L + t) * E + c] = s_g[t];
 }
 
 // Window features: f[b][w] = (max_tau a, mean_tau a over the window's lags,
@@ -416,22 +549,22 @@ __global__ void __launch_bounds__(1024) windows_to_periods_kernel(const double *
 using namespace cetra;
 
 extern "C" int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p,
-                                     int32_t E, float *e) {
+                                     int32_t E, int32_t relu, float *e) {
     clear_error();
     CETRA_REQUIRE(h && P && p && e, "net_project_fwd: NULL pointer");
     CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_fwd: bad sizes");
     hipLaunchKernelGGL(project_fwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), (const __bf16 *)h, n_pos, P, p, E, e);
+                       as_stream(stream), (const __bf16 *)h, n_pos, P, p, E, relu, e);
     return check_launch("net_project_fwd");
 }
 
 extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *e, const float *ge, int64_t n_pos,
-                                     const float *P, int32_t E, float *dh, float *dP, float *dp) {
+                                     const float *P, int32_t E, int32_t relu, float *dh, float *dP, float *dp) {
     clear_error();
     CETRA_REQUIRE(h && e && ge && P && dh && dP && dp, "net_project_bwd: NULL pointer");
     CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_bwd: bad sizes");
     hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), (const __bf16 *)h, e, ge, n_pos, P, E, dh, dP, dp);
+                       as_stream(stream), (const __bf16 *)h, e, ge, n_pos, P, E, relu, dh, dP, dp);
     return check_launch("net_project_bwd");
 }
 
@@ -463,6 +596,36 @@ extern "C" int cetra_net_lag_norm_bwd(void *stream, const float *gn, const float
     hipLaunchKernelGGL(lag_norm_bwd_kernel, dim3((unsigned)n_rows), dim3(kT), 0, as_stream(stream), gn, an, sd, n_tau,
                        ga);
     return check_launch("net_lag_norm_bwd");
+}
+
+static int foldpool_args_ok(int32_t B, int32_t L, int32_t E, int32_t W, int32_t S) {
+    CETRA_REQUIRE(B >= 1 && B <= 65535 && L >= 1 && L <= kMaxL && E >= 1 && E <= kMaxE,
+                  "net_foldpool: need 1 <= B <= 65535, 1 <= L <= 8192, 1 <= E <= 16");
+    CETRA_REQUIRE(W >= 1 && S >= 1 && S <= 32, "net_foldpool: need W >= 1 and 1 <= S <= 32");
+    return CETRA_OK;
+}
+
+extern "C" int cetra_net_foldpool_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E,
+                                      const double *trials, int32_t W, int32_t S, const float *win_q, float *f,
+                                      int32_t *arg) {
+    clear_error();
+    CETRA_REQUIRE(e && trials && win_q && f && arg, "net_foldpool_fwd: NULL pointer");
+    int rc = foldpool_args_ok(B, L, E, W, S);
+    if (rc) return rc;
+    hipLaunchKernelGGL(foldpool_fwd_kernel, dim3((unsigned)E, (unsigned)B), dim3(kT), 0, as_stream(stream), e, L, E,
+                       trials, W, S, win_q, f, arg);
+    return check_launch("net_foldpool_fwd");
+}
+
+extern "C" int cetra_net_foldpool_bwd(void *stream, const float *gf, const int32_t *arg, const double *trials,
+                                      int32_t B, int32_t L, int32_t E, int32_t W, int32_t S, float *ge) {
+    clear_error();
+    CETRA_REQUIRE(gf && arg && trials && ge, "net_foldpool_bwd: NULL pointer");
+    int rc = foldpool_args_ok(B, L, E, W, S);
+    if (rc) return rc;
+    hipLaunchKernelGGL(foldpool_bwd_kernel, dim3((unsigned)E, (unsigned)B), dim3(kT), 0, as_stream(stream), gf, arg,
+                       trials, L, E, W, S, ge);
+    return check_launch("net_foldpool_bwd");
 }
 
 extern "C" int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,

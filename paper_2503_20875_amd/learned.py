@@ -128,7 +128,8 @@ def save_weights(net: ProposalNet, path: str, meta: dict) -> None:
 def load_weights(path: str) -> tuple:
     with np.load(path, allow_pickle=False) as z:
         meta = json.loads(bytes(z["__meta__"]).decode())
-        net = ProposalNet(n_event=meta["n_event"], hidden=meta["hidden"])
+        net = ProposalNet(n_event=meta["n_event"], hidden=meta["hidden"], pool=meta.get("pool", "lag"),
+                          n_trial=meta.get("n_trial", 4))
         import torch
         for name in net.offsets:
             net.view(name).copy_(torch.as_tensor(z[name]))

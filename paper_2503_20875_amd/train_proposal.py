@@ -77,6 +77,8 @@ def main(argv=None) -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--pos-weight", type=float, default=32.0)
     ap.add_argument("--seed", type=int, default=20250401)
+    ap.add_argument("--pool", default="fold", choices=["fold", "lag"])
+    ap.add_argument("--n-trial", type=int, default=4)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -90,9 +92,11 @@ def main(argv=None) -> int:
     log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
         f"lags {pipe.windows.tau_lo}..{pipe.windows.tau_lo + pipe.windows.n_tau - 1}")
     x, y, _ = build_dataset(pipe, a.n_train, a.seed)
-    net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed)
+    net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, pool=a.pool,
+                      n_trial=a.n_trial)
     losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)
-    meta = dict(n_event=net.E, hidden=net.H, n_train=a.n_train, epochs=a.epochs, batch=a.batch, lr=a.lr,
+    meta = dict(n_event=net.E, hidden=net.H, pool=net.pool, n_trial=net.S, n_train=a.n_train, epochs=a.epochs,
+                batch=a.batch, lr=a.lr,
                 pos_weight=a.pos_weight, seed=a.seed, losses=losses, n_bins=pipe.cfg.n_bins,
                 n_windows=pipe.cfg.n_windows, p_lo=pipe.cfg.p_lo, p_hi=pipe.cfg.p_hi)
     save_weights(net, a.out, meta)

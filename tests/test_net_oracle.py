@@ -130,3 +130,69 @@ def test_standardise_zero_mean_unit_variance_and_affine_invariant():
     # constant input: no signal, output zero
     n0, _ = net.standardise(np.full((1, 1, 10), 0.25))
     assert np.all(n0 == 0)
+
+
+def test_fold_pool_recovers_a_period():
+    """Spikes every 10 bins starting at bin 3: the trial of 10 bins peaks at
+    phase 3 with score n / sqrt(n) = sqrt(10); a detuned trial scores less."""
+    e = np.zeros((1, 1, 100))
+    e[0, 0, 3::10] = 1.0
+    trials = np.array([[9.37, 10.0]])
+    g, arg = net.fold_pool(e, trials)
+    assert arg[0, 0, 0].tolist() == [1, 3]
+    assert g[0, 0, 0] == pytest.approx(np.sqrt(10.0), abs=1e-12)
+    g9, _ = net.fold_pool(e, trials[:, :1])
+    assert g9[0, 0, 0] < np.sqrt(10.0)
+
+
+def test_fold_offsets_are_nearest_multiples():
+    """The fixed-point transit offsets equal round-half-up of k T, exactly
+    (Fraction arithmetic on the FP64 trial)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(4)
+    for T in rng.uniform(1.0, 300.0, 20):
+        R = net.fold_step(T)
+        assert abs(Fraction(R, 2 ** 32) - Fraction(T)) <= Fraction(1, 2 ** 33)
+        for k in range(0, 60, 7):
+            assert ((k * R + 2 ** 31) >> 32) == int(np.floor(Fraction(k * R, 2 ** 32) + Fraction(1, 2)))
+
+
+def test_fold_trials_inside_windows():
+    lo, hi, q, edges = net.windows_for(32, 1.0, 100.0, 0.05)
+    t = net.fold_trials(edges, 4, 0.05)
+    assert t.shape == (32, 4)
+    assert np.all(t * 0.05 > edges[:-1, None]) and np.all(t * 0.05 < edges[1:, None])
+    assert np.all(np.diff(t, axis=1) > 0)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_fold_pool_gradients_match_central_differences(seed):
+    rng = np.random.default_rng(seed)
+    B, C, L, W = 2, 3, 60, 5
+    p = net.init_params(c_in=C, width=5, n_layers=5, n_event=2, hidden=6, seed=seed, fold=True)
+    for k in p:
+        if k.startswith("b") or k in ("p", "u"):
+            p[k] = rng.normal(0, 0.1, p[k].shape)
+    x = rng.uniform(0, 1, (B, C, L))
+    edges = np.geomspace(2.0, 20.0, W + 1)
+    trials = net.fold_trials(edges, 3, 1.0)
+    lo = hi = np.zeros(W, dtype=np.int64)
+    q = (np.arange(W) + 0.5) / W
+    y = np.zeros((B, W))
+    y[0, 1] = y[1, 3] = 1
+    z, cache = net.forward(p, x, lo, hi, q, keep=True, trials=trials)
+    _, gz = net.bce_loss(z, y, pos_weight=3.0)
+    g = net.backward(p, cache, gz, lo, hi)
+    h = 1e-6
+    for name in list(p.keys()) + ["x"]:
+        arr = x if name == "x" else p[name]
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, min(5, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = net.bce_loss(net.forward(p, x, lo, hi, q, trials=trials), y, 3.0)[0]
+            flat[idx] = old - h
+            lm = net.bce_loss(net.forward(p, x, lo, hi, q, trials=trials), y, 3.0)[0]
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (name, idx, fd)

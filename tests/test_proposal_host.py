@@ -33,3 +33,13 @@ def test_windows_rejects_bad_arguments():
     for args in ((0, 1.0, 2.0, 0.1), (4, 2.0, 1.0, 0.1), (4, 1.0, 2.0, 0.0)):
         with pytest.raises(ValueError):
             Windows.log_spaced(*args)
+
+
+def test_k_for_recall():
+    from paper_2503_20875_amd.learned import k_for_recall
+    ranks = [0, 3, 10, 200]
+    assert k_for_recall(ranks, 1.0, 512) == 201  # all four inside the top 201
+    assert k_for_recall(ranks, 0.75, 512) == 11
+    assert k_for_recall(ranks, 0.5, 512) == 4
+    assert k_for_recall([], 0.99, 512) == 1
+    assert k_for_recall([600], 0.99, 512) == 512  # capped at the number of windows
