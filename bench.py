@@ -95,6 +95,65 @@ def cpu_baseline(wl, stride: int = 10):
                 seconds_measured=round(t_lin + t_fold, 2))
 
 
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def net_block(batch: int = 32, length: int = 8192, reps: int = 10) -> dict:
+    """MFMA roofline of the proposal network's 64-channel convolution (the
+    dominant kernel of training): forward and backward (weights and input)
+    of one 64 -> 64 channel, 9-tap layer over batch x length positions,
+    timed with HIP events, against the dense BF16 MFMA peak; plus one full
+    training step (forward, backward, Adam) of the network."""
+    import torch
+    from paper_2503_20875_amd import proposal as P
+    g = torch.Generator(device="cpu").manual_seed(7)
+    x = torch.rand((batch, length, 64), generator=g).to("cuda", torch.bfloat16)
+    w = (torch.randn((64, 576), generator=g) * 0.06).to("cuda", torch.bfloat16)
+    bias = torch.zeros(64, device="cuda")
+    dy = torch.randn((batch, length, 64), generator=g).to("cuda")
+    y = P.conv1d_fwd(x, w, bias)
+    P.conv1d_bwd(dy, y, x, w)
+    flop_fwd = 2.0 * 64 * 64 * 9 * length * batch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        P.conv1d_fwd(x, w, bias)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        P.conv1d_bwd(dy, y, x, w)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ms_f = ev[0].elapsed_time(ev[1]) / reps
+    ms_b = ev[2].elapsed_time(ev[3]) / reps
+    tf_f = flop_fwd / (ms_f / 1e3) / 1e12
+    tf_b = 2 * flop_fwd / (ms_b / 1e3) / 1e12  # weight and input gradients
+    # one training step of the whole network on random inputs
+    net = P.ProposalNet()
+    win = P.Windows.log_spaced(512, 1.0, 100.0, 111.1 / length)
+    xin = torch.rand((batch, length, 16), generator=g).to("cuda", torch.bfloat16)
+    lab = torch.zeros((batch, 512), device="cuda")
+    lab[:, 100] = 1.0
+    for _ in range(2):
+        net.forward(xin, win)
+        net.backward(lab, pos_weight=32.0)
+        net.adam()
+    ev[0].record()
+    for _ in range(3):
+        net.forward(xin, win)
+        net.backward(lab, pos_weight=32.0)
+        net.adam()
+    ev[1].record()
+    torch.cuda.synchronize()
+    step_ms = ev[0].elapsed_time(ev[1]) / 3
+    return {"kernel": "conv_fwd_kernel / conv_bwd (64 -> 64 channels, 9 taps, bf16 MFMA, FP32 accumulation)",
+            "bound": "mfma", "achieved": tf_f, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf_f / BF16_MFMA_PEAK_TFLOPS, "backward_achieved": tf_b,
+            "backward_frac": tf_b / BF16_MFMA_PEAK_TFLOPS, "fwd_ms": ms_f, "bwd_ms": ms_b,
+            "shape": f"batch {batch} x {length} positions", "algorithmic_flop_fwd": flop_fwd,
+            "train_step_ms": step_ms, "train_examples_per_s": batch / (step_ms / 1e3)}
+
+
 def learned_block(n_curves: int, seed: int = 20250402, target: float = 0.99) -> dict:
     """Learned proposal versus the plain periodic search on held-out curves of
     the learned-proposal workload (80 000 points at 2-min cadence, half with
@@ -123,6 +182,7 @@ def learned_block(n_curves: int, seed: int = 20250402, target: float = 0.99) -> 
         "target_recall": target,
         "k_windows": k_target,
         "recall_at_snr7": test["recall"], "n_detections": test["n_detections"], "n_recalled": test["n_recalled"],
+        "recall_true_detections": test["recall_true"], "n_true_detections": test["n_true_detections"],
         "plain_ms_per_curve": test["plain_ms_per_curve"], "learned_ms_per_curve": test["learned_ms_per_curve"],
         "speedup": test["speedup"], "periods_folded_fraction": test["periods_folded_fraction"],
         "at_k64": {"recall_test": float(np.mean(ranks < 64)) if ranks.size else None,
@@ -293,6 +353,8 @@ def main():
         "wall_s_timed": wall,
         "best": {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"]},
     }
+    if args.workload == "high_cadence":
+        out["roofline_net"] = net_block()
     if args.learned_curves > 0 and args.workload == "high_cadence":
         out["learned"] = learned_block(args.learned_curves)
     if not args.no_cpu_baseline:

@@ -281,12 +281,12 @@ int cetra_batch_search(const cetra_batch_plan *plan, void *stream, const double 
  * Period-window proposal network (an addition, not part of the paper).
  *
  * A small 1-D convolutional network reads the linear search's single-event
- * statistics (Sec. 2.2), downsampled to L bins, and scores W period windows;
- * the periodic search (Sec. 2.3) then folds only the periods of the K
- * best-scored windows (cetra_periodic_search's subset argument).  The calls
- * below are the network's forward and backward stages and its optimiser, so
- * that training and inference run on the device; the host only sequences
- * them.  Conventions:
+ * statistics (Sec. 2.2), downsampled to L bins, and scores W log-spaced
+ * period windows; the periodic search (Sec. 2.3) then folds only the periods
+ * of the K best-scored windows (cetra_periodic_search's subset argument).
+ * The calls below are the network's forward and backward stages and its
+ * optimiser, so that training and inference run on the device; the host
+ * only sequences them.  Conventions:
  *   bf16   device buffers of IEEE bfloat16 values (passed as void*)
  *   x      input [batch][L][16] bf16 (channel-last; channels = durations)
  *   h      trunk activations [batch][L][64] bf16 (after ReLU)
@@ -295,13 +295,10 @@ int cetra_batch_search(const cetra_batch_plan *plan, void *stream, const double 
  *          (zero padding 4), k32 = 9*cin rounded up to a multiple of 32,
  *          padding columns zero (tap-major, channel-minor; FP32 masters and
  *          weight gradients use the same [64][k32] layout)
- *   e      event channels [batch][L][E] FP32, E <= 16
- *   a      lag correlation [batch][E][n_tau] FP32, lags tau_lo .. tau_lo+n_tau-1,
- *          standardised per row before the window pooling
- *   windows  win_lo/win_hi: device int32[W] inclusive lag ranges (absolute
- *          lags), win_q: device float[W] window position in [0, 1]
- *   f      window features [batch][W][2E+1] FP32 = (max_c, mean_c, q)
- *   z      logits [batch][W] FP32
+ *   e      event channels [batch][L][E] FP32, E <= 16 (linear projection)
+ *   f      window features [batch][W][E+1] FP32 = (best fold score per
+ *          channel, window position q in [0, 1])
+ *   z      logits [batch][W]
  * Gradient outputs named d* / g* that are parameters accumulate (+=): the
  * caller clears them before each step; activation gradients are overwritten.
  * Every call only enqueues work on `stream`; errors as for the other calls.
@@ -330,14 +327,14 @@ int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, const void *x
                      int32_t batch, const void *w, int32_t k32, void *g_scratch, void *wt_scratch, float *dx,
                      float *dw, float *db);
 
-/* e[pos][c] = P[c][:] . h[pos][:] + p[c] over n_pos = batch*L positions,
- * through a ReLU when relu != 0; P [E][64], p[E] FP32. */
+/* e[pos][c] = P[c][:] . h[pos][:] + p[c] over n_pos = batch*L positions;
+ * P [E][64], p[E] FP32. */
 int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p, int32_t E,
-                          int32_t relu, float *e);
+                          float *e);
 /* Backward of the projection given ge [n_pos][E]: dh [n_pos][64] FP32
  * (overwritten), dP [E][64] and dp[E] accumulate. */
-int cetra_net_project_bwd(void *stream, const void *h, const float *e, const float *ge, int64_t n_pos,
-                          const float *P, int32_t E, int32_t relu, float *dh, float *dP, float *dp);
+int cetra_net_project_bwd(void *stream, const void *h, const float *ge, int64_t n_pos, const float *P, int32_t E,
+                          float *dh, float *dP, float *dp);
 
 /* Fold pooling: a coarse version of the periodic search on the event series.
  * For window w and trial t < S, T = trials[w][t] bins (device FP64 [W][S];
@@ -356,27 +353,8 @@ int cetra_net_foldpool_fwd(void *stream, const float *e, int32_t B, int32_t L, i
 int cetra_net_foldpool_bwd(void *stream, const float *gf, const int32_t *arg, const double *trials, int32_t B,
                            int32_t L, int32_t E, int32_t W, int32_t S, float *ge);
 
-/* a[b][c][i] = (1/L) sum_t e[b][t][c] e[b][t+tau][c], tau = tau_lo + i
- * (terms past the end are zero).  L <= 8192, tau_lo >= 1. */
-int cetra_net_lag_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E, int32_t tau_lo,
-                      int32_t n_tau, float *a);
-/* Standardise each of the n_rows = B*E rows of a [n_rows][n_tau] over its
- * lags: an = (a - mean) / sd, sd = sqrt(population variance + 1e-12);
- * sd[n_rows] is kept for the backward pass (all device FP32). */
-int cetra_net_lag_norm_fwd(void *stream, const float *a, int64_t n_rows, int32_t n_tau, float *an, float *sd);
-/* Backward of the standardisation: ga = (gn - mean(gn) - an mean(gn an)) / sd
- * per row (overwritten). */
-int cetra_net_lag_norm_bwd(void *stream, const float *gn, const float *an, const float *sd, int64_t n_rows,
-                           int32_t n_tau, float *ga);
-/* Window max / mean of the (standardised) correlation a over each window's
- * lags (clipped to the computed lags) plus q; arg[b][w][c] = index into a's
- * lag axis of the first maximum (-1 for an empty window, whose features are
- * 0). */
-int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
-                       const int32_t *win_lo, const int32_t *win_hi, const float *win_q, int32_t W, float *f,
-                       int32_t *arg);
 /* z = v . relu(U f + u) + v0 per (example, window); U [H][nf], H <= 128,
- * nf = 2E+1. */
+ * nf = E+1. */
 int cetra_net_head_fwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U, const float *u,
                        const float *v, const float *v0, int32_t H, float *z);
 /* Weighted binary cross-entropy with logits, mean over the n logits:
@@ -388,13 +366,6 @@ int cetra_net_bce(void *stream, const float *z, const float *y, int64_t n, float
 int cetra_net_head_bwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U, const float *u,
                        const float *v, int32_t H, const float *gz, float *gU, float *gu, float *gv, float *gv0,
                        float *gf);
-/* Pool backward: ga [B][E][n_tau] accumulates (the caller zeroes it). */
-int cetra_net_pool_bwd(void *stream, const float *gf, const int32_t *arg, int32_t B, int32_t E, int32_t n_tau,
-                       int32_t tau_lo, const int32_t *win_lo, const int32_t *win_hi, int32_t W, float *ga);
-/* Lag-correlation backward: ge [B][L][E] (overwritten). n_tau <= 8192. */
-int cetra_net_lag_bwd(void *stream, const float *e, const float *ga, int32_t B, int32_t L, int32_t E,
-                      int32_t tau_lo, int32_t n_tau, float *ge);
-
 /* One Adam step (bias-corrected, step >= 1) on n FP32 parameters p with
  * gradient g and moments m, v (device, updated in place). */
 int cetra_adam_step(void *stream, float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1,

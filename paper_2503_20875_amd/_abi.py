@@ -120,19 +120,13 @@ SIGNATURES = {
     "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),
     "cetra_conv1d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _P, _i32, _P, _P, _P, _P, _P]),
-    "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _i32, _P]),
-    "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _P, _i32, _i32, _P, _P, _P]),
+    "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _P]),
+    "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _i64, _P, _i32, _P, _P, _P]),
     "cetra_net_foldpool_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _i32, _P, _P, _P]),
     "cetra_net_foldpool_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
-    "cetra_net_lag_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
-    "cetra_net_lag_norm_fwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P]),
-    "cetra_net_lag_norm_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i64, _i32, _P]),
-    "cetra_net_pool_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _i32, _P, _P, _P, _i32, _P, _P]),
     "cetra_net_head_fwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P, _P, _P, _i32, _P]),
     "cetra_net_bce": (ctypes.c_int, [_P, _P, _P, _i64, _f32, _P, _P]),
     "cetra_net_head_bwd": (ctypes.c_int, [_P, _P, _i64, _i32, _P, _P, _P, _i32, _P, _P, _P, _P, _P, _P]),
-    "cetra_net_pool_bwd": (ctypes.c_int, [_P, _P, _P, _i32, _i32, _i32, _i32, _P, _P, _i32, _P]),
-    "cetra_net_lag_bwd": (ctypes.c_int, [_P, _P, _P, _i32, _i32, _i32, _i32, _i32, _P]),
     "cetra_adam_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _i64, _f32, _f32, _f32, _f32, _i64]),
     "cetra_net_pack_conv_w": (ctypes.c_int, [_P, _P, _i32, _i32, _P]),
     "cetra_topk_windows": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P]),

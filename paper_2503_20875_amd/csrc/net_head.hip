@@ -1,14 +1,14 @@
-// Proposal network, after the convolutional trunk: 1x1 event projection, lag
-// correlation pooled over period windows, a shared MLP head per window, the
-// weighted binary cross-entropy, the Adam step, and the top-K window
+// Proposal network, after the convolutional trunk: the linear event
+// projection, fold pooling (a coarse periodic search of each event channel
+// at a few trial periods per period window), a shared MLP head per window,
+// the weighted binary cross-entropy, the Adam step, and the top-K window
 // selection that restricts the periodic search (Sec. 2.3) to the proposed
 // period windows.  VALU kernels (the work here is small next to the
 // convolutions).
 //
 // Shapes: B examples, L bins, E event channels (<= 16), W windows; e is
-// [B][L][E] FP32, lag correlation a is [B][E][n_tau] (lags tau_lo ..
-// tau_lo + n_tau - 1), window features f are [B][W][2E + 1] = (max, mean,
-// window position), logits z are [B][W].
+// [B][L][E] FP32, window features f are [B][W][E + 1] = (best fold score per
+// channel, window position), logits z are [B][W].
 #include <cmath>
 
 #include "common.h"
@@ -18,15 +18,16 @@ namespace {
 constexpr int kT = 256;
 constexpr int kWidth = 64;
 constexpr int kMaxE = 16;
+constexpr int kMaxL = 8192;  // bins of an event series (staged in LDS)
 
 __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// e[b][t][c] = sum_ci P[c][ci] h[b][t][ci] + p[c], through a ReLU if relu
+// e[b][t][c] = sum_ci P[c][ci] h[b][t][ci] + p[c]
 __global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, const float *__restrict__ P,
-                                   const float *__restrict__ p, int32_t E, int32_t relu, float *__restrict__ e) {
+                                   const float *__restrict__ p, int32_t E, float *__restrict__ e) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= n_pos) return;
     float hv[kWidth];
@@ -36,25 +37,22 @@ __global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, 
         float s = p[c];
 #pragma unroll
         for (int ci = 0; ci < kWidth; ++ci) s = fmaf(P[c * kWidth + ci], hv[ci], s);
-        e[pos * E + c] = relu ? fmaxf(s, 0.0f) : s;
+        e[pos * E + c] = s;
     }
 }
 
-// gpre = ge * (e > 0) (ge itself without the ReLU); dh[pos][ci] =
-// sum_c P[c][ci] gpre[c]; dP[c][ci] += sum_pos gpre[c] h[pos][ci];
-// dp[c] += sum_pos gpre[c] (wave-level reductions, one atomic per wave and
+// dh[pos][ci] = sum_c P[c][ci] ge[c]; dP[c][ci] += sum_pos ge[c] h[pos][ci];
+// dp[c] += sum_pos ge[c] (wave-level reductions, one atomic per wave and
 // parameter).
-__global__ void __launch_bounds__(kT) project_bwd_kernel(const __bf16 *__restrict__ h, const float *__restrict__ e,
-                                                         const float *__restrict__ ge, int64_t n_pos,
-                                                         const float *__restrict__ P, int32_t E, int32_t relu,
+__global__ void __launch_bounds__(kT) project_bwd_kernel(const __bf16 *__restrict__ h, const float *__restrict__ ge,
+                                                         int64_t n_pos, const float *__restrict__ P, int32_t E,
                                                          float *__restrict__ dh, float *__restrict__ dP,
                                                          float *__restrict__ dp) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = pos < n_pos;
     const int lane = threadIdx.x & 63;
     float g[kMaxE];
-    for (int c = 0; c < E; ++c)
-        g[c] = (ok && (!relu || e[pos * E + c] > 0.0f)) ? ge[pos * E + c] : 0.0f;
+    for (int c = 0; c < E; ++c) g[c] = ok ? ge[pos * E + c] : 0.0f;
     for (int ci = 0; ci < kWidth; ++ci) {
         const float hv = ok ? (float)h[pos * kWidth + ci] : 0.0f;
         float s = 0.0f;
@@ -69,94 +67,6 @@ __global__ void __launch_bounds__(kT) project_bwd_kernel(const __bf16 *__restric
         const float r = wave_sum(g[c]);
         if (lane == 0) atomicAdd(&dp[c], r);
     }
-}
-
-// a[b][c][i] = (1/L) sum_t e[b][t][c] e[b][t + tau][c], tau = tau_lo + i.
-// Workgroup: (block of 1024 lags, channel, example); e of the channel is
-// staged in LDS; each lane computes four consecutive lags.
-constexpr int kLagsPerLane = 4;
-constexpr int kMaxL = 8192;
-__global__ void __launch_bounds__(kT) lag_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
-                                                     int32_t tau_lo, int32_t n_tau, float *__restrict__ a) {
-    __shared__ float s_e[kMaxL];
-    const int32_t c = blockIdx.y;
-    const int64_t b = blockIdx.z;
-    for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
-    __syncthreads();
-    const int32_t i0 = (blockIdx.x * kT + threadIdx.x) * kLagsPerLane;
-    if (i0 >= n_tau) return;
-    const int32_t tau0 = tau_lo + i0;
-    // FP64 sums: the correlation is standardised over the lags next, which
-    // subtracts its mean level and so magnifies relative summation error
-    double acc[kLagsPerLane] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t t = 0; t + tau0 < L; ++t) {
-        const double x = (double)s_e[t];
-#pragma unroll
-        for (int q = 0; q < kLagsPerLane; ++q) {
-            const int32_t u = t + tau0 + q;
-            acc[q] = fma(x, u < L ? (double)s_e[u] : 0.0, acc[q]);
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < kLagsPerLane; ++q)
-        if (i0 + q < n_tau) a[(b * E + c) * n_tau + i0 + q] = (float)(acc[q] / (double)L);
-}
-
-__device__ __forceinline__ double wave_sum_f64(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum over the workgroup (256 lanes) in FP64; every lane gets the total.
-__device__ __forceinline__ double block_sum(double v, double *s_red) {
-    v = wave_sum_f64(v);
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();  // s_red may still be read from a previous call
-    if ((threadIdx.x & 63) == 0) s_red[wave] = v;
-    __syncthreads();
-    return s_red[0] + s_red[1] + s_red[2] + s_red[3];
-}
-
-// Standardise each (example, channel) row of the lag correlation over its
-// n_tau lags: an = (a - mean) / sqrt(var + eps), population variance of the
-// centred values; sd[b][c] keeps the divisor for the backward pass.
-constexpr float kLagEps = 1e-12f;
-__global__ void __launch_bounds__(kT) lag_norm_fwd_kernel(const float *__restrict__ a, int32_t n_tau,
-                                                          float *__restrict__ an, float *__restrict__ sd) {
-    __shared__ double s_red[4];
-    const int64_t row = blockIdx.x;
-    const float *x = a + row * n_tau;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n_tau; i += kT) s += (double)x[i];
-    const double mu = block_sum(s, s_red) / (double)n_tau;
-    double q = 0.0;
-    for (int i = threadIdx.x; i < n_tau; i += kT) {
-        const double d = (double)x[i] - mu;
-        q = fma(d, d, q);
-    }
-    const double sdv = sqrt(block_sum(q, s_red) / (double)n_tau + (double)kLagEps);
-    for (int i = threadIdx.x; i < n_tau; i += kT) an[row * n_tau + i] = (float)(((double)x[i] - mu) / sdv);
-    if (threadIdx.x == 0) sd[row] = (float)sdv;
-}
-
-// ga = (gn - mean(gn) - an * mean(gn * an)) / sd per row.
-__global__ void __launch_bounds__(kT) lag_norm_bwd_kernel(const float *__restrict__ gn, const float *__restrict__ an,
-                                                          const float *__restrict__ sd, int32_t n_tau,
-                                                          float *__restrict__ ga) {
-    __shared__ double s_red[4];
-    const int64_t row = blockIdx.x;
-    const float *g = gn + row * n_tau;
-    const float *z = an + row * n_tau;
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < n_tau; i += kT) {
-        s1 += (double)g[i];
-        s2 = fma((double)g[i], (double)z[i], s2);
-    }
-    const double m1 = block_sum(s1, s_red) / (double)n_tau;
-    const double m2 = block_sum(s2, s_red) / (double)n_tau;
-    const double inv = 1.0 / (double)sd[row];
-    for (int i = threadIdx.x; i < n_tau; i += kT)
-        ga[row * n_tau + i] = (float)(((double)g[i] - m1 - (double)z[i] * m2) * inv);
 }
 
 // ---------------------------------------------------------- fold pooling
@@ -290,39 +200,6 @@ __global__ void __launch_bounds__(kT) foldpool_bwd_kernel(const float *__restric
     for (int t = threadIdx.x; t < L; t += kT) ge[(b * L + t) * E + c] = s_g[t];
 }
 
-// Window features: f[b][w] = (max_tau a, mean_tau a over the window's lags,
-// q_w); arg[b][w][c] = lag index of the first maximum.
-__global__ void pool_fwd_kernel(const float *__restrict__ a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
-                                const int32_t *__restrict__ win_lo, const int32_t *__restrict__ win_hi,
-                                const float *__restrict__ win_q, int32_t W, float *__restrict__ f,
-                                int32_t *__restrict__ arg) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (int64_t)B * W * E) return;
-    const int32_t c = (int32_t)(id % E);
-    const int64_t bw = id / E;
-    const int32_t w = (int32_t)(bw % W);
-    const int64_t b = bw / W;
-    const float *ac = a + (b * E + c) * n_tau;
-    // lag range clipped to the computed lags; an empty range gives zero
-    // features and no argmax (-1)
-    const int32_t lo = max(win_lo[w] - tau_lo, 0), hi = min(win_hi[w] - tau_lo, n_tau - 1);
-    float mx = -INFINITY, s = 0.0f;
-    int32_t am = -1;
-    for (int32_t i = lo; i <= hi; ++i) {
-        const float v = ac[i];
-        if (v > mx) {
-            mx = v;
-            am = i;
-        }
-        s += v;
-    }
-    const int32_t nf = 2 * E + 1;
-    f[bw * nf + c] = am >= 0 ? mx : 0.0f;
-    f[bw * nf + E + c] = am >= 0 ? s / (float)(hi - lo + 1) : 0.0f;
-    arg[id] = am;
-    if (c == 0) f[bw * nf + 2 * E] = win_q[w];
-}
-
 // z[b][w] = v . relu(U f + u) + v0 (hidden width <= 128)
 constexpr int kMaxHidden = 128;
 __global__ void head_fwd_kernel(const float *__restrict__ f, int64_t n_bw, int32_t nf, const float *__restrict__ U,
@@ -389,53 +266,6 @@ __global__ void __launch_bounds__(kT) head_bwd_kernel(const float *__restrict__ 
     if (lane == 0) atomicAdd(gv0, t4);
     if (ok)
         for (int k = 0; k < nf; ++k) gf[bw * nf + k] = gfv[k];
-}
-
-// Pool backward: ga[b][c][i] += gmax at the argmax lag and gmean / n over
-// the window's lags (windows may share lags: atomics).
-__global__ void pool_bwd_kernel(const float *__restrict__ gf, const int32_t *__restrict__ arg, int32_t B, int32_t E,
-                                int32_t n_tau, int32_t tau_lo, const int32_t *__restrict__ win_lo,
-                                const int32_t *__restrict__ win_hi, int32_t W, float *__restrict__ ga) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= (int64_t)B * W * E) return;
-    const int32_t c = (int32_t)(id % E);
-    const int64_t bw = id / E;
-    const int32_t w = (int32_t)(bw % W);
-    const int64_t b = bw / W;
-    const int32_t nf = 2 * E + 1;
-    float *gac = ga + (b * E + c) * n_tau;
-    const int32_t am = arg[id];
-    if (am < 0 || am >= n_tau) return;
-    atomicAdd(&gac[am], gf[bw * nf + c]);
-    const int32_t lo = max(win_lo[w] - tau_lo, 0), hi = min(win_hi[w] - tau_lo, n_tau - 1);
-    const float gm = gf[bw * nf + E + c] / (float)(hi - lo + 1);
-    for (int32_t i = lo; i <= hi; ++i) atomicAdd(&gac[i], gm);
-}
-
-// ge[b][t][c] = (1/L) sum_i ga[i] (e[t + tau_i] + e[t - tau_i]); e and ga of
-// the channel staged in LDS.
-__global__ void __launch_bounds__(kT) lag_bwd_kernel(const float *__restrict__ e, const float *__restrict__ ga,
-                                                     int32_t L, int32_t E, int32_t tau_lo, int32_t n_tau,
-                                                     float *__restrict__ ge) {
-    __shared__ float s_e[kMaxL];
-    __shared__ float s_g[kMaxL];
-    const int32_t c = blockIdx.y;
-    const int64_t b = blockIdx.z;
-    for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
-    for (int i = threadIdx.x; i < n_tau; i += kT) s_g[i] = ga[(b * E + c) * n_tau + i];
-    __syncthreads();
-    const int32_t t = blockIdx.x * kT + threadIdx.x;
-    if (t >= L) return;
-    // FP64 sums: ga is mean-free over the lags, so its products with the
-    // (non-negative) events cancel
-    double s = 0.0;
-    for (int32_t i = 0; i < n_tau; ++i) {
-        const int32_t tau = tau_lo + i;
-        const float up = t + tau < L ? s_e[t + tau] : 0.0f;
-        const float dn = t - tau >= 0 ? s_e[t - tau] : 0.0f;
-        s = fma((double)s_g[i], (double)up + (double)dn, s);
-    }
-    ge[(b * L + t) * E + c] = (float)(s / (double)L);
 }
 
 // Adam on FP32 master parameters.
@@ -549,53 +379,23 @@ __global__ void __launch_bounds__(1024) windows_to_periods_kernel(const double *
 using namespace cetra;
 
 extern "C" int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p,
-                                     int32_t E, int32_t relu, float *e) {
+                                     int32_t E, float *e) {
     clear_error();
     CETRA_REQUIRE(h && P && p && e, "net_project_fwd: NULL pointer");
     CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_fwd: bad sizes");
     hipLaunchKernelGGL(project_fwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), (const __bf16 *)h, n_pos, P, p, E, relu, e);
+                       as_stream(stream), (const __bf16 *)h, n_pos, P, p, E, e);
     return check_launch("net_project_fwd");
 }
 
-extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *e, const float *ge, int64_t n_pos,
-                                     const float *P, int32_t E, int32_t relu, float *dh, float *dP, float *dp) {
+extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *ge, int64_t n_pos, const float *P,
+                                     int32_t E, float *dh, float *dP, float *dp) {
     clear_error();
-    CETRA_REQUIRE(h && e && ge && P && dh && dP && dp, "net_project_bwd: NULL pointer");
+    CETRA_REQUIRE(h && ge && P && dh && dP && dp, "net_project_bwd: NULL pointer");
     CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_bwd: bad sizes");
     hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), (const __bf16 *)h, e, ge, n_pos, P, E, relu, dh, dP, dp);
+                       as_stream(stream), (const __bf16 *)h, ge, n_pos, P, E, dh, dP, dp);
     return check_launch("net_project_bwd");
-}
-
-extern "C" int cetra_net_lag_fwd(void *stream, const float *e, int32_t B, int32_t L, int32_t E, int32_t tau_lo,
-                                 int32_t n_tau, float *a) {
-    clear_error();
-    CETRA_REQUIRE(e && a, "net_lag_fwd: NULL pointer");
-    CETRA_REQUIRE(L >= 1 && L <= kMaxL && E >= 1 && E <= kMaxE && B >= 1 && tau_lo >= 1 && n_tau >= 1,
-                  "net_lag_fwd: bad sizes");
-    hipLaunchKernelGGL(lag_fwd_kernel, dim3((unsigned)ceil_div(n_tau, kT * kLagsPerLane), E, B), dim3(kT), 0,
-                       as_stream(stream), e, L, E, tau_lo, n_tau, a);
-    return check_launch("net_lag_fwd");
-}
-
-extern "C" int cetra_net_lag_norm_fwd(void *stream, const float *a, int64_t n_rows, int32_t n_tau, float *an,
-                                      float *sd) {
-    clear_error();
-    CETRA_REQUIRE(a && an && sd, "net_lag_norm_fwd: NULL pointer");
-    CETRA_REQUIRE(n_rows >= 1 && n_rows <= INT32_MAX && n_tau >= 1, "net_lag_norm_fwd: bad sizes");
-    hipLaunchKernelGGL(lag_norm_fwd_kernel, dim3((unsigned)n_rows), dim3(kT), 0, as_stream(stream), a, n_tau, an, sd);
-    return check_launch("net_lag_norm_fwd");
-}
-
-extern "C" int cetra_net_lag_norm_bwd(void *stream, const float *gn, const float *an, const float *sd,
-                                      int64_t n_rows, int32_t n_tau, float *ga) {
-    clear_error();
-    CETRA_REQUIRE(gn && an && sd && ga, "net_lag_norm_bwd: NULL pointer");
-    CETRA_REQUIRE(n_rows >= 1 && n_rows <= INT32_MAX && n_tau >= 1, "net_lag_norm_bwd: bad sizes");
-    hipLaunchKernelGGL(lag_norm_bwd_kernel, dim3((unsigned)n_rows), dim3(kT), 0, as_stream(stream), gn, an, sd, n_tau,
-                       ga);
-    return check_launch("net_lag_norm_bwd");
 }
 
 static int foldpool_args_ok(int32_t B, int32_t L, int32_t E, int32_t W, int32_t S) {
@@ -628,17 +428,6 @@ extern "C" int cetra_net_foldpool_bwd(void *stream, const float *gf, const int32
     return check_launch("net_foldpool_bwd");
 }
 
-extern "C" int cetra_net_pool_fwd(void *stream, const float *a, int32_t B, int32_t E, int32_t n_tau, int32_t tau_lo,
-                                  const int32_t *win_lo, const int32_t *win_hi, const float *win_q, int32_t W,
-                                  float *f, int32_t *arg) {
-    clear_error();
-    CETRA_REQUIRE(a && win_lo && win_hi && win_q && f && arg, "net_pool_fwd: NULL pointer");
-    const int64_t n = (int64_t)B * W * E;
-    hipLaunchKernelGGL(pool_fwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), a, B, E, n_tau, tau_lo, win_lo, win_hi, win_q, W, f, arg);
-    return check_launch("net_pool_fwd");
-}
-
 extern "C" int cetra_net_head_fwd(void *stream, const float *f, int64_t n_bw, int32_t nf, const float *U,
                                   const float *u, const float *v, const float *v0, int32_t H, float *z) {
     clear_error();
@@ -667,28 +456,6 @@ extern "C" int cetra_net_head_bwd(void *stream, const float *f, int64_t n_bw, in
     hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_bw, 1), kT)), dim3(kT), 0,
                        as_stream(stream), f, n_bw, nf, U, u, v, H, gz, gU, gu, gv, gv0, gf);
     return check_launch("net_head_bwd");
-}
-
-extern "C" int cetra_net_pool_bwd(void *stream, const float *gf, const int32_t *arg, int32_t B, int32_t E,
-                                  int32_t n_tau, int32_t tau_lo, const int32_t *win_lo, const int32_t *win_hi,
-                                  int32_t W, float *ga) {
-    clear_error();
-    CETRA_REQUIRE(gf && arg && win_lo && win_hi && ga, "net_pool_bwd: NULL pointer");
-    const int64_t n = (int64_t)B * W * E;
-    hipLaunchKernelGGL(pool_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), gf, arg, B, E, n_tau, tau_lo, win_lo, win_hi, W, ga);
-    return check_launch("net_pool_bwd");
-}
-
-extern "C" int cetra_net_lag_bwd(void *stream, const float *e, const float *ga, int32_t B, int32_t L, int32_t E,
-                                 int32_t tau_lo, int32_t n_tau, float *ge) {
-    clear_error();
-    CETRA_REQUIRE(e && ga && ge, "net_lag_bwd: NULL pointer");
-    CETRA_REQUIRE(L >= 1 && L <= kMaxL && n_tau >= 1 && n_tau <= kMaxL && E >= 1 && E <= kMaxE && B >= 1,
-                  "net_lag_bwd: bad sizes");
-    hipLaunchKernelGGL(lag_bwd_kernel, dim3((unsigned)ceil_div(L, kT), E, B), dim3(kT), 0, as_stream(stream), e, ga,
-                       L, E, tau_lo, n_tau, ge);
-    return check_launch("net_lag_bwd");
 }
 
 extern "C" int cetra_adam_step(void *stream, float *p, const float *g, float *m, float *v, int64_t n, float lr,

@@ -128,8 +128,9 @@ def save_weights(net: ProposalNet, path: str, meta: dict) -> None:
 def load_weights(path: str) -> tuple:
     with np.load(path, allow_pickle=False) as z:
         meta = json.loads(bytes(z["__meta__"]).decode())
-        net = ProposalNet(n_event=meta["n_event"], hidden=meta["hidden"], pool=meta.get("pool", "lag"),
-                          n_trial=meta.get("n_trial", 4))
+        if meta.get("pool", "fold") != "fold":
+            raise ValueError(f"{path}: weights of an unsupported pooling ({meta.get('pool')})")
+        net = ProposalNet(n_event=meta["n_event"], hidden=meta["hidden"], n_trial=meta.get("n_trial", 4))
         import torch
         for name in net.offsets:
             net.view(name).copy_(torch.as_tensor(z[name]))
@@ -150,7 +151,7 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
     network + top-K + subset + restricted search + best."""
     import torch
     top_k = int(top_k or pipe.cfg.top_k)
-    n_det = n_hit = 0
+    n_det = n_hit = n_true = n_true_hit = 0
     t_plain = t_learned = 0.0
     n_folded = 0
     rows, ranks = [], []
@@ -173,6 +174,11 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
         n_folded += n_sub
         det = bool(bp["k"] >= 0 and bp["snr"] > snr_min)
         hit = bool(det and bl is not None and bl["k"] == bp["k"])
+        # the paper's recovery criterion: within 1% of P, P/2 or 2P
+        true = bool(det and any(abs(bp["period"] / (i.period * m) - 1.0) < 0.01
+                                for i in injs for m in (1.0, 0.5, 2.0)))
+        n_true += true
+        n_true_hit += true and hit
         rank = -1
         if det:
             zs = z[0].float().cpu().numpy()
@@ -183,12 +189,14 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
         n_hit += hit
         rows.append(dict(curve=ci, plain_k=int(bp["k"]), plain_period=float(bp["period"]), plain_snr=float(bp["snr"]),
                          learned_k=-1 if bl is None else int(bl["k"]), detected=det, recalled=hit, rank=rank,
+                         true_detection=true,
                          injected=[float(i.period) for i in injs]))
         if log and (ci + 1) % 16 == 0:
             log(f"eval {ci + 1}/{len(curves)}: detections {n_det}, recalled {n_hit}")
     n = max(len(curves), 1)
     return dict(n_curves=len(curves), top_k=top_k, n_detections=n_det, n_recalled=n_hit,
-                recall=(n_hit / n_det) if n_det else None, plain_ms_per_curve=t_plain / n,
+                recall=(n_hit / n_det) if n_det else None, n_true_detections=n_true,
+                recall_true=(n_true_hit / n_true) if n_true else None, plain_ms_per_curve=t_plain / n,
                 learned_ms_per_curve=t_learned / n, speedup=(t_plain / t_learned) if t_learned > 0 else None,
                 periods_folded_fraction=n_folded / (n * pipe.K), ranks=ranks, rows=rows)
 

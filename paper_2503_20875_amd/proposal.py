@@ -41,13 +41,10 @@ def _lib():
 
 @dataclass
 class Windows:
-    """Log-spaced period windows over [p_lo, p_hi] days on a lag axis of
-    bins of bin_days: window w covers periods [edges[w], edges[w+1]) and
-    lags [lo[w], hi[w]] (inclusive, >= 1, rounded to the nearest bin); q[w]
-    is its position (w + 1/2) / n in [0, 1]."""
+    """Log-spaced period windows over [p_lo, p_hi] days on an axis of bins of
+    bin_days: window w covers periods [edges[w], edges[w+1]); q[w] is its
+    position (w + 1/2) / n in [0, 1]."""
 
-    lo: np.ndarray
-    hi: np.ndarray
     q: np.ndarray
     edges: np.ndarray
     bin_days: float
@@ -57,29 +54,17 @@ class Windows:
         if not (n >= 1 and 0 < p_lo < p_hi and bin_days > 0):
             raise ValueError("windows: need n >= 1, 0 < p_lo < p_hi, bin_days > 0")
         edges = p_lo * np.power(p_hi / p_lo, np.arange(n + 1, dtype=np.float64) / n)
-        lo = np.maximum(1, np.rint(edges[:-1] / bin_days)).astype(np.int32)
-        hi = np.maximum(lo, np.rint(edges[1:] / bin_days).astype(np.int32))
         q = ((np.arange(n) + 0.5) / n).astype(np.float32)
-        return cls(lo, hi, q, edges, float(bin_days))
+        return cls(q, edges, float(bin_days))
 
     @property
     def n(self) -> int:
-        return int(self.lo.shape[0])
-
-    @property
-    def tau_lo(self) -> int:
-        return int(self.lo.min())
-
-    @property
-    def n_tau(self) -> int:
-        return int(self.hi.max()) - self.tau_lo + 1
+        return int(self.q.shape[0])
 
     def device(self):
         import torch
         if not hasattr(self, "_dev"):
-            self._dev = dict(lo=torch.as_tensor(self.lo, device="cuda"), hi=torch.as_tensor(self.hi, device="cuda"),
-                             q=torch.as_tensor(self.q, device="cuda"),
-                             edges=torch.as_tensor(self.edges, device="cuda"))
+            self._dev = dict(q=torch.as_tensor(self.q, device="cuda"), edges=torch.as_tensor(self.edges, device="cuda"))
         return self._dev
 
     def trials(self, n_trial: int) -> np.ndarray:
@@ -108,23 +93,19 @@ class Windows:
 
 
 class ProposalNet:
-    """Five 9-tap convolutions of 64 channels (ReLU), a 1x1 projection to E
-    event channels, a pooling per period window, and a shared MLP head
-    (hidden width H) giving one logit per window.  pool="fold": a linear
-    projection and the coarse fold of each event channel at S trial periods
-    per window (feature: the best phase score); pool="lag": a ReLU
-    projection and the lag correlation of each channel standardised over its
-    lags (features: max and mean over the window's lags)."""
+    """Five 9-tap convolutions of 64 channels (ReLU), a linear 1x1
+    projection to E event channels, fold pooling -- the coarse fold of each
+    event channel at S trial periods per window, keeping the best phase
+    score -- and a shared MLP head (hidden width H) giving one logit per
+    window."""
 
-    def __init__(self, n_event: int = 8, hidden: int = 64, seed: int = 0, pool: str = "fold", n_trial: int = 4):
+    def __init__(self, n_event: int = 8, hidden: int = 64, seed: int = 0, n_trial: int = 4):
         import torch
         self.E, self.H = int(n_event), int(hidden)
-        if not (1 <= self.E <= 16 and 1 <= self.H <= 128):
-            raise ValueError("proposal net: need 1 <= n_event <= 16 and 1 <= hidden <= 128")
-        if pool not in ("fold", "lag"):
-            raise ValueError("proposal net: pool must be 'fold' or 'lag'")
-        self.pool, self.S = pool, int(n_trial)
-        self.nf = self.E + 1 if pool == "fold" else 2 * self.E + 1
+        if not (1 <= self.E <= 16 and 1 <= self.H <= 128 and 1 <= n_trial <= 32):
+            raise ValueError("proposal net: need 1 <= n_event <= 16, 1 <= hidden <= 128, 1 <= n_trial <= 32")
+        self.S = int(n_trial)
+        self.nf = self.E + 1
         shapes = []
         cin = C_IN
         for l in range(N_LAYERS):
@@ -219,23 +200,18 @@ class ProposalNet:
     # --------------------------------------------------------------- buffers
     def _buffers(self, B: int, L: int, win: Windows):
         import torch
-        key = (B, L, win.n, win.n_tau)
+        key = (B, L, win.n)
         if key in self._bufs:
             return self._bufs[key]
         dev, f32, bf = "cuda", torch.float32, torch.bfloat16
         b = dict(
             h=[None] + [torch.empty((B, L, WIDTH), dtype=bf, device=dev) for _ in range(N_LAYERS)],
             e=torch.empty((B, L, self.E), dtype=f32, device=dev),
-            a=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
-            an=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
-            sd=torch.empty((B, self.E), dtype=f32, device=dev),
-            gan=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
             f=torch.empty((B, win.n, self.nf), dtype=f32, device=dev),
             arg=torch.empty((B, win.n, self.E), dtype=torch.int32, device=dev),
             z=torch.empty((B, win.n), dtype=f32, device=dev),
             gz=torch.empty((B, win.n), dtype=f32, device=dev),
             gf=torch.empty((B, win.n, self.nf), dtype=f32, device=dev),
-            ga=torch.empty((B, self.E, win.n_tau), dtype=f32, device=dev),
             ge=torch.empty((B, L, self.E), dtype=f32, device=dev),
             dh=[torch.empty((B, L, WIDTH), dtype=f32, device=dev) for _ in range(2)],
             g_scratch=torch.empty((B, L, WIDTH), dtype=bf, device=dev),
@@ -253,8 +229,8 @@ class ProposalNet:
         if x.dtype != torch.bfloat16 or x.dim() != 3 or x.shape[2] != C_IN:
             raise ValueError("proposal forward: x must be bfloat16 [B][L][16]")
         B, L = int(x.shape[0]), int(x.shape[1])
-        if L > 8192 or (self.pool == "lag" and win.n_tau > 8192):
-            raise ValueError("proposal forward: L and the lag range must be <= 8192")
+        if L > 8192:
+            raise ValueError("proposal forward: L must be <= 8192")
         lib, s = _lib(), _stream(stream)
         bufs = self._buffers(B, L, win)
         bufs["h"][0] = x.contiguous()
@@ -264,26 +240,15 @@ class ProposalNet:
             _abi.check(lib.cetra_conv1d_fwd(s, _ptr(bufs["h"][l]), cin, L, B, _ptr(self.packed[l]), _k32(cin),
                                             _ptr(self.view(f"b{l}")), _ptr(bufs["h"][l + 1])))
             cin = WIDTH
-        relu = 0 if self.pool == "fold" else 1
         _abi.check(lib.cetra_net_project_fwd(s, _ptr(bufs["h"][N_LAYERS]), B * L, _ptr(self.view("P")),
-                                             _ptr(self.view("p")), self.E, relu, _ptr(bufs["e"])))
-        if self.pool == "fold":
-            _abi.check(lib.cetra_net_foldpool_fwd(s, _ptr(bufs["e"]), B, L, self.E, _ptr(win.trials_device(self.S)),
-                                                  win.n, self.S, _ptr(dw["q"]), _ptr(bufs["f"]), _ptr(bufs["arg"])))
-        else:
-            self._lag_forward(lib, s, bufs, dw, B, L, win)
+                                             _ptr(self.view("p")), self.E, _ptr(bufs["e"])))
+        _abi.check(lib.cetra_net_foldpool_fwd(s, _ptr(bufs["e"]), B, L, self.E, _ptr(win.trials_device(self.S)),
+                                              win.n, self.S, _ptr(dw["q"]), _ptr(bufs["f"]), _ptr(bufs["arg"])))
         _abi.check(lib.cetra_net_head_fwd(s, _ptr(bufs["f"]), B * win.n, self.nf, _ptr(self.view("U")),
                                           _ptr(self.view("u")), _ptr(self.view("v")), _ptr(self.view("v0")), self.H,
                                           _ptr(bufs["z"])))
         self._last = (B, L, win)
         return bufs["z"]
-
-    def _lag_forward(self, lib, s, bufs, dw, B, L, win):
-        _abi.check(lib.cetra_net_lag_fwd(s, _ptr(bufs["e"]), B, L, self.E, win.tau_lo, win.n_tau, _ptr(bufs["a"])))
-        _abi.check(lib.cetra_net_lag_norm_fwd(s, _ptr(bufs["a"]), B * self.E, win.n_tau, _ptr(bufs["an"]),
-                                              _ptr(bufs["sd"])))
-        _abi.check(lib.cetra_net_pool_fwd(s, _ptr(bufs["an"]), B, self.E, win.n_tau, win.tau_lo, _ptr(dw["lo"]),
-                                          _ptr(dw["hi"]), _ptr(dw["q"]), win.n, _ptr(bufs["f"]), _ptr(bufs["arg"])))
 
     # -------------------------------------------------------------- backward
     def backward(self, y, pos_weight: float = 1.0, stream=None, want_dx: bool = False):
@@ -293,12 +258,9 @@ class ProposalNet:
         import torch
         B, L, win = self._last
         lib, s = _lib(), _stream(stream)
-        bufs = self._bufs[(B, L, win.n, win.n_tau)]
-        dw = win.device()
+        bufs = self._bufs[(B, L, win.n)]
         self.grad.zero_()
         bufs["loss"].zero_()
-        if self.pool == "lag":
-            bufs["gan"].zero_()
         n_bw = B * win.n
         _abi.check(lib.cetra_net_bce(s, _ptr(bufs["z"]), _ptr(y), n_bw, float(pos_weight), _ptr(bufs["gz"]),
                                      _ptr(bufs["loss"])))
@@ -307,21 +269,11 @@ class ProposalNet:
                                           _ptr(self.view("U", self.grad)), _ptr(self.view("u", self.grad)),
                                           _ptr(self.view("v", self.grad)), _ptr(self.view("v0", self.grad)),
                                           _ptr(bufs["gf"])))
-        if self.pool == "fold":
-            _abi.check(lib.cetra_net_foldpool_bwd(s, _ptr(bufs["gf"]), _ptr(bufs["arg"]),
-                                                  _ptr(win.trials_device(self.S)), B, L, self.E, win.n, self.S,
-                                                  _ptr(bufs["ge"])))
-        else:
-            _abi.check(lib.cetra_net_pool_bwd(s, _ptr(bufs["gf"]), _ptr(bufs["arg"]), B, self.E, win.n_tau,
-                                              win.tau_lo, _ptr(dw["lo"]), _ptr(dw["hi"]), win.n, _ptr(bufs["gan"])))
-            _abi.check(lib.cetra_net_lag_norm_bwd(s, _ptr(bufs["gan"]), _ptr(bufs["an"]), _ptr(bufs["sd"]),
-                                                  B * self.E, win.n_tau, _ptr(bufs["ga"])))
-            _abi.check(lib.cetra_net_lag_bwd(s, _ptr(bufs["e"]), _ptr(bufs["ga"]), B, L, self.E, win.tau_lo,
-                                             win.n_tau, _ptr(bufs["ge"])))
+        _abi.check(lib.cetra_net_foldpool_bwd(s, _ptr(bufs["gf"]), _ptr(bufs["arg"]), _ptr(win.trials_device(self.S)),
+                                              B, L, self.E, win.n, self.S, _ptr(bufs["ge"])))
         dh_in, dh_out = bufs["dh"]
-        relu = 0 if self.pool == "fold" else 1
-        _abi.check(lib.cetra_net_project_bwd(s, _ptr(bufs["h"][N_LAYERS]), _ptr(bufs["e"]), _ptr(bufs["ge"]), B * L,
-                                             _ptr(self.view("P")), self.E, relu, _ptr(dh_in),
+        _abi.check(lib.cetra_net_project_bwd(s, _ptr(bufs["h"][N_LAYERS]), _ptr(bufs["ge"]), B * L,
+                                             _ptr(self.view("P")), self.E, _ptr(dh_in),
                                              _ptr(self.view("P", self.grad)), _ptr(self.view("p", self.grad))))
         dx = None
         for l in reversed(range(N_LAYERS)):
@@ -409,30 +361,6 @@ def windows_to_periods(periods, win: Windows, sel, stream=None):
     _abi.check(_lib().cetra_windows_to_periods(_stream(stream), _ptr(periods), K, _ptr(win.device()["edges"]), win.n,
                                                _ptr(sel), int(sel.shape[0]), _ptr(subset), _ptr(n)))
     return subset, n
-
-
-def pool_fwd(a, win: Windows, tau_lo: int, stream=None):
-    """Window features f [B][W][2E+1] and argmax lags [B][W][E] of a
-    (standardised) lag correlation a [B][E][n_tau] whose first lag is tau_lo."""
-    import torch
-    B, E, n_tau = (int(v) for v in a.shape)
-    f = torch.empty((B, win.n, 2 * E + 1), dtype=torch.float32, device="cuda")
-    arg = torch.empty((B, win.n, E), dtype=torch.int32, device="cuda")
-    d = win.device()
-    _abi.check(_lib().cetra_net_pool_fwd(_stream(stream), _ptr(a.contiguous()), B, E, n_tau, int(tau_lo), _ptr(d["lo"]),
-                                         _ptr(d["hi"]), _ptr(d["q"]), win.n, _ptr(f), _ptr(arg)))
-    return f, arg
-
-
-def pool_bwd(gf, arg, win: Windows, E: int, n_tau: int, tau_lo: int, stream=None):
-    """Gradient [B][E][n_tau] of the window features' loss w.r.t. a."""
-    import torch
-    B = int(gf.shape[0])
-    ga = torch.zeros((B, E, n_tau), dtype=torch.float32, device="cuda")
-    d = win.device()
-    _abi.check(_lib().cetra_net_pool_bwd(_stream(stream), _ptr(gf.contiguous()), _ptr(arg), B, int(E), int(n_tau),
-                                         int(tau_lo), _ptr(d["lo"]), _ptr(d["hi"]), win.n, _ptr(ga)))
-    return ga
 
 
 def foldpool_fwd(e, win: Windows, n_trial: int, stream=None):

@@ -35,13 +35,23 @@ def make_pipeline(cfg=None):
                     cfg or LearnedConfig())
 
 
+LABEL_BAND = 0.02  # relative half-width of the labelled period band
+
+
 def labels_for(pipe, injections) -> np.ndarray:
+    """Multi-hot window labels: every window overlapping [P (1 - band),
+    P (1 + band)] for the injected period P, its half and its double (the
+    aliases a fold may prefer).  The band covers the period scatter of
+    planets with only a few transits in the span."""
     y = np.zeros(pipe.windows.n, dtype=np.float32)
     for inj in injections:
         for mult in (1.0, 0.5, 2.0):
-            w = pipe.window_of(inj.period * mult)
-            if w >= 0:
-                y[w] = 1.0
+            P = inj.period * mult
+            lo = np.searchsorted(pipe.windows.edges, P * (1 - LABEL_BAND), side="right") - 1
+            hi = np.searchsorted(pipe.windows.edges, P * (1 + LABEL_BAND), side="right") - 1
+            lo, hi = max(lo, 0), min(hi, pipe.windows.n - 1)
+            if lo <= hi:
+                y[lo:hi + 1] = 1.0
     return y
 
 
@@ -77,7 +87,6 @@ def main(argv=None) -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--pos-weight", type=float, default=32.0)
     ap.add_argument("--seed", type=int, default=20250401)
-    ap.add_argument("--pool", default="fold", choices=["fold", "lag"])
     ap.add_argument("--n-trial", type=int, default=4)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
@@ -92,10 +101,9 @@ def main(argv=None) -> int:
     log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
         f"lags {pipe.windows.tau_lo}..{pipe.windows.tau_lo + pipe.windows.n_tau - 1}")
     x, y, _ = build_dataset(pipe, a.n_train, a.seed)
-    net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, pool=a.pool,
-                      n_trial=a.n_trial)
+    net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, n_trial=a.n_trial)
     losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)
-    meta = dict(n_event=net.E, hidden=net.H, pool=net.pool, n_trial=net.S, n_train=a.n_train, epochs=a.epochs,
+    meta = dict(n_event=net.E, hidden=net.H, pool="fold", n_trial=net.S, n_train=a.n_train, epochs=a.epochs,
                 batch=a.batch, lr=a.lr,
                 pos_weight=a.pos_weight, seed=a.seed, losses=losses, n_bins=pipe.cfg.n_bins,
                 n_windows=pipe.cfg.n_windows, p_lo=pipe.cfg.p_lo, p_hi=pipe.cfg.p_hi)

@@ -114,74 +114,45 @@ def test_conv_backward(torch, pn, cin, L, B):
         assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-5 * scale)
 
 
-def net_case(seed=0, B=2, L=700, n_win=48, single_lag=True, fold=False):
-    """Parameters, input, windows and labels.  With single_lag every window
-    is one lag (5, 10, ..., 240), so the window max has no argmax to decide
-    and the backward pass is unique; the multi-lag pooling is tested on its
-    own (test_pool_forward_backward), where the inputs keep maxima apart."""
+def net_case(seed=0, B=2, L=700, n_win=16):
+    """Parameters (FP32-exact), a bfloat16-exact input, log windows over
+    0.1-5 d on 0.02-d bins and one positive window per example."""
     rng = np.random.default_rng(seed)
-    p = onet.init_params(c_in=16, width=64, n_layers=5, n_event=8, hidden=64, seed=seed, fold=fold)
+    p = onet.init_params(c_in=16, width=64, n_layers=5, n_event=8, hidden=64, seed=seed)
     for k in p:
         if k.startswith("b") or k in ("p", "u"):
             p[k] = rng.normal(0, 0.05, p[k].shape)
     for k in p:  # FP32-exact parameters (the device masters are FP32)
         p[k] = p[k].astype(np.float32).astype(np.float64)
     x = bf16_exact(rng, (B, 16, L), 0.0, 1.0)
-    if single_lag:
-        lo = hi = np.arange(1, n_win + 1, dtype=np.int64) * 5
-        q = (np.arange(n_win) + 0.5) / n_win
-        edges = np.arange(n_win + 1, dtype=np.float64) * 0.1 + 0.05
-    else:
-        lo, hi, q, edges = onet.windows_for(n_win, 0.1, 5.0, 0.02)
+    q, edges = onet.windows_for(n_win, 0.1, 5.0)
     q = q.astype(np.float32).astype(np.float64)
     y = np.zeros((B, n_win))
     for b in range(B):
         y[b, rng.integers(n_win)] = 1.0
-    return p, x, (lo, hi, q, edges), y
+    return p, x, q, edges, y
 
 
-@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("seed", [0, 4])
 def test_network_forward_backward(torch, pn, seed):
-    p, x, (lo, hi, q, edges), y = net_case(seed)
-    z_ref, cache = onet.forward(p, x, lo, hi, q, keep=True, bf16_trunk=True)
+    """The whole network (trunk, projection, fold pooling at 4 trial periods
+    per window, head, loss) forward and backward against the oracle."""
+    p, x, q, edges, y = net_case(seed)
+    win = pn.Windows.log_spaced(len(q), 0.1, 5.0, 0.02)
+    assert np.allclose(win.edges, edges, rtol=1e-15) and np.allclose(win.q, q)
+    trials = win.trials(4)
+    assert np.allclose(trials, onet.fold_trials(edges, 4, 0.02), rtol=1e-15, atol=0)
+    z_ref, cache = onet.forward(p, x, q, trials, keep=True, bf16_trunk=True)
+    # the backward follows each window's winning phase: the case is usable
+    # only if every winner beats the runner-up by far more than the FP32
+    # summation error of the device, so both sides pick the same phase
+    g1, _, g2 = onet.fold_pool(cache["e"], trials, runner_up=True)
+    assert np.all(g1 - g2 > 1e-4 * np.maximum(np.abs(g1), 1.0)), "test case has near-tied fold maxima"
     loss_ref, gz = onet.bce_loss(z_ref, y, pos_weight=4.0)
-    g_ref = onet.backward(p, cache, gz, lo, hi)
-
-    win = pn.Windows(lo.astype(np.int32), hi.astype(np.int32), q.astype(np.float32), edges, 0.02)
-    model = pn.ProposalNet(n_event=8, hidden=64, pool="lag")
+    g_ref = onet.backward(p, cache, gz)
+    model = pn.ProposalNet(n_event=8, hidden=64, n_trial=4)
     model.load_arrays(p)
-    print(f"[net] forward/backward seed={seed} B={x.shape[0]} L={x.shape[2]} W={len(lo)}", flush=True)
-    z = model.forward(to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16), win)
-    loss, dx = model.backward(to_dev(torch, y, torch.float32), pos_weight=4.0, want_dx=True)
-    torch.cuda.synchronize()
-    zg = z.cpu().numpy()
-    assert np.all(np.abs(zg - z_ref) <= 3e-3 * max(1.0, np.abs(z_ref).max()))
-    assert abs(float(loss.item()) - loss_ref) <= 3e-3 * abs(loss_ref)
-    g = model.grad_arrays()
-    for name, ref in g_ref.items():
-        if name == "x":
-            continue
-        assert rel_norm(g[name], ref) < 3e-3, (name, rel_norm(g[name], ref))
-    gx = dx.cpu().numpy().transpose(0, 2, 1).astype(np.float64)
-    mag = onet.conv1d_backward(x, np.abs(onet.bf16(p["W0"])), np.abs(cache["G0"]))[0]
-    assert np.all(np.abs(gx - g_ref["x"]) <= 2.0 ** -6 * mag + 1e-12), \
-        float(np.max(np.abs(gx - g_ref["x"]) / (mag + 1e-30)))
-
-
-@pytest.mark.parametrize("seed", [0, 1])
-def test_network_fold_pool_forward_backward(torch, pn, seed):
-    """The fold-pooling network (linear projection, coarse fold at 4 trial
-    periods per log window) end to end against the oracle."""
-    p, x, (lo, hi, q, edges), y = net_case(seed, single_lag=False, fold=True)
-    win = pn.Windows.log_spaced(len(lo), 0.1, 5.0, 0.02)
-    trials = onet.fold_trials(win.edges, 4, 0.02)
-    assert np.allclose(win.trials(4), trials, rtol=1e-15, atol=0)
-    z_ref, cache = onet.forward(p, x, lo, hi, q, keep=True, bf16_trunk=True, trials=win.trials(4))
-    loss_ref, gz = onet.bce_loss(z_ref, y, pos_weight=4.0)
-    g_ref = onet.backward(p, cache, gz, lo, hi)
-    model = pn.ProposalNet(n_event=8, hidden=64, pool="fold", n_trial=4)
-    model.load_arrays(p)
-    print(f"[net] fold-pool forward/backward seed={seed}", flush=True)
+    print(f"[net] forward/backward seed={seed} B={x.shape[0]} L={x.shape[2]} W={len(q)}", flush=True)
     z = model.forward(to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16), win)
     loss, dx = model.backward(to_dev(torch, y, torch.float32), pos_weight=4.0, want_dx=True)
     torch.cuda.synchronize()
@@ -194,7 +165,8 @@ def test_network_fold_pool_forward_backward(torch, pn, seed):
         assert rel_norm(g[name], ref) < 3e-3, (name, rel_norm(g[name], ref))
     gx = dx.cpu().numpy().transpose(0, 2, 1).astype(np.float64)
     mag = onet.conv1d_backward(x, np.abs(onet.bf16(p["W0"])), np.abs(cache["G0"]))[0]
-    assert np.all(np.abs(gx - g_ref["x"]) <= 2.0 ** -6 * mag + 1e-12)
+    assert np.all(np.abs(gx - g_ref["x"]) <= 2.0 ** -6 * mag + 1e-12), \
+        float(np.max(np.abs(gx - g_ref["x"]) / (mag + 1e-30)))
 
 
 def test_fold_pool_kernels(torch, pn):
@@ -209,7 +181,7 @@ def test_fold_pool_kernels(torch, pn):
                        [149.5, 151.0, 152.5], [0.2, 0.6, 0.9]])
     q = np.linspace(0.05, 0.95, W).astype(np.float32)
     g_ref, arg_ref = onet.fold_pool(e, trials)
-    win = pn.Windows(np.zeros(W, np.int32), np.zeros(W, np.int32), q, np.arange(W + 1, dtype=np.float64), 1.0)
+    win = pn.Windows(q, np.arange(W + 1, dtype=np.float64) + 1.0, 1.0)
     win._trials3 = torch.as_tensor(trials, device="cuda")
     model_e = torch.as_tensor(e.transpose(0, 2, 1).copy(), dtype=torch.float32, device="cuda")
     f, arg = pn.foldpool_fwd(model_e, win, S)
@@ -226,50 +198,6 @@ def test_fold_pool_kernels(torch, pn):
     ge = pn.foldpool_bwd(torch.as_tensor(gg, device="cuda"), torch.as_tensor(arg, device="cuda"), win, E, L, S)
     ref = onet.fold_pool_backward(gg[:, :, :E].astype(np.float64), arg_ref, trials, L)
     assert np.allclose(ge.cpu().numpy().transpose(0, 2, 1), ref, rtol=1e-5, atol=1e-6)
-
-
-@pytest.mark.parametrize("seed", [2])
-def test_network_forward_log_windows(torch, pn, seed):
-    """Forward pass with the log-spaced multi-lag windows: the logits are
-    continuous in the window maxima even where an argmax is a near-tie."""
-    p, x, (lo, hi, q, edges), y = net_case(seed, single_lag=False)
-    z_ref = onet.forward(p, x, lo, hi, q, bf16_trunk=True)
-    win = pn.Windows.log_spaced(len(lo), 0.1, 5.0, 0.02)
-    assert np.array_equal(win.lo, lo) and np.array_equal(win.hi, hi)
-    model = pn.ProposalNet(n_event=8, hidden=64, pool="lag")
-    model.load_arrays(p)
-    z = model.forward(to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16), win).cpu().numpy()
-    assert np.all(np.abs(z - z_ref) <= 3e-3 * max(1.0, np.abs(z_ref).max()))
-
-
-def test_pool_forward_backward(torch, pn):
-    """Window max / mean / position and their backward on values whose
-    maxima are well separated (a permutation of a grid), against a direct
-    loop; windows overlap and one is clipped by the lag range."""
-    rng = np.random.default_rng(13)
-    B, E, n_tau, tau_lo = 2, 3, 40, 4
-    a = rng.permutation(B * E * n_tau).reshape(B, E, n_tau).astype(np.float64) / 7.0
-    lo = np.array([4, 6, 6, 20, 43, 40], dtype=np.int32)
-    hi = np.array([5, 12, 6, 30, 43, 50], dtype=np.int32)  # last clipped to lag 43
-    q = np.linspace(0.1, 0.9, len(lo)).astype(np.float32)
-    win = pn.Windows(lo, hi, q, np.arange(len(lo) + 1, dtype=np.float64), 1.0)
-    f, arg = pn.pool_fwd(torch.as_tensor(a, dtype=torch.float32, device="cuda"), win, tau_lo)
-    gf = rng.normal(size=(B, len(lo), 2 * E + 1)).astype(np.float32)
-    ga = pn.pool_bwd(torch.as_tensor(gf, device="cuda"), arg, win, E, n_tau, tau_lo)
-    f, arg, ga = f.cpu().numpy(), arg.cpu().numpy(), ga.cpu().numpy()
-    ref_ga = np.zeros_like(a)
-    for b in range(B):
-        for w in range(len(lo)):
-            l0, l1 = max(lo[w] - tau_lo, 0), min(hi[w] - tau_lo, n_tau - 1)
-            for c in range(E):
-                seg = a[b, c, l0:l1 + 1]
-                assert arg[b, w, c] == l0 + int(np.argmax(seg))
-                assert f[b, w, c] == np.float32(seg.max())
-                assert abs(f[b, w, E + c] - seg.mean()) <= 1e-6 * abs(seg.mean()) + 1e-6
-                ref_ga[b, c, l0 + int(np.argmax(seg))] += gf[b, w, c]
-                ref_ga[b, c, l0:l1 + 1] += gf[b, w, E + c] / (l1 - l0 + 1)
-            assert f[b, w, 2 * E] == q[w]
-    assert np.allclose(ga, ref_ga, rtol=1e-5, atol=1e-6)
 
 
 def test_adam_step(torch, pn):

@@ -10,10 +10,9 @@ from paper_2503_20875_amd.proposal import Windows
 def test_windows_match_oracle_definition():
     for n, lo_p, hi_p, bin_days in ((512, 1.0, 100.0, 111.1 / 8192), (48, 0.1, 5.0, 0.02), (7, 0.5, 45.0, 0.3)):
         w = Windows.log_spaced(n, lo_p, hi_p, bin_days)
-        lo, hi, q, edges = onet.windows_for(n, lo_p, hi_p, bin_days)
-        assert np.array_equal(w.lo, lo) and np.array_equal(w.hi, hi)
+        q, edges = onet.windows_for(n, lo_p, hi_p)
         assert np.allclose(w.q, q) and np.allclose(w.edges, edges, rtol=1e-15)
-        assert w.tau_lo == lo.min() and w.n_tau == hi.max() - lo.min() + 1
+        assert np.allclose(w.trials(4), onet.fold_trials(edges, 4, bin_days), rtol=1e-15)
 
 
 def test_labels_one_window_per_period():
