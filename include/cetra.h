@@ -102,7 +102,10 @@ typedef struct cetra_tuning {
     int32_t fold_period_block;  /* trial periods accumulated per lane: 4, 8 or 16     */
     int32_t fold_wgs_per_cu;    /* resident workgroups per compute unit, 1..32       */
     int32_t fold_units_per_wg;  /* target work units per workgroup, 1..64            */
-    int32_t fold_lds;           /* 1: stage each transit step's window in LDS       */
+    int32_t fold_variant;       /* 0: register fold, lane epochs 64 apart;
+                                   1: each transit step's window staged in LDS;
+                                   2: register fold, adjacent lane epochs and
+                                      16-byte loads                                   */
     int32_t reserved[4];
 } cetra_tuning;
 

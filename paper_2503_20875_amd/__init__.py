@@ -59,12 +59,12 @@ def get_tuning() -> dict:
     t = Tuning()
     _abi.check(_abi.load().cetra_get_tuning(ctypes.byref(t)))
     return dict(fold_period_block=t.fold_period_block, fold_wgs_per_cu=t.fold_wgs_per_cu,
-                fold_units_per_wg=t.fold_units_per_wg, fold_lds=t.fold_lds)
+                fold_units_per_wg=t.fold_units_per_wg, fold_variant=t.fold_variant)
 
 
 def set_tuning(fold_period_block: int = 4, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
-               fold_lds: int = 0) -> None:
-    t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_lds)
+               fold_variant: int = 0) -> None:
+    t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_variant)
     _abi.check(_abi.load().cetra_set_tuning(ctypes.byref(t)))
 
 

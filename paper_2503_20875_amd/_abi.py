@@ -65,7 +65,7 @@ class Tuning(ctypes.Structure):
         ("fold_period_block", ctypes.c_int32),
         ("fold_wgs_per_cu", ctypes.c_int32),
         ("fold_units_per_wg", ctypes.c_int32),
-        ("fold_lds", ctypes.c_int32),
+        ("fold_variant", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 4),
     ]
 

@@ -2,8 +2,9 @@
 
 Times the fold (``cetra_periodic_search``) on the caller's own grid,
 fold-ready array and periods under each candidate tuning -- period block,
-resident workgroups per compute unit, units per workgroup and the
-register/LDS variant -- and keeps the fastest with ``cetra_set_tuning``.
+resident workgroups per compute unit, units per workgroup and the fold
+variant (register, LDS-staged, register with 16-byte loads) -- and keeps
+the fastest with ``cetra_set_tuning``.
 Results do not depend on the tuning (the parity tests check that every
 variant returns identical records); only the time does.
 """
@@ -15,7 +16,7 @@ import itertools
 from . import get_tuning, periodic_search, periodic_workspace, set_tuning
 
 DEFAULT_CANDIDATES = tuple(
-    (b, w, u, lds) for b, w, u, lds in itertools.product((4, 8), (8,), (4, 16), (0, 1)))
+    (b, w, u, v) for b, w, u, v in itertools.product((4, 8), (8,), (4, 16), (0, 1, 2)))
 
 
 def tune_fold(grid, fold, periods, candidates=DEFAULT_CANDIDATES, repeats: int = 2, apply: bool = True):
@@ -44,7 +45,7 @@ def tune_fold(grid, fold, periods, candidates=DEFAULT_CANDIDATES, repeats: int =
     finally:
         set_tuning(**before)
     best = min(times, key=times.get)
-    cfg = dict(fold_period_block=best[0], fold_wgs_per_cu=best[1], fold_units_per_wg=best[2], fold_lds=best[3])
+    cfg = dict(fold_period_block=best[0], fold_wgs_per_cu=best[1], fold_units_per_wg=best[2], fold_variant=best[3])
     if apply:
         set_tuning(**cfg)
     return cfg, times

@@ -101,11 +101,13 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 }
 
 // Persistent grid over units (period block of B periods, duration j, epoch
-// chunk), ordered block-fastest; each unit is one dev::fold_unit (kLds:
-// dev::fold_unit_lds).
-template <int B, bool kLds>
+// chunk), ordered block-fastest; each unit is one dev::fold_unit (variant 0:
+// lane epochs 64 apart; 2: adjacent lane epochs, 16-byte loads) or
+// dev::fold_unit_lds (variant 1).
+template <int B, int kVariant>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
                                                         int32_t I, int32_t n_chunks, int64_t n_units) {
+    constexpr bool kLds = kVariant == 1;
     __shared__ float2 s_buf[kLds ? 2 * cetra::dev::kFoldLdsCap : 1];
     const int64_t n_pblk = (n_eval + B - 1) / B;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
         if (kLds)
             cetra::dev::fold_unit_lds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0, s_buf);
         else
-            cetra::dev::fold_unit<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
+            cetra::dev::fold_unit<B, kVariant == 2>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
     }
 }
 
@@ -272,12 +274,17 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
     const int64_t n_pblk = ceil_div(n_eval, B);
     // persistent grid: no more workgroups than can be resident at once
     const void *kern = nullptr;
-    if (tu.fold_lds)
-        kern = B == 4 ? (const void *)fold_kernel<4, true> : B == 16 ? (const void *)fold_kernel<16, true>
-                                                                    : (const void *)fold_kernel<8, true>;
-    else
-        kern = B == 4 ? (const void *)fold_kernel<4, false> : B == 16 ? (const void *)fold_kernel<16, false>
-                                                                     : (const void *)fold_kernel<8, false>;
+    switch (tu.fold_variant * 3 + (B == 4 ? 0 : B == 8 ? 1 : 2)) {
+        case 0: kern = (const void *)fold_kernel<4, 0>; break;
+        case 1: kern = (const void *)fold_kernel<8, 0>; break;
+        case 2: kern = (const void *)fold_kernel<16, 0>; break;
+        case 3: kern = (const void *)fold_kernel<4, 1>; break;
+        case 4: kern = (const void *)fold_kernel<8, 1>; break;
+        case 5: kern = (const void *)fold_kernel<16, 1>; break;
+        case 6: kern = (const void *)fold_kernel<4, 2>; break;
+        case 7: kern = (const void *)fold_kernel<8, 2>; break;
+        default: kern = (const void *)fold_kernel<16, 2>; break;
+    }
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0) != hipSuccess || occ <= 0) occ = 1;
     const int64_t wgs = (int64_t)device_cu_count() * std::min(tu.fold_wgs_per_cu, occ);

@@ -262,16 +262,28 @@ __device__ __forceinline__ uint64_t fold_key(float lr, uint32_t flat) {
     return ((uint64_t)__float_as_uint(lr) << 32) | (uint64_t)(0xFFFFFFFFu - flat);
 }
 
+// 16 bytes (two float pairs) at a byte offset: four dword loads that the
+// compiler merges into one 16-byte load.
+__device__ __forceinline__ float4 load_quad(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+    const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+    const float y = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off + 4, 0, 0));
+    const float z = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off + 8, 0, 0));
+    const float w = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off + 12, 0, 0));
+    return make_float4(x, y, z, w);
+}
+
 // One fold unit: B periods (R[b], ipb[b]; ipb = 0 means "skip"), duration row
 // `row` (index j), epochs [e_lo, e_hi).  Each wave owns 128 consecutive
-// epochs, lane l the epochs e_wave + l and e_wave + 64 + l (so a wave's loads
-// stay contiguous and a lane's two loads are never adjacent).  Per transit
-// step and period: two 8-byte buffer loads and four FP32 adds; offsets and the
-// loop exit are wave-uniform (scalar registers).  FP32 chunks of 32 transits
+// epochs.  kPair = false: lane l takes epochs e_wave + l and e_wave + 64 + l
+// (two 8-byte loads per period and step, each wave load 512 contiguous
+// bytes); kPair = true: lane l takes the adjacent epochs e_wave + 2l and
+// e_wave + 2l + 1 (one 16-byte load, the wave load 1 KB contiguous: half the
+// load instructions).  Per transit step and period: four FP32 adds; offsets
+// and the loop exit are wave-uniform (scalar registers).  FP32 chunks of 32 transits
 // fold into FP32 totals (error below (31 + n/32) u of the absolute sum); the
 // sums only rank candidates -- the epilogue recomputes the winner in FP64.
 // The per-period maxima go to keys[b] by 64-bit atomicMax.
-template <int B>
+template <int B, bool kPair = false>
 __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
                                           const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys) {
     const int lane = threadIdx.x & 63;
@@ -284,7 +296,8 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
     for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
         const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
         if (e_wave >= e_hi) break;
-        const int32_t e = e_wave + lane;  // epochs e and e + 64
+        const int32_t e = e_wave + (kPair ? 2 * lane : lane);  // epochs e and e + kStride
+        constexpr int32_t kStride = kPair ? 1 : 64;
         const uint32_t e_bytes = (uint32_t)e * 8u;
         float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
         uint64_t acc[B];
@@ -319,8 +332,14 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     const uint32_t off = e_bytes + o[b] * 8u;
-                    v0[b] = load_pair(rsrc, off, 0);
-                    v1[b] = load_pair(rsrc, off, 64 * 8);
+                    if (kPair) {
+                        const float4 v = load_quad(rsrc, off);
+                        v0[b] = make_float2(v.x, v.y);
+                        v1[b] = make_float2(v.z, v.w);
+                    } else {
+                        v0[b] = load_pair(rsrc, off, 0);
+                        v1[b] = load_pair(rsrc, off, 64 * 8);
+                    }
                 }
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
@@ -343,7 +362,7 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
         for (int b = 0; b < B; ++b) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int32_t eh = e + 64 * h;
+                const int32_t eh = e + kStride * h;
                 const float A = h ? ta1[b] : ta0[b];
                 const float S = h ? ts1[b] : ts0[b];
                 if (eh < ipb[b] && eh < e_hi && S > 0.0f) {

@@ -3,8 +3,8 @@
 Synthetic light curves of the learned-proposal workload (80 000 points at
 2-min cadence, half with one injected planet) go through the library's own
 linear search on the GPU; the downsampled single-event statistics are the
-inputs and the windows of the injected period (and of its half and double,
-the aliases a fold can prefer) are the labels.  Training runs the library's
+inputs and the windows within 2% of the injected period (and of its half
+and double, the aliases a fold can prefer) are the labels.  Training runs the library's
 forward, backward and Adam kernels.  The weights are written as a NumPy
 archive together with the settings they were trained with.
 
@@ -99,7 +99,7 @@ def main(argv=None) -> int:
     from .proposal import ProposalNet
     pipe = make_pipeline()
     log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
-        f"lags {pipe.windows.tau_lo}..{pipe.windows.tau_lo + pipe.windows.n_tau - 1}")
+        f"bin {pipe.windows.bin_days:.5f} d")
     x, y, _ = build_dataset(pipe, a.n_train, a.seed)
     net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, n_trial=a.n_trial)
     losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)

@@ -281,7 +281,7 @@ def test_high_cadence_full_size_sampled(cm, ora):
     assert b["lr"] == pytest.approx(alt[0], rel=TOL)
 
 
-@pytest.mark.parametrize("cfg", [(8, 8, 4, 1), (4, 8, 4, 1), (8, 8, 4, 0), (4, 8, 16, 0)])
+@pytest.mark.parametrize("cfg", [(8, 8, 4, 1), (4, 8, 4, 1), (8, 8, 4, 0), (4, 8, 16, 0), (4, 8, 4, 2), (8, 8, 4, 2)])
 def test_fold_variants_identical(cm, ora, tiny_pair, tiny_wl, cfg):
     """Register and LDS fold variants, period blocks 4 and 8: the same
     per-period records, bit for bit (the FP32 ranking sums are accumulated in
