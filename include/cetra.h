@@ -96,7 +96,7 @@ typedef struct cetra_best_record {
 } cetra_best_record;
 
 /* Launch tuning of the periodic search, process-wide for this library
- * instance (an autotuner sets it; the defaults are 4, 8, 4, 0).  Results do not
+ * instance (an autotuner sets it; the defaults are 8, 8, 4, 2).  Results do not
  * depend on it except through near-ties of the argmax. */
 typedef struct cetra_tuning {
     int32_t fold_period_block;  /* trial periods accumulated per lane: 4, 8 or 16     */

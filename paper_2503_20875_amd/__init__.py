@@ -62,8 +62,8 @@ def get_tuning() -> dict:
                 fold_units_per_wg=t.fold_units_per_wg, fold_variant=t.fold_variant)
 
 
-def set_tuning(fold_period_block: int = 4, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
-               fold_variant: int = 0) -> None:
+def set_tuning(fold_period_block: int = 8, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
+               fold_variant: int = 2) -> None:
     t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_variant)
     _abi.check(_abi.load().cetra_set_tuning(ctypes.byref(t)))
 

@@ -46,7 +46,7 @@ int check_launch(const char *what) {
 }
 
 static std::mutex g_tuning_mu;
-static cetra_tuning g_tuning = {4, 8, 4, 0, {0, 0, 0, 0}};
+static cetra_tuning g_tuning = {8, 8, 4, 2, {0, 0, 0, 0}};
 
 cetra_tuning current_tuning() {
     std::lock_guard<std::mutex> lock(g_tuning_mu);
@@ -93,7 +93,7 @@ extern "C" int cetra_get_tuning(cetra_tuning *out) {
 
 extern "C" int cetra_set_tuning(const cetra_tuning *in) {
     clear_error();
-    cetra_tuning t = {4, 8, 4, 0, {0, 0, 0, 0}};
+    cetra_tuning t = {8, 8, 4, 2, {0, 0, 0, 0}};
     if (in) {
         CETRA_REQUIRE(in->fold_period_block == 4 || in->fold_period_block == 8 || in->fold_period_block == 16,
                       "set_tuning: fold_period_block must be 4, 8 or 16");

@@ -89,14 +89,16 @@ def test_calls_reject_bad_arguments_without_a_gpu(lib):
 def test_tuning_roundtrip_and_validation(lib):
     import paper_2503_20875_amd as cm
     cm.reset_tuning()
-    assert cm.get_tuning() == dict(fold_period_block=4, fold_wgs_per_cu=8, fold_units_per_wg=4, fold_variant=0)
-    cm.set_tuning(8, 6, 2, 1)
-    assert cm.get_tuning() == dict(fold_period_block=8, fold_wgs_per_cu=6, fold_units_per_wg=2, fold_variant=1)
+    assert cm.get_tuning() == dict(fold_period_block=8, fold_wgs_per_cu=8, fold_units_per_wg=4, fold_variant=2)
+    cm.set_tuning(4, 6, 2, 1)
+    assert cm.get_tuning() == dict(fold_period_block=4, fold_wgs_per_cu=6, fold_units_per_wg=2, fold_variant=1)
     with pytest.raises(cm.CetraError, match="fold_period_block"):
         cm.set_tuning(5, 6, 2)
-    assert cm.get_tuning()["fold_period_block"] == 8  # unchanged after a rejected call
+    with pytest.raises(cm.CetraError, match="fold_variant"):
+        cm.set_tuning(4, 6, 2, 3)
+    assert cm.get_tuning()["fold_period_block"] == 4  # unchanged after a rejected call
     cm.reset_tuning()
-    assert cm.get_tuning()["fold_period_block"] == 4
+    assert cm.get_tuning()["fold_period_block"] == 8
 
 
 def _survey_batch(cm, n, seed, n_min, n_max):
