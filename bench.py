@@ -204,6 +204,9 @@ def main():
                          "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
                          "times (calibrates the HBM byte counters)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--fold-tuning", default="",
+                    help="period block, workgroups per CU, units per workgroup, variant (e.g. 4,8,4,0); "
+                         "default: the library's")
     ap.add_argument("--learned-curves", type=int, default=64,
                     help="held-out curves for the learned-versus-plain comparison (0: skip)")
     args = ap.parse_args()
@@ -228,6 +231,8 @@ def main():
         print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                           "launches": args.steps}), flush=True)
         return
+    if args.fold_tuning:
+        cm.set_tuning(*(int(v) for v in args.fold_tuning.split(",")))
     wl = W.WORKLOADS[args.workload]()
     dev = "cuda"
     t_d = torch.as_tensor(wl.t, device=dev)
@@ -276,7 +281,7 @@ def main():
             cm.periodic_search(grid, fold, per_d, work=work, out=per)
         torch.cuda.synchronize()
         work_alg = algorithmic_work(wl, grid)
-        print(json.dumps({"mode": "fold", "launches": args.steps, "workload": args.workload,
+        print(json.dumps({"mode": "fold", "launches": args.steps, "workload": args.workload, "tuning": cm.get_tuning(),
                           "fold_source_sha256_16": fold_source_hash(),
                           "algorithmic_bytes_per_launch": work_alg["fold_bytes"]}), flush=True)
         return
@@ -337,6 +342,7 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": work_alg["fold_bytes"],
             "avg_launch_ms": fold_s * 1e3,
+            "tuning": cm.get_tuning(),
         },
         "roofline_linear": {
             "kernel": "linear_kernel (linear search, all durations)",
