@@ -95,6 +95,52 @@ def cpu_baseline(wl, stride: int = 10):
                 seconds_measured=round(t_lin + t_fold, 2))
 
 
+def batched_block(n_curves: int = 32, seed: int = 20250328) -> dict:
+    """Batched search over survey curves of uneven length (5 000-120 000
+    points at 2-min cadence, 16 durations, per-curve duty-cycle period grids
+    over 0.5-min(40, T/2) d): one eager pass, then the same batch captured in
+    a HIP graph and replayed, both timed with HIP events; throughput is
+    sum over curves of N_obs x K_c per second."""
+    import torch
+    import paper_2503_20875_amd as cm
+    from synthlc import workloads as W
+    curves = W.batched_survey(n_curves, seed=seed)
+    grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations, 0.0, c.n_model) for c in curves]
+    oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
+    po = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
+    dev = "cuda"
+    t = torch.as_tensor(np.concatenate([c.t for c in curves]), device=dev)
+    f = torch.as_tensor(np.concatenate([c.f for c in curves]), device=dev)
+    s_ = torch.as_tensor(np.concatenate([c.sigma for c in curves]), device=dev)
+    p = torch.as_tensor(np.concatenate([c.periods for c in curves]), device=dev)
+    model = cm.template_resample(torch.as_tensor(curves[0].dense, device=dev), curves[0].n_model)
+    plan = cm.batch_plan(grids, oo, po)
+    work = cm.batch_workspace(plan)
+    out = cm.batch_search(plan, t, f, s_, model, p, work=work)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    cm.batch_search(plan, t, f, s_, model, p, work=work, out=out)
+    e[1].record()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            cm.batch_search(plan, t, f, s_, model, p, work=work, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    e[2].record()
+    g.replay()
+    e[3].record()
+    torch.cuda.synchronize()
+    work_units = float(sum(c.n_obs * len(c.periods) for c in curves))
+    ms_eager, ms_graph = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])
+    return {"workload": f"{n_curves} survey curves, {int(oo[-1])} observations, {int(po[-1])} trial periods in all",
+            "n_launches": plan.info["n_launches"], "ms_eager": ms_eager, "ms_graph_replay": ms_graph,
+            "value": work_units / (min(ms_eager, ms_graph) / 1e3), "unit": "LC points x trial periods / s",
+            "status": int(out["status"].item())}
+
+
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
@@ -204,6 +250,8 @@ def main():
                          "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
                          "times (calibrates the HBM byte counters)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--batch-curves", type=int, default=32,
+                    help="survey curves of the batched-search measurement (0: skip)")
     ap.add_argument("--fold-tuning", default="",
                     help="period block, workgroups per CU, units per workgroup, variant (e.g. 4,8,4,0); "
                          "default: the library's")
@@ -361,6 +409,8 @@ def main():
     }
     if args.workload == "high_cadence":
         out["roofline_net"] = net_block()
+        if args.batch_curves > 0:
+            out["batched"] = batched_block(args.batch_curves)
     if args.learned_curves > 0 and args.workload == "high_cadence":
         out["learned"] = learned_block(args.learned_curves)
     if not args.no_cpu_baseline:

@@ -168,12 +168,14 @@ __global__ void __launch_bounds__(kT) conv_bwd_x_kernel(const __bf16 *__restrict
 
 // ------------------------------------------------------ conv backward-w
 // dW[co][k] += sum over 256 positions of one example of G[t][co] X[t+tap-4][ci]
-// (k = tap * cin + ci).  Workgroup: (position chunk of 256, example, block of
-// 64 reduction columns k); the chunk of G and of X (with a 4-position halo)
-// is staged in LDS transposed to position-fastest order so every MFMA
-// fragment is one 16-byte LDS read.  Partial results are added to dW (FP32
-// atomics); db[co] gets the column sums of G.
+// (k = tap * cin + ci).  Workgroup: (8 chunks of 256 positions, example,
+// block of 64 reduction columns k); each chunk of G and of X (with a
+// 4-position halo) is staged in LDS transposed to position-fastest order so
+// every MFMA fragment is one 16-byte LDS read.  The workgroup's partial sums
+// over its 2048 positions are added to dW (FP32 atomics); db[co] gets the
+// column sums of G.
 constexpr int kPosChunk = 256;
+constexpr int kChunksPerWg = 8;
 __global__ void __launch_bounds__(kT) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
                                                         int32_t cin, int32_t L, int32_t k32,
                                                         float *__restrict__ dw, float *__restrict__ db) {
@@ -181,50 +183,52 @@ __global__ void __launch_bounds__(kT) conv_bwd_w_kernel(const __bf16 *__restrict
     __shared__ __attribute__((aligned(16))) __bf16 s_x[kWidth][kPosChunk + 16];       // 34 KB (cin <= 64)
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.y;
-    const int32_t p0 = blockIdx.x * kPosChunk;
     const int32_t kb = blockIdx.z * 64;  // this workgroup's 64 reduction columns
     const __bf16 *gb = g + b * (int64_t)L * kWidth;
     const __bf16 *xb = x + b * (int64_t)L * cin;
-    for (int i = threadIdx.x; i < kWidth * kPosChunk; i += kT) {
-        const int p = i / kWidth, co = i % kWidth;
-        s_g[co][p] = (p0 + p < L) ? gb[(int64_t)(p0 + p) * kWidth + co] : (__bf16)0.0f;
-    }
-    for (int i = threadIdx.x; i < cin * (kPosChunk + 16); i += kT) {
-        const int p = i / cin, ci = i % cin;
-        const int32_t src = p0 + p - 4;
-        s_x[ci][p] = (src >= 0 && src < L) ? xb[(int64_t)src * cin + ci] : (__bf16)0.0f;
-    }
-    __syncthreads();
-    if (blockIdx.z == 0 && b >= 0) {
-        // bias gradient: column sums of G over this chunk (wave 0 only)
-        if (wave == 0) {
-            float s = 0.0f;
-            for (int p = 0; p < kPosChunk; ++p) s += (float)s_g[l][p];
-            atomicAdd(&db[l], s);
-        }
-    }
-    // wave w: output rows co in [16 w, 16 w + 16), columns k in [kb, kb + 64) (4 tiles)
+    // wave w: output rows co in [16 w, 16 w + 16), columns k in [kb, kb + 64)
+    // (4 tiles), accumulated over kChunksPerWg position chunks before the
+    // atomics
     f32x4 acc[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bias_acc = 0.0f;
     const int co = 16 * wave + (l % 16);
-    for (int32_t q0 = 0; q0 < kPosChunk; q0 += 32) {
-        const int q = q0 + 8 * (l / 16);
-        const bf16x8 afrag = *reinterpret_cast<const bf16x8 *>(&s_g[co][q]);
+    for (int32_t ch = 0; ch < kChunksPerWg; ++ch) {
+        const int32_t p0 = (blockIdx.x * kChunksPerWg + ch) * kPosChunk;
+        if (p0 >= L) break;  // uniform over the workgroup
+        __syncthreads();     // the previous chunk's reads are done
+        for (int i = threadIdx.x; i < kWidth * kPosChunk; i += kT) {
+            const int p = i / kWidth, c = i % kWidth;
+            s_g[c][p] = (p0 + p < L) ? gb[(int64_t)(p0 + p) * kWidth + c] : (__bf16)0.0f;
+        }
+        for (int i = threadIdx.x; i < cin * (kPosChunk + 16); i += kT) {
+            const int p = i / cin, ci = i % cin;
+            const int32_t src = p0 + p - 4;
+            s_x[ci][p] = (src >= 0 && src < L) ? xb[(int64_t)src * cin + ci] : (__bf16)0.0f;
+        }
+        __syncthreads();
+        if (blockIdx.z == 0 && wave == 0)  // bias gradient: column sums of G
+            for (int p = 0; p < kPosChunk; ++p) bias_acc += (float)s_g[l][p];
+        for (int32_t q0 = 0; q0 < kPosChunk; q0 += 32) {
+            const int q = q0 + 8 * (l / 16);
+            const bf16x8 afrag = *reinterpret_cast<const bf16x8 *>(&s_g[co][q]);
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const int32_t k = kb + 16 * n + (l % 16);
-            const int32_t tap = k / cin, ci = k % cin;
-            bf16x8 bfrag;
-            if (k < kTaps * cin) {
+            for (int n = 0; n < 4; ++n) {
+                const int32_t k = kb + 16 * n + (l % 16);
+                const int32_t tap = k / cin, ci = k % cin;
+                bf16x8 bfrag;
+                if (k < kTaps * cin) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) bfrag[i] = s_x[ci][q + i + tap];
-            } else {
-                bfrag = zero8();
+                    for (int i = 0; i < 8; ++i) bfrag[i] = s_x[ci][q + i + tap];
+                } else {
+                    bfrag = zero8();
+                }
+                acc[n] = mfma16(afrag, bfrag, acc[n]);
             }
-            acc[n] = mfma16(afrag, bfrag, acc[n]);
         }
     }
+    if (blockIdx.z == 0 && wave == 0) atomicAdd(&db[l], bias_acc);
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
 #pragma unroll
@@ -289,7 +293,7 @@ extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, co
     hipLaunchKernelGGL(relu_mask_kernel, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, dy, (const __bf16 *)y, n,
                        (__bf16 *)g_scratch);
     if ((rc = check_launch("conv1d_bwd/mask"))) return rc;
-    hipLaunchKernelGGL(conv_bwd_w_kernel, dim3((unsigned)ceil_div(L, kPosChunk), (unsigned)batch,
+    hipLaunchKernelGGL(conv_bwd_w_kernel, dim3((unsigned)ceil_div(L, kPosChunk * kChunksPerWg), (unsigned)batch,
                                                (unsigned)ceil_div(kTaps * cin, 64)),
                        dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, cin, L, k32, dw, db);
     if ((rc = check_launch("conv1d_bwd/w"))) return rc;

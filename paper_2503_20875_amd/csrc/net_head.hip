@@ -41,32 +41,52 @@ __global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, 
     }
 }
 
-// dh[pos][ci] = sum_c P[c][ci] ge[c]; dP[c][ci] += sum_pos ge[c] h[pos][ci];
-// dp[c] += sum_pos ge[c] (wave-level reductions, one atomic per wave and
-// parameter).
-__global__ void __launch_bounds__(kT) project_bwd_kernel(const __bf16 *__restrict__ h, const float *__restrict__ ge,
-                                                         int64_t n_pos, const float *__restrict__ P, int32_t E,
-                                                         float *__restrict__ dh, float *__restrict__ dP,
-                                                         float *__restrict__ dp) {
+// dh[pos][ci] = sum_c P[c][ci] ge[pos][c] (one lane per position).
+__global__ void __launch_bounds__(kT) project_bwd_dh_kernel(const float *__restrict__ ge, int64_t n_pos,
+                                                            const float *__restrict__ P, int32_t E,
+                                                            float *__restrict__ dh) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = pos < n_pos;
-    const int lane = threadIdx.x & 63;
+    if (pos >= n_pos) return;
     float g[kMaxE];
-    for (int c = 0; c < E; ++c) g[c] = ok ? ge[pos * E + c] : 0.0f;
+    for (int c = 0; c < E; ++c) g[c] = ge[pos * E + c];
     for (int ci = 0; ci < kWidth; ++ci) {
-        const float hv = ok ? (float)h[pos * kWidth + ci] : 0.0f;
         float s = 0.0f;
-        for (int c = 0; c < E; ++c) {
-            s = fmaf(P[c * kWidth + ci], g[c], s);
-            const float r = wave_sum(g[c] * hv);
-            if (lane == 0) atomicAdd(&dP[c * kWidth + ci], r);
+        for (int c = 0; c < E; ++c) s = fmaf(P[c * kWidth + ci], g[c], s);
+        dh[pos * kWidth + ci] = s;
+    }
+}
+
+// dP[c][ci] += sum_pos ge[pos][c] h[pos][ci] and dp[c] += sum_pos ge[pos][c]
+// over a chunk of positions per workgroup: lane t accumulates the (c, ci)
+// pairs t, t + 256, ... in registers and adds them once (one atomic per pair
+// and workgroup).
+constexpr int kProjChunk = 1024;
+__global__ void __launch_bounds__(kT) project_bwd_dp_kernel(const __bf16 *__restrict__ h,
+                                                            const float *__restrict__ ge, int64_t n_pos, int32_t E,
+                                                            float *__restrict__ dP, float *__restrict__ dp) {
+    constexpr int kPairs = kMaxE * kWidth / kT;  // pairs per lane at most (4)
+    const int64_t p0 = (int64_t)blockIdx.x * kProjChunk;
+    const int64_t p1 = min(p0 + kProjChunk, n_pos);
+    const int32_t n_pairs = E * kWidth;
+    float acc[kPairs] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float accb = 0.0f;
+    for (int64_t pos = p0; pos < p1; ++pos) {
+#pragma unroll
+        for (int k = 0; k < kPairs; ++k) {
+            const int32_t pr = threadIdx.x + k * kT;
+            if (pr < n_pairs) {
+                const int32_t c = pr / kWidth, ci = pr % kWidth;
+                acc[k] = fmaf(ge[pos * E + c], (float)h[pos * kWidth + ci], acc[k]);
+            }
         }
-        if (ok) dh[pos * kWidth + ci] = s;
+        if (threadIdx.x < E) accb += ge[pos * E + threadIdx.x];
     }
-    for (int c = 0; c < E; ++c) {
-        const float r = wave_sum(g[c]);
-        if (lane == 0) atomicAdd(&dp[c], r);
+#pragma unroll
+    for (int k = 0; k < kPairs; ++k) {
+        const int32_t pr = threadIdx.x + k * kT;
+        if (pr < n_pairs) atomicAdd(&dP[pr], acc[k]);
     }
+    if (threadIdx.x < E) atomicAdd(&dp[threadIdx.x], accb);
 }
 
 // ---------------------------------------------------------- fold pooling
@@ -110,6 +130,33 @@ __device__ __forceinline__ void best_pair_reduce(double &v, int32_t &j, double *
         }
 }
 
+// Sum of s_e over the transit positions ph + ((k R + 2^31) >> 32) < L and
+// their count; four independent partial sums (FP32), so consecutive LDS
+// reads do not wait on each other.
+__device__ __forceinline__ float fold_sum(const float *s_e, int32_t L, uint64_t R, int32_t ph, int32_t &n) {
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    int32_t cnt = 0;
+    const uint64_t uL = (uint64_t)L;
+    for (uint64_t o = 2147483648ull;; o += 4 * R) {
+        const uint64_t x0 = (uint64_t)ph + (o >> 32);
+        if (x0 >= uL) break;
+        const uint64_t x1 = (uint64_t)ph + ((o + R) >> 32);
+        const uint64_t x2 = (uint64_t)ph + ((o + 2 * R) >> 32);
+        const uint64_t x3 = (uint64_t)ph + ((o + 3 * R) >> 32);
+        const bool k1 = x1 < uL, k2 = x2 < uL, k3 = x3 < uL;
+        const float v1 = s_e[k1 ? x1 : x0], v2 = s_e[k2 ? x2 : x0], v3 = s_e[k3 ? x3 : x0];
+        a0 += s_e[x0];
+        a1 += k1 ? v1 : 0.0f;
+        a2 += k2 ? v2 : 0.0f;
+        a3 += k3 ? v3 : 0.0f;
+        cnt += 1 + (int32_t)k1 + (int32_t)k2 + (int32_t)k3;
+    }
+    n = cnt;
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Grid (channel, example, window group): each workgroup stages its event
+// series in LDS and takes the windows w = group, group + n_groups, ...
 __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
                                                           const double *__restrict__ trials, int32_t W, int32_t S,
                                                           const float *__restrict__ win_q, float *__restrict__ f,
@@ -122,7 +169,7 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
     const int32_t nf = E + 1;
     for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
     __syncthreads();
-    for (int32_t w = 0; w < W; ++w) {
+    for (int32_t w = blockIdx.z; w < W; w += gridDim.z) {
         int32_t n_ph_max = 0;
         for (int32_t q = 0; q < S; ++q) {
             const uint64_t R = trial_step(trials[w * S + q]);
@@ -142,14 +189,8 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
             const int32_t q = jj / n_ph_max, ph = jj % n_ph_max;
             const uint64_t R = trial_step(trials[w * S + q]);
             if (R == 0 || (uint64_t)ph >= ((R + 4294967295ull) >> 32)) continue;
-            float acc = 0.0f;
             int32_t n = 0;
-            for (uint64_t o = 2147483648ull;; o += R) {
-                const uint64_t x = (uint64_t)ph + (o >> 32);
-                if (x >= (uint64_t)L) break;
-                acc += s_e[x];
-                ++n;
-            }
+            const float acc = fold_sum(s_e, L, R, ph, n);
             const double sc = (double)acc / sqrt((double)n);
             if (sc > best || (sc == best && jj < bj)) {
                 best = sc;
@@ -393,8 +434,13 @@ extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *g
     clear_error();
     CETRA_REQUIRE(h && ge && P && dh && dP && dp, "net_project_bwd: NULL pointer");
     CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_bwd: bad sizes");
-    hipLaunchKernelGGL(project_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT), 0,
-                       as_stream(stream), (const __bf16 *)h, ge, n_pos, P, E, dh, dP, dp);
+    hipStream_t st = as_stream(stream);
+    hipLaunchKernelGGL(project_bwd_dh_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT),
+                       0, st, ge, n_pos, P, E, dh);
+    int rc = check_launch("net_project_bwd/dh");
+    if (rc) return rc;
+    hipLaunchKernelGGL(project_bwd_dp_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kProjChunk)),
+                       dim3(kT), 0, st, (const __bf16 *)h, ge, n_pos, E, dP, dp);
     return check_launch("net_project_bwd");
 }
 
@@ -412,8 +458,11 @@ extern "C" int cetra_net_foldpool_fwd(void *stream, const float *e, int32_t B, i
     CETRA_REQUIRE(e && trials && win_q && f && arg, "net_foldpool_fwd: NULL pointer");
     int rc = foldpool_args_ok(B, L, E, W, S);
     if (rc) return rc;
-    hipLaunchKernelGGL(foldpool_fwd_kernel, dim3((unsigned)E, (unsigned)B), dim3(kT), 0, as_stream(stream), e, L, E,
-                       trials, W, S, win_q, f, arg);
+    // window groups: enough workgroups to fill the chip even for one example
+    const int64_t want = (int64_t)4 * device_cu_count();
+    const int32_t groups = (int32_t)std::max<int64_t>(1, std::min<int64_t>(W, ceil_div(want, (int64_t)E * B)));
+    hipLaunchKernelGGL(foldpool_fwd_kernel, dim3((unsigned)E, (unsigned)B, (unsigned)groups), dim3(kT), 0,
+                       as_stream(stream), e, L, E, trials, W, S, win_q, f, arg);
     return check_launch("net_foldpool_fwd");
 }
 
