@@ -197,7 +197,9 @@ int cetra_periodic_workspace(const cetra_grid *grid, int64_t n_eval, size_t *byt
  * i + round(m P_k/dt), m = 0, 1, ... (nearest reference time) with a common
  * inverse-variance depth Z; its likelihood ratio, the sum of Eq. 4 over the
  * transits, equals (sum S_fm)^2 / (2 sum S_mm).  The maximum over (j, i) is
- * kept, ties going to the smallest j, then the smallest i.
+ * kept, ties going to the smallest j, then the smallest i; candidates are
+ * ranked on FP32 sums (two whose LR agree to within a few 1e-6 relative may
+ * be taken in either order) and the winner's record is recomputed in FP64.
  * fold[J][I][2] (device) from cetra_linear_search.
  * periods[n_periods] (device, FP64, days; ascending order gives the best
  *   performance but is not required).  A period shorter than the

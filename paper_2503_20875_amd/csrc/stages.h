@@ -272,23 +272,57 @@ __device__ __forceinline__ float4 load_quad(__amdgpu_buffer_rsrc_t r, uint32_t b
     return make_float4(x, y, z, w);
 }
 
+// Ranking value of a fold candidate, LR = A^2 / (2 S), with the hardware
+// reciprocal (error of a few FP32 units, below that of the FP32 transit sums
+// it is computed from); the winner's LR is recomputed in FP64 afterwards.
+__device__ __forceinline__ float fold_rank_lr(float A, float S) {
+    return 0.5f * A * (A * __builtin_amdgcn_rcpf(S));
+}
+
+// (hi:lo) += (rh:rl) on the scalar unit: one add and one add-with-carry
+// (the compiler's own lowering of a wave-uniform 64-bit add whose high word
+// is then clamped takes five scalar instructions).
+__device__ __forceinline__ void acc_add(uint32_t &lo, uint32_t &hi, uint32_t rl, uint32_t rh) {
+    asm("s_add_u32 %0, %0, %2\n\ts_addc_u32 %1, %1, %3" : "+s"(lo), "+s"(hi) : "s"(rl), "s"(rh) : "scc");
+}
+
 // One fold unit: B periods (R[b], ipb[b]; ipb = 0 means "skip"), duration row
 // `row` (index j), epochs [e_lo, e_hi).  Each wave owns 128 consecutive
 // epochs.  kPair = false: lane l takes epochs e_wave + l and e_wave + 64 + l
 // (two 8-byte loads per period and step, each wave load 512 contiguous
 // bytes); kPair = true: lane l takes the adjacent epochs e_wave + 2l and
 // e_wave + 2l + 1 (one 16-byte load, the wave load 1 KB contiguous: half the
-// load instructions).  Per transit step and period: four FP32 adds; offsets
-// and the loop exit are wave-uniform (scalar registers).  FP32 chunks of 32 transits
-// fold into FP32 totals (error below (31 + n/32) u of the absolute sum); the
-// sums only rank candidates -- the epilogue recomputes the winner in FP64.
-// The per-period maxima go to keys[b] by 64-bit atomicMax.
+// load instructions).  Per transit step and period: four FP32 adds, one
+// address add, and three scalar instructions that advance the 32.32
+// fixed-point transit offset (its integer part saturates at I, where loads
+// read zero).  Offsets and the loop exit are wave-uniform.  The transit
+// offset round(m R / 2^32) does not decrease as R grows, so the evaluated
+// period with the smallest step is the last to leave the row: its offset
+// alone ends the loop.  FP32 chunks of 32 transits fold into FP32 totals
+// (error below (31 + n/32) u of the absolute sum); the sums only rank
+// candidates -- the epilogue recomputes the winner in FP64.  The per-period
+// maxima go to keys[b] by 64-bit atomicMax.
 template <int B, bool kPair = false>
 __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
                                           const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    const uint32_t uI = (uint32_t)I;
+    // steps split into integer and fraction words (wave-uniform: kept in
+    // scalar registers, so the offset updates run on the scalar unit); the
+    // slowest period
+    uint32_t Rh[B], Rl[B];
+    uint64_t r_min = ~0ull;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        Rh[b] = __builtin_amdgcn_readfirstlane((uint32_t)(R[b] >> 32));
+        Rl[b] = __builtin_amdgcn_readfirstlane((uint32_t)R[b]);
+        r_min = ipb[b] > 0 && R[b] < r_min ? R[b] : r_min;
+    }
+    if (r_min == ~0ull) return;  // no period of the block is evaluated on this row
+    const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
+    const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
     uint64_t best[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) best[b] = 0;
@@ -299,39 +333,26 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
         const int32_t e = e_wave + (kPair ? 2 * lane : lane);  // epochs e and e + kStride
         constexpr int32_t kStride = kPair ? 1 : 64;
         const uint32_t e_bytes = (uint32_t)e * 8u;
+        // a transit at offset o is inside the row for some lane iff o < lim
+        const uint32_t lim = uI - (uint32_t)e_wave;
         float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
-        uint64_t acc[B];
+        uint32_t hi[B], lo[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
             ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
-            acc[b] = 2147483648ull;  // + 1/2: round half up
+            hi[b] = 0;
+            lo[b] = 0x80000000u;  // + 1/2: round half up
         }
-        bool done = false;
-        while (!done) {
-            for (int mm = 0; mm < kFoldChunk; ++mm) {
-                uint32_t o[B];
-                bool any = false;
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    // saturate at I: finished periods read past the row
-                    // (zeros) and the byte offset stays below 2^32
-                    const uint32_t hi = (uint32_t)(acc[b] >> 32);
-                    const bool live = hi < (uint32_t)I;
-                    o[b] = live ? hi : (uint32_t)I;
-                    acc[b] += live ? R[b] : 0ull;
-                    any |= ipb[b] > 0 && (uint32_t)e_wave + o[b] < (uint32_t)I;
-                }
-                if (!any) {
-                    done = true;
-                    break;
-                }
+        uint32_t h_min = 0, l_min = 0x80000000u;
+        while (h_min < lim) {
+            for (int mm = 0; mm < kFoldChunk && h_min < lim; ++mm) {
                 // all 2B loads of the step are issued before the first add
                 // consumes one, so a wave keeps 2B loads in flight
                 float2 v0[B], v1[B];
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    const uint32_t off = e_bytes + o[b] * 8u;
+                    const uint32_t off = e_bytes + hi[b] * 8u;
                     if (kPair) {
                         const float4 v = load_quad(rsrc, off);
                         v0[b] = make_float2(v.x, v.y);
@@ -341,6 +362,13 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
                         v1[b] = load_pair(rsrc, off, 64 * 8);
                     }
                 }
+                // next offsets: hi < 2^31 and Rh < 2^31, so no sum wraps
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                    hi[b] = min(hi[b], uI);
+                }
+                acc_add(l_min, h_min, Rl_min, Rh_min);
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     a0[b] += v0[b].x;
@@ -365,10 +393,9 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
                 const int32_t eh = e + kStride * h;
                 const float A = h ? ta1[b] : ta0[b];
                 const float S = h ? ts1[b] : ts0[b];
-                if (eh < ipb[b] && eh < e_hi && S > 0.0f) {
-                    const uint64_t key = fold_key(0.5f * A * (A / S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
-                    best[b] = key > best[b] ? key : best[b];
-                }
+                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
+                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
+                best[b] = ok && key > best[b] ? key : best[b];
             }
         }
     }
@@ -539,10 +566,9 @@ __device__ __forceinline__ void fold_unit_lds(const float2 *row, int32_t j, int3
                 const int32_t eh = e0 + tid + kThreads * h;
                 const float A = h ? ta1[b] : ta0[b];
                 const float S = h ? ts1[b] : ts0[b];
-                if (eh < ipb[b] && eh < e_hi && S > 0.0f) {
-                    const uint64_t key = fold_key(0.5f * A * (A / S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
-                    best[b] = key > best[b] ? key : best[b];
-                }
+                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
+                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
+                best[b] = ok && key > best[b] ? key : best[b];
             }
         }
     }

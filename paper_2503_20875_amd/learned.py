@@ -55,6 +55,7 @@ class Pipeline:
         self.windows = Windows.log_spaced(cfg.n_windows, cfg.p_lo, cfg.p_hi, bin_days)
         self.work = torch.empty(max(periodic_workspace(self.grid, self.K), 1), dtype=torch.uint8, device="cuda")
         self.per = None
+        self.last_scores = None
 
     # ------------------------------------------------------------ features
     def linear(self, t, f, sigma):
@@ -87,6 +88,23 @@ class Pipeline:
         self.per = periodic_search(self.grid, fold, self.periods, subset=subset[:n_sub], work=self.work,
                                    out=self.per)
         return best_record(best(self.grid, self.periods, self.per)), n_sub
+
+    def search(self, net: ProposalNet, fold, top_k: int = 0, fallback_snr=None):
+        """Proposal + restricted search of one curve, with the full-fold
+        fallback: when the restricted best is missing or its SNR is below
+        `fallback_snr`, the plain search over every period runs and its
+        result is returned instead.  Returns (host best record, restricted
+        SNR (-inf when nothing was folded), fell back, periods folded).  The
+        window scores [1][W] stay in `last_scores`."""
+        x = self.features(fold)
+        z = net.forward(x.unsqueeze(0), self.windows)
+        self.last_scores = z
+        sel = topk_windows(z, int(top_k or self.cfg.top_k))
+        rec, n_sub = self.restricted(fold, sel[0])
+        snr_r = float(rec["snr"]) if rec is not None and rec["k"] >= 0 else float("-inf")
+        if fallback_snr is not None and snr_r < fallback_snr:
+            return self.plain(fold), snr_r, True, n_sub + self.K
+        return rec, snr_r, False, n_sub
 
     def window_of(self, period: float) -> int:
         w = int(np.searchsorted(self.windows.edges, period, side="right") - 1)
@@ -139,19 +157,23 @@ def load_weights(path: str) -> tuple:
 
 
 # ---------------------------------------------------------------- evaluation
-def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top_k: int = 0, log=None) -> dict:
+def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top_k: int = 0, fallback_snr=None,
+             log=None) -> dict:
     """Plain search versus proposal + restricted search on each curve
     (t, f, sigma, injections).  A plain detection is a best period with
-    SNR > snr_min; it is recalled when the restricted search over the top_k
-    windows (default: the pipeline's) returns the same best period.  Also
-    returned: for every detection, the rank of its window among the network's
-    scores (0 = best; ties to the smaller window), so recall at any K is the
-    fraction of ranks below K.  Times are device times per curve (events on
-    the current stream): the plain periodic search + best, and downsample +
-    network + top-K + subset + restricted search + best."""
+    SNR > snr_min; it is recalled when the learned search (restricted search
+    over the top_k windows, default the pipeline's, with the full-fold
+    fallback below `fallback_snr` when given) returns the same best period.
+    Also returned: for every detection, the rank of its window among the
+    network's scores (0 = best; ties to the smaller window), so recall at any
+    K is the fraction of ranks below K, and per curve the restricted best
+    SNR, from which a fallback threshold can be chosen.  Times are device
+    times per curve (events on the current stream): the plain periodic search
+    + best, and downsample + network + top-K + subset + restricted search +
+    best (+ the fallback's full search when it runs)."""
     import torch
     top_k = int(top_k or pipe.cfg.top_k)
-    n_det = n_hit = n_true = n_true_hit = 0
+    n_det = n_hit = n_true = n_true_hit = n_fb = 0
     t_plain = t_learned = 0.0
     n_folded = 0
     rows, ranks = [], []
@@ -163,15 +185,14 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
         bp = pipe.plain(fold)
         e[1].record()
         e[2].record()
-        x = pipe.features(fold)
-        z = net.forward(x.unsqueeze(0), pipe.windows)
-        sel = topk_windows(z, top_k)
-        bl, n_sub = pipe.restricted(fold, sel[0])
+        bl, snr_r, fell_back, n_sub = pipe.search(net, fold, top_k, fallback_snr)
         e[3].record()
         torch.cuda.synchronize()
+        z = pipe.last_scores
         t_plain += e[0].elapsed_time(e[1])
         t_learned += e[2].elapsed_time(e[3])
         n_folded += n_sub
+        n_fb += fell_back
         det = bool(bp["k"] >= 0 and bp["snr"] > snr_min)
         hit = bool(det and bl is not None and bl["k"] == bp["k"])
         # the paper's recovery criterion: within 1% of P, P/2 or 2P
@@ -188,17 +209,34 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
         n_det += det
         n_hit += hit
         rows.append(dict(curve=ci, plain_k=int(bp["k"]), plain_period=float(bp["period"]), plain_snr=float(bp["snr"]),
-                         learned_k=-1 if bl is None else int(bl["k"]), detected=det, recalled=hit, rank=rank,
-                         true_detection=true,
+                         learned_k=-1 if bl is None else int(bl["k"]), restricted_snr=snr_r, fell_back=fell_back,
+                         detected=det, recalled=hit, rank=rank, true_detection=true,
                          injected=[float(i.period) for i in injs]))
         if log and (ci + 1) % 16 == 0:
             log(f"eval {ci + 1}/{len(curves)}: detections {n_det}, recalled {n_hit}")
     n = max(len(curves), 1)
-    return dict(n_curves=len(curves), top_k=top_k, n_detections=n_det, n_recalled=n_hit,
+    return dict(n_curves=len(curves), top_k=top_k, fallback_snr=fallback_snr, n_detections=n_det, n_recalled=n_hit,
                 recall=(n_hit / n_det) if n_det else None, n_true_detections=n_true,
                 recall_true=(n_true_hit / n_true) if n_true else None, plain_ms_per_curve=t_plain / n,
                 learned_ms_per_curve=t_learned / n, speedup=(t_plain / t_learned) if t_learned > 0 else None,
-                periods_folded_fraction=n_folded / (n * pipe.K), ranks=ranks, rows=rows)
+                fallback_fraction=n_fb / n, periods_folded_fraction=n_folded / (n * pipe.K), ranks=ranks, rows=rows)
+
+
+def fallback_threshold(rows, target: float) -> float:
+    """Smallest restricted-SNR threshold for the full-fold fallback at which
+    at least `target` of the plain detections in `rows` (evaluated without a
+    fallback) are recalled: a missed detection is rescued when its curve's
+    restricted best SNR is below the threshold.  -inf when the proposal alone
+    already reaches the target."""
+    det = [r for r in rows if r["detected"]]
+    if not det:
+        return float("-inf")
+    allowed = int(np.floor((1.0 - target) * len(det) + 1e-9))
+    miss = sorted((r["restricted_snr"] for r in det if not r["recalled"]), reverse=True)
+    if len(miss) <= allowed:
+        return float("-inf")
+    # rescue every miss except the `allowed` ones with the highest restricted SNR
+    return float(np.nextafter(miss[allowed], np.inf))
 
 
 def k_for_recall(ranks, target: float, n_windows: int) -> int:

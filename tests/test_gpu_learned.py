@@ -1,0 +1,69 @@
+"""Learned search path end to end on one curve of the learned-proposal
+workload (80 000 points, 16 durations, 63 141 periods over 1-100 d): the
+restricted search's per-period records equal the plain search's records bit
+for bit on the selected periods and are null elsewhere, its best is the
+plain records' best over that subset, and the full-fold fallback returns the
+plain search's best.  The network has random weights here: only the
+plumbing from window scores to periods to records is under test."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_20875_amd.proposal import ProposalNet
+    from paper_2503_20875_amd.train_proposal import make_pipeline
+    from synthlc import workloads as W
+    pipe = make_pipeline()
+    t, f, s, _ = W.learned_curve(np.random.default_rng(77))
+    fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
+                       torch.as_tensor(s, device="cuda"))
+    bp = pipe.plain(fold)
+    plain = {k: v.cpu().numpy().copy() for k, v in pipe.per.items()}
+    net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=3)
+    return pipe, fold, bp, plain, net
+
+
+@pytest.mark.parametrize("top_k", [1, 64, 512])
+def test_restricted_records_match_plain(setup, top_k):
+    from paper_2503_20875_amd.proposal import topk_windows, windows_to_periods
+    pipe, fold, bp, plain, net = setup
+    rec, snr_r, fell_back, n_sub = pipe.search(net, fold, top_k)
+    assert not fell_back
+    sel = topk_windows(pipe.last_scores, top_k)[0]
+    subset, n = windows_to_periods(pipe.periods, pipe.windows, sel)
+    idx = np.sort(subset[:int(n.item())].cpu().numpy())
+    assert idx.size == n_sub > 0 and np.all(np.diff(idx) > 0)
+    # the selected windows' periods are exactly those whose window was chosen
+    w_of = np.searchsorted(pipe.windows.edges, pipe.periods_host, side="right") - 1
+    chosen = np.zeros(pipe.windows.n + 1, bool)
+    chosen[sel.cpu().numpy()] = True
+    want = np.flatnonzero((w_of >= 0) & (w_of < pipe.windows.n) & chosen[np.clip(w_of, 0, pipe.windows.n)])
+    np.testing.assert_array_equal(idx, want)
+    got = {k: v.cpu().numpy() for k, v in pipe.per.items()}
+    other = np.setdiff1d(np.arange(pipe.K), idx)
+    for name in ("lr", "epoch", "dur", "depth", "depth_var"):
+        np.testing.assert_array_equal(got[name][idx].view(np.uint32), plain[name][idx].view(np.uint32), err_msg=name)
+    assert np.all(got["lr"][other] == 0) and np.all(got["epoch"][other] == -1)
+    # best over the subset: largest LR, ties to the smallest period index
+    k_best = idx[np.argmax(plain["lr"][idx])]
+    assert rec["k"] == k_best
+    if top_k == pipe.windows.n and 0 <= w_of[bp["k"]] < pipe.windows.n:
+        assert rec["k"] == bp["k"]
+    assert snr_r == pytest.approx(float(rec["snr"]))
+
+
+def test_fallback_returns_plain(setup):
+    pipe, fold, bp, plain, net = setup
+    rec, snr_r, fell_back, n_sub = pipe.search(net, fold, 64)
+    rec_fb, snr_fb, fell_fb, n_fb = pipe.search(net, fold, 64, fallback_snr=snr_r + 1.0)
+    assert fell_fb and snr_fb == snr_r and n_fb == n_sub + pipe.K
+    assert rec_fb["k"] == bp["k"] and rec_fb["snr"] == bp["snr"]
+    rec_nf, _, fell_nf, _ = pipe.search(net, fold, 64, fallback_snr=snr_r)  # equal SNR: no fallback
+    assert not fell_nf and rec_nf["k"] == rec["k"]

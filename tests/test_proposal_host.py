@@ -42,3 +42,24 @@ def test_k_for_recall():
     assert k_for_recall(ranks, 0.5, 512) == 4
     assert k_for_recall([], 0.99, 512) == 1
     assert k_for_recall([600], 0.99, 512) == 512  # capped at the number of windows
+
+
+def test_fallback_threshold():
+    from paper_2503_20875_amd.learned import fallback_threshold
+
+    def row(det, rec, snr):
+        return dict(detected=det, recalled=rec, restricted_snr=snr)
+
+    rows = [row(True, True, 12.0)] * 97 + [row(True, False, 6.5), row(True, False, 6.9), row(True, False, 5.0),
+                                           row(False, False, 9.0)]
+    # 100 detections, 3 missed: at 99% one miss may stay, so the two lowest
+    # restricted SNRs must fall back; the threshold sits just above 6.5
+    tau = fallback_threshold(rows, 0.99)
+    assert 6.5 < tau < 6.5 + 1e-12
+    assert sum(r["detected"] and (r["recalled"] or r["restricted_snr"] < tau) for r in rows) == 99
+    # every miss rescued at a 100% target; none needed at 97%
+    assert 6.9 < fallback_threshold(rows, 1.0) < 6.9 + 1e-12
+    assert fallback_threshold(rows, 0.97) == float("-inf")
+    assert fallback_threshold([row(False, False, 3.0)], 0.99) == float("-inf")
+    # a curve where nothing was folded has a restricted SNR of -inf and always falls back
+    assert fallback_threshold([row(True, False, float("-inf"))] + [row(True, True, 9.0)] * 3, 1.0) > float("-inf")
