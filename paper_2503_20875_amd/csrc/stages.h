@@ -345,8 +345,35 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
             lo[b] = 0x80000000u;  // + 1/2: round half up
         }
         uint32_t h_min = 0, l_min = 0x80000000u;
+        {
+            // transit 0 sits at offset 0 for every period (and lim > 0):
+            // one load serves the whole block
+            float2 v0, v1;
+            if (kPair) {
+                const float4 v = load_quad(rsrc, e_bytes);
+                v0 = make_float2(v.x, v.y);
+                v1 = make_float2(v.z, v.w);
+            } else {
+                v0 = load_pair(rsrc, e_bytes, 0);
+                v1 = load_pair(rsrc, e_bytes, 64 * 8);
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                hi[b] = min(hi[b], uI);
+            }
+            acc_add(l_min, h_min, Rl_min, Rh_min);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a0[b] += v0.x;
+                s0[b] += v0.y;
+                a1[b] += v1.x;
+                s1[b] += v1.y;
+            }
+        }
+        int mm0 = 1;  // the first chunk already holds transit 0
         while (h_min < lim) {
-            for (int mm = 0; mm < kFoldChunk && h_min < lim; ++mm) {
+            for (int mm = mm0; mm < kFoldChunk && h_min < lim; ++mm) {
                 // all 2B loads of the step are issued before the first add
                 // consumes one, so a wave keeps 2B loads in flight
                 float2 v0[B], v1[B];
@@ -377,6 +404,7 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
                     s1[b] += v1[b].y;
                 }
             }
+            mm0 = 0;
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 ta0[b] += a0[b];
@@ -384,6 +412,15 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
                 ta1[b] += a1[b];
                 ts1[b] += s1[b];
                 a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            }
+        }
+        if (mm0) {  // a single transit: its sums are still in the chunk partials
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ta0[b] += a0[b];
+                ts0[b] += s0[b];
+                ta1[b] += a1[b];
+                ts1[b] += s1[b];
             }
         }
 #pragma unroll
