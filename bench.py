@@ -148,6 +148,69 @@ def batched_block(n_curves: int = 32, seed: int = 20250328) -> dict:
             "status": int(out["status"].item())}
 
 
+def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> dict:
+    """The Earth-analogue curve (730.5 d at 25 s: 2 524 608 points, J = 30,
+    I = 1 755 200, K = 399 404): a 421 MB fold-ready array, larger than the
+    256 MB Infinity Cache (the concurrent workgroups sweep one 14 MB duration
+    row at a time).  Resample + linear search, then the periodic search under
+    each tuning (one untimed launch, then `reps` timed ones), with HIP events;
+    algorithmic fold bytes over the mean launch time against the HBM peak."""
+    import torch
+    import paper_2503_20875_amd as cm
+    from synthlc import workloads as W
+    wl = W.long_baseline()
+    dev = "cuda"
+    grid = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
+    K = len(wl.periods)
+    t_d, f_d, s_d = (torch.as_tensor(a, device=dev) for a in (wl.t, wl.f, wl.sigma))
+    per_d = torch.as_tensor(wl.periods, device=dev)
+    fold = torch.empty((grid.n_dur, grid.n_t0, 2), dtype=torch.float32, device=dev)
+    work = torch.empty(cm.periodic_workspace(grid, K), dtype=torch.uint8, device=dev)
+    model = cm.template_resample(torch.as_tensor(wl.dense, device=dev), wl.n_model)
+
+    def linear():
+        flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
+        cm.linear_search(grid, flux, ivar, model, fold=fold)
+
+    linear()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    linear()
+    e1.record()
+    torch.cuda.synchronize()
+    lin_ms = e0.elapsed_time(e1)
+    before = cm.get_tuning()
+    per = None
+    fold_ms = {}
+    try:
+        for tun in tunings:
+            cm.set_tuning(*tun)
+            per = cm.periodic_search(grid, fold, per_d, work=work, out=per)
+            ms = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                cm.periodic_search(grid, fold, per_d, work=work, out=per)
+                b.record()
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+            fold_ms[",".join(map(str, tun))] = sum(ms) / len(ms)
+    finally:
+        cm.set_tuning(**before)
+    rec = cm.best_record(cm.best(grid, per_d, per))
+    alg = algorithmic_work(wl, grid)
+    fastest = min(fold_ms, key=fold_ms.get)
+    gbps = alg["fold_bytes"] / (fold_ms[fastest] / 1e3) / 1e9
+    return {"workload": (f"long baseline: {wl.n_obs} points at 25 s over 730.5 d, J = {grid.n_dur}, "
+                         f"I = {grid.n_t0}, K = {K}; fold-ready array {grid.n_dur * grid.n_t0 * 8 / 1e6:.0f} MB"),
+            "linear_ms": lin_ms, "fold_ms_by_tuning": fold_ms, "fastest_tuning": fastest,
+            "fold_algorithmic_bytes": alg["fold_bytes"], "fold_effective_GBps": gbps,
+            "frac_of_hbm_peak": gbps / HBM_PEAK_GBS,
+            "search_ms": lin_ms + fold_ms[fastest],
+            "points_x_periods_per_s": wl.n_obs * K / ((lin_ms + fold_ms[fastest]) / 1e3),
+            "best": {"period": rec["period"], "snr": rec["snr"], "duration": rec["duration"]}}
+
+
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
@@ -261,7 +324,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="high_cadence", choices=["high_cadence", "tiny"])
+    ap.add_argument("--workload", default="high_cadence", choices=["high_cadence", "tiny", "long_baseline"])
+    ap.add_argument("--no-long-baseline", action="store_true",
+                    help="skip the long-baseline (2 yr at 25 s) fold measurement")
     ap.add_argument("--mode", default="full", choices=["full", "fold", "copy"],
                     help="full: the benchmark; fold: setup once, then --steps fold launches only "
                          "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
@@ -425,6 +490,8 @@ def main():
         "best": {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"]},
     }
     if args.workload == "high_cadence":
+        if not args.no_long_baseline:
+            out["long_baseline"] = long_baseline_block()
         out["roofline_net"] = net_block()
         if args.batch_curves > 0:
             out["batched"] = batched_block(args.batch_curves)

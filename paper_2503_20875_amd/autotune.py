@@ -3,7 +3,8 @@
 Times the fold (``cetra_periodic_search``) on the caller's own grid,
 fold-ready array and periods under each candidate tuning -- period block,
 resident workgroups per compute unit, units per workgroup and the fold
-variant (register, LDS-staged, register with 16-byte loads) -- and keeps
+variant (register, workgroup LDS windows, register with 16-byte loads, wave
+LDS windows) -- and keeps
 the fastest with ``cetra_set_tuning``.
 Results do not depend on the tuning (the parity tests check that every
 variant returns identical records); only the time does.
@@ -16,7 +17,7 @@ import itertools
 from . import get_tuning, periodic_search, periodic_workspace, set_tuning
 
 DEFAULT_CANDIDATES = tuple(
-    (b, w, u, v) for b, w, u, v in itertools.product((4, 8), (8,), (4, 16), (0, 1, 2)))
+    (b, w, u, v) for b, w, u, v in itertools.product((4, 8, 16), (8,), (4, 16), (0, 1, 2, 3)))
 
 
 def tune_fold(grid, fold, periods, candidates=DEFAULT_CANDIDATES, repeats: int = 2, apply: bool = True):

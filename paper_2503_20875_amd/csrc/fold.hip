@@ -102,13 +102,18 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 
 // Persistent grid over units (period block of B periods, duration j, epoch
 // chunk), ordered block-fastest; each unit is one dev::fold_unit (variant 0:
-// lane epochs 64 apart; 2: adjacent lane epochs, 16-byte loads) or
-// dev::fold_unit_lds (variant 1).
+// lane epochs 64 apart; 2: adjacent lane epochs, 16-byte loads),
+// dev::fold_unit_lds (variant 1: workgroup-wide LDS windows) or
+// dev::fold_unit_wlds (variant 3: wave-private LDS windows).
 template <int B, int kVariant>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
                                                         int32_t I, int32_t n_chunks, int64_t n_units) {
     constexpr bool kLds = kVariant == 1;
-    __shared__ float2 s_buf[kLds ? 2 * cetra::dev::kFoldLdsCap : 1];
+    constexpr bool kWaveLds = kVariant == 3;
+    // float4 storage keeps every window 16-byte aligned
+    __shared__ float4 s_mem[kLds ? cetra::dev::kFoldLdsCap
+                                 : kWaveLds ? (kThreads / 64) * cetra::dev::kFoldWCap : 1];
+    float2 *s_buf = reinterpret_cast<float2 *>(s_mem);
     const int64_t n_pblk = (n_eval + B - 1) / B;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pb = u % n_pblk;
@@ -135,6 +140,9 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
         if (e_lo >= e_hi) continue;
         if (kLds)
             cetra::dev::fold_unit_lds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0, s_buf);
+        else if (kWaveLds)
+            cetra::dev::fold_unit_wlds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0,
+                                          s_buf + (threadIdx.x >> 6) * 2 * cetra::dev::kFoldWCap);
         else
             cetra::dev::fold_unit<B, kVariant == 2>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
     }
@@ -283,7 +291,10 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
         case 5: kern = (const void *)fold_kernel<16, 1>; break;
         case 6: kern = (const void *)fold_kernel<4, 2>; break;
         case 7: kern = (const void *)fold_kernel<8, 2>; break;
-        default: kern = (const void *)fold_kernel<16, 2>; break;
+        case 8: kern = (const void *)fold_kernel<16, 2>; break;
+        case 9: kern = (const void *)fold_kernel<4, 3>; break;
+        case 10: kern = (const void *)fold_kernel<8, 3>; break;
+        default: kern = (const void *)fold_kernel<16, 3>; break;
     }
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0) != hipSuccess || occ <= 0) occ = 1;

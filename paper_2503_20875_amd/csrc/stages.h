@@ -443,6 +443,218 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
     }
 }
 
+// Wave-private LDS fold unit (variant 3).  At each transit step the B
+// periods of the block read B windows of 128 epochs that overlap: they all lie
+// inside [o_slow, min(o_fast, lim) + 128) relative to the wave's first epoch,
+// with o_slow and o_fast the offsets of the periods with the smallest and
+// largest step (offsets grow with the step).  When that union fits kFoldWCap
+// pairs the wave loads it once with 16-byte loads (out-of-row pairs read zero)
+// into its own half of a double buffer and serves every period from there, so
+// a step costs ceil(span / 128) global loads instead of B; the next step's
+// window is loaded into registers while this step is summed.  Lane l owns
+// epochs e_wave + l and e_wave + 64 + l, so each half of a period's LDS read
+// is 512 contiguous bytes (no bank conflicts).  The buffer is private to the
+// wave and LDS operations of one wave complete in issue order, so no barrier
+// is needed.  A step whose union is wider is summed with direct loads.  Every
+// epoch receives the same values in the same order as in fold_unit, so the
+// sums, the keys and the records are bit-identical to variants 0 and 2.
+constexpr int kFoldWCap = 384;             // pairs per half of a wave's double buffer (3 KB)
+constexpr int kFoldWLd = kFoldWCap / 128;  // 16-byte loads per lane for a full window
+
+template <int B>
+__device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
+                                               const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
+                                               float2 *s_wave) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    const uint32_t uI = (uint32_t)I;
+    uint64_t r_min = ~0ull, r_max = 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        r_min = ipb[b] > 0 && R[b] < r_min ? R[b] : r_min;
+        r_max = ipb[b] > 0 && R[b] > r_max ? R[b] : r_max;
+    }
+    if (r_min == ~0ull) return;  // no period of the block is evaluated on this row
+    // a period not evaluated on this row follows the slowest one (its sums
+    // are discarded), so every offset lies between the slowest and the fastest
+    uint32_t Rh[B], Rl[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t r = ipb[b] > 0 ? R[b] : r_min;
+        Rh[b] = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
+        Rl[b] = __builtin_amdgcn_readfirstlane((uint32_t)r);
+    }
+    const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
+    const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
+    const uint32_t Rh_max = __builtin_amdgcn_readfirstlane((uint32_t)(r_max >> 32));
+    const uint32_t Rl_max = __builtin_amdgcn_readfirstlane((uint32_t)r_max);
+    uint64_t best[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) best[b] = 0;
+
+    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
+        const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
+        if (e_wave >= e_hi) break;
+        const int32_t e = e_wave + lane;  // epochs e and e + 64
+        const uint32_t e_bytes = (uint32_t)e * 8u;
+        const uint32_t w_bytes = (uint32_t)(e_wave + 2 * lane) * 8u;  // this lane's 16 bytes of a window
+        const uint32_t lim = uI - (uint32_t)e_wave;
+        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
+        uint32_t hi[B], lo[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
+            hi[b] = 0;
+            lo[b] = 0x80000000u;  // + 1/2: round half up
+        }
+        uint32_t h_min = 0, l_min = 0x80000000u, h_max = 0, l_max = 0x80000000u;
+        {
+            // transit 0 sits at offset 0 for every period: one load serves the block
+            const float2 v0 = load_pair(rsrc, e_bytes, 0);
+            const float2 v1 = load_pair(rsrc, e_bytes, 64 * 8);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                hi[b] = min(hi[b], uI);
+            }
+            acc_add(l_min, h_min, Rl_min, Rh_min);
+            acc_add(l_max, h_max, Rl_max, Rh_max);
+            h_max = min(h_max, uI);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a0[b] += v0.x;
+                s0[b] += v0.y;
+                a1[b] += v1.x;
+                s1[b] += v1.y;
+            }
+        }
+        int n_in_chunk = 1;
+        bool have = h_min < lim;
+        uint32_t ws = h_min;
+        uint32_t span = have ? min(h_max, lim) - ws + 128u : 0u;
+        bool in_lds = span <= (uint32_t)kFoldWCap;
+        int half = 0;
+        float4 pf[kFoldWLd];
+        if (have && in_lds) {
+#pragma unroll
+            for (int k = 0; k < kFoldWLd; ++k)
+                if ((uint32_t)(k * 128) < span) pf[k] = load_quad(rsrc, w_bytes + (ws + 128u * k) * 8u);
+            float4 *dst = reinterpret_cast<float4 *>(s_wave);
+#pragma unroll
+            for (int k = 0; k < kFoldWLd; ++k)
+                if ((uint32_t)(k * 128) < span) dst[64 * k + lane] = pf[k];
+        }
+        while (have) {
+            uint32_t o[B];  // this step's offsets, out-of-row ones clamped to the row end
+#pragma unroll
+            for (int b = 0; b < B; ++b) o[b] = min(hi[b], lim);
+            const uint32_t ws_c = ws;
+            const bool in_lds_c = in_lds;
+            // advance to the next step and start loading its window
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                hi[b] = min(hi[b], uI);
+            }
+            acc_add(l_min, h_min, Rl_min, Rh_min);
+            acc_add(l_max, h_max, Rl_max, Rh_max);
+            h_max = min(h_max, uI);
+            have = h_min < lim;
+            ws = h_min;
+            span = have ? min(h_max, lim) - ws + 128u : 0u;
+            in_lds = span <= (uint32_t)kFoldWCap;
+            const bool pre = have && in_lds;
+            if (pre) {
+#pragma unroll
+                for (int k = 0; k < kFoldWLd; ++k)
+                    if ((uint32_t)(k * 128) < span) pf[k] = load_quad(rsrc, w_bytes + (ws + 128u * k) * 8u);
+            }
+            // each branch consumes its own reads, so the LDS branch never
+            // waits on the global loads of the prefetch
+            if (in_lds_c) {
+                const float2 *buf = s_wave + half * kFoldWCap + lane;
+                float2 v0[B], v1[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const uint32_t q = o[b] - ws_c;
+                    v0[b] = buf[q];
+                    v1[b] = buf[q + 64];
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    a0[b] += v0[b].x;
+                    s0[b] += v0[b].y;
+                    a1[b] += v1[b].x;
+                    s1[b] += v1[b].y;
+                }
+                // distinct markers end the two branches, so their identical
+                // adds are not merged into one block after the branch
+                asm volatile("; fold step from LDS");
+            } else {
+                float2 v0[B], v1[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    v0[b] = load_pair(rsrc, e_bytes + o[b] * 8u, 0);
+                    v1[b] = load_pair(rsrc, e_bytes + o[b] * 8u, 64 * 8);
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    a0[b] += v0[b].x;
+                    s0[b] += v0[b].y;
+                    a1[b] += v1[b].x;
+                    s1[b] += v1[b].y;
+                }
+                asm volatile("; fold step from direct loads");
+            }
+            if (++n_in_chunk == kFoldChunk) {
+                n_in_chunk = 0;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    ta0[b] += a0[b];
+                    ts0[b] += s0[b];
+                    ta1[b] += a1[b];
+                    ts1[b] += s1[b];
+                    a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                }
+            }
+            if (pre) {
+                float4 *dst = reinterpret_cast<float4 *>(s_wave + (half ^ 1) * kFoldWCap);
+#pragma unroll
+                for (int k = 0; k < kFoldWLd; ++k)
+                    if ((uint32_t)(k * 128) < span) dst[64 * k + lane] = pf[k];
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // keep the next reads after these writes
+            half ^= 1;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            ta0[b] += a0[b];
+            ts0[b] += s0[b];
+            ta1[b] += a1[b];
+            ts1[b] += s1[b];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int32_t eh = e + 64 * h;
+                const float A = h ? ta1[b] : ta0[b];
+                const float S = h ? ts1[b] : ts0[b];
+                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
+                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
+                best[b] = ok && key > best[b] ? key : best[b];
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t m = wave_max_u64(best[b]);
+        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
+    }
+}
+
 // LDS-staged fold unit.  The workgroup owns 512 consecutive epochs of B
 // periods: lane t accumulates epochs e0 + t and e0 + t + 256.  For every
 // transit step the union of the B periods' element windows, [e0 + o_min,

@@ -279,9 +279,32 @@ def batched_survey(n_curves: int, seed: int = 20250328, n_min: int = 5000, n_max
     return curves
 
 
+def long_baseline(seed: int = 20250329) -> Workload:
+    """Earth analogue: one 730.5-d light curve at 25-s cadence (2 524 608
+    points, PLATO-like), white noise 200 ppm per point, no gaps.  One transit
+    signal P = 365.25 d, depth 100 ppm, duration 13 h, its epoch drawn so that
+    both transits fall inside the data.  30 log-spaced durations 1-20 h;
+    400 000 duty-cycle periods over 1-400 d (alpha = 0.263)."""
+    rng = np.random.default_rng(seed)
+    c = 25.0 / DAY_S
+    n = int(round(730.5 / c))
+    t = np.arange(n, dtype=np.float64) * c
+    sig = 200e-6
+    inj = Injection(period=365.25, epoch=rng.uniform(1.0, t[-1] - 365.25 - 1.0), duration=13.0 * HOUR,
+                    depth=100e-6)
+    y = 1.0 - inject(t, inj) + rng.normal(0.0, sig, n)
+    durs = log_durations(1.0, 20.0, 30)
+    return Workload(
+        name="earth-analogue 730.5d@25s (long baseline)", t=t, f=to_offset(y),
+        sigma=np.full(n, sig, dtype=np.float32), cadence=c, durations=durs,
+        periods=duty_cycle_periods(1.0, 400.0, t[-1], durs[0], alpha=0.263),
+        dense=transit.dense_template(), injections=[inj], seed=seed)
+
+
 WORKLOADS = {
     "tiny": tiny_single,
     "high_cadence": high_cadence,
+    "long_baseline": long_baseline,
 }
 
 

@@ -281,9 +281,45 @@ def test_high_cadence_full_size_sampled(cm, ora):
     assert b["lr"] == pytest.approx(alt[0], rel=TOL)
 
 
-@pytest.mark.parametrize("cfg", [(8, 8, 4, 1), (4, 8, 4, 1), (8, 8, 4, 0), (4, 8, 16, 0), (4, 8, 4, 2), (8, 8, 4, 2)])
+def test_long_baseline_full_size_sampled(cm, ora):
+    """Earth analogue, 730.5 d at 25 s (2 524 608 points, I = 1 755 200,
+    J = 30, K = 399 404; the fold-ready array is 421 MB) in the benchmark's
+    launch configuration.  Linear search: 20 000 sampled elements recomputed
+    one by one by the oracle.  Periodic search: 48 sampled periods, the
+    periods around the injected 365.25 d and its half, and the shortest and
+    longest, against the oracle's fold over its own full linear search; the
+    best period is the injected one."""
+    import torch
+    wl = W.long_baseline()
+    print(f"[case] {wl.name} K={len(wl.periods)}", flush=True)
+    r = cm.search(wl.t, wl.f, wl.sigma, wl.cadence, wl.durations, wl.periods, wl.dense, public=True)
+    torch.cuda.synchronize()
+    og = ora.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, wl.n_model)
+    model = ora.template(wl.dense, wl.n_model)
+    of, oi = ora.resample(og, wl.t, wl.f, wl.sigma)
+    rng = np.random.default_rng(2)
+    idx = rng.integers(0, og.n_dur * og.n_t0, 20000)
+    samp = ora.linear_at(og, of, oi, model, idx)
+    d, v, l = (a.reshape(-1)[idx] for a in lin_arrays(r))
+    print("linear sample", check_linear(d, v, l, samp), flush=True)
+    lin = ora.linear(og, of, oi, model)
+    K = len(wl.periods)
+    near = [np.searchsorted(wl.periods, P) + o for P in (365.25, 182.625) for o in (-2, -1, 0, 1)]
+    sel = np.unique(np.concatenate([rng.choice(K, 48, replace=False), near, [0, 1, K - 2, K - 1]]))
+    per = ora.periodic(og, lin, wl.periods, sel=sel)
+    g = {k: v.cpu().numpy() for k, v in r["periodic"].items()}
+    res = check_periodic(g, per, lambda P, i, j: ora.fold_at(og, lin, P, i, j), wl.periods, sel=sel)
+    print("periodic sample", res)
+    b = cm.best_record(r["best_raw"])
+    assert abs(b["period"] / 365.25 - 1) < 0.002
+    alt = ora.fold_at(og, lin, b["period"], b["epoch"], b["dur"])
+    assert b["lr"] == pytest.approx(alt[0], rel=TOL)
+
+
+@pytest.mark.parametrize("cfg", [(8, 8, 4, 1), (4, 8, 4, 1), (8, 8, 4, 0), (4, 8, 16, 0), (4, 8, 4, 2), (8, 8, 4, 2),
+                                 (4, 8, 4, 3), (8, 8, 4, 3), (16, 8, 4, 3)])
 def test_fold_variants_identical(cm, ora, tiny_pair, tiny_wl, cfg):
-    """Register and LDS fold variants, period blocks 4 and 8: the same
+    """Register and LDS fold variants, period blocks 4 to 16: the same
     per-period records, bit for bit (the FP32 ranking sums are accumulated in
     the same order), and parity with the oracle."""
     import torch
@@ -298,3 +334,49 @@ def test_fold_variants_identical(cm, ora, tiny_pair, tiny_wl, cfg):
     for k in ("lr", "epoch", "dur", "depth", "depth_var"):
         assert np.array_equal(h[k], g[k], equal_nan=True), (cfg, k)
     check_periodic(h, o["periodic"], fold_at(ora, o), tiny_wl.periods)
+
+
+def mixed_periods(seed=11):
+    """Periods that drive every path of the fold variants on the tiny grid
+    (27.4 d, durations 0.5-6 h): 160 close periods of 0.12-0.3 d (90-230
+    transits, several FP32 chunks, narrow windows that fit a wave's LDS
+    buffer; the shortest exclude the longer durations), 120 periods of
+    0.5-13 d (windows that outgrow the buffer after a few transits), and 40
+    in random order (period blocks with widely different steps)."""
+    rng = np.random.default_rng(seed)
+    short = 1.0 / np.linspace(1 / 0.12, 1 / 0.3, 160)[::-1]
+    mid = 1.0 / np.linspace(1 / 0.5, 1 / 13.0, 120)[::-1]
+    loose = rng.uniform(0.15, 13.0, 40)
+    return np.concatenate([short, mid, loose])
+
+
+@pytest.mark.parametrize("B", [4, 8, 16])
+def test_fold_variants_identical_mixed_periods(cm, ora, tiny_pair, B):
+    """Every fold variant returns the records of the default variant bit for
+    bit on mixed periods with a duration-range restriction, and those
+    records match the oracle."""
+    import torch
+    r, o, _ = tiny_pair
+    periods = mixed_periods()
+    K = len(periods)
+    rng = np.random.default_rng(5)
+    jr = np.stack([rng.integers(0, 3, K), rng.integers(4, 8, K)], axis=1).astype(np.int32)
+    print(f"[case] mixed periods K={K} B={B}", flush=True)
+    out = {}
+    try:
+        for v in (2, 0, 1, 3):
+            cm.set_tuning(B, 8, 4, v)
+            per = cm.periodic_search(r["grid"], r["fold"], periods, jrange=jr)
+            torch.cuda.synchronize()
+            out[v] = {k: x.cpu().numpy() for k, x in per.items()}
+    finally:
+        cm.reset_tuning()
+    for v in (0, 1, 3):
+        for k in ("lr", "epoch", "dur", "depth", "depth_var"):
+            assert np.array_equal(out[v][k], out[2][k], equal_nan=True), (B, v, k)
+    if B == 8:
+        op = ora.periodic(o["grid"], o["linear"], periods, jrange=jr)
+        check_periodic(out[3], op, fold_at(ora, o), periods)
+        for k in range(K):
+            if out[3]["dur"][k] >= 0:
+                assert jr[k, 0] <= out[3]["dur"][k] <= jr[k, 1]
