@@ -149,6 +149,37 @@ int cetra_set_tuning(const cetra_tuning *in);
 int cetra_grid_plan(double t_first, double t_last, double cadence, const double *durations,
                     int32_t n_dur, double t0_step, int32_t n_model, cetra_grid *out);
 
+/* Period grid of the default search (Sec. 2.1.3, which adopts the optimally
+ * sampled grid of Ofir 2014 as used by TLS).  Frequencies are spaced evenly
+ * in f^(1/3): a step moves the last transit of a span of `span` days by
+ * 1/oversample of the duty cycle q(f) = (3 pi / (G rho))^(1/3) f^(2/3) / pi
+ * of a central transit across a star of mean density `rho` (g cm^-3), i.e.
+ * d(f^(1/3)) = (3 pi / (G rho))^(1/3) / (3 pi span oversample).  The grid
+ * starts at 1/p_max and covers [p_min, p_max] days.  *n_out (host) receives
+ * the number of periods; if `periods` (host) is not NULL it receives them in
+ * ascending order and must hold `cap` >= *n_out values (else
+ * CETRA_ERR_INVALID).  Invalid ranges fail with CETRA_ERR_INVALID. */
+int cetra_period_grid(double span, double p_min, double p_max, double rho, double oversample, double *periods,
+                      int64_t cap, int64_t *n_out);
+
+/* Keplerian duration limits for one period (days), the range Sec. 2.1.3
+ * keeps per period: circular orbits around stars of mean density
+ * [rho_min, rho_max] (g cm^-3), with first-to-last-contact duration
+ * T = (P/pi) asin(sqrt((1+k)^2 - b^2) / (a/R sin i)), (a/R)^3 = G rho P^2/(3 pi),
+ * cos i = b/(a/R).  *d_max is T at rho_min, radius ratio k_max and b = 0;
+ * *d_min is T at rho_max, k = 0 and b = b_max (0 <= k_max, b_max < 1).  An
+ * orbit inside the star gives P/2, a non-transiting one 0.  Host only. */
+int cetra_duration_limits(double period, double rho_min, double rho_max, double k_max, double b_max,
+                          double *d_min, double *d_max);
+
+/* Per-period duration-index ranges for cetra_periodic_search's `jrange`
+ * (host arrays): jrange[k] = {first j with durations[j] >= d_min(P_k), last j
+ * with durations[j] <= d_max(P_k)} for the limits of cetra_duration_limits
+ * (an empty range, lo > hi, when no duration qualifies).  durations[n_dur]
+ * ascending, days; periods[n_periods] days.  Host only. */
+int cetra_keplerian_jrange(const double *periods, int64_t n_periods, const double *durations, int32_t n_dur,
+                           double rho_min, double rho_max, double k_max, double b_max, int32_t *jrange);
+
 /* Template resampling (Sec. 2.1.2): the dense template dense[n_dense]
  * (device, FP64, contact-normalised time from first to last contact, max
  * offset 1) is resampled by linear interpolation to model[n_model] (device,

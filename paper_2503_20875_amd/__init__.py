@@ -82,6 +82,48 @@ def grid_plan(t_first: float, t_last: float, cadence: float, durations, t0_step:
     return g
 
 
+SOLAR_DENSITY = 1.408  # g cm^-3
+
+
+def period_grid(span: float, p_min: float, p_max: float, rho: float = SOLAR_DENSITY,
+                oversample: float = 3.0) -> np.ndarray:
+    """Optimally sampled period grid (ascending, days): evenly spaced in
+    f^(1/3), one step moving the last transit of the span by 1/oversample of
+    a central transit's duty cycle around a star of density rho (g/cm^3)."""
+    lib = _abi.load()
+    n = ctypes.c_int64()
+    _abi.check(lib.cetra_period_grid(float(span), float(p_min), float(p_max), float(rho), float(oversample),
+                                     None, 0, ctypes.byref(n)))
+    out = np.empty(n.value, dtype=np.float64)
+    _abi.check(lib.cetra_period_grid(float(span), float(p_min), float(p_max), float(rho), float(oversample),
+                                     out.ctypes.data_as(ctypes.c_void_p), out.shape[0], ctypes.byref(n)))
+    return out
+
+
+def duration_limits(period: float, rho_min: float, rho_max: float, k_max: float = 0.2,
+                    b_max: float = 0.9) -> tuple:
+    """(d_min, d_max) in days: the Keplerian transit-duration range of one
+    period for circular orbits around stars of density [rho_min, rho_max]."""
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _abi.check(_abi.load().cetra_duration_limits(float(period), float(rho_min), float(rho_max), float(k_max),
+                                                 float(b_max), ctypes.byref(lo), ctypes.byref(hi)))
+    return lo.value, hi.value
+
+
+def keplerian_jrange(periods, durations, rho_min: float, rho_max: float, k_max: float = 0.2,
+                     b_max: float = 0.9) -> np.ndarray:
+    """int32 [K][2] duration-index ranges (host) for periodic_search's jrange:
+    the durations inside each period's Keplerian limits."""
+    p = np.ascontiguousarray(periods, dtype=np.float64)
+    d = np.ascontiguousarray(durations, dtype=np.float64)
+    out = np.empty((p.shape[0], 2), dtype=np.int32)
+    _abi.check(_abi.load().cetra_keplerian_jrange(p.ctypes.data_as(ctypes.c_void_p), p.shape[0],
+                                                  d.ctypes.data_as(ctypes.c_void_p), d.shape[0], float(rho_min),
+                                                  float(rho_max), float(k_max), float(b_max),
+                                                  out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
 def template_resample(dense, n_model: int = 1024, stream=None):
     torch = _torch()
     d = _dev(dense, torch.float64)

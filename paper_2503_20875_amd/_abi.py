@@ -103,6 +103,9 @@ SIGNATURES = {
     "cetra_get_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "cetra_set_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "cetra_grid_plan": (ctypes.c_int, [_d, _d, _d, _P, _i32, _d, _i32, ctypes.POINTER(Grid)]),
+    "cetra_period_grid": (ctypes.c_int, [_d, _d, _d, _d, _d, _P, _i64, _P]),
+    "cetra_duration_limits": (ctypes.c_int, [_d, _d, _d, _d, _d, _P, _P]),
+    "cetra_keplerian_jrange": (ctypes.c_int, [_P, _i64, _P, _i32, _d, _d, _d, _d, _P]),
     "cetra_template_resample": (ctypes.c_int, [_P, _P, _i64, _i32, _P]),
     "cetra_resample": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _P, _i64, _P, _P, _P]),
     "cetra_linear_search": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P]),

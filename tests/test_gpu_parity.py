@@ -380,3 +380,22 @@ def test_fold_variants_identical_mixed_periods(cm, ora, tiny_pair, B):
         for k in range(K):
             if out[3]["dur"][k] >= 0:
                 assert jr[k, 0] <= out[3]["dur"][k] <= jr[k, 1]
+
+
+def test_keplerian_duration_filter(cm, ora, tiny_wl):
+    """The fold restricted to each period's Keplerian durations (Sun-like
+    densities 0.5-3 g/cm^3, k <= 0.2, b <= 0.9): the library's ranges equal
+    the grid oracle's, and the records match the oracle's fold under the
+    same ranges.  Periods whose range is empty get the null record."""
+    from oracle import grids as og
+    wl = tiny_wl
+    jr = cm.keplerian_jrange(wl.periods, wl.durations, 0.5, 3.0, 0.2, 0.9)
+    assert np.array_equal(jr, og.keplerian_jrange(wl.periods, wl.durations, 0.5, 3.0, 0.2, 0.9))
+    assert np.any(jr[:, 0] > 0) and np.any(jr[:, 1] < len(wl.durations) - 1)
+    r, o, g = run_both(cm, ora, wl, jrange=jr)
+    check_periodic(g, o["periodic"], fold_at(ora, o), wl.periods)
+    for k in range(len(wl.periods)):
+        if g["dur"][k] >= 0:
+            assert jr[k, 0] <= g["dur"][k] <= jr[k, 1]
+        else:
+            assert jr[k, 0] > jr[k, 1] or wl.durations[jr[k, 0]] >= wl.periods[k]
