@@ -381,6 +381,9 @@ def main():
     ap.add_argument("--workload", default="high_cadence", choices=["high_cadence", "tiny", "long_baseline"])
     ap.add_argument("--no-long-baseline", action="store_true",
                     help="skip the long-baseline (2 yr at 25 s) fold measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the benchmark steps only (no filter, long-baseline, network, batched, learned or "
+                         "CPU measurements), e.g. for kernel traces of the headline search")
     ap.add_argument("--mode", default="full", choices=["full", "fold", "copy"],
                     help="full: the benchmark; fold: setup once, then --steps fold launches only "
                          "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
@@ -543,6 +546,9 @@ def main():
         "wall_s_timed": wall,
         "best": {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"]},
     }
+    if args.no_extras:
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "high_cadence":
         out["keplerian"] = keplerian_block()
         if not args.no_long_baseline:
