@@ -154,7 +154,9 @@ def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> 
     256 MB Infinity Cache (the concurrent workgroups sweep one 14 MB duration
     row at a time).  Resample + linear search, then the periodic search under
     each tuning (one untimed launch, then `reps` timed ones), with HIP events;
-    algorithmic fold bytes over the mean launch time against the HBM peak."""
+    algorithmic fold bytes over the mean launch time against the HBM peak.
+    Also the monotransit-only search (resample + linear search + the five
+    strongest single events), timed once after a warm-up."""
     import torch
     import paper_2503_20875_amd as cm
     from synthlc import workloads as W
@@ -198,6 +200,16 @@ def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> 
     finally:
         cm.set_tuning(**before)
     rec = cm.best_record(cm.best(grid, per_d, per))
+    # monotransit-only search: resample + linear search + the 5 strongest single events
+    ev_out = cm.single_events(grid, fold, 5)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    linear()
+    cm.single_events(grid, fold, 5, out=ev_out)
+    b.record()
+    b.synchronize()
+    mono_ms = a.elapsed_time(b)
+    events = cm.event_records(ev_out)
     alg = algorithmic_work(wl, grid)
     fastest = min(fold_ms, key=fold_ms.get)
     gbps = alg["fold_bytes"] / (fold_ms[fastest] / 1e3) / 1e9
@@ -208,7 +220,9 @@ def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> 
             "frac_of_hbm_peak": gbps / HBM_PEAK_GBS,
             "search_ms": lin_ms + fold_ms[fastest],
             "points_x_periods_per_s": wl.n_obs * K / ((lin_ms + fold_ms[fastest]) / 1e3),
-            "best": {"period": rec["period"], "snr": rec["snr"], "duration": rec["duration"]}}
+            "best": {"period": rec["period"], "snr": rec["snr"], "duration": rec["duration"]},
+            "monotransit_search_ms": mono_ms,
+            "single_events": [{"t0_abs": e["t0_abs"], "duration": e["duration"], "snr": e["snr"]} for e in events[:3]]}
 
 
 def keplerian_block(rho=(0.5, 3.0), k_max: float = 0.2, b_max: float = 0.9, reps: int = 2) -> dict:

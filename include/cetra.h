@@ -95,6 +95,23 @@ typedef struct cetra_best_record {
     double snr;         /* depth / sqrt(depth_var)                                */
 } cetra_best_record;
 
+/* Most single events one cetra_single_events call returns. */
+#define CETRA_MAX_EVENTS 64
+
+/* One single-transit candidate (written to device memory by
+ * cetra_single_events). */
+typedef struct cetra_event {
+    int32_t epoch;      /* reference-time index i, -1 if no candidate remained  */
+    int32_t dur;        /* duration index j                                       */
+    double t0;          /* mid-transit time relative to t_origin (days)           */
+    double t0_abs;      /* the same in the input's time system                    */
+    double duration;    /* days                                                   */
+    double lr;          /* log-likelihood ratio (Eq. 2 at the best depth)          */
+    double depth;       /* maximum-likelihood depth                               */
+    double depth_var;   /* its variance                                           */
+    double snr;         /* depth / sqrt(depth_var)                                */
+} cetra_event;
+
 /* Launch tuning of the periodic search, process-wide for this library
  * instance (an autotuner sets it; the defaults are 8, 8, 4, 2).  Results do not
  * depend on it except through near-ties of the argmax. */
@@ -257,6 +274,31 @@ int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fol
 int cetra_best(void *stream, const cetra_grid *grid, const double *periods, int64_t n_periods,
                const float *lr, const int32_t *epoch, const int32_t *dur, const float *depth,
                const float *depth_var, cetra_best_record *out);
+
+/* Single-event (monotransit) search on the linear search's results (the
+ * search for single transits in the linear output that Sec. 1 and Sec. 5
+ * describe).  Event e is the element (j, i) of fold[J][I][2] (device, from
+ * cetra_linear_search) with the largest likelihood ratio
+ * LR = S_fm^2 / (2 S_mm) among the non-null elements whose transit window
+ * overlaps none of events 0..e-1 (|t_i - t_e| < (D_j + D_e) / 2 excludes
+ * it); candidates are ranked on FP32 and the winner's record is computed
+ * in FP64 from its pair, ties going to the smallest j, then i.  out[n_events]
+ * (device) receives the events in order; once no candidate remains the rest
+ * have epoch -1.  1 <= n_events <= CETRA_MAX_EVENTS.  work/work_bytes: device
+ * workspace of cetra_single_events_workspace(n_events) bytes. */
+int cetra_single_events_workspace(int32_t n_events, size_t *bytes);
+int cetra_single_events(void *stream, const cetra_grid *grid, const float *fold, int32_t n_events, void *work,
+                        size_t work_bytes, cetra_event *out);
+
+/* Nulls a found signal for the next search (the iterative search of Sec. 5,
+ * which nullifies the flux in and around the strongest signal before
+ * searching again): every resampled point q (time q c after t_origin) with
+ * |q c - t0 - n P| <= width * duration / 2 for the nearest integer n gets
+ * flux = ivar = 0 (device arrays [N] from cetra_resample).  A period that is
+ * not a finite positive number nulls the single event at t0 only.  t0 is
+ * relative to t_origin (as in cetra_best_record and cetra_event). */
+int cetra_mask_transits(void *stream, const cetra_grid *grid, double period, double t0, double duration,
+                        double width, float *flux, float *ivar);
 
 /* ---------------------------------------------------------- batched search */
 

@@ -221,6 +221,71 @@ def best(grid: Grid, periods, per: dict, out=None, stream=None):
     return out
 
 
+def single_events(grid: Grid, fold, n_events: int = 5, out=None, stream=None):
+    """The n strongest non-overlapping single-transit candidates of a
+    linear search (fold-ready [J][I][2]); returns a uint8 device tensor of
+    n cetra_event records (``event_records`` reads them on the host)."""
+    torch = _torch()
+    n = int(n_events)
+    if not 1 <= n <= _abi.MAX_EVENTS:
+        raise ValueError(f"n_events must lie in [1, {_abi.MAX_EVENTS}]")
+    size = ctypes.c_size_t()
+    _abi.check(_abi.load().cetra_single_events_workspace(n, ctypes.byref(size)))
+    work = torch.empty(size.value, dtype=torch.uint8, device=fold.device)
+    if out is None:
+        out = torch.empty((n, ctypes.sizeof(_abi.Event)), dtype=torch.uint8, device=fold.device)
+    _abi.check(_abi.load().cetra_single_events(_stream(stream), ctypes.byref(grid), _ptr(fold), n, _ptr(work),
+                                               work.numel(), _ptr(out)))
+    return out
+
+
+def event_records(raw) -> list:
+    """Host copies of the cetra_event records written by ``single_events``."""
+    data = raw.cpu().numpy()
+    recs = []
+    for row in data.reshape(-1, ctypes.sizeof(_abi.Event)):
+        e = _abi.Event.from_buffer_copy(bytes(row.tobytes()))
+        recs.append({name: getattr(e, name) for name, _ in _abi.Event._fields_})
+    return recs
+
+
+def mask_transits(grid: Grid, flux, ivar, period: float, t0: float, duration: float, width: float = 1.5,
+                  stream=None) -> None:
+    """Null (in place) the resampled points within width * duration / 2 of
+    every transit t0 + n P (t0 relative to the grid origin); a period that is
+    not finite and positive masks the single event at t0."""
+    _abi.check(_abi.load().cetra_mask_transits(_stream(stream), ctypes.byref(grid), float(period), float(t0),
+                                               float(duration), float(width), _ptr(flux), _ptr(ivar)))
+
+
+def iterative_search(t, f, sigma, cadence: float, durations, periods, dense, n_signals: int = 3,
+                     mask_width: float = 1.5, n_model: int = 1024, t0_step: float = 0.0, jrange=None,
+                     stream=None) -> list:
+    """Multi-signal search: after each search the strongest periodic signal
+    is nulled in the resampled light curve (mask_transits) and the linear
+    and periodic searches run again.  Returns the best record of every
+    pass (a pass that finds nothing ends the loop)."""
+    torch = _torch()
+    t_host = np.asarray(t) if not hasattr(t, "cpu") else t.cpu().numpy()
+    grid = grid_plan(t_host[0], t_host[-1], cadence, durations, t0_step, n_model)
+    model = template_resample(dense, n_model, stream=stream)
+    flux, ivar, _ = resample(grid, t, f, sigma, status=False, stream=stream)
+    per_d = _dev(periods, torch.float64)
+    K = per_d.numel()
+    work = torch.empty(max(periodic_workspace(grid, K), 1), dtype=torch.uint8, device=per_d.device)
+    fold = per = None
+    found = []
+    for _ in range(int(n_signals)):
+        fold = linear_search(grid, flux, ivar, model, fold=fold, stream=stream)
+        per = periodic_search(grid, fold, per_d, jrange=jrange, work=work, out=per, stream=stream)
+        b = best_record(best(grid, per_d, per, stream=stream))
+        found.append(b)
+        if b["k"] < 0:
+            break
+        mask_transits(grid, flux, ivar, b["period"], b["t0"], b["duration"], mask_width, stream=stream)
+    return found
+
+
 def best_record(raw) -> dict:
     """Host copy of a cetra_best_record produced by ``best``."""
     b = BestRecord.from_buffer_copy(bytes(raw.cpu().numpy().tobytes()))

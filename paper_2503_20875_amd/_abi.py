@@ -42,6 +42,24 @@ class Grid(ctypes.Structure):
     ]
 
 
+class Event(ctypes.Structure):
+    """Mirror of ``cetra_event``."""
+    _fields_ = [
+        ("epoch", ctypes.c_int32),
+        ("dur", ctypes.c_int32),
+        ("t0", ctypes.c_double),
+        ("t0_abs", ctypes.c_double),
+        ("duration", ctypes.c_double),
+        ("lr", ctypes.c_double),
+        ("depth", ctypes.c_double),
+        ("depth_var", ctypes.c_double),
+        ("snr", ctypes.c_double),
+    ]
+
+
+MAX_EVENTS = 64
+
+
 class BestRecord(ctypes.Structure):
     """Mirror of ``cetra_best_record``."""
     _fields_ = [
@@ -104,6 +122,9 @@ SIGNATURES = {
     "cetra_set_tuning": (ctypes.c_int, [ctypes.POINTER(Tuning)]),
     "cetra_grid_plan": (ctypes.c_int, [_d, _d, _d, _P, _i32, _d, _i32, ctypes.POINTER(Grid)]),
     "cetra_period_grid": (ctypes.c_int, [_d, _d, _d, _d, _d, _P, _i64, _P]),
+    "cetra_single_events_workspace": (ctypes.c_int, [_i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "cetra_single_events": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _i32, _P, ctypes.c_size_t, _P]),
+    "cetra_mask_transits": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _d, _d, _d, _d, _P, _P]),
     "cetra_duration_limits": (ctypes.c_int, [_d, _d, _d, _d, _d, _P, _P]),
     "cetra_keplerian_jrange": (ctypes.c_int, [_P, _i64, _P, _i32, _d, _d, _d, _d, _P]),
     "cetra_template_resample": (ctypes.c_int, [_P, _P, _i64, _i32, _P]),

@@ -135,6 +135,31 @@ def tiny_single(seed: int = 20250326) -> Workload:
         dense=transit.dense_template(), injections=[inj], seed=seed)
 
 
+def tiny_two_planets(seed: int = 20250330) -> Workload:
+    """The tiny light curve with two planets: 27.4 d at 2-min cadence, white
+    noise 1000 ppm, two random 1-d gaps; P = 5.3 d / 2000 ppm / 3 h and
+    P = 2.1 d / 1500 ppm / 2 h at random epochs.  8 log-spaced durations
+    0.5-6 h; 1000 periods uniform in frequency over 1-13 d."""
+    rng = np.random.default_rng(seed)
+    c = 120.0 / DAY_S
+    n = int(round(27.4 / c))
+    t = np.arange(n, dtype=np.float64) * c
+    keep = np.ones(n, dtype=bool)
+    for s in random_gaps(rng, 0.0, t[-1], 2, 1.0):
+        keep &= ~((t >= s) & (t < s + 1.0))
+    t = t[keep]
+    sig = 1000e-6
+    injs = [Injection(period=5.3, epoch=rng.uniform(0.0, 5.3), duration=3.0 * HOUR, depth=2000e-6),
+            Injection(period=2.1, epoch=rng.uniform(0.0, 2.1), duration=2.0 * HOUR, depth=1500e-6)]
+    y = 1.0 - sum(inject(t, i) for i in injs) + rng.normal(0.0, sig, t.shape[0])
+    return Workload(
+        name="two-planet 27.4d@120s (tiny)", t=t, f=to_offset(y),
+        sigma=np.full(t.shape[0], sig, dtype=np.float32), cadence=c,
+        durations=log_durations(0.5, 6.0, 8),
+        periods=uniform_frequency_periods(1.0, 13.0, 1000),
+        dense=transit.dense_template(), injections=injs, seed=seed)
+
+
 def high_cadence(seed: int = 20250327) -> Workload:
     """One 90-d light curve at 20-s cadence (TESS-20s-like): AR(1) red noise
     (phi = 0.9, marginal 300 ppm) plus 500 ppm white noise, pre-whitened by a
