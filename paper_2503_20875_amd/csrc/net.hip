@@ -75,39 +75,89 @@ __global__ void downsample_kernel(const float2 *__restrict__ fold, int32_t J, in
 }
 
 // ------------------------------------------------------------ conv forward
-// Workgroup: 64 positions x 64 output channels of one example; wave w owns
-// positions [16 w, 16 w + 16) and all 64 channels (4 MFMA row tiles).
-__global__ void __launch_bounds__(kT) conv_fwd_kernel(const __bf16 *__restrict__ x, int32_t cin, int32_t L,
+// Implicit GEMM with a 64 x 64 register tile per wave.  Workgroup: 256
+// positions x 64 output channels of one example; wave w owns positions
+// [64 w, 64 w + 64) (4 MFMA column tiles) and all 64 channels (4 row tiles),
+// so each k-step's 4 weight and 4 input fragments (16-byte loads) feed 16
+// MFMAs, and the next k-step's fragments are loaded while this one's MFMAs
+// issue.  Positions outside [0, L) and reduction indices past 9 cin read
+// zero.
+constexpr int kConvPos = 256;
+
+template <int MT>
+struct ConvFrags {
+    bf16x8 a[MT];
+    bf16x8 b[4];
+};
+
+// Fragments of k-step k0: A rows r of `a_mat` (row stride a_ld, 16 MT rows),
+// B the inputs at source position t + shift(k) - 4 (sign +1 forward, -1 for
+// the input gradient) and channel k % c of `src` (channel-last, c channels).
+template <int MT>
+__device__ __forceinline__ void conv_load(ConvFrags<MT> &f, const __bf16 *__restrict__ a_mat, int32_t a_ld,
+                                          const __bf16 *__restrict__ src, int32_t c, int32_t k_valid, int32_t L,
+                                          int32_t t0, int sign, int32_t k0, int l) {
+    const int32_t k = k0 + 8 * (l / 16);
+    const int32_t tap = k / c, ci = k % c;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) f.a[m] = load8(a_mat + (int64_t)(16 * m + (l % 16)) * a_ld + k);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const int32_t t = t0 + 16 * n;
+        const int32_t s = t + sign * (tap - 4);
+        f.b[n] = (k < k_valid && s >= 0 && s < L && t < L) ? load8(src + (int64_t)s * c + ci) : zero8();
+    }
+}
+
+template <int MT>
+__device__ __forceinline__ void conv_mfma(f32x4 (&acc)[MT][4], const ConvFrags<MT> &f) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = mfma16(f.a[m], f.b[n], acc[m][n]);
+}
+
+// acc[m][n] = sum over the k-steps of A rows x B columns (ping-pong over two
+// fragment sets).
+template <int MT>
+__device__ __forceinline__ void conv_gemm(f32x4 (&acc)[MT][4], const __bf16 *__restrict__ a_mat, int32_t a_ld,
+                                          const __bf16 *__restrict__ src, int32_t c, int32_t k_valid, int32_t k_end,
+                                          int32_t L, int32_t t0, int sign, int l) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    ConvFrags<MT> f0, f1;
+    conv_load<MT>(f0, a_mat, a_ld, src, c, k_valid, L, t0, sign, 0, l);
+    for (int32_t k0 = 0; k0 < k_end; k0 += 64) {
+        const bool more = k0 + 32 < k_end;
+        if (more) conv_load<MT>(f1, a_mat, a_ld, src, c, k_valid, L, t0, sign, k0 + 32, l);
+        conv_mfma<MT>(acc, f0);
+        if (!more) break;
+        if (k0 + 64 < k_end) conv_load<MT>(f0, a_mat, a_ld, src, c, k_valid, L, t0, sign, k0 + 64, l);
+        conv_mfma<MT>(acc, f1);
+    }
+}
+
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) conv_fwd_kernel(const __bf16 *__restrict__ x, int32_t cin, int32_t L,
                                                       const __bf16 *__restrict__ w, int32_t k32,
                                                       const float *__restrict__ bias, __bf16 *__restrict__ y) {
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.y;
-    const int32_t t = blockIdx.x * 64 + wave * 16 + (l % 16);  // output position of this lane's B column
-    const __bf16 *xb = x + b * (int64_t)L * cin;
-    f32x4 acc[4];
+    const int32_t t0 = blockIdx.x * kConvPos + wave * 64 + (l % 16);  // this lane's column of tile n: t0 + 16 n
+    f32x4 acc[4][4];
+    conv_gemm<4>(acc, w, k32, x + b * (int64_t)L * cin, cin, kTaps * cin, k32, L, t0, +1, l);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int32_t k0 = 0; k0 < k32; k0 += 32) {
-        const int32_t k = k0 + 8 * (l / 16);  // first of this lane's 8 reduction indices
-        const int32_t tap = k / cin, ci = k % cin;
-        const int32_t src = t + tap - 4;
-        const bf16x8 bfrag = (tap < kTaps && src >= 0 && src < L && t < L) ? load8(xb + (int64_t)src * cin + ci)
-                                                                            : zero8();
+    for (int n = 0; n < 4; ++n) {
+        const int32_t t = t0 + 16 * n;
+        if (t >= L) continue;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const bf16x8 afrag = load8(w + (int64_t)(16 * m + (l % 16)) * k32 + k);
-            acc[m] = mfma16(afrag, bfrag, acc[m]);
-        }
-    }
-    if (t >= L) return;
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = 16 * m + 4 * (l / 16) + r;
-            const float v = fmaxf(acc[m][r] + bias[co], 0.0f);
-            y[(b * L + t) * kWidth + co] = (__bf16)v;
-        }
+            for (int r = 0; r < 4; ++r) {
+                const int co = 16 * m + 4 * (l / 16) + r;
+                y[(b * L + t) * kWidth + co] = (__bf16)fmaxf(acc[m][n][r] + bias[co], 0.0f);
+            }
     }
 }
 
@@ -130,113 +180,144 @@ __global__ void conv_transpose_w_kernel(const __bf16 *__restrict__ w, int32_t ci
 }
 
 // ------------------------------------------------------- conv backward-x
-// dX[b][t][ci] (FP32) = sum over tap, co of WT[ci][tap*64 + co] G[b][t - tap + 4][co].
-// Workgroup: 64 positions of one example; wave w owns 16 positions and all
-// cin input channels (cin / 16 MFMA row tiles, cin in {16, 64}).
+// dX[b][t][ci] (FP32) = sum over tap, co of WT[ci][tap*64 + co] G[b][t - tap + 4][co],
+// the same register-tiled implicit GEMM as the forward pass with cin / 16
+// row tiles (cin in {16, 64}); workgroup: 256 positions of one example.
+template <int MT>
 __global__ void __launch_bounds__(kT) conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L,
-                                                        const __bf16 *__restrict__ wt, int32_t cin,
-                                                        float *__restrict__ dx) {
+                                                        const __bf16 *__restrict__ wt, float *__restrict__ dx) {
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.y;
-    const int32_t t = blockIdx.x * 64 + wave * 16 + (l % 16);
-    const __bf16 *gb = g + b * (int64_t)L * kWidth;
-    const int mt = cin / 16;
-    f32x4 acc[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int32_t t0 = blockIdx.x * kConvPos + wave * 64 + (l % 16);
     constexpr int32_t kK = kTaps * kWidth;  // 576, a multiple of 32
-    for (int32_t k0 = 0; k0 < kK; k0 += 32) {
-        const int32_t k = k0 + 8 * (l / 16);
-        const int32_t tap = k / kWidth, co = k % kWidth;
-        const int32_t src = t - tap + 4;
-        const bf16x8 bfrag = (src >= 0 && src < L && t < L) ? load8(gb + (int64_t)src * kWidth + co) : zero8();
+    constexpr int cin = 16 * MT;
+    f32x4 acc[MT][4];
+    conv_gemm<MT>(acc, wt, kK, g + b * (int64_t)L * kWidth, kWidth, kK, kK, L, t0, -1, l);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m >= mt) break;
-            const bf16x8 afrag = load8(wt + (int64_t)(16 * m + (l % 16)) * kK + k);
-            acc[m] = mfma16(afrag, bfrag, acc[m]);
-        }
-    }
-    if (t >= L) return;
+    for (int n = 0; n < 4; ++n) {
+        const int32_t t = t0 + 16 * n;
+        if (t >= L) continue;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        if (m >= mt) break;
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dx[(b * L + t) * cin + 16 * m + 4 * (l / 16) + r] = acc[m][r];
+            for (int r = 0; r < 4; ++r) dx[(b * L + t) * cin + 16 * m + 4 * (l / 16) + r] = acc[m][n][r];
     }
 }
 
 // ------------------------------------------------------ conv backward-w
-// dW[co][k] += sum over 256 positions of one example of G[t][co] X[t+tap-4][ci]
-// (k = tap * cin + ci).  Workgroup: (8 chunks of 256 positions, example,
-// block of 64 reduction columns k); each chunk of G and of X (with a
-// 4-position halo) is staged in LDS transposed to position-fastest order so
-// every MFMA fragment is one 16-byte LDS read.  The workgroup's partial sums
-// over its 2048 positions are added to dW (FP32 atomics); db[co] gets the
-// column sums of G.
+// dW[co][tap * cin + ci] += sum over positions t of G[t][co] X[t + tap - 4][ci]
+// and db[co] += sum over t of G[t][co]: a GEMM whose reduction runs over
+// positions, so both operands are staged in LDS position-fastest (one chunk
+// of 256 positions at a time; X with a 4-position halo on each side).
+// Workgroup: kChunksPerWg chunks of one example; wave w owns output channels
+// [16 w, 16 w + 16) and every (ci tile, tap) column tile, 9 cin / 16 tiles
+// of FP32 accumulators.  Per 32-position step a lane reads its G fragment
+// (8 positions) and, per ci tile, 16 consecutive positions of X (two aligned
+// 16-byte reads); the nine taps' fragments are the 8-position windows of
+// those 16 values starting at the tap (a register selection for even taps,
+// one byte-align per dword for odd taps).  The bias gradient is one more
+// MFMA against a fragment of ones.  The workgroup's sums go to dW and db by
+// FP32 atomics.
 constexpr int kPosChunk = 256;
 constexpr int kChunksPerWg = 8;
-__global__ void __launch_bounds__(kT) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
-                                                        int32_t cin, int32_t L, int32_t k32,
-                                                        float *__restrict__ dw, float *__restrict__ db) {
-    __shared__ __attribute__((aligned(16))) __bf16 s_g[kWidth][kPosChunk];            // 32 KB
-    __shared__ __attribute__((aligned(16))) __bf16 s_x[kWidth][kPosChunk + 16];       // 34 KB (cin <= 64)
+constexpr int kHalo = 4;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Window of 8 bf16 starting at element s (0..8) of the 16 held in lo, hi.
+template <int S>
+__device__ __forceinline__ bf16x8 window8(const u32x4 &lo, const u32x4 &hi) {
+    const uint32_t v[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    u32x4 w;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        constexpr int q = S / 2;
+        if (S % 2 == 0)
+            w[d] = v[q + d];
+        else  // high half of v[q + d] and low half of v[q + d + 1]
+            w[d] = __builtin_amdgcn_alignbyte(v[q + d + 1], v[q + d], 2);
+    }
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+template <int CT>
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
+                                                        int32_t L, int32_t k32, float *__restrict__ dw,
+                                                        float *__restrict__ db) {
+    constexpr int cin = 16 * CT;
+    // rows of 264 elements (528 bytes, 16 bytes past a multiple of 256): the
+    // 16 rows one MFMA fragment read touches start on distinct bank groups
+    constexpr int kRow = kPosChunk + 2 * kHalo;
+    __shared__ __attribute__((aligned(16))) __bf16 s_g[kWidth][kRow];  // 33 KB
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[cin][kRow];     // <= 33 KB
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.y;
-    const int32_t kb = blockIdx.z * 64;  // this workgroup's 64 reduction columns
     const __bf16 *gb = g + b * (int64_t)L * kWidth;
     const __bf16 *xb = x + b * (int64_t)L * cin;
-    // wave w: output rows co in [16 w, 16 w + 16), columns k in [kb, kb + 64)
-    // (4 tiles), accumulated over kChunksPerWg position chunks before the
-    // atomics
-    f32x4 acc[4];
+    f32x4 acc[CT][kTaps];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    float bias_acc = 0.0f;
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int tap = 0; tap < kTaps; ++tap) acc[c][tap] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 acc_b = {0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
     const int co = 16 * wave + (l % 16);
     for (int32_t ch = 0; ch < kChunksPerWg; ++ch) {
         const int32_t p0 = (blockIdx.x * kChunksPerWg + ch) * kPosChunk;
         if (p0 >= L) break;  // uniform over the workgroup
         __syncthreads();     // the previous chunk's reads are done
-        for (int i = threadIdx.x; i < kWidth * kPosChunk; i += kT) {
-            const int p = i / kWidth, c = i % kWidth;
-            s_g[c][p] = (p0 + p < L) ? gb[(int64_t)(p0 + p) * kWidth + c] : (__bf16)0.0f;
+        // transposing copies: a lane takes one position and 8 channels at a
+        // time (one 16-byte load), consecutive lanes consecutive positions,
+        // so each LDS row is written contiguously
+        for (int i = threadIdx.x; i < (kWidth / 8) * kPosChunk; i += kT) {
+            const int p = i % kPosChunk, c8 = 8 * (i / kPosChunk);
+            const bf16x8 v = (p0 + p < L) ? load8(gb + (int64_t)(p0 + p) * kWidth + c8) : zero8();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s_g[c8 + j][p] = v[j];
         }
-        for (int i = threadIdx.x; i < cin * (kPosChunk + 16); i += kT) {
-            const int p = i / cin, ci = i % cin;
-            const int32_t src = p0 + p - 4;
-            s_x[ci][p] = (src >= 0 && src < L) ? xb[(int64_t)src * cin + ci] : (__bf16)0.0f;
+        // s_x[ci][pp] = X[p0 + pp - kHalo]
+        for (int i = threadIdx.x; i < (cin / 8) * kRow; i += kT) {
+            const int pp = i % kRow, c8 = 8 * (i / kRow);
+            const int32_t src = p0 + pp - kHalo;
+            const bf16x8 v = (src >= 0 && src < L) ? load8(xb + (int64_t)src * cin + c8) : zero8();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s_x[c8 + j][pp] = v[j];
         }
         __syncthreads();
-        if (blockIdx.z == 0 && wave == 0)  // bias gradient: column sums of G
-            for (int p = 0; p < kPosChunk; ++p) bias_acc += (float)s_g[l][p];
         for (int32_t q0 = 0; q0 < kPosChunk; q0 += 32) {
-            const int q = q0 + 8 * (l / 16);
+            const int q = q0 + 8 * (l / 16);  // this lane's 8 positions
             const bf16x8 afrag = *reinterpret_cast<const bf16x8 *>(&s_g[co][q]);
+            acc_b = mfma16(afrag, ones, acc_b);
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const int32_t k = kb + 16 * n + (l % 16);
-                const int32_t tap = k / cin, ci = k % cin;
-                bf16x8 bfrag;
-                if (k < kTaps * cin) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) bfrag[i] = s_x[ci][q + i + tap];
-                } else {
-                    bfrag = zero8();
-                }
-                acc[n] = mfma16(afrag, bfrag, acc[n]);
+            for (int c = 0; c < CT; ++c) {
+                // X[p0 + q + tap - 4 + i] = s_x[ci][q + tap + i], i < 8, tap < 9
+                const __bf16 *row = &s_x[16 * c + (l % 16)][q];
+                const u32x4 lo = *reinterpret_cast<const u32x4 *>(row);
+                const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 8);
+                acc[c][0] = mfma16(afrag, window8<0>(lo, hi), acc[c][0]);
+                acc[c][1] = mfma16(afrag, window8<1>(lo, hi), acc[c][1]);
+                acc[c][2] = mfma16(afrag, window8<2>(lo, hi), acc[c][2]);
+                acc[c][3] = mfma16(afrag, window8<3>(lo, hi), acc[c][3]);
+                acc[c][4] = mfma16(afrag, window8<4>(lo, hi), acc[c][4]);
+                acc[c][5] = mfma16(afrag, window8<5>(lo, hi), acc[c][5]);
+                acc[c][6] = mfma16(afrag, window8<6>(lo, hi), acc[c][6]);
+                acc[c][7] = mfma16(afrag, window8<7>(lo, hi), acc[c][7]);
+                acc[c][8] = mfma16(afrag, window8<8>(lo, hi), acc[c][8]);
             }
         }
     }
-    if (blockIdx.z == 0 && wave == 0) atomicAdd(&db[l], bias_acc);
+    // C layout: lane holds rows 4 (l / 16) + r of the tile, column l % 16
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wave + 4 * (l / 16) + r;
+        if (l % 16 == 0) atomicAdd(&db[row], acc_b[r]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * wave + 4 * (l / 16) + r;
-            const int32_t k = kb + 16 * n + (l % 16);
-            if (k < k32) atomicAdd(&dw[row * k32 + k], acc[n][r]);
-        }
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int tap = 0; tap < kTaps; ++tap)
+                atomicAdd(&dw[row * k32 + tap * cin + 16 * c + (l % 16)], acc[c][tap][r]);
     }
 }
 
@@ -276,7 +357,7 @@ extern "C" int cetra_conv1d_fwd(void *stream, const void *x, int32_t cin, int32_
     CETRA_REQUIRE(x && w && bias && y, "conv1d_fwd: NULL pointer");
     int rc = conv_args_ok(cin, L, batch, k32);
     if (rc) return rc;
-    hipLaunchKernelGGL(conv_fwd_kernel, dim3((unsigned)ceil_div(L, 64), (unsigned)batch), dim3(kT), 0,
+    hipLaunchKernelGGL(conv_fwd_kernel, dim3((unsigned)ceil_div(L, kConvPos), (unsigned)batch), dim3(kT), 0,
                        as_stream(stream), (const __bf16 *)x, cin, L, (const __bf16 *)w, k32, bias, (__bf16 *)y);
     return check_launch("conv1d_fwd");
 }
@@ -293,15 +374,24 @@ extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, co
     hipLaunchKernelGGL(relu_mask_kernel, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, dy, (const __bf16 *)y, n,
                        (__bf16 *)g_scratch);
     if ((rc = check_launch("conv1d_bwd/mask"))) return rc;
-    hipLaunchKernelGGL(conv_bwd_w_kernel, dim3((unsigned)ceil_div(L, kPosChunk * kChunksPerWg), (unsigned)batch,
-                                               (unsigned)ceil_div(kTaps * cin, 64)),
-                       dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, cin, L, k32, dw, db);
+    const dim3 gw((unsigned)ceil_div(L, kPosChunk * kChunksPerWg), (unsigned)batch);
+    if (cin == 16)
+        hipLaunchKernelGGL(conv_bwd_w_kernel<1>, gw, dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
+                           k32, dw, db);
+    else
+        hipLaunchKernelGGL(conv_bwd_w_kernel<4>, gw, dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
+                           k32, dw, db);
     if ((rc = check_launch("conv1d_bwd/w"))) return rc;
     if (!dx) return CETRA_OK;
     hipLaunchKernelGGL(conv_transpose_w_kernel, dim3((unsigned)ceil_div(kWidth * kTaps * cin, kT)), dim3(kT), 0, s,
                        (const __bf16 *)w, cin, k32, (__bf16 *)wt_scratch);
     if ((rc = check_launch("conv1d_bwd/transpose"))) return rc;
-    hipLaunchKernelGGL(conv_bwd_x_kernel, dim3((unsigned)ceil_div(L, 64), (unsigned)batch), dim3(kT), 0, s,
-                       (const __bf16 *)g_scratch, L, (const __bf16 *)wt_scratch, cin, dx);
+    const dim3 gx((unsigned)ceil_div(L, kConvPos), (unsigned)batch);
+    if (cin == 16)
+        hipLaunchKernelGGL(conv_bwd_x_kernel<1>, gx, dim3(kT), 0, s, (const __bf16 *)g_scratch, L,
+                           (const __bf16 *)wt_scratch, dx);
+    else
+        hipLaunchKernelGGL(conv_bwd_x_kernel<4>, gx, dim3(kT), 0, s, (const __bf16 *)g_scratch, L,
+                           (const __bf16 *)wt_scratch, dx);
     return check_launch("conv1d_bwd/x");
 }
