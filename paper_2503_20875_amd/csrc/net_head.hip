@@ -105,78 +105,64 @@ __device__ __forceinline__ uint64_t trial_step(double T) {
     return (T >= 1.0 && T < 1.0e9) ? (uint64_t)floor(4294967296.0 * T + 0.5) : 0ull;
 }
 
-__device__ __forceinline__ void best_pair_reduce(double &v, int32_t &j, double *s_v, int32_t *s_j) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int32_t oj = __shfl_xor(j, off, 64);
-        if (ov > v || (ov == v && oj < j)) {
-            v = ov;
-            j = oj;
-        }
-    }
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-        s_v[wave] = v;
-        s_j[wave] = j;
-    }
-    __syncthreads();
-    v = s_v[0];
-    j = s_j[0];
-    for (int q = 1; q < kT / 64; ++q)
-        if (s_v[q] > v || (s_v[q] == v && s_j[q] < j)) {
-            v = s_v[q];
-            j = s_j[q];
-        }
-}
-
 // Sum of s_e over the transit positions ph + ((k R + 2^31) >> 32) < L and
-// their count; four independent partial sums (FP32), so consecutive LDS
-// reads do not wait on each other.
-__device__ __forceinline__ float fold_sum(const float *s_e, int32_t L, uint64_t R, int32_t ph, int32_t &n) {
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+// their count; four independent partial sums (FP32, element k into sum
+// k mod 4), so consecutive LDS reads do not wait on each other.  The 32.32
+// offsets advance by a 32-bit add with carry.
+__device__ __forceinline__ float fold_sum(const float *s_e, int32_t L, uint32_t Rh, uint32_t Rl, int32_t ph,
+                                          int32_t &n) {
+    float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     int32_t cnt = 0;
-    const uint64_t uL = (uint64_t)L;
-    for (uint64_t o = 2147483648ull;; o += 4 * R) {
-        const uint64_t x0 = (uint64_t)ph + (o >> 32);
-        if (x0 >= uL) break;
-        const uint64_t x1 = (uint64_t)ph + ((o + R) >> 32);
-        const uint64_t x2 = (uint64_t)ph + ((o + 2 * R) >> 32);
-        const uint64_t x3 = (uint64_t)ph + ((o + 3 * R) >> 32);
-        const bool k1 = x1 < uL, k2 = x2 < uL, k3 = x3 < uL;
-        const float v1 = s_e[k1 ? x1 : x0], v2 = s_e[k2 ? x2 : x0], v3 = s_e[k3 ? x3 : x0];
-        a0 += s_e[x0];
-        a1 += k1 ? v1 : 0.0f;
-        a2 += k2 ? v2 : 0.0f;
-        a3 += k3 ? v3 : 0.0f;
-        cnt += 1 + (int32_t)k1 + (int32_t)k2 + (int32_t)k3;
+    uint32_t hi = 0, lo = 0x80000000u;  // + 1/2: round half up
+    const uint32_t lim = (uint32_t)(L - ph);  // ph < L
+    bool done = false;
+    while (!done) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (hi >= lim) {
+                done = true;
+                break;
+            }
+            a[u] += s_e[ph + hi];
+            ++cnt;
+            const uint32_t l2 = lo + Rl;
+            hi += Rh + (l2 < lo ? 1u : 0u);
+            lo = l2;
+        }
     }
     n = cnt;
-    return (a0 + a1) + (a2 + a3);
+    return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
-// Grid (channel, example, window group): each workgroup stages its event
-// series in LDS and takes the windows w = group, group + n_groups, ...
+// Grid (channel, example, window group); each workgroup stages its event
+// series in LDS, and each wave takes whole windows (wave index = group * 4
+// + wave, striding by 4 n_groups), so a window's maximum is a wave reduction.
+// Lane candidates are (trial q, phase ph), numbered jj = q n_ph_max + ph; a
+// phase is scored exactly, (double) sum / sqrt(n), only if its FP32 score
+// sum * rsqrt(n), within a few 1e-7 of the exact one, does not fall below
+// the lane's best by more than 1e-5 of it -- a phase rejected that way cannot
+// win or tie, so the maxima are those of exact scoring.
 __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
                                                           const double *__restrict__ trials, int32_t W, int32_t S,
                                                           const float *__restrict__ win_q, float *__restrict__ f,
                                                           int32_t *__restrict__ arg) {
     __shared__ float s_e[kMaxL];
-    __shared__ double s_v[kT / 64];
-    __shared__ int32_t s_j[kT / 64];
     const int32_t c = blockIdx.x;
     const int64_t b = blockIdx.y;
     const int32_t nf = E + 1;
+    const int lane = threadIdx.x & 63;
+    const int32_t wave_id = blockIdx.z * (kT / 64) + (threadIdx.x >> 6);
+    const int32_t n_waves = gridDim.z * (kT / 64);
     for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
     __syncthreads();
-    for (int32_t w = blockIdx.z; w < W; w += gridDim.z) {
+    for (int32_t w = wave_id; w < W; w += n_waves) {
         int32_t n_ph_max = 0;
         for (int32_t q = 0; q < S; ++q) {
             const uint64_t R = trial_step(trials[w * S + q]);
             n_ph_max = max(n_ph_max, (int32_t)min<uint64_t>((uint64_t)L, (R + 4294967295ull) >> 32));
         }
         if (n_ph_max == 0) {  // no valid trial: zero feature, no argmax
-            if (threadIdx.x == 0) {
+            if (lane == 0) {
                 f[(b * W + w) * nf + c] = 0.0f;
                 arg[(b * W + w) * E + c] = -1;
                 if (c == 0) f[(b * W + w) * nf + E] = win_q[w];
@@ -184,21 +170,36 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
             continue;
         }
         double best = -INFINITY;
+        float cut = -INFINITY;
         int32_t bj = INT_MAX;
-        for (int32_t jj = threadIdx.x; jj < S * n_ph_max; jj += kT) {
-            const int32_t q = jj / n_ph_max, ph = jj % n_ph_max;
+        for (int32_t q = 0; q < S; ++q) {
             const uint64_t R = trial_step(trials[w * S + q]);
-            if (R == 0 || (uint64_t)ph >= ((R + 4294967295ull) >> 32)) continue;
-            int32_t n = 0;
-            const float acc = fold_sum(s_e, L, R, ph, n);
-            const double sc = (double)acc / sqrt((double)n);
-            if (sc > best || (sc == best && jj < bj)) {
-                best = sc;
-                bj = jj;
+            if (R == 0) continue;
+            const int32_t n_ph = (int32_t)min<uint64_t>((uint64_t)L, (R + 4294967295ull) >> 32);
+            const uint32_t Rh = (uint32_t)(R >> 32), Rl = (uint32_t)R;
+            for (int32_t ph = lane; ph < n_ph; ph += 64) {
+                int32_t n = 0;
+                const float acc = fold_sum(s_e, L, Rh, Rl, ph, n);
+                if (acc * rsqrtf((float)n) < cut) continue;
+                const double sc = (double)acc / sqrt((double)n);
+                const int32_t jj = q * n_ph_max + ph;
+                if (sc > best || (sc == best && jj < bj)) {
+                    best = sc;
+                    bj = jj;
+                    const float fb = (float)sc;
+                    cut = fb - 1e-5f * fabsf(fb) - 1e-30f;
+                }
             }
         }
-        best_pair_reduce(best, bj, s_v, s_j);
-        if (threadIdx.x == 0) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(best, off, 64);
+            const int32_t oj = __shfl_xor(bj, off, 64);
+            if (ov > best || (ov == best && oj < bj)) {
+                best = ov;
+                bj = oj;
+            }
+        }
+        if (lane == 0) {
             const int32_t q = bj / n_ph_max, ph = bj % n_ph_max;
             f[(b * W + w) * nf + c] = (float)best;
             arg[(b * W + w) * E + c] = q * 65536 + ph;
@@ -460,7 +461,8 @@ extern "C" int cetra_net_foldpool_fwd(void *stream, const float *e, int32_t B, i
     if (rc) return rc;
     // window groups: enough workgroups to fill the chip even for one example
     const int64_t want = (int64_t)4 * device_cu_count();
-    const int32_t groups = (int32_t)std::max<int64_t>(1, std::min<int64_t>(W, ceil_div(want, (int64_t)E * B)));
+    const int32_t groups = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(ceil_div(W, kT / 64), ceil_div(want, (int64_t)E * B)));
     hipLaunchKernelGGL(foldpool_fwd_kernel, dim3((unsigned)E, (unsigned)B, (unsigned)groups), dim3(kT), 0,
                        as_stream(stream), e, L, E, trials, W, S, win_q, f, arg);
     return check_launch("net_foldpool_fwd");
