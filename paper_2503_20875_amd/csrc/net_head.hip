@@ -105,29 +105,39 @@ __device__ __forceinline__ uint64_t trial_step(double T) {
     return (T >= 1.0 && T < 1.0e9) ? (uint64_t)floor(4294967296.0 * T + 0.5) : 0ull;
 }
 
-// Sum of s_e over the transit positions ph + ((k R + 2^31) >> 32) < L and
-// their count; four independent partial sums (FP32, element k into sum
-// k mod 4), so consecutive LDS reads do not wait on each other.  The 32.32
-// offsets advance by a 32-bit add with carry.
-__device__ __forceinline__ float fold_sum(const float *s_e, int32_t L, uint32_t Rh, uint32_t Rl, int32_t ph,
-                                          int32_t &n) {
+// Sums of s_e over the transit positions ph + ((k R + 2^31) >> 32) < L for
+// the 64 consecutive phases ph = ph0 + lane of a wave, and their counts.  The
+// offset of transit k does not depend on the phase, so it is stepped once per
+// wave (32.32 fixed point in scalar registers); a lane only tests its bound,
+// reads and adds.  Four partial sums (element k into sum k mod 4, FP32).
+__device__ __forceinline__ float fold_sum_wave(const float *s_e, int32_t L, uint64_t R, int32_t ph0, int lane,
+                                               int32_t &n) {
     float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     int32_t cnt = 0;
-    uint32_t hi = 0, lo = 0x80000000u;  // + 1/2: round half up
-    const uint32_t lim = (uint32_t)(L - ph);  // ph < L
-    bool done = false;
-    while (!done) {
+    const uint32_t Rh = __builtin_amdgcn_readfirstlane((uint32_t)(R >> 32));
+    const uint32_t Rl = __builtin_amdgcn_readfirstlane((uint32_t)R);
+    const uint64_t step = ((uint64_t)Rh << 32) | Rl;
+    uint64_t o = 2147483648ull;  // + 1/2: round half up
+    const uint32_t uL = (uint32_t)L;
+    const uint32_t ph = (uint32_t)(ph0 + lane);
+    const uint32_t lim0 = uL - (uint32_t)ph0;  // ph0 < L: lane 0 is in range at transit 0
+    // groups of four transits, branch-free inside: out-of-range elements read
+    // a clamped index and add zero, so the four LDS reads are in flight together
+    while ((uint32_t)(o >> 32) < lim0) {
+        uint32_t x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (hi >= lim) {
-                done = true;
-                break;
-            }
-            a[u] += s_e[ph + hi];
-            ++cnt;
-            const uint32_t l2 = lo + Rl;
-            hi += Rh + (l2 < lo ? 1u : 0u);
-            lo = l2;
+            x[u] = ph + (uint32_t)(o >> 32);
+            o += step;
+        }
+        float val[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) val[u] = s_e[x[u] < uL ? x[u] : uL - 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = x[u] < uL;
+            a[u] += in ? val[u] : 0.0f;
+            cnt += in ? 1 : 0;
         }
     }
     n = cnt;
@@ -176,11 +186,11 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
             const uint64_t R = trial_step(trials[w * S + q]);
             if (R == 0) continue;
             const int32_t n_ph = (int32_t)min<uint64_t>((uint64_t)L, (R + 4294967295ull) >> 32);
-            const uint32_t Rh = (uint32_t)(R >> 32), Rl = (uint32_t)R;
-            for (int32_t ph = lane; ph < n_ph; ph += 64) {
+            for (int32_t ph0 = 0; ph0 < n_ph; ph0 += 64) {
+                const int32_t ph = ph0 + lane;
                 int32_t n = 0;
-                const float acc = fold_sum(s_e, L, Rh, Rl, ph, n);
-                if (acc * rsqrtf((float)n) < cut) continue;
+                const float acc = fold_sum_wave(s_e, L, R, ph0, lane, n);
+                if (ph >= n_ph || acc * rsqrtf((float)n) < cut) continue;
                 const double sc = (double)acc / sqrt((double)n);
                 const int32_t jj = q * n_ph_max + ph;
                 if (sc > best || (sc == best && jj < bj)) {
@@ -273,41 +283,65 @@ __global__ void bce_kernel(const float *__restrict__ z, const float *__restrict_
     if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
 }
 
-// Head backward: gradients of U, u, v, v0 (wave reductions + atomics) and of
-// the window features gf[b][w][k].
+// Head backward: the window-feature gradients gf[b][w][k] per row, and the
+// parameter gradients summed over the workgroup's kHeadRows rows in LDS
+// (per-row terms staged there; one thread per parameter sums them), so each
+// workgroup adds one FP32 atomic per parameter.
+constexpr int kHeadRows = 64;
 __global__ void __launch_bounds__(kT) head_bwd_kernel(const float *__restrict__ f, int64_t n_bw, int32_t nf,
                                                       const float *__restrict__ U, const float *__restrict__ u,
                                                       const float *__restrict__ v, int32_t H,
                                                       const float *__restrict__ gz, float *__restrict__ gU,
                                                       float *__restrict__ gu, float *__restrict__ gv,
                                                       float *__restrict__ gv0, float *__restrict__ gf) {
-    const int64_t bw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = bw < n_bw;
-    const int lane = threadIdx.x & 63;
-    const float g = ok ? gz[bw] : 0.0f;
-    float fv[2 * kMaxE + 1];
-    for (int k = 0; k < nf; ++k) fv[k] = ok ? f[bw * nf + k] : 0.0f;
-    float gfv[2 * kMaxE + 1];
-    for (int k = 0; k < nf; ++k) gfv[k] = 0.0f;
-    for (int hh = 0; hh < H; ++hh) {
-        float r = u[hh];
-        for (int k = 0; k < nf; ++k) r = fmaf(U[hh * nf + k], fv[k], r);
-        const float rr = fmaxf(r, 0.0f);
-        const float t1 = wave_sum(g * rr);
-        if (lane == 0) atomicAdd(&gv[hh], t1);
-        const float gp = r > 0.0f ? g * v[hh] : 0.0f;
-        const float t2 = wave_sum(gp);
-        if (lane == 0) atomicAdd(&gu[hh], t2);
-        for (int k = 0; k < nf; ++k) {
-            const float t3 = wave_sum(gp * fv[k]);
-            if (lane == 0) atomicAdd(&gU[hh * nf + k], t3);
-            gfv[k] = fmaf(U[hh * nf + k], gp, gfv[k]);
+    __shared__ float s_gp[kHeadRows][kMaxHidden + 1];   // dL/d(pre-activation) of the hidden units
+    __shared__ float s_grr[kHeadRows][kMaxHidden + 1];  // gz times the hidden activation
+    __shared__ float s_f[kHeadRows][2 * kMaxE + 1];
+    __shared__ float s_g[kHeadRows];
+    const int64_t row0 = (int64_t)blockIdx.x * kHeadRows;
+    for (int r = threadIdx.x; r < kHeadRows; r += blockDim.x) {
+        const int64_t bw = row0 + r;
+        const bool ok = bw < n_bw;
+        const float g = ok ? gz[bw] : 0.0f;
+        float fv[2 * kMaxE + 1];
+        for (int k = 0; k < nf; ++k) fv[k] = ok ? f[bw * nf + k] : 0.0f;
+        float gfv[2 * kMaxE + 1];
+        for (int k = 0; k < nf; ++k) gfv[k] = 0.0f;
+        for (int hh = 0; hh < H; ++hh) {
+            float pre = u[hh];
+            for (int k = 0; k < nf; ++k) pre = fmaf(U[hh * nf + k], fv[k], pre);
+            const float gp = pre > 0.0f ? g * v[hh] : 0.0f;
+            s_gp[r][hh] = gp;
+            s_grr[r][hh] = g * fmaxf(pre, 0.0f);
+            for (int k = 0; k < nf; ++k) gfv[k] = fmaf(U[hh * nf + k], gp, gfv[k]);
+        }
+        for (int k = 0; k < nf; ++k) s_f[r][k] = fv[k];
+        s_g[r] = g;
+        if (ok)
+            for (int k = 0; k < nf; ++k) gf[bw * nf + k] = gfv[k];
+    }
+    __syncthreads();
+    // parameters: gU[hh][k] (H nf), gu[hh] (H), gv[hh] (H), gv0 (1)
+    const int n_par = H * nf + 2 * H + 1;
+    for (int p = threadIdx.x; p < n_par; p += blockDim.x) {
+        float acc = 0.0f;
+        if (p < H * nf) {
+            const int hh = p / nf, k = p % nf;
+            for (int r = 0; r < kHeadRows; ++r) acc = fmaf(s_gp[r][hh], s_f[r][k], acc);
+            atomicAdd(&gU[p], acc);
+        } else if (p < H * nf + H) {
+            const int hh = p - H * nf;
+            for (int r = 0; r < kHeadRows; ++r) acc += s_gp[r][hh];
+            atomicAdd(&gu[hh], acc);
+        } else if (p < H * nf + 2 * H) {
+            const int hh = p - H * nf - H;
+            for (int r = 0; r < kHeadRows; ++r) acc += s_grr[r][hh];
+            atomicAdd(&gv[hh], acc);
+        } else {
+            for (int r = 0; r < kHeadRows; ++r) acc += s_g[r];
+            atomicAdd(gv0, acc);
         }
     }
-    const float t4 = wave_sum(g);
-    if (lane == 0) atomicAdd(gv0, t4);
-    if (ok)
-        for (int k = 0; k < nf; ++k) gf[bw * nf + k] = gfv[k];
 }
 
 // Adam on FP32 master parameters.
@@ -504,7 +538,7 @@ extern "C" int cetra_net_head_bwd(void *stream, const float *f, int64_t n_bw, in
     clear_error();
     CETRA_REQUIRE(f && U && u && v && gz && gU && gu && gv && gv0 && gf, "net_head_bwd: NULL pointer");
     CETRA_REQUIRE(nf >= 1 && nf <= 2 * kMaxE + 1 && H >= 1 && H <= kMaxHidden, "net_head_bwd: bad sizes");
-    hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_bw, 1), kT)), dim3(kT), 0,
+    hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_bw, 1), kHeadRows)), dim3(kT), 0,
                        as_stream(stream), f, n_bw, nf, U, u, v, H, gz, gU, gu, gv, gv0, gf);
     return check_launch("net_head_bwd");
 }
