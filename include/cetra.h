@@ -290,6 +290,18 @@ int cetra_single_events_workspace(int32_t n_events, size_t *bytes);
 int cetra_single_events(void *stream, const cetra_grid *grid, const float *fold, int32_t n_events, void *work,
                         size_t work_bytes, cetra_event *out);
 
+/* Per-period merge of n_sets period searches stacked set after set (device
+ * arrays [n_sets][n_periods], as cetra_periodic_search writes them), e.g.
+ * one per template when searching across a sequence of impact parameters
+ * (Sec. 2.1.2): each output period takes the record of the set with the
+ * largest LR (ties: the smaller set index); null records (epoch -1) never
+ * win over a valid one, and a period null in every set stays null.
+ * out_set[k] (device int32) is the winning set, -1 if none. */
+int cetra_periodic_merge(void *stream, int32_t n_sets, int64_t n_periods, const float *lr, const int32_t *epoch,
+                         const int32_t *dur, const float *depth, const float *depth_var, float *out_lr,
+                         int32_t *out_epoch, int32_t *out_dur, float *out_depth, float *out_depth_var,
+                         int32_t *out_set);
+
 /* Nulls a found signal for the next search (the iterative search of Sec. 5,
  * which nullifies the flux in and around the strongest signal before
  * searching again): every resampled point q (time q c after t_origin) with

@@ -87,3 +87,23 @@ def iterative(wl, n_signals: int, width: float = 1.5, sel=None):
         j = per["j"][kb]
         flux, ivar = mask(g, flux, ivar, periods[k], per["i"][kb] * g.t0_step, g.durations_array[j], width)
     return passes
+
+
+def multi_template(wl, denses, sel=None):
+    """One oracle search per template on the same light curve, merged per
+    period: the largest likelihood ratio, ties to the earlier template; a
+    null record (epoch -1) never wins over a valid one."""
+    runs = []
+    for dense in denses:
+        w2 = type(wl)(**{**wl.__dict__, "dense": dense})
+        runs.append(oracle.search(w2, sel=sel))
+    per = [r["periodic"] for r in runs]
+    K = len(per[0]["lr"])
+    win = np.full(K, -1, dtype=np.int64)
+    for k in range(K):
+        for s_, p in enumerate(per):
+            if p["i"][k] < 0:
+                continue
+            if win[k] < 0 or p["lr"][k] > per[win[k]]["lr"][k]:
+                win[k] = s_
+    return runs, win

@@ -286,6 +286,45 @@ def iterative_search(t, f, sigma, cadence: float, durations, periods, dense, n_s
     return found
 
 
+def multi_template_search(t, f, sigma, cadence: float, durations, periods, denses, n_model: int = 1024,
+                          t0_step: float = 0.0, jrange=None, stream=None) -> dict:
+    """The search run once per template (e.g. a sequence of impact
+    parameters, Sec. 2.1.2) on one resampled light curve, merged per period
+    (cetra_periodic_merge: largest LR, ties to the earlier template).
+    Returns the merged per-period records, the winning template per period
+    ("set") and the best record with its template index."""
+    torch = _torch()
+    t_host = np.asarray(t) if not hasattr(t, "cpu") else t.cpu().numpy()
+    grid = grid_plan(t_host[0], t_host[-1], cadence, durations, t0_step, n_model)
+    flux, ivar, _ = resample(grid, t, f, sigma, status=False, stream=stream)
+    per_d = _dev(periods, torch.float64)
+    K = per_d.numel()
+    T = len(denses)
+    dev = per_d.device
+    stack = dict(lr=torch.empty((T, K), dtype=torch.float32, device=dev),
+                 epoch=torch.empty((T, K), dtype=torch.int32, device=dev),
+                 dur=torch.empty((T, K), dtype=torch.int32, device=dev),
+                 depth=torch.empty((T, K), dtype=torch.float32, device=dev),
+                 depth_var=torch.empty((T, K), dtype=torch.float32, device=dev))
+    work = torch.empty(max(periodic_workspace(grid, K), 1), dtype=torch.uint8, device=dev)
+    fold = None
+    for s_, dense in enumerate(denses):
+        model = template_resample(dense, n_model, stream=stream)
+        fold = linear_search(grid, flux, ivar, model, fold=fold, stream=stream)
+        periodic_search(grid, fold, per_d, jrange=jrange, work=work, out={k: v[s_] for k, v in stack.items()},
+                        stream=stream)
+    out = {k: torch.empty(K, dtype=v.dtype, device=dev) for k, v in stack.items()}
+    out["set"] = torch.empty(K, dtype=torch.int32, device=dev)
+    _abi.check(_abi.load().cetra_periodic_merge(_stream(stream), T, K, _ptr(stack["lr"]), _ptr(stack["epoch"]),
+                                                _ptr(stack["dur"]), _ptr(stack["depth"]), _ptr(stack["depth_var"]),
+                                                _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]),
+                                                _ptr(out["depth"]), _ptr(out["depth_var"]), _ptr(out["set"])))
+    per = {k: out[k] for k in ("lr", "epoch", "dur", "depth", "depth_var")}
+    b = best_record(best(grid, per_d, per, stream=stream))
+    b["template"] = int(out["set"][b["k"]].item()) if b["k"] >= 0 else -1
+    return dict(grid=grid, periodic=per, set=out["set"], best=b)
+
+
 def best_record(raw) -> dict:
     """Host copy of a cetra_best_record produced by ``best``."""
     b = BestRecord.from_buffer_copy(bytes(raw.cpu().numpy().tobytes()))

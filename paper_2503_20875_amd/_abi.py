@@ -125,6 +125,7 @@ SIGNATURES = {
     "cetra_single_events_workspace": (ctypes.c_int, [_i32, ctypes.POINTER(ctypes.c_size_t)]),
     "cetra_single_events": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _i32, _P, ctypes.c_size_t, _P]),
     "cetra_mask_transits": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _d, _d, _d, _d, _P, _P]),
+    "cetra_periodic_merge": (ctypes.c_int, [_P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "cetra_duration_limits": (ctypes.c_int, [_d, _d, _d, _d, _d, _P, _P]),
     "cetra_keplerian_jrange": (ctypes.c_int, [_P, _i64, _P, _i32, _d, _d, _d, _d, _P]),
     "cetra_template_resample": (ctypes.c_int, [_P, _P, _i64, _i32, _P]),

@@ -1,8 +1,10 @@
-// Single-event (monotransit) search over the linear search's results, and
-// the nulling of a found signal's transits for the next search (Sec. 1 and
+// Single-event (monotransit) search over the linear search's results, the
+// nulling of a found signal's transits for the next search (Sec. 1 and
 // Sec. 5: single transits are searched for in the linear-search output; a
 // multi-planet search re-runs after nulling the flux in and around the
-// strongest signal).
+// strongest signal), and the per-period merge of searches run with several
+// templates (Sec. 2.1.2 suggests searching across a sequence of impact
+// parameters).
 #include <cmath>
 
 #include "common.h"
@@ -111,7 +113,56 @@ __global__ void mask_kernel(int64_t n, double cadence, double period, double t0,
     }
 }
 
+// Per period, the record with the largest LR over n_sets stacked period
+// searches (ties: the first set); null records never win over a valid one.
+__global__ void merge_kernel(int32_t n_sets, int64_t n, const float *__restrict__ lr, const int32_t *__restrict__ ep,
+                             const int32_t *__restrict__ du, const float *__restrict__ z,
+                             const float *__restrict__ zv, float *__restrict__ o_lr, int32_t *__restrict__ o_ep,
+                             int32_t *__restrict__ o_du, float *__restrict__ o_z, float *__restrict__ o_zv,
+                             int32_t *__restrict__ o_set) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int32_t best = -1;
+    for (int32_t s = 0; s < n_sets; ++s) {
+        const int64_t q = (int64_t)s * n + k;
+        if (ep[q] < 0) continue;
+        if (best < 0 || lr[q] > lr[(int64_t)best * n + k]) best = s;
+    }
+    if (best < 0) {
+        o_lr[k] = 0.0f;
+        o_ep[k] = -1;
+        o_du[k] = -1;
+        o_z[k] = __builtin_nanf("");
+        o_zv[k] = __builtin_inff();
+        o_set[k] = -1;
+        return;
+    }
+    const int64_t q = (int64_t)best * n + k;
+    o_lr[k] = lr[q];
+    o_ep[k] = ep[q];
+    o_du[k] = du[q];
+    o_z[k] = z[q];
+    o_zv[k] = zv[q];
+    o_set[k] = best;
+}
+
 }  // namespace
+
+extern "C" int cetra_periodic_merge(void *stream, int32_t n_sets, int64_t n_periods, const float *lr,
+                                    const int32_t *epoch, const int32_t *dur, const float *depth,
+                                    const float *depth_var, float *out_lr, int32_t *out_epoch, int32_t *out_dur,
+                                    float *out_depth, float *out_depth_var, int32_t *out_set) {
+    clear_error();
+    CETRA_REQUIRE(n_sets >= 1 && n_periods >= 0, "periodic_merge: bad sizes");
+    CETRA_REQUIRE(n_periods == 0 || (lr && epoch && dur && depth && depth_var && out_lr && out_epoch && out_dur &&
+                                     out_depth && out_depth_var && out_set),
+                  "periodic_merge: NULL pointer");
+    if (n_periods == 0) return CETRA_OK;
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)ceil_div(n_periods, 256)), dim3(256), 0, as_stream(stream),
+                       n_sets, n_periods, lr, epoch, dur, depth, depth_var, out_lr, out_epoch, out_dur, out_depth,
+                       out_depth_var, out_set);
+    return check_launch("periodic_merge");
+}
 
 extern "C" int cetra_single_events_workspace(int32_t n_events, size_t *bytes) {
     clear_error();

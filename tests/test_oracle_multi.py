@@ -101,3 +101,14 @@ def test_mask_nulls_exactly_the_transit_windows(ora, period, width):
     got = set(np.flatnonzero((mi == 0) & (ivar != 0)))
     assert got == {q for q in want if ivar[q] != 0}
     assert np.all(mf[list(want)] == 0)
+
+
+def test_multi_template_ties_go_to_the_first():
+    # two identical templates give identical searches: every period's
+    # record is a tie, which the merge resolves to the first template
+    from synthlc import workloads as W
+    wl = W.tiny_single()
+    sel = np.arange(0, len(wl.periods), 50)
+    runs, win = multi.multi_template(wl, [wl.dense, wl.dense.copy()], sel=sel)
+    assert np.array_equal(runs[0]["periodic"]["lr"], runs[1]["periodic"]["lr"])
+    assert np.all(win[runs[0]["periodic"]["i"] >= 0] == 0)
