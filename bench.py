@@ -30,6 +30,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_high_cadence_counters.json")
+PROFILE_PIPELINE = os.path.join(ROOT, "profiles", "fold_high_cadence_pipeline_counters.json")
+# Vector-memory load path of one CU: the address unit takes a 16-lane quarter
+# of a wave load per cycle, at most 16 bytes per lane, i.e. 64 B per cycle.
+L1_PEAK_GBS = 64.0 * 256 * 2.4
 FOLD_SOURCES = [os.path.join(ROOT, "paper_2503_20875_amd", "csrc", name) for name in ("fold.hip", "stages.h")]
 PROPOSAL_WEIGHTS = os.path.join(ROOT, "paper_2503_20875_amd", "weights", "proposal.npz")
 
@@ -510,6 +514,14 @@ def main():
             prof = json.load(fh)
         if prof.get("fold_source_sha256_16") == fold_source_hash() and prof.get("workload") == args.workload:
             traffic = prof.get("hbm_bytes_per_launch")
+    ta_busy = None
+    if os.path.exists(PROFILE_PIPELINE):
+        with open(PROFILE_PIPELINE) as fh:
+            pipe = json.load(fh)
+        if (pipe.get("fold_source_sha256_16") == fold_source_hash() and pipe.get("workload") == args.workload
+                and pipe.get("tuning") == [cm.get_tuning()[k] for k in ("fold_period_block", "fold_wgs_per_cu",
+                                                                          "fold_units_per_wg", "fold_variant")]):
+            ta_busy = pipe.get("ta_busy_frac")
     lin_s = float(np.mean(ms_lin)) / 1e3
     value = wl.n_obs * K / (ms_step / 1e3)
     out = {
@@ -544,6 +556,17 @@ def main():
             "algorithmic_bytes_per_launch": work_alg["fold_bytes"],
             "avg_launch_ms": fold_s * 1e3,
             "tuning": cm.get_tuning(),
+        },
+        "roofline_l1": {
+            "kernel": "fold_kernel (periodic search)",
+            "bound": "vector-memory address unit (cache-resident working set)",
+            "achieved": achieved,
+            "peak": L1_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / L1_PEAK_GBS,
+            "ta_busy_frac": ta_busy,
+            "note": "achieved counts 8 B per element visit; transit 0 of a period block is one load for all its "
+                    "periods, so the bytes the unit delivers are slightly fewer",
         },
         "roofline_linear": {
             "kernel": "linear_kernel (linear search, all durations)",
