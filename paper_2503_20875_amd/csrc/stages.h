@@ -443,21 +443,23 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
     }
 }
 
-// Wave-private LDS fold unit (variant 3).  At each transit step the B
-// periods of the block read B windows of 128 epochs that overlap: they all lie
-// inside [o_slow, min(o_fast, lim) + 128) relative to the wave's first epoch,
-// with o_slow and o_fast the offsets of the periods with the smallest and
-// largest step (offsets grow with the step).  When that union fits kFoldWCap
-// pairs the wave loads it once with 16-byte loads (out-of-row pairs read zero)
-// into its own half of a double buffer and serves every period from there, so
-// a step costs ceil(span / 128) global loads instead of B; the next step's
-// window is loaded into registers while this step is summed.  Lane l owns
-// epochs e_wave + l and e_wave + 64 + l, so each half of a period's LDS read
-// is 512 contiguous bytes (no bank conflicts).  The buffer is private to the
-// wave and LDS operations of one wave complete in issue order, so no barrier
-// is needed.  A step whose union is wider is summed with direct loads.  Every
-// epoch receives the same values in the same order as in fold_unit, so the
-// sums, the keys and the records are bit-identical to variants 0 and 2.
+// Wave-private LDS fold unit (variant 3).  At transit step m the B periods
+// of the block read windows of 128 epochs at offsets o_b(m) that lie in
+// [o_slow(m), o_slow(m) + spread], o_slow being the offset of the period with
+// the smallest step (offsets grow with the step).  Over a tile the spread is
+// largest at the last step and is bounded before the tile starts; when the
+// bound leaves room in a kFoldWCap-pair buffer the whole tile runs from LDS:
+// per step the wave loads the union window once with 16-byte loads
+// (out-of-row pairs read zero, which also serves periods already past the
+// row end) into its half of a private double buffer, the next step's window
+// is loaded into registers while this step is summed, and every period reads
+// its window from LDS at o_b - o_slow.  Lane l owns epochs e_wave + l and
+// e_wave + 64 + l, so each half of a period's LDS read is 512 contiguous
+// bytes (no bank conflicts).  The buffer is private to the wave and LDS
+// operations of one wave complete in issue order, so no barrier is needed.
+// A tile whose bound is too wide is summed with direct loads.  Every epoch
+// receives the same values in the same order as in fold_unit, so the sums,
+// the keys and the records are bit-identical to variants 0 and 2.
 constexpr int kFoldWCap = 384;             // pairs per half of a wave's double buffer (3 KB)
 constexpr int kFoldWLd = kFoldWCap / 128;  // 16-byte loads per lane for a full window
 
@@ -487,8 +489,10 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
     }
     const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
     const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
-    const uint32_t Rh_max = __builtin_amdgcn_readfirstlane((uint32_t)(r_max >> 32));
-    const uint32_t Rl_max = __builtin_amdgcn_readfirstlane((uint32_t)r_max);
+    // o_b(m) - o_slow(m) <= m (R_max - R_min) / 2^32 + 1, and a tile's steps
+    // m satisfy o_slow(m) < lim, i.e. m < (lim + 1/2) 2^32 / R_min
+    const double steps_per_epoch = 4294967296.0 / (double)r_min;
+    const double spread_per_step = (double)(r_max - r_min) / 4294967296.0;
     uint64_t best[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) best[b] = 0;
@@ -498,8 +502,16 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
         if (e_wave >= e_hi) break;
         const int32_t e = e_wave + lane;  // epochs e and e + 64
         const uint32_t e_bytes = (uint32_t)e * 8u;
-        const uint32_t w_bytes = (uint32_t)(e_wave + 2 * lane) * 8u;  // this lane's 16 bytes of a window
         const uint32_t lim = uI - (uint32_t)e_wave;
+        // steps m < m_lds run from LDS: there the spread bound leaves room in
+        // the buffer; later steps (if any) use direct loads
+        const double m_max = ((double)lim + 0.5) * steps_per_epoch;
+        const double m_fit = spread_per_step > 0.0 ? ((double)(kFoldWCap - 128) - 2.0) / spread_per_step : m_max;
+        const double m_cut = fmin(m_max, fmax(m_fit, 0.0));
+        const int32_t m_lds = (int32_t)fmin(m_cut, 2.0e9);                       // wave-uniform
+        const double spread = (double)m_lds * spread_per_step + 2.0;
+        const int n_ld = (int)((spread + 128.0 + 127.0) / 128.0);                // window loads per step
+        const bool in_lds = m_lds > 1;
         float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
         uint32_t hi[B], lo[B];
 #pragma unroll
@@ -509,7 +521,7 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
             hi[b] = 0;
             lo[b] = 0x80000000u;  // + 1/2: round half up
         }
-        uint32_t h_min = 0, l_min = 0x80000000u, h_max = 0, l_max = 0x80000000u;
+        uint32_t h_min = 0, l_min = 0x80000000u;
         {
             // transit 0 sits at offset 0 for every period: one load serves the block
             const float2 v0 = load_pair(rsrc, e_bytes, 0);
@@ -520,8 +532,6 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
                 hi[b] = min(hi[b], uI);
             }
             acc_add(l_min, h_min, Rl_min, Rh_min);
-            acc_add(l_max, h_max, Rl_max, Rh_max);
-            h_max = min(h_max, uI);
 #pragma unroll
             for (int b = 0; b < B; ++b) {
                 a0[b] += v0.x;
@@ -531,56 +541,45 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
             }
         }
         int n_in_chunk = 1;
-        bool have = h_min < lim;
-        uint32_t ws = h_min;
-        uint32_t span = have ? min(h_max, lim) - ws + 128u : 0u;
-        bool in_lds = span <= (uint32_t)kFoldWCap;
-        int half = 0;
-        float4 pf[kFoldWLd];
-        if (have && in_lds) {
-#pragma unroll
-            for (int k = 0; k < kFoldWLd; ++k)
-                if ((uint32_t)(k * 128) < span) pf[k] = load_quad(rsrc, w_bytes + (ws + 128u * k) * 8u);
-            float4 *dst = reinterpret_cast<float4 *>(s_wave);
-#pragma unroll
-            for (int k = 0; k < kFoldWLd; ++k)
-                if ((uint32_t)(k * 128) < span) dst[64 * k + lane] = pf[k];
-        }
-        while (have) {
-            uint32_t o[B];  // this step's offsets, out-of-row ones clamped to the row end
-#pragma unroll
-            for (int b = 0; b < B; ++b) o[b] = min(hi[b], lim);
-            const uint32_t ws_c = ws;
-            const bool in_lds_c = in_lds;
-            // advance to the next step and start loading its window
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                hi[b] = min(hi[b], uI);
-            }
-            acc_add(l_min, h_min, Rl_min, Rh_min);
-            acc_add(l_max, h_max, Rl_max, Rh_max);
-            h_max = min(h_max, uI);
-            have = h_min < lim;
-            ws = h_min;
-            span = have ? min(h_max, lim) - ws + 128u : 0u;
-            in_lds = span <= (uint32_t)kFoldWCap;
-            const bool pre = have && in_lds;
-            if (pre) {
+        int32_t m = 1;  // the next step
+        if (in_lds) {
+            const uint32_t w_bytes = (uint32_t)(e_wave + 2 * lane) * 8u;  // this lane's 16 bytes of a window
+            float4 pf[kFoldWLd];
+            bool have = h_min < lim && m < m_lds;
+            if (have) {
 #pragma unroll
                 for (int k = 0; k < kFoldWLd; ++k)
-                    if ((uint32_t)(k * 128) < span) pf[k] = load_quad(rsrc, w_bytes + (ws + 128u * k) * 8u);
+                    if (k < n_ld) pf[k] = load_quad(rsrc, w_bytes + (h_min + 128u * k) * 8u);
+                float4 *dst = reinterpret_cast<float4 *>(s_wave);
+#pragma unroll
+                for (int k = 0; k < kFoldWLd; ++k)
+                    if (k < n_ld) dst[64 * k + lane] = pf[k];
             }
-            // each branch consumes its own reads, so the LDS branch never
-            // waits on the global loads of the prefetch
-            if (in_lds_c) {
+            int half = 0;
+            while (have) {
+                uint32_t q[B];  // this step's window positions; the buffer covers them
+#pragma unroll
+                for (int b = 0; b < B; ++b) q[b] = hi[b] - h_min;
+                // advance to the next step and start loading its window
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                    hi[b] = min(hi[b], uI);
+                }
+                acc_add(l_min, h_min, Rl_min, Rh_min);
+                ++m;
+                have = h_min < lim && m < m_lds;
+                if (have) {
+#pragma unroll
+                    for (int k = 0; k < kFoldWLd; ++k)
+                        if (k < n_ld) pf[k] = load_quad(rsrc, w_bytes + (h_min + 128u * k) * 8u);
+                }
                 const float2 *buf = s_wave + half * kFoldWCap + lane;
                 float2 v0[B], v1[B];
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    const uint32_t q = o[b] - ws_c;
-                    v0[b] = buf[q];
-                    v1[b] = buf[q + 64];
+                    v0[b] = buf[q[b]];
+                    v1[b] = buf[q[b] + 64];
                 }
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
@@ -589,16 +588,41 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
                     a1[b] += v1[b].x;
                     s1[b] += v1[b].y;
                 }
-                // distinct markers end the two branches, so their identical
-                // adds are not merged into one block after the branch
-                asm volatile("; fold step from LDS");
-            } else {
+                if (++n_in_chunk == kFoldChunk) {
+                    n_in_chunk = 0;
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        ta0[b] += a0[b];
+                        ts0[b] += s0[b];
+                        ta1[b] += a1[b];
+                        ts1[b] += s1[b];
+                        a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                    }
+                }
+                if (have) {
+                    float4 *dst = reinterpret_cast<float4 *>(s_wave + (half ^ 1) * kFoldWCap);
+#pragma unroll
+                    for (int k = 0; k < kFoldWLd; ++k)
+                        if (k < n_ld) dst[64 * k + lane] = pf[k];
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);  // keep the next reads after these writes
+                half ^= 1;
+            }
+        }
+        {
+            while (h_min < lim) {
                 float2 v0[B], v1[B];
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
-                    v0[b] = load_pair(rsrc, e_bytes + o[b] * 8u, 0);
-                    v1[b] = load_pair(rsrc, e_bytes + o[b] * 8u, 64 * 8);
+                    v0[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 0);
+                    v1[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 64 * 8);
                 }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                    hi[b] = min(hi[b], uI);
+                }
+                acc_add(l_min, h_min, Rl_min, Rh_min);
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     a0[b] += v0[b].x;
@@ -606,27 +630,18 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
                     a1[b] += v1[b].x;
                     s1[b] += v1[b].y;
                 }
-                asm volatile("; fold step from direct loads");
-            }
-            if (++n_in_chunk == kFoldChunk) {
-                n_in_chunk = 0;
+                if (++n_in_chunk == kFoldChunk) {
+                    n_in_chunk = 0;
 #pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    ta0[b] += a0[b];
-                    ts0[b] += s0[b];
-                    ta1[b] += a1[b];
-                    ts1[b] += s1[b];
-                    a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                    for (int b = 0; b < B; ++b) {
+                        ta0[b] += a0[b];
+                        ts0[b] += s0[b];
+                        ta1[b] += a1[b];
+                        ts1[b] += s1[b];
+                        a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                    }
                 }
             }
-            if (pre) {
-                float4 *dst = reinterpret_cast<float4 *>(s_wave + (half ^ 1) * kFoldWCap);
-#pragma unroll
-                for (int k = 0; k < kFoldWLd; ++k)
-                    if ((uint32_t)(k * 128) < span) dst[64 * k + lane] = pf[k];
-            }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);  // keep the next reads after these writes
-            half ^= 1;
         }
 #pragma unroll
         for (int b = 0; b < B; ++b) {
