@@ -1,0 +1,82 @@
+"""Evaluate a trained period-window proposal against the plain periodic
+search on held-out curves of the learned-proposal workload.
+
+The first half of the curves (calibration, run at K = 64 windows without a
+fallback) fixes two operating points that keep `target` of the plain
+detections above SNR 7: the smallest number of windows K whose top-K holds
+them, and the smallest restricted-SNR threshold of the full-fold fallback at
+K = 64.  The second half (test) runs K = 64 alone, the calibrated K, and
+K = 64 with the calibrated fallback, and reports recall (over all plain
+detections and over those of injected planets) and the device-time speedup
+over the full periodic search, fallback runs included.
+
+    python -m paper_2503_20875_amd.eval_proposal --weights weights/proposal.npz --n 1000 --out eval.json
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+
+def log(msg: str) -> None:
+    print(f"[eval] {msg}", flush=True)
+
+
+def summary(r: dict) -> dict:
+    keys = ("top_k", "fallback_snr", "n_detections", "n_recalled", "recall", "n_true_detections", "recall_true",
+            "plain_ms_per_curve", "learned_ms_per_curve", "speedup", "periods_folded_fraction", "fallback_fraction")
+    return {k: r[k] for k in keys}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    here = os.path.dirname(os.path.abspath(__file__))
+    ap.add_argument("--weights", default=os.path.join(here, "weights", "proposal.npz"))
+    ap.add_argument("--n", type=int, default=1000, help="held-out curves (half calibration, half test)")
+    ap.add_argument("--target", type=float, default=0.99)
+    ap.add_argument("--seed", type=int, default=20250410)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    import torch
+    if not torch.cuda.is_available():
+        print("eval_proposal: no GPU", file=sys.stderr)
+        return 2
+    from synthlc import workloads as W
+    from .learned import evaluate, fallback_threshold, k_for_recall, load_weights
+    from .train_proposal import make_pipeline
+    net, meta = load_weights(a.weights)
+    pipe = make_pipeline()
+    n_cal = a.n // 2
+    rng_cal, rng_test = np.random.default_rng(a.seed), np.random.default_rng(a.seed + 1)
+    cal = evaluate(pipe, net, [W.learned_curve(rng_cal) for _ in range(n_cal)], log=log)
+    k_target = k_for_recall(cal["ranks"], a.target, pipe.windows.n)
+    tau = fallback_threshold(cal["rows"], a.target)
+    log(f"calibration: {cal['n_detections']} detections, recall at K=64 {cal['recall']:.3f}; "
+        f"K for target {k_target}, fallback threshold {tau:.3f}")
+    test_curves = [W.learned_curve(rng_test) for _ in range(a.n - n_cal)]
+    out = {"n_curves": a.n, "seed": a.seed, "target_recall": a.target,
+           "calibration": {"k64": summary(cal), "k_for_target": k_target,
+                           "fallback_snr_for_target": tau if np.isfinite(tau) else None},
+           "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "batch", "lr", "seed")}}
+    test_k64 = evaluate(pipe, net, test_curves, top_k=64, log=log)
+    out["test_k64"] = summary(test_k64)
+    out["test_rank_recall"] = {K: float(np.mean(np.asarray(test_k64["ranks"]) < K))
+                               for K in (16, 32, 64, 96, 128, 192, 256, 384)}
+    out["test_k_target"] = summary(evaluate(pipe, net, test_curves, top_k=k_target, log=log))
+    out["test_fallback"] = summary(evaluate(pipe, net, test_curves, top_k=64,
+                                            fallback_snr=tau if np.isfinite(tau) else None, log=log))
+    text = json.dumps(out)
+    print(text, flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(text + "\n")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
