@@ -32,6 +32,7 @@ class LearnedConfig:
     p_hi: float = 100.0
     n_event: int = 8
     hidden: int = 64
+    feature_rows: tuple = ()  # duration rows read by the network (all when empty)
 
 
 class Pipeline:
@@ -41,8 +42,9 @@ class Pipeline:
     def __init__(self, t_first: float, t_last: float, cadence: float, durations, periods, dense,
                  cfg: LearnedConfig = LearnedConfig(), n_model: int = 1024):
         import torch
-        if len(durations) != C_IN:
-            raise ValueError(f"the proposal network reads {C_IN} durations")
+        rows = cfg.feature_rows or tuple(range(len(durations)))
+        if len(rows) != C_IN or max(rows) >= len(durations) or min(rows) < 0:
+            raise ValueError(f"the proposal network reads {C_IN} of the durations")
         self.cfg = cfg
         self.grid = grid_plan(t_first, t_last, cadence, durations, 0.0, n_model)
         self.model = template_resample(torch.as_tensor(np.asarray(dense, np.float64), device="cuda"), n_model)
@@ -56,6 +58,7 @@ class Pipeline:
         self.work = torch.empty(max(periodic_workspace(self.grid, self.K), 1), dtype=torch.uint8, device="cuda")
         self.per = None
         self.last_scores = None
+        self.rows = None if not cfg.feature_rows else torch.as_tensor(list(cfg.feature_rows), device="cuda")
 
     # ------------------------------------------------------------ features
     def linear(self, t, f, sigma):
@@ -64,7 +67,10 @@ class Pipeline:
         return linear_search(self.grid, flux, ivar, self.model)
 
     def features(self, fold, out=None):
-        """bf16 [n_bins][J] network input from a fold-ready array."""
+        """bf16 [n_bins][16] network input from a fold-ready array (its
+        feature rows only, when the grid has more durations)."""
+        if self.rows is not None:
+            fold = fold.index_select(0, self.rows)
         return downsample(fold, self.cfg.n_bins, out=out)
 
     # -------------------------------------------------------------- search
@@ -158,7 +164,7 @@ def load_weights(path: str) -> tuple:
 
 # ---------------------------------------------------------------- evaluation
 def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top_k: int = 0, fallback_snr=None,
-             log=None) -> dict:
+             log=None, plain=None) -> dict:
     """Plain search versus proposal + restricted search on each curve
     (t, f, sigma, injections).  A plain detection is a best period with
     SNR > snr_min; it is recalled when the learned search (restricted search
@@ -170,26 +176,34 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
     SNR, from which a fallback threshold can be chosen.  Times are device
     times per curve (events on the current stream): the plain periodic search
     + best, and downsample + network + top-K + subset + restricted search +
-    best (+ the fallback's full search when it runs)."""
+    best (+ the fallback's full search when it runs).  `plain`, the "plain"
+    list of an earlier evaluation of the same curves, reuses its full-search
+    records and times."""
     import torch
     top_k = int(top_k or pipe.cfg.top_k)
     n_det = n_hit = n_true = n_true_hit = n_fb = 0
     t_plain = t_learned = 0.0
     n_folded = 0
-    rows, ranks = [], []
+    rows, ranks, plain_out = [], [], []
     for ci, (t, f, s, injs) in enumerate(curves):
         fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
                            torch.as_tensor(s, device="cuda"))
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        e[0].record()
-        bp = pipe.plain(fold)
-        e[1].record()
+        if plain is None:
+            e[0].record()
+            bp = pipe.plain(fold)
+            e[1].record()
         e[2].record()
         bl, snr_r, fell_back, n_sub = pipe.search(net, fold, top_k, fallback_snr)
         e[3].record()
         torch.cuda.synchronize()
         z = pipe.last_scores
-        t_plain += e[0].elapsed_time(e[1])
+        if plain is None:
+            ms_plain = e[0].elapsed_time(e[1])
+        else:
+            bp, ms_plain = plain[ci]
+        plain_out.append((bp, ms_plain))
+        t_plain += ms_plain
         t_learned += e[2].elapsed_time(e[3])
         n_folded += n_sub
         n_fb += fell_back
@@ -219,7 +233,8 @@ def evaluate(pipe: Pipeline, net: ProposalNet, curves, snr_min: float = 7.0, top
                 recall=(n_hit / n_det) if n_det else None, n_true_detections=n_true,
                 recall_true=(n_true_hit / n_true) if n_true else None, plain_ms_per_curve=t_plain / n,
                 learned_ms_per_curve=t_learned / n, speedup=(t_plain / t_learned) if t_learned > 0 else None,
-                fallback_fraction=n_fb / n, periods_folded_fraction=n_folded / (n * pipe.K), ranks=ranks, rows=rows)
+                fallback_fraction=n_fb / n, periods_folded_fraction=n_folded / (n * pipe.K), ranks=ranks, rows=rows,
+                plain=plain_out)
 
 
 def fallback_threshold(rows, target: float) -> float:

@@ -25,14 +25,34 @@ def log(msg: str) -> None:
     print(f"[train] {msg}", flush=True)
 
 
-def make_pipeline(cfg=None):
+# Duration rows the network reads on the long-baseline grid (16 of its 30).
+LONG_FEATURE_ROWS = (0, 2, 4, 6, 8, 10, 12, 14, 15, 17, 19, 21, 23, 25, 27, 29)
+
+
+def make_pipeline(cfg=None, workload: str = "learned"):
+    """Search pipeline of the learned-proposal workload (80 000 points at
+    120 s, periods 1-100 d) or of the long-baseline workload (2.5 M points
+    at 25 s, periods 1-400 d, 16 of its 30 durations as network input)."""
     from synthlc import transit
     from synthlc import workloads as W
     from .learned import LearnedConfig, Pipeline
+    if workload == "long":
+        sh = W.long_baseline_shape()
+        return Pipeline(0.0, sh["span"], sh["cadence"], sh["durations"], sh["periods"], transit.dense_template(),
+                        cfg or LearnedConfig(p_lo=1.0, p_hi=400.0, feature_rows=LONG_FEATURE_ROWS))
     durations, periods = W.learned_grid()
     cad = 120.0 / 86400.0
     return Pipeline(0.0, (W.LEARNED_N_POINTS - 1) * cad, cad, durations, periods, transit.dense_template(),
                     cfg or LearnedConfig())
+
+
+def curve_source(workload: str, seed: int):
+    """A callable returning one (t, f, sigma, injections) curve per call."""
+    from synthlc import workloads as W
+    if workload == "long":
+        return W.LongCurves(seed).draw
+    rng = np.random.default_rng(seed)
+    return lambda: W.learned_curve(rng)
 
 
 LABEL_BAND = 0.02  # relative half-width of the labelled period band
@@ -55,19 +75,18 @@ def labels_for(pipe, injections) -> np.ndarray:
     return y
 
 
-def build_dataset(pipe, n: int, seed: int):
-    """Device features [n][n_bins][J] (bf16) and labels [n][W], plus the
+def build_dataset(pipe, n: int, seed: int, workload: str = "learned"):
+    """Device features [n][n_bins][16] (bf16) and labels [n][W], plus the
     injections of every curve."""
     import torch
-    from synthlc import workloads as W
-    rng = np.random.default_rng(seed)
-    x = torch.empty((n, pipe.cfg.n_bins, pipe.grid.n_dur), dtype=torch.bfloat16,
-                    device="cuda")
+    from .proposal import C_IN
+    draw = curve_source(workload, seed)
+    x = torch.empty((n, pipe.cfg.n_bins, C_IN), dtype=torch.bfloat16, device="cuda")
     y = np.zeros((n, pipe.windows.n), dtype=np.float32)
     injs = []
     t0 = time.time()
     for i in range(n):
-        t, f, s, inj = W.learned_curve(rng)
+        t, f, s, inj = draw()
         fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
                            torch.as_tensor(s, device="cuda"))
         pipe.features(fold, out=x[i])
@@ -88,6 +107,7 @@ def main(argv=None) -> int:
     ap.add_argument("--pos-weight", type=float, default=32.0)
     ap.add_argument("--seed", type=int, default=20250401)
     ap.add_argument("--n-trial", type=int, default=4)
+    ap.add_argument("--workload", default="learned", choices=["learned", "long"])
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -97,13 +117,14 @@ def main(argv=None) -> int:
         return 2
     from .learned import save_weights, train
     from .proposal import ProposalNet
-    pipe = make_pipeline()
+    pipe = make_pipeline(workload=a.workload)
     log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
         f"bin {pipe.windows.bin_days:.5f} d")
-    x, y, _ = build_dataset(pipe, a.n_train, a.seed)
+    x, y, _ = build_dataset(pipe, a.n_train, a.seed, a.workload)
     net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, n_trial=a.n_trial)
     losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)
-    meta = dict(n_event=net.E, hidden=net.H, pool="fold", n_trial=net.S, n_train=a.n_train, epochs=a.epochs,
+    meta = dict(n_event=net.E, hidden=net.H, pool="fold", n_trial=net.S, workload=a.workload,
+                feature_rows=list(pipe.cfg.feature_rows), n_train=a.n_train, epochs=a.epochs,
                 batch=a.batch, lr=a.lr,
                 pos_weight=a.pos_weight, seed=a.seed, losses=losses, n_bins=pipe.cfg.n_bins,
                 n_windows=pipe.cfg.n_windows, p_lo=pipe.cfg.p_lo, p_hi=pipe.cfg.p_hi)

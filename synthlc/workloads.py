@@ -354,3 +354,76 @@ def learned_grid():
     span = (LEARNED_N_POINTS - 1) * 120.0 / DAY_S
     periods = duty_cycle_periods(LEARNED_P_RANGE[0], LEARNED_P_RANGE[1], span, durations[0])
     return durations, periods
+
+
+# Long-baseline proposal workload: curves of the Earth-analogue set-up (730.5 d
+# at 25 s, white noise 200 ppm per point, 30 durations 1-20 h, 399 404
+# periods 1-400 d), half with one planet (P log-uniform 1-400 d, depth
+# log-uniform 20-400 ppm, b uniform 0-0.9 rounded to 0.01, circular orbit
+# around a Sun-density star).  Generated on the GPU: 2.5 M points per curve.
+LONG_P_RANGE = (1.0, 400.0)
+LONG_DEPTH_RANGE = (20e-6, 400e-6)
+LONG_SIGMA = 200e-6
+
+
+def long_grid():
+    """Durations (days) and periods of the long-baseline workload."""
+    wl = long_baseline_shape()
+    return wl["durations"], wl["periods"]
+
+
+def long_baseline_shape():
+    c = 25.0 / DAY_S
+    n = int(round(730.5 / c))
+    span = (n - 1) * c
+    durs = log_durations(1.0, 20.0, 30)
+    return dict(n=n, cadence=c, span=span, durations=durs,
+                periods=duty_cycle_periods(1.0, 400.0, span, durs[0], alpha=0.263))
+
+
+class LongCurves:
+    """Light curves of the long-baseline proposal workload, generated on a
+    torch device: the time grid is shared, the noise comes from a seeded
+    device generator and the injection parameters from a seeded numpy
+    generator.  draw() returns device (t, f, sigma) and the injections."""
+
+    def __init__(self, seed: int, device="cuda", planet_frac: float = 0.5):
+        import torch
+        sh = long_baseline_shape()
+        self.n, self.cadence = sh["n"], sh["cadence"]
+        self.torch = torch
+        self.device = device
+        self.t = torch.arange(self.n, dtype=torch.float64, device=device) * self.cadence
+        self.sigma = torch.full((self.n,), LONG_SIGMA, dtype=torch.float32, device=device)
+        self.rng = np.random.default_rng(seed)
+        self.gen = torch.Generator(device=device)
+        self.gen.manual_seed(int(seed))
+        self.planet_frac = planet_frac
+        self.dense = {}
+
+    def _dense(self, b: float):
+        if b not in self.dense:
+            self.dense[b] = self.torch.as_tensor(transit.dense_template(b=b), device=self.device)
+        return self.dense[b]
+
+    def draw(self):
+        torch = self.torch
+        off = -LONG_SIGMA * torch.randn(self.n, generator=self.gen, dtype=torch.float64, device=self.device)
+        injs = []
+        if self.rng.uniform() < self.planet_frac:
+            P = float(np.exp(self.rng.uniform(np.log(LONG_P_RANGE[0]), np.log(LONG_P_RANGE[1]))))
+            b = round(round(float(self.rng.uniform(0.0, 0.9)) / 0.01) * 0.01, 6)
+            dur = transit.transit_duration_days(P, b)
+            depth = float(np.exp(self.rng.uniform(np.log(LONG_DEPTH_RANGE[0]), np.log(LONG_DEPTH_RANGE[1]))))
+            inj = Injection(P, float(self.rng.uniform(0.0, P)), dur, depth, b)
+            dense = self._dense(b)
+            phase = torch.remainder(self.t - inj.epoch + 0.5 * P, P) - 0.5 * P
+            tau = phase / dur + 0.5
+            x = tau.clamp(0.0, 1.0) * (dense.shape[0] - 1)
+            i0 = x.floor().clamp(max=dense.shape[0] - 2).long()
+            w = x - i0
+            shape = dense[i0] * (1.0 - w) + dense[i0 + 1] * w
+            shape = torch.where((tau >= 0.0) & (tau <= 1.0), shape, torch.zeros_like(shape))
+            off = off + depth * shape
+            injs.append(inj)
+        return self.t, off.to(torch.float32), self.sigma, injs
