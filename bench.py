@@ -152,6 +152,41 @@ def batched_block(n_curves: int = 32, seed: int = 20250328) -> dict:
             "status": int(out["status"].item())}
 
 
+PROPOSAL_WEIGHTS_LONG = os.path.join(ROOT, "paper_2503_20875_amd", "weights", "proposal_long.npz")
+
+
+def learned_long_block(wl, top_k: int = 64) -> dict:
+    """The learned form on the Earth-analogue curve: the proposal trained
+    for two-year, 25-s curves picks the top_k of 512 windows over 1-400 d
+    and the periodic search folds their periods only; timed (downsample,
+    network, window selection, restricted fold, best) against the full
+    periodic search on the same fold-ready array, one warm-up each."""
+    if not os.path.exists(PROPOSAL_WEIGHTS_LONG):
+        return {"status": "no trained long-baseline proposal weights in the tree"}
+    import torch
+    from paper_2503_20875_amd.learned import load_weights
+    from paper_2503_20875_amd.train_proposal import make_pipeline
+    net, meta = load_weights(PROPOSAL_WEIGHTS_LONG)
+    pipe = make_pipeline(workload="long")
+    fold = pipe.linear(torch.as_tensor(wl.t, device="cuda"), torch.as_tensor(wl.f, device="cuda"),
+                       torch.as_tensor(wl.sigma, device="cuda"))
+    pipe.plain(fold)
+    pipe.search(net, fold, top_k)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    bp = pipe.plain(fold)
+    e[1].record()
+    e[2].record()
+    rec, _, _, n_sub = pipe.search(net, fold, top_k)
+    e[3].record()
+    torch.cuda.synchronize()
+    ms_plain, ms_learned = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])
+    return {"top_k": top_k, "periods_folded_fraction": n_sub / pipe.K, "plain_ms": ms_plain,
+            "learned_ms": ms_learned, "speedup": ms_plain / ms_learned,
+            "same_best": bool(rec is not None and rec["k"] == bp["k"]), "best_period": bp["period"],
+            "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "n_trial", "seed")}}
+
+
 def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> dict:
     """The Earth-analogue curve (730.5 d at 25 s: 2 524 608 points, J = 30,
     I = 1 755 200, K = 399 404): a 421 MB fold-ready array, larger than the
@@ -217,6 +252,7 @@ def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> 
     alg = algorithmic_work(wl, grid)
     fastest = min(fold_ms, key=fold_ms.get)
     gbps = alg["fold_bytes"] / (fold_ms[fastest] / 1e3) / 1e9
+    learned = learned_long_block(wl)
     return {"workload": (f"long baseline: {wl.n_obs} points at 25 s over 730.5 d, J = {grid.n_dur}, "
                          f"I = {grid.n_t0}, K = {K}; fold-ready array {grid.n_dur * grid.n_t0 * 8 / 1e6:.0f} MB"),
             "linear_ms": lin_ms, "fold_ms_by_tuning": fold_ms, "fastest_tuning": fastest,
@@ -226,6 +262,7 @@ def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> 
             "points_x_periods_per_s": wl.n_obs * K / ((lin_ms + fold_ms[fastest]) / 1e3),
             "best": {"period": rec["period"], "snr": rec["snr"], "duration": rec["duration"]},
             "monotransit_search_ms": mono_ms,
+            "learned": learned,
             "single_events": [{"t0_abs": e["t0_abs"], "duration": e["duration"], "snr": e["snr"]} for e in events[:3]]}
 
 

@@ -96,3 +96,30 @@ def test_trained_network_gain():
     blind = np.mean([pipe.window_of(x["plain_period"]) % 8 == 0 for x in rows])
     assert r["recall_true"] >= 0.75 and r["recall_true"] >= blind + 0.5
     assert r["speedup"] > 3.0
+
+
+def test_long_baseline_proposal_finds_the_earth_analogue():
+    """The proposal trained for the two-year, 25-s curves, on the Earth
+    analogue (P = 365.25 d, 100 ppm, 13 h, two transits): the search
+    restricted to its 64 best windows (about an eighth of the 399 404 periods)
+    returns the full search's best period."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_20875_amd.learned import load_weights
+    from paper_2503_20875_amd.train_proposal import make_pipeline
+    from synthlc import workloads as W
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2503_20875_amd", "weights", "proposal_long.npz")
+    net, meta = load_weights(path)
+    assert meta["workload"] == "long"
+    pipe = make_pipeline(workload="long")
+    wl = W.long_baseline()
+    print(f"[case] {wl.name}", flush=True)
+    fold = pipe.linear(torch.as_tensor(wl.t, device="cuda"), torch.as_tensor(wl.f, device="cuda"),
+                       torch.as_tensor(wl.sigma, device="cuda"))
+    bp = pipe.plain(fold)
+    rec, snr_r, fell_back, n_sub = pipe.search(net, fold, 64)
+    assert not fell_back and n_sub < pipe.K // 4
+    assert abs(bp["period"] / 365.25 - 1) < 0.002
+    assert rec["k"] == bp["k"] and rec["epoch"] == bp["epoch"] and rec["dur"] == bp["dur"]
