@@ -31,20 +31,44 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_high_cadence_counters.json")
 PROFILE_PIPELINE = os.path.join(ROOT, "profiles", "fold_high_cadence_pipeline_counters.json")
-# Vector-memory load path of one CU: the address unit takes a 16-lane quarter
-# of a wave load per cycle, at most 16 bytes per lane, i.e. 64 B per cycle.
+# Vector-memory load path of one CU: a wave load of 16 bytes per lane (1 KB)
+# keeps the address unit busy 16 cycles (its busy counter), i.e. 64 B per cycle.
 L1_PEAK_GBS = 64.0 * 256 * 2.4
 FOLD_SOURCES = [os.path.join(ROOT, "paper_2503_20875_amd", "csrc", name) for name in ("fold.hip", "stages.h")]
 PROPOSAL_WEIGHTS = os.path.join(ROOT, "paper_2503_20875_amd", "weights", "proposal.npz")
 
 
+def strip_comments(src: str) -> str:
+    """C++ source without its comments and blank lines (string and character
+    literals are kept as they are)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(line.rstrip() for line in "".join(out).splitlines() if line.strip())
+
+
 def fold_source_hash() -> str:
-    """Hash of the sources the fold kernel is compiled from (counter figures
-    are only reported for the kernel they were taken on)."""
+    """Hash of the code the fold kernel is compiled from, comments excluded
+    (counter figures are only reported for the kernel they were taken on)."""
     h = hashlib.sha256()
     for path in FOLD_SOURCES:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

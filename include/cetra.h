@@ -125,7 +125,10 @@ typedef struct cetra_tuning {
                                    2: register fold, adjacent lane epochs and
                                       16-byte loads;
                                    3: as 2, each wave staging its period block's
-                                      window in its own LDS buffer              */
+                                      window in its own LDS buffer;
+                                   4: as 3, the windows loaded straight into a
+                                      four-slot LDS ring per wave, three steps
+                                      ahead                                    */
     int32_t reserved[4];
 } cetra_tuning;
 

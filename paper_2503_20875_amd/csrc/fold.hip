@@ -104,15 +104,20 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 // chunk), ordered block-fastest; each unit is one dev::fold_unit (variant 0:
 // lane epochs 64 apart; 2: adjacent lane epochs, 16-byte loads),
 // dev::fold_unit_lds (variant 1: workgroup-wide LDS windows) or
-// dev::fold_unit_wlds (variant 3: wave-private LDS windows).
+// dev::fold_unit_wlds (variant 3: wave-private LDS windows) or
+// dev::fold_unit_dma (variant 4: wave-private LDS ring filled by
+// direct-to-LDS loads).
 template <int B, int kVariant>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
                                                         int32_t I, int32_t n_chunks, int64_t n_units) {
     constexpr bool kLds = kVariant == 1;
     constexpr bool kWaveLds = kVariant == 3;
+    constexpr bool kDma = kVariant == 4;
     // float4 storage keeps every window 16-byte aligned
-    __shared__ float4 s_mem[kLds ? cetra::dev::kFoldLdsCap
-                                 : kWaveLds ? (kThreads / 64) * cetra::dev::kFoldWCap : 1];
+    __shared__ float4 s_mem[kLds       ? cetra::dev::kFoldLdsCap
+                            : kWaveLds ? (kThreads / 64) * cetra::dev::kFoldWCap
+                            : kDma     ? (kThreads / 64) * cetra::dev::kFoldDmaSlots * cetra::dev::kFoldDmaCap / 2
+                                       : 1];
     float2 *s_buf = reinterpret_cast<float2 *>(s_mem);
     const int64_t n_pblk = (n_eval + B - 1) / B;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
@@ -143,6 +148,10 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
         else if (kWaveLds)
             cetra::dev::fold_unit_wlds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0,
                                           s_buf + (threadIdx.x >> 6) * 2 * cetra::dev::kFoldWCap);
+        else if (kDma)
+            cetra::dev::fold_unit_dma<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0,
+                                         s_buf + (threadIdx.x >> 6) * cetra::dev::kFoldDmaSlots *
+                                                     cetra::dev::kFoldDmaCap);
         else
             cetra::dev::fold_unit<B, kVariant == 2>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
     }
@@ -294,7 +303,10 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
         case 8: kern = (const void *)fold_kernel<16, 2>; break;
         case 9: kern = (const void *)fold_kernel<4, 3>; break;
         case 10: kern = (const void *)fold_kernel<8, 3>; break;
-        default: kern = (const void *)fold_kernel<16, 3>; break;
+        case 11: kern = (const void *)fold_kernel<16, 3>; break;
+        case 12: kern = (const void *)fold_kernel<4, 4>; break;
+        case 13: kern = (const void *)fold_kernel<8, 4>; break;
+        default: kern = (const void *)fold_kernel<16, 4>; break;
     }
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0) != hipSuccess || occ <= 0) occ = 1;

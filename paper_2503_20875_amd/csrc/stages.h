@@ -7,6 +7,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "cetra.h"
 
@@ -640,6 +641,272 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
                         ts1[b] += s1[b];
                         a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
                     }
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            ta0[b] += a0[b];
+            ts0[b] += s0[b];
+            ta1[b] += a1[b];
+            ts1[b] += s1[b];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int32_t eh = e + 64 * h;
+                const float A = h ? ta1[b] : ta0[b];
+                const float S = h ? ts1[b] : ts0[b];
+                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
+                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
+                best[b] = ok && key > best[b] ? key : best[b];
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t m = wave_max_u64(best[b]);
+        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
+    }
+}
+
+// Wave-private LDS ring filled by direct-to-LDS loads (variant 4).  The
+// windows, their bound and the summation are those of fold_unit_wlds, but a
+// step's union window goes from memory straight into LDS: with
+// buffer_load_dwordx4 ... lds, lane l's 16 bytes land at M0 + offset + 16 l
+// and dwords past the row end are written as zero.  No registers stage the
+// window, so the wave keeps the windows of up to kFoldDmaSlots - 1 later
+// steps in flight in a ring of kFoldDmaSlots slots while it sums the current
+// one.  The compiler does not track these loads: the wave waits for a
+// step's window with an explicit vmcnt that leaves the later steps' loads
+// outstanding (loads retire in issue order), and a slot is refilled only
+// after the LDS reads of the step that used it have returned (lgkmcnt(0)).
+// The loads take their LDS base from M0, which the asm sets; no other
+// instruction of the fold kernels reads M0.  Bit-identical to variants 2
+// and 3 but slower on gfx950: the windows (sized for a tile's largest
+// spread) take a third fewer loads than the direct loads of variant 2, yet
+// the address unit spends about 1.25 times as many cycles on a load into
+// LDS as on the same load into registers (variant 3), so it stays the
+// busiest unit.
+constexpr int kFoldDmaSlots = 4;
+constexpr int kFoldDmaCap = 384;  // pairs per slot (3 KB): up to three 1 KB wave loads
+
+__device__ __forceinline__ uint32_t lds_address(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// One step's window: NLD wave loads of 1 KB into the slot at LDS byte
+// address `slot` (wave-uniform); `voff` is the lane's byte offset in the row.
+template <int NLD>
+__device__ __forceinline__ void dma_window(__amdgpu_buffer_rsrc_t r, uint32_t slot, uint32_t voff) {
+    static_assert(NLD == 2 || NLD == 3, "a window spans two or three wave loads");
+    if constexpr (NLD == 2)
+        asm volatile(
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "s_mov_b32 m0, %0\n\t"
+            "s_nop 0\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen lds\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen offset:1024 lds"
+            :
+            : "s"(slot), "v"(voff), "s"(r)
+            : "memory", "m0");
+    else
+        asm volatile(
+            "s_waitcnt lgkmcnt(0)\n\t"
+            "s_mov_b32 m0, %0\n\t"
+            "s_nop 0\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen lds\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen offset:1024 lds\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen offset:2048 lds"
+            :
+            : "s"(slot), "v"(voff), "s"(r)
+            : "memory", "m0");
+}
+
+// Wait until at most N vector-memory loads of this wave are outstanding.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" : : "n"(N) : "memory");
+}
+
+template <int B>
+__device__ __forceinline__ void fold_unit_dma(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
+                                              const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
+                                              float2 *s_wave) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    const uint32_t uI = (uint32_t)I;
+    uint64_t r_min = ~0ull, r_max = 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        r_min = ipb[b] > 0 && R[b] < r_min ? R[b] : r_min;
+        r_max = ipb[b] > 0 && R[b] > r_max ? R[b] : r_max;
+    }
+    if (r_min == ~0ull) return;  // no period of the block is evaluated on this row
+    // a period not evaluated on this row follows the slowest one (its sums
+    // are discarded), so every offset lies between the slowest and the fastest
+    uint32_t Rh[B], Rl[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t r = ipb[b] > 0 ? R[b] : r_min;
+        Rh[b] = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
+        Rl[b] = __builtin_amdgcn_readfirstlane((uint32_t)r);
+    }
+    const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
+    const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
+    const double steps_per_epoch = 4294967296.0 / (double)r_min;
+    const double spread_per_step = (double)(r_max - r_min) / 4294967296.0;
+    const uint32_t ring = __builtin_amdgcn_readfirstlane(lds_address(s_wave));
+    const uint32_t lane_bytes = (uint32_t)lane * 16u;
+    uint64_t best[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) best[b] = 0;
+
+    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
+        const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
+        if (e_wave >= e_hi) break;
+        const int32_t e = e_wave + lane;  // epochs e and e + 64
+        const uint32_t e_bytes = (uint32_t)e * 8u;
+        const uint32_t lim = uI - (uint32_t)e_wave;
+        // steps m < m_lds run from the ring (the spread bound leaves room in
+        // a slot); later steps (if any) use direct loads
+        const double m_max = ((double)lim + 0.5) * steps_per_epoch;
+        const double m_fit =
+            spread_per_step > 0.0 ? ((double)(kFoldDmaCap - 128) - 2.0) / spread_per_step : m_max;
+        const int32_t m_lds =
+            __builtin_amdgcn_readfirstlane((int32_t)fmin(fmin(m_max, fmax(m_fit, 0.0)), 2.0e9));  // wave-uniform
+        const double spread = (double)m_lds * spread_per_step + 2.0;
+        const int n_ld = __builtin_amdgcn_readfirstlane((int)((spread + 128.0 + 127.0) / 128.0));  // 2 or 3
+        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
+        uint32_t hi[B], lo[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
+            hi[b] = 0;
+            lo[b] = 0x80000000u;  // + 1/2: round half up
+        }
+        uint32_t h_min = 0, l_min = 0x80000000u;
+        {
+            // transit 0 sits at offset 0 for every period: one load serves the block
+            const float2 v0 = load_pair(rsrc, e_bytes, 0);
+            const float2 v1 = load_pair(rsrc, e_bytes, 64 * 8);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                hi[b] = min(hi[b], uI);
+            }
+            acc_add(l_min, h_min, Rl_min, Rh_min);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a0[b] += v0.x;
+                s0[b] += v0.y;
+                a1[b] += v1.x;
+                s1[b] += v1.y;
+            }
+        }
+        int n_in_chunk = 1;
+        int32_t m = 1;  // the next step
+        auto ring_steps = [&](auto nld) {
+            constexpr int NLD = decltype(nld)::value;
+            // the lead: the slowest period's offset at the next step to load
+            uint32_t h_lead = h_min, l_lead = l_min;
+            int32_t m_lead = m;
+            auto lead_ok = [&]() { return m_lead < m_lds && h_lead < lim; };
+            auto issue = [&]() {  // the slot of step m_lead is the one step m_lead - 4 used
+                dma_window<NLD>(rsrc, ring + (uint32_t)(m_lead & (kFoldDmaSlots - 1)) * (kFoldDmaCap * 8u),
+                                lane_bytes + ((uint32_t)e_wave + h_lead) * 8u);
+                acc_add(l_lead, h_lead, Rl_min, Rh_min);
+                ++m_lead;
+            };
+            // sum step m from its slot; inside the window the transit offsets
+            // need no clamp (pairs past the row end were loaded as zero)
+            auto consume = [&]() {
+                const float2 *buf = s_wave + (m & (kFoldDmaSlots - 1)) * kFoldDmaCap + lane;
+                float2 v0[B], v1[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    const uint32_t q = hi[b] - h_min;  // inside the window by the spread bound
+                    v0[b] = buf[q];
+                    v1[b] = buf[q + 64];
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                acc_add(l_min, h_min, Rl_min, Rh_min);
+                ++m;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    a0[b] += v0[b].x;
+                    s0[b] += v0[b].y;
+                    a1[b] += v1[b].x;
+                    s1[b] += v1[b].y;
+                }
+                if (++n_in_chunk == kFoldChunk) {
+                    n_in_chunk = 0;
+#pragma unroll
+                    for (int b = 0; b < B; ++b) {
+                        ta0[b] += a0[b];
+                        ts0[b] += s0[b];
+                        ta1[b] += a1[b];
+                        ts1[b] += s1[b];
+                        a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+                    }
+                }
+            };
+#pragma unroll
+            for (int d = 0; d < kFoldDmaSlots - 1; ++d)
+                if (lead_ok()) issue();
+            // steady state: three later windows stay in flight while step m is summed
+            while (lead_ok()) {
+                issue();
+                wait_vm<(kFoldDmaSlots - 1) * NLD>();
+                consume();
+            }
+            if (m < m_lead) {
+                wait_vm<0>();
+                do consume();
+                while (m < m_lead);
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) hi[b] = min(hi[b], uI);  // the direct loads rely on the clamp
+        };
+        if (m < m_lds && h_min < lim) {
+            if (n_ld <= 2)
+                ring_steps(std::integral_constant<int, 2>());
+            else
+                ring_steps(std::integral_constant<int, 3>());
+        }
+        while (h_min < lim) {
+            float2 v0[B], v1[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                v0[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 0);
+                v1[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 64 * 8);
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                hi[b] = min(hi[b], uI);
+            }
+            acc_add(l_min, h_min, Rl_min, Rh_min);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a0[b] += v0[b].x;
+                s0[b] += v0[b].y;
+                a1[b] += v1[b].x;
+                s1[b] += v1[b].y;
+            }
+            if (++n_in_chunk == kFoldChunk) {
+                n_in_chunk = 0;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    ta0[b] += a0[b];
+                    ts0[b] += s0[b];
+                    ta1[b] += a1[b];
+                    ts1[b] += s1[b];
+                    a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
                 }
             }
         }

@@ -95,7 +95,7 @@ def test_tuning_roundtrip_and_validation(lib):
     with pytest.raises(cm.CetraError, match="fold_period_block"):
         cm.set_tuning(5, 6, 2)
     with pytest.raises(cm.CetraError, match="fold_variant"):
-        cm.set_tuning(4, 6, 2, 4)
+        cm.set_tuning(4, 6, 2, 5)
     assert cm.get_tuning()["fold_period_block"] == 4  # unchanged after a rejected call
     cm.reset_tuning()
     assert cm.get_tuning()["fold_period_block"] == 8

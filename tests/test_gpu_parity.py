@@ -317,7 +317,8 @@ def test_long_baseline_full_size_sampled(cm, ora):
 
 
 @pytest.mark.parametrize("cfg", [(8, 8, 4, 1), (4, 8, 4, 1), (8, 8, 4, 0), (4, 8, 16, 0), (4, 8, 4, 2), (8, 8, 4, 2),
-                                 (4, 8, 4, 3), (8, 8, 4, 3), (16, 8, 4, 3)])
+                                 (4, 8, 4, 3), (8, 8, 4, 3), (16, 8, 4, 3), (4, 8, 4, 4), (8, 8, 4, 4),
+                                 (16, 8, 4, 4)])
 def test_fold_variants_identical(cm, ora, tiny_pair, tiny_wl, cfg):
     """Register and LDS fold variants, period blocks 4 to 16: the same
     per-period records, bit for bit (the FP32 ranking sums are accumulated in
@@ -364,22 +365,23 @@ def test_fold_variants_identical_mixed_periods(cm, ora, tiny_pair, B):
     print(f"[case] mixed periods K={K} B={B}", flush=True)
     out = {}
     try:
-        for v in (2, 0, 1, 3):
+        for v in (2, 0, 1, 3, 4):
             cm.set_tuning(B, 8, 4, v)
             per = cm.periodic_search(r["grid"], r["fold"], periods, jrange=jr)
             torch.cuda.synchronize()
             out[v] = {k: x.cpu().numpy() for k, x in per.items()}
     finally:
         cm.reset_tuning()
-    for v in (0, 1, 3):
+    for v in (0, 1, 3, 4):
         for k in ("lr", "epoch", "dur", "depth", "depth_var"):
             assert np.array_equal(out[v][k], out[2][k], equal_nan=True), (B, v, k)
     if B == 8:
         op = ora.periodic(o["grid"], o["linear"], periods, jrange=jr)
-        check_periodic(out[3], op, fold_at(ora, o), periods)
-        for k in range(K):
-            if out[3]["dur"][k] >= 0:
-                assert jr[k, 0] <= out[3]["dur"][k] <= jr[k, 1]
+        for v in (3, 4):
+            check_periodic(out[v], op, fold_at(ora, o), periods)
+            for k in range(K):
+                if out[v]["dur"][k] >= 0:
+                    assert jr[k, 0] <= out[v]["dur"][k] <= jr[k, 1]
 
 
 def test_keplerian_duration_filter(cm, ora, tiny_wl):
