@@ -83,7 +83,7 @@ def lib():
             L.ora_linear_at.restype = None
             L.ora_loglike0.argtypes = [P(Grid), P(d), P(d)]
             L.ora_loglike0.restype = d
-            L.ora_periodic.argtypes = [P(Grid), P(d), P(d), P(d), P(d), P(d), P(i32), P(i64), i64,
+            L.ora_periodic.argtypes = [P(Grid), P(d), P(d), P(d), P(d), P(d), P(i32), P(i64), i64, P(i32),
                                        P(d), P(i32), P(i32), P(d), P(d), P(d)]
             L.ora_periodic.restype = None
             L.ora_fold_at.argtypes = [P(Grid), P(d), P(d), P(d), P(d), d, i64, i32, P(d), P(d), P(d), P(d)]
@@ -170,21 +170,26 @@ def loglike0(g: Grid, flux, ivar) -> float:
     return float(lib().ora_loglike0(ctypes.byref(g), _p(flux, ctypes.c_double), _p(ivar, ctypes.c_double)))
 
 
-def periodic(g: Grid, lin: dict, periods, jrange=None, sel=None) -> dict:
-    """Periodic search over periods[sel] (all periods if sel is None)."""
+def periodic(g: Grid, lin: dict, periods, jrange=None, sel=None, stride=None) -> dict:
+    """Periodic search over periods[sel] (all periods if sel is None).  With
+    `stride` ([J] int, >= 1), duration j evaluates only the epochs that are
+    multiples of stride[j]."""
     periods = np.ascontiguousarray(periods, dtype=np.float64)
     if sel is None:
         sel = np.arange(periods.shape[0], dtype=np.int64)
     sel = np.ascontiguousarray(sel, dtype=np.int64)
     n = sel.shape[0]
     jr = None if jrange is None else np.ascontiguousarray(jrange, dtype=np.int32).reshape(-1)
+    st = None if stride is None else np.ascontiguousarray(stride, dtype=np.int32)
+    if st is not None and (st.shape != (g.n_dur,) or np.any(st < 1)):
+        raise ValueError("stride: one integer >= 1 per duration")
     out = dict(lr=np.empty(n), i=np.empty(n, dtype=np.int32), j=np.empty(n, dtype=np.int32),
                z=np.empty(n), zvar=np.empty(n), aabs=np.empty(n))
     arrs = [np.ascontiguousarray(lin[k], dtype=np.float64) for k in ("depth", "var", "lr", "aabs")]
     lib().ora_periodic(ctypes.byref(g), *[_p(a, ctypes.c_double) for a in arrs],
                        _p(periods, ctypes.c_double),
                        None if jr is None else _p(jr, ctypes.c_int32),
-                       _p(sel, ctypes.c_int64), n,
+                       _p(sel, ctypes.c_int64), n, None if st is None else _p(st, ctypes.c_int32),
                        _p(out["lr"], ctypes.c_double), _p(out["i"], ctypes.c_int32),
                        _p(out["j"], ctypes.c_int32), _p(out["z"], ctypes.c_double),
                        _p(out["zvar"], ctypes.c_double), _p(out["aabs"], ctypes.c_double))

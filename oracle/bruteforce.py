@@ -124,9 +124,10 @@ def linear(bg: BruteGrid, flux, w, model, elements=None):
     return out
 
 
-def periodic(bg: BruteGrid, flux, w, model, periods, windows=None):
+def periodic(bg: BruteGrid, flux, w, model, periods, windows=None, stride=None):
     """Exhaustive periodic search: per period, best (lr, i, j, z, zvar).
-    Windows are cached per (i, j) across periods."""
+    Windows are cached per (i, j) across periods.  With `stride`, duration j
+    tries only the epochs that are multiples of stride[j]."""
     cache = {} if windows is None else windows
 
     def win(i, j):
@@ -140,7 +141,7 @@ def periodic(bg: BruteGrid, flux, w, model, periods, windows=None):
         for j, D in enumerate(bg.durations):
             if not D < P:
                 continue
-            for i in range(bg.epochs_per_period(P)):
+            for i in range(0, bg.epochs_per_period(P), 1 if stride is None else int(stride[j])):
                 g = np.zeros(bg.N)
                 any_win = False
                 for x in bg.transit_epochs(i, P):

@@ -84,3 +84,17 @@ def keplerian_jrange(periods, durations, rho_min, rho_max, k_max, b_max):
         assert not inside or (inside[0] == first and inside[-1] == last)
         out[k] = (first, last)
     return out
+
+
+def epoch_strides(durations, t0_step, fraction):
+    """int32 [J]: per duration, the fold's epoch stride on the fixed
+    reference-time grid for a TLS-style step that grows with the duration
+    (Sec. 2.1.3 mentions adopting it): the largest multiple of the fixed step
+    not exceeding `fraction` of the duration, and at least one step.  The
+    1e-9 keeps exact ratios (D_j a whole multiple of D_min) from landing one
+    short by rounding."""
+    out = np.empty(len(durations), dtype=np.int32)
+    for j, D in enumerate(durations):
+        q = fraction * float(D) / t0_step
+        out[j] = max(1, int(np.floor(q + 1e-9)))
+    return out

@@ -326,7 +326,7 @@ static void allowed_range(const ora_grid *g, double period, const int32_t *jrang
  * the smallest duration index, then the smallest epoch. */
 void ora_periodic(const ora_grid *g, const double *depth, const double *var, const double *lr,
                   const double *aabs, const double *periods, const int32_t *jrange,
-                  const int64_t *sel, int64_t n_sel, double *lr_out, int32_t *i_out,
+                  const int64_t *sel, int64_t n_sel, const int32_t *stride, double *lr_out, int32_t *i_out,
                   int32_t *j_out, double *z_out, double *zvar_out, double *aabs_out) {
     int64_t I = g->n_t0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -341,7 +341,11 @@ void ora_periodic(const ora_grid *g, const double *depth, const double *var, con
         double best = -1.0, bz = NAN, bzv = INFINITY, bab = 0.0;
         int32_t bi = -1, bj = -1;
         for (int j = jlo; j <= jhi; ++j) {
-            for (int64_t i = 0; i < IP; ++i) {
+            /* optional coarser epoch grid for duration j: only the epochs that
+               are multiples of stride[j] (a TLS-style reference-time step
+               that grows with the duration, Sec. 2.1.3) */
+            int64_t di = stride ? stride[j] : 1;
+            for (int64_t i = 0; i < IP; i += di) {
                 double l, z, zv, ab;
                 if (!fold_one(g, depth, var, lr, aabs, R, i, j, &l, &z, &zv, &ab)) continue;
                 if (l > best) {
