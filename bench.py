@@ -309,17 +309,17 @@ def keplerian_block(rho=(0.5, 3.0), k_max: float = 0.2, b_max: float = 0.9, reps
                                 torch.as_tensor(wl.sigma, device=dev), status=False)
     fold = cm.linear_search(grid, flux, ivar, model)
 
-    def timed(periods, jrange=None):
+    def timed(periods, jrange=None, stride=None):
         K = len(periods)
         per_d = torch.as_tensor(periods, device=dev)
         jr_d = None if jrange is None else torch.as_tensor(jrange, device=dev)
         work = torch.empty(max(cm.periodic_workspace(grid, K), 1), dtype=torch.uint8, device=dev)
-        out = cm.periodic_search(grid, fold, per_d, jrange=jr_d, work=work)
+        out = cm.periodic_search(grid, fold, per_d, jrange=jr_d, work=work, stride=stride)
         ms = []
         for _ in range(reps):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
-            cm.periodic_search(grid, fold, per_d, jrange=jr_d, work=work, out=out)
+            cm.periodic_search(grid, fold, per_d, jrange=jr_d, work=work, out=out, stride=stride)
             b.record()
             b.synchronize()
             ms.append(a.elapsed_time(b))
@@ -333,7 +333,12 @@ def keplerian_block(rho=(0.5, 3.0), k_max: float = 0.2, b_max: float = 0.9, reps
     ms_kep, b_kep = timed(wl.periods, jr)
     span = wl.t[-1] - wl.t[0]
     ofir = cm.period_grid(span, float(wl.periods[0]), float(wl.periods[-1]), cm.SOLAR_DENSITY, 3.0)
-    ms_ofir, b_ofir = timed(ofir, cm.keplerian_jrange(ofir, durs, rho[0], rho[1], k_max, b_max))
+    jr_ofir = cm.keplerian_jrange(ofir, durs, rho[0], rho[1], k_max, b_max)
+    ms_ofir, b_ofir = timed(ofir, jr_ofir)
+    # the duration-scaled epoch grid (reference-time step 1% of each duration)
+    st = cm.epoch_strides(grid, 0.01)
+    ms_st, b_st = timed(wl.periods, stride=st)
+    ms_st_all, b_st_all = timed(ofir, jr_ofir, stride=st)
     return {"workload": f"90 d at 20 s, J = {len(durs)}, K = {len(wl.periods)} duty-cycle periods 0.5-45 d",
             "filter": {"rho_g_cm3": list(rho), "k_max": k_max, "b_max": b_max},
             "fold_visits_kept": float(kept.sum() / allowed.sum()),
@@ -341,7 +346,21 @@ def keplerian_block(rho=(0.5, 3.0), k_max: float = 0.2, b_max: float = 0.9, reps
             "best_all": {"period": b_all["period"], "snr": b_all["snr"], "duration": b_all["duration"]},
             "best_keplerian": {"period": b_kep["period"], "snr": b_kep["snr"], "duration": b_kep["duration"]},
             "optimal_grid": {"n_periods": int(len(ofir)), "fold_ms_keplerian": ms_ofir,
-                             "best": {"period": b_ofir["period"], "snr": b_ofir["snr"]}}}
+                             "best": {"period": b_ofir["period"], "snr": b_ofir["snr"]}},
+            "duration_scaled_epochs": {"fraction": 0.01, "strides": st.tolist(),
+                                       "fold_visits_kept": float(np.sum(allowed_rows(durs, wl.periods) / st[None, :])
+                                                                 / allowed.sum()),
+                                       "fold_ms_all_durations": ms_st,
+                                       "best": {"period": b_st["period"], "snr": b_st["snr"]},
+                                       "with_optimal_grid_and_filter_ms": ms_st_all,
+                                       "best_with_optimal_grid_and_filter": {"period": b_st_all["period"],
+                                                                             "snr": b_st_all["snr"]}}}
+
+
+def allowed_rows(durs, periods):
+    """[K][J] 1 where duration j is shorter than period k (the rows a fold
+    evaluates), else 0."""
+    return (np.asarray(durs)[None, :] < np.asarray(periods)[:, None]).astype(np.float64)
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0

@@ -270,6 +270,28 @@ int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fol
                           const int64_t *subset, int64_t n_subset, void *work, size_t work_bytes,
                           float *lr, int32_t *epoch, int32_t *dur, float *depth, float *depth_var);
 
+/* Fold epoch strides for a reference-time step that grows with the duration,
+ * the TLS grid that Sec. 2.1.3 mentions adopting (the paper itself keeps one
+ * step): on the fixed grid of step dt, stride[j] = max(1, floor(fraction *
+ * D_j / dt + 1e-9)), the largest whole number of steps not above `fraction`
+ * of D_j (the 1e-9 keeps whole multiples from landing one short).
+ * stride[n_dur] (host) out.  fraction must be finite and > 0, else
+ * CETRA_ERR_INVALID.  Host only. */
+int cetra_epoch_strides(const cetra_grid *grid, double fraction, int32_t *stride);
+
+/* cetra_periodic_search on a coarser epoch grid per duration: duration j
+ * evaluates only the epochs i that are multiples of stride[j] (host int32
+ * [n_dur], each >= 1, else CETRA_ERR_INVALID; NULL evaluates every epoch,
+ * as cetra_periodic_search does).  Transits stay at i + round(m P_k/dt) on the
+ * fixed grid, so every record is the plain search's value at the (i*, j*) it
+ * reports, and the fold visits about 1/stride[j] of duration j's elements.
+ * Other arguments, outputs and workspace as cetra_periodic_search. */
+int cetra_periodic_search_strided(void *stream, const cetra_grid *grid, const float *fold,
+                                  const double *periods, int64_t n_periods, const int32_t *jrange,
+                                  const int64_t *subset, int64_t n_subset, const int32_t *stride,
+                                  void *work, size_t work_bytes, float *lr, int32_t *epoch, int32_t *dur,
+                                  float *depth, float *depth_var);
+
 /* Best period of a periodogram (Sec. 2.3 outputs): the maximum LR over the
  * n_periods records (ties to the smallest index), with SNR = Z / sqrt(var_Z)
  * and the epoch converted to time.  Inputs are the device outputs of

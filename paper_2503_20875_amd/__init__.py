@@ -181,10 +181,21 @@ def periodic_workspace(grid: Grid, n_eval: int) -> int:
     return int(n.value)
 
 
+def epoch_strides(grid: Grid, fraction: float = 0.01) -> np.ndarray:
+    """int32 [J] (host) epoch strides for periodic_search's `stride`: per
+    duration, the largest whole number of reference-time steps not above
+    `fraction` of the duration (a step that grows with the duration)."""
+    out = np.empty(grid.n_dur, dtype=np.int32)
+    _abi.check(_abi.load().cetra_epoch_strides(ctypes.byref(grid), float(fraction),
+                                               out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
 def periodic_search(grid: Grid, fold, periods, jrange=None, subset=None, work=None, out=None,
-                    stream=None) -> dict:
+                    stream=None, stride=None) -> dict:
     """Per-period maximum-likelihood records: dict of device tensors
-    lr, epoch, dur, depth, depth_var ([K] each)."""
+    lr, epoch, dur, depth, depth_var ([K] each).  `stride` (host ints, one
+    per duration, >= 1) evaluates only the epochs that are multiples of it."""
     torch = _torch()
     dev = fold.device
     periods = _dev(periods, torch.float64)
@@ -201,10 +212,19 @@ def periodic_search(grid: Grid, fold, periods, jrange=None, subset=None, work=No
                    dur=torch.empty(K, dtype=torch.int32, device=dev),
                    depth=torch.empty(K, dtype=torch.float32, device=dev),
                    depth_var=torch.empty(K, dtype=torch.float32, device=dev))
-    _abi.check(_abi.load().cetra_periodic_search(
+    if stride is None:
+        _abi.check(_abi.load().cetra_periodic_search(
+            _stream(stream), ctypes.byref(grid), _ptr(fold), _ptr(periods), K, _ptr(jr), _ptr(sub),
+            0 if sub is None else sub.numel(), _ptr(work), work.numel(), _ptr(out["lr"]), _ptr(out["epoch"]),
+            _ptr(out["dur"]), _ptr(out["depth"]), _ptr(out["depth_var"])))
+        return out
+    st = np.ascontiguousarray(stride, dtype=np.int32)
+    if st.shape != (grid.n_dur,):
+        raise ValueError(f"stride: one value per duration ({grid.n_dur})")
+    _abi.check(_abi.load().cetra_periodic_search_strided(
         _stream(stream), ctypes.byref(grid), _ptr(fold), _ptr(periods), K, _ptr(jr), _ptr(sub),
-        0 if sub is None else sub.numel(), _ptr(work), work.numel(), _ptr(out["lr"]), _ptr(out["epoch"]),
-        _ptr(out["dur"]), _ptr(out["depth"]), _ptr(out["depth_var"])))
+        0 if sub is None else sub.numel(), st.ctypes.data_as(ctypes.c_void_p), _ptr(work), work.numel(),
+        _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]), _ptr(out["depth"]), _ptr(out["depth_var"])))
     return out
 
 

@@ -135,6 +135,9 @@ SIGNATURES = {
     "cetra_periodic_workspace": (ctypes.c_int, [ctypes.POINTER(Grid), _i64, ctypes.POINTER(_sz)]),
     "cetra_periodic_search": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _i64, _P, _P, _i64, _P, _sz,
                                              _P, _P, _P, _P, _P]),
+    "cetra_periodic_search_strided": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _i64, _P, _P, _i64, _P,
+                                                     _P, _sz, _P, _P, _P, _P, _P]),
+    "cetra_epoch_strides": (ctypes.c_int, [ctypes.POINTER(Grid), _d, _P]),
     "cetra_best": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _i64, _P, _P, _P, _P, _P, _P]),
     "cetra_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P)]),
     "cetra_batch_plan_destroy": (ctypes.c_int, [_P]),

@@ -72,6 +72,13 @@ struct Durations {
     double d[CETRA_MAX_DURATIONS];
 };
 
+// Per-duration epoch strides of a coarser fold epoch grid; any = 0 when
+// every stride is 1 (the fixed grid).
+struct Strides {
+    int32_t s[CETRA_MAX_DURATIONS];
+    int32_t any;
+};
+
 // Per evaluated period: fixed-point step, epoch count, allowed durations
 // (D_j < P_k, Sec. 2.3, intersected with the caller's range); clears its key.
 __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_periods,
@@ -106,10 +113,12 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 // dev::fold_unit_lds (variant 1: workgroup-wide LDS windows) or
 // dev::fold_unit_wlds (variant 3: wave-private LDS windows) or
 // dev::fold_unit_dma (variant 4: wave-private LDS ring filled by
-// direct-to-LDS loads).
-template <int B, int kVariant>
+// direct-to-LDS loads).  kStrided: rows whose epoch stride exceeds 1 run
+// dev::fold_unit_strided on the coarser epoch grid (a separate
+// instantiation, so the plain kernels keep their register budget).
+template <int B, int kVariant, bool kStrided = false>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
-                                                        int32_t I, int32_t n_chunks, int64_t n_units) {
+                                                        int32_t I, int32_t n_chunks, int64_t n_units, Strides st) {
     constexpr bool kLds = kVariant == 1;
     constexpr bool kWaveLds = kVariant == 3;
     constexpr bool kDma = kVariant == 4;
@@ -139,6 +148,19 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
             ipmax = max(ipmax, ipb[b]);
         }
         if (ipmax == 0) continue;
+        if (kStrided && st.s[j] > 1) {
+            // coarser epoch grid for this duration: count epochs in strides
+            const int32_t sj = st.s[j];
+#pragma unroll
+            for (int b = 0; b < B; ++b) ipb[b] = (int32_t)(((int64_t)ipb[b] + sj - 1) / sj);
+            const int32_t ipc = (int32_t)(((int64_t)ipmax + sj - 1) / sj);
+            const int32_t chunk = (ipc + n_chunks - 1) / n_chunks;
+            const int32_t e_lo = c * chunk;
+            const int32_t e_hi = min(ipc, e_lo + chunk);
+            if (e_lo < e_hi)
+                cetra::dev::fold_unit_strided<B>(fold + (int64_t)j * I, j, I, sj, R, ipb, e_lo, e_hi, w.key + s0);
+            continue;
+        }
         const int32_t chunk = (ipmax + n_chunks - 1) / n_chunks;
         const int32_t e_lo = c * chunk;
         const int32_t e_hi = min(ipmax, e_lo + chunk);
@@ -256,13 +278,25 @@ extern "C" int cetra_periodic_workspace(const cetra_grid *grid, int64_t n_eval, 
     return CETRA_OK;
 }
 
-extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fold, const double *periods,
-                                     int64_t n_periods, const int32_t *jrange, const int64_t *subset,
-                                     int64_t n_subset, void *work, size_t work_bytes, float *lr, int32_t *epoch,
-                                     int32_t *dur, float *depth, float *depth_var) {
+namespace {
+
+int periodic_search(void *stream, const cetra_grid *grid, const float *fold, const double *periods,
+                    int64_t n_periods, const int32_t *jrange, const int64_t *subset, int64_t n_subset,
+                    const int32_t *stride, void *work, size_t work_bytes, float *lr, int32_t *epoch, int32_t *dur,
+                    float *depth, float *depth_var) {
     clear_error();
     int rc = check_grid(grid);
     if (rc) return rc;
+    Strides st{};
+    st.any = 0;
+    for (int j = 0; j < CETRA_MAX_DURATIONS; ++j) st.s[j] = 1;
+    if (stride) {
+        for (int j = 0; j < grid->n_dur; ++j) {
+            if (stride[j] < 1) return set_error(CETRA_ERR_INVALID, "periodic_search: stride[%d] = %d < 1", j, stride[j]);
+            st.s[j] = stride[j];
+            st.any |= stride[j] > 1;
+        }
+    }
     CETRA_REQUIRE(fold && lr && epoch && dur && depth && depth_var, "periodic_search: NULL pointer");
     CETRA_REQUIRE(n_periods >= 0 && (n_periods == 0 || periods), "periodic_search: bad periods");
     CETRA_REQUIRE(!subset || n_subset >= 0, "periodic_search: bad subset");
@@ -308,6 +342,10 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
         case 13: kern = (const void *)fold_kernel<8, 4>; break;
         default: kern = (const void *)fold_kernel<16, 4>; break;
     }
+    if (st.any)  // a coarser epoch grid: its own instantiation, variant 2 for the rows of stride 1
+        kern = B == 4 ? (const void *)fold_kernel<4, 2, true>
+             : B == 8 ? (const void *)fold_kernel<8, 2, true>
+                      : (const void *)fold_kernel<16, 2, true>;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0) != hipSuccess || occ <= 0) occ = 1;
     const int64_t wgs = (int64_t)device_cu_count() * std::min(tu.fold_wgs_per_cu, occ);
@@ -319,13 +357,33 @@ extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const
     const auto *f2 = reinterpret_cast<const float2 *>(fold);
     const int32_t I = (int32_t)grid->n_t0;
     const int32_t n_chunks32 = (int32_t)n_chunks;
-    void *args[] = {(void *)&f2, (void *)&w, (void *)&n_eval, (void *)&I, (void *)&n_chunks32, (void *)&n_units};
+    void *args[] = {(void *)&f2,         (void *)&w,       (void *)&n_eval, (void *)&I,
+                    (void *)&n_chunks32, (void *)&n_units, (void *)&st};
     const hipError_t le = hipLaunchKernel(kern, dim3((unsigned)grid_wgs), dim3(kThreads), args, 0, s);
     if (le != hipSuccess) return set_error(CETRA_ERR_HIP, "periodic_search/fold: %s", hipGetErrorString(le));
     hipLaunchKernelGGL(fold_epilogue_kernel, dim3((unsigned)ceil_div(n_eval, 256)), dim3(256), 0, s,
                        reinterpret_cast<const float2 *>(fold), w, n_eval, grid->n_t0, grid->n_dur, lr, epoch, dur,
                        depth, depth_var);
     return check_launch("periodic_search/epilogue");
+}
+
+}  // namespace
+
+extern "C" int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fold, const double *periods,
+                                     int64_t n_periods, const int32_t *jrange, const int64_t *subset,
+                                     int64_t n_subset, void *work, size_t work_bytes, float *lr, int32_t *epoch,
+                                     int32_t *dur, float *depth, float *depth_var) {
+    return periodic_search(stream, grid, fold, periods, n_periods, jrange, subset, n_subset, nullptr, work,
+                           work_bytes, lr, epoch, dur, depth, depth_var);
+}
+
+extern "C" int cetra_periodic_search_strided(void *stream, const cetra_grid *grid, const float *fold,
+                                             const double *periods, int64_t n_periods, const int32_t *jrange,
+                                             const int64_t *subset, int64_t n_subset, const int32_t *stride,
+                                             void *work, size_t work_bytes, float *lr, int32_t *epoch, int32_t *dur,
+                                             float *depth, float *depth_var) {
+    return periodic_search(stream, grid, fold, periods, n_periods, jrange, subset, n_subset, stride, work,
+                           work_bytes, lr, epoch, dur, depth, depth_var);
 }
 
 extern "C" int cetra_best(void *stream, const cetra_grid *grid, const double *periods, int64_t n_periods,

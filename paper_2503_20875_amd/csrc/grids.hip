@@ -127,3 +127,20 @@ extern "C" int cetra_keplerian_jrange(const double *periods, int64_t n_periods, 
     }
     return CETRA_OK;
 }
+
+// Epoch strides of a reference-time step that grows with the duration (the
+// TLS-style grid Sec. 2.1.3 mentions adopting), on the fixed grid of step dt:
+// the largest whole number of steps not above `fraction` of each duration.
+extern "C" int cetra_epoch_strides(const cetra_grid *grid, double fraction, int32_t *stride) {
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    CETRA_REQUIRE(stride != nullptr, "epoch_strides: NULL output");
+    CETRA_REQUIRE(std::isfinite(fraction) && fraction > 0.0, "epoch_strides: fraction must be finite and > 0");
+    for (int32_t j = 0; j < grid->n_dur; ++j) {
+        const double q = fraction * grid->durations[j] / grid->t0_step;
+        const double f = std::floor(q + 1e-9);
+        stride[j] = f < 1.0 ? 1 : f > (double)INT32_MAX ? INT32_MAX : (int32_t)f;
+    }
+    return CETRA_OK;
+}

@@ -444,6 +444,137 @@ __device__ __forceinline__ void fold_unit(const float2 *row, int32_t j, int32_t 
     }
 }
 
+// Fold unit on a coarser epoch grid: epochs e (in units of `s` reference
+// times) of duration row j, i.e. fine epochs i = e s, with the transits at
+// i + round(m R / 2^32) on the fixed grid as in fold_unit.  Lane l takes
+// coarse epochs e_wave + l and e_wave + 64 + l (one 8-byte load each per
+// period and step; lanes s elements apart).  ipb[b] counts coarse epochs.
+// Offsets, the loop exit, the FP32 chunking and the keys (fine flat index)
+// follow fold_unit, so a kept candidate ranks exactly as there.
+template <int B>
+__device__ __forceinline__ void fold_unit_strided(const float2 *row, int32_t j, int32_t I, int32_t s,
+                                                  const uint64_t (&R)[B], const int32_t (&ipb)[B], int32_t e_lo,
+                                                  int32_t e_hi, uint64_t *keys) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
+    const uint32_t uI = (uint32_t)I;
+    uint32_t Rh[B], Rl[B];
+    uint64_t r_min = ~0ull;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        Rh[b] = __builtin_amdgcn_readfirstlane((uint32_t)(R[b] >> 32));
+        Rl[b] = __builtin_amdgcn_readfirstlane((uint32_t)R[b]);
+        r_min = ipb[b] > 0 && R[b] < r_min ? R[b] : r_min;
+    }
+    if (r_min == ~0ull) return;
+    const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
+    const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
+    uint64_t best[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) best[b] = 0;
+
+    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
+        const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
+        if (e_wave >= e_hi) break;
+        const int32_t e = e_wave + lane;  // coarse epochs e and e + 64
+        // fine epochs, saturated at I (past the row every load reads zero and
+        // the epoch is not a candidate), so byte offsets stay below 16 I
+        const uint32_t f0 = (uint32_t)min((int64_t)e * s, (int64_t)I);
+        const uint32_t f1 = (uint32_t)min((int64_t)(e + 64) * s, (int64_t)I);
+        const uint32_t b0 = f0 * 8u, b1 = f1 * 8u;
+        // e_wave < ceil(I_P / s) gives e_wave s < I_P <= I
+        const uint32_t lim = uI - (uint32_t)e_wave * (uint32_t)s;
+        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
+        uint32_t hi[B], lo[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
+            hi[b] = 0;
+            lo[b] = 0x80000000u;  // + 1/2: round half up
+        }
+        uint32_t h_min = 0, l_min = 0x80000000u;
+        {
+            const float2 v0 = load_pair(rsrc, b0, 0);
+            const float2 v1 = load_pair(rsrc, b1, 0);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                hi[b] = min(hi[b], uI);
+            }
+            acc_add(l_min, h_min, Rl_min, Rh_min);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                a0[b] += v0.x;
+                s0[b] += v0.y;
+                a1[b] += v1.x;
+                s1[b] += v1.y;
+            }
+        }
+        int mm0 = 1;
+        while (h_min < lim) {
+            for (int mm = mm0; mm < kFoldChunk && h_min < lim; ++mm) {
+                float2 v0[B], v1[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    v0[b] = load_pair(rsrc, b0 + hi[b] * 8u, 0);
+                    v1[b] = load_pair(rsrc, b1 + hi[b] * 8u, 0);
+                }
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    acc_add(lo[b], hi[b], Rl[b], Rh[b]);
+                    hi[b] = min(hi[b], uI);
+                }
+                acc_add(l_min, h_min, Rl_min, Rh_min);
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    a0[b] += v0[b].x;
+                    s0[b] += v0[b].y;
+                    a1[b] += v1[b].x;
+                    s1[b] += v1[b].y;
+                }
+            }
+            mm0 = 0;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ta0[b] += a0[b];
+                ts0[b] += s0[b];
+                ta1[b] += a1[b];
+                ts1[b] += s1[b];
+                a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
+            }
+        }
+        if (mm0) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                ta0[b] += a0[b];
+                ts0[b] += s0[b];
+                ta1[b] += a1[b];
+                ts1[b] += s1[b];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int32_t eh = e + 64 * h;
+                const float A = h ? ta1[b] : ta0[b];
+                const float S = h ? ts1[b] : ts0[b];
+                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
+                const uint32_t fine = h ? f1 : f0;
+                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + fine);
+                best[b] = ok && key > best[b] ? key : best[b];
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const uint64_t m = wave_max_u64(best[b]);
+        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
+    }
+}
+
 // Wave-private LDS fold unit (variant 3).  At transit step m the B periods
 // of the block read windows of 128 epochs at offsets o_b(m) that lie in
 // [o_slow(m), o_slow(m) + spread], o_slow being the offset of the period with

@@ -274,6 +274,14 @@ def test_high_cadence_full_size_sampled(cm, ora):
     g = {k: v.cpu().numpy() for k, v in r["periodic"].items()}
     res = check_periodic(g, per, lambda P, i, j: ora.fold_at(og, lin, P, i, j), wl.periods, sel=sel)
     print("periodic sample", res)
+    # the duration-scaled epoch grid (1% of each duration) on the same arrays
+    st = cm.epoch_strides(r["grid"], 0.01)
+    per_s = cm.periodic_search(r["grid"], r["fold"], wl.periods, stride=st)
+    gs = {k: v.cpu().numpy() for k, v in per_s.items()}
+    ps = ora.periodic(og, lin, wl.periods, sel=sel, stride=st)
+    print("strided sample", check_periodic(gs, ps, lambda P, i, j: ora.fold_at(og, lin, P, i, j), wl.periods,
+                                           sel=sel))
+    check_on_coarse_grid(gs, st)
     b = cm.best_record(r["best_raw"])
     # one of the two injected signals (17.1 d or 3.2 d), or an alias, is the strongest
     assert min(abs(b["period"] / (P * f) - 1) for P in (17.1, 3.2) for f in (0.5, 1, 2)) < 0.01
@@ -382,6 +390,71 @@ def test_fold_variants_identical_mixed_periods(cm, ora, tiny_pair, B):
             for k in range(K):
                 if out[v]["dur"][k] >= 0:
                     assert jr[k, 0] <= out[v]["dur"][k] <= jr[k, 1]
+
+
+def check_on_coarse_grid(h, st):
+    for k in range(len(h["epoch"])):
+        if h["epoch"][k] >= 0:
+            assert h["epoch"][k] % st[h["dur"][k]] == 0, (k, h["epoch"][k], h["dur"][k])
+
+
+@pytest.mark.parametrize("B", [4, 8, 16])
+def test_strided_fold_matches_oracle(cm, ora, tiny_pair, tiny_wl, B):
+    """Duration-scaled epoch grid (strides 1 to 34, one far above any
+    period's epoch count) against the oracle on the same grid, for every
+    period block; unit strides return the plain search bit for bit."""
+    import torch
+    r, o, g = tiny_pair
+    J = o["grid"].n_dur
+    st = np.array([1, 2, 3, 5, 8, 13, 34, 10**6][:J], dtype=np.int32)
+    print(f"[case] strided tiny B={B} strides={st.tolist()}", flush=True)
+    cm.set_tuning(B, 8, 4, 2)
+    try:
+        per = cm.periodic_search(r["grid"], r["fold"], tiny_wl.periods, stride=st)
+        ones = cm.periodic_search(r["grid"], r["fold"], tiny_wl.periods, stride=np.ones(J, dtype=np.int32))
+        torch.cuda.synchronize()
+    finally:
+        cm.reset_tuning()
+    h = {k: v.cpu().numpy() for k, v in per.items()}
+    op = ora.periodic(o["grid"], o["linear"], tiny_wl.periods, stride=st)
+    print("strided", check_periodic(h, op, fold_at(ora, o), tiny_wl.periods))
+    check_on_coarse_grid(h, st)
+    assert np.any(h["dur"] >= 1)  # winners on strided rows too
+    h1 = {k: v.cpu().numpy() for k, v in ones.items()}
+    for k in h1:
+        assert np.array_equal(h1[k], g[k], equal_nan=True), k
+
+
+def test_strided_fold_mixed_periods_and_ranges(cm, ora, tiny_pair):
+    """Strided fold on the mixed period set with duration-range
+    restrictions and a subset of the periods, against the oracle."""
+    import torch
+    r, o, _ = tiny_pair
+    periods = mixed_periods()
+    K = len(periods)
+    rng = np.random.default_rng(9)
+    jr = np.stack([rng.integers(0, 3, K), rng.integers(4, 8, K)], axis=1).astype(np.int32)
+    sub = np.sort(rng.choice(K, K // 2, replace=False))
+    st = cm.epoch_strides(r["grid"], 0.04)
+    assert st.max() > 1
+    print(f"[case] strided mixed periods K={K} strides={st.tolist()}", flush=True)
+    per = cm.periodic_search(r["grid"], r["fold"], periods, jrange=jr, subset=sub, stride=st)
+    torch.cuda.synchronize()
+    h = {k: v.cpu().numpy() for k, v in per.items()}
+    op = ora.periodic(o["grid"], o["linear"], periods, jrange=jr, sel=sub, stride=st)
+    print("strided mixed", check_periodic(h, op, fold_at(ora, o), periods, sel=sub))
+    check_on_coarse_grid(h, st)
+    rest = np.setdiff1d(np.arange(K), sub)
+    assert np.all(h["epoch"][rest] == -1)
+
+
+def test_strided_fold_rejects_bad_strides(cm, tiny_pair, tiny_wl):
+    r, o, _ = tiny_pair
+    J = o["grid"].n_dur
+    with pytest.raises(cm.CetraError, match="stride"):
+        cm.periodic_search(r["grid"], r["fold"], tiny_wl.periods, stride=np.zeros(J, dtype=np.int32))
+    with pytest.raises(ValueError):
+        cm.periodic_search(r["grid"], r["fold"], tiny_wl.periods, stride=np.ones(J + 1, dtype=np.int32))
 
 
 def test_keplerian_duration_filter(cm, ora, tiny_wl):

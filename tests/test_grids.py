@@ -58,3 +58,30 @@ def test_keplerian_jrange_matches_oracle(cm):
     # every period keeps at least one duration on this grid, and some lose some
     assert np.all(got[:, 0] <= got[:, 1])
     assert np.any(got[:, 0] > 0) and np.any(got[:, 1] < len(wl.durations) - 1)
+
+
+@pytest.mark.parametrize("name", ["tiny", "high_cadence", "long_baseline"])
+@pytest.mark.parametrize("fraction", [0.01, 0.03])
+def test_epoch_strides_match_oracle(cm, name, fraction):
+    """The host's duration-scaled epoch strides equal the grid oracle's
+    exactly on each workload's grid."""
+    if name == "long_baseline":
+        sh = W.long_baseline_shape()
+        g = cm.grid_plan(0.0, sh["span"], sh["cadence"], sh["durations"], 0.0, 1024)
+        durs = sh["durations"]
+    else:
+        wl = W.WORKLOADS[name]()
+        g = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, 1024)
+        durs = wl.durations
+    got = cm.epoch_strides(g, fraction)
+    want = og.epoch_strides(durs, g.t0_step, fraction)
+    assert np.array_equal(got, want)
+    assert got[0] == max(1, int(fraction / 0.01 + 1e-9))
+
+
+def test_epoch_strides_reject_bad_fractions(cm):
+    wl = W.tiny_single()
+    g = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, 1024)
+    for bad in (0.0, -0.01, float("nan"), float("inf")):
+        with pytest.raises(cm.CetraError, match="fraction"):
+            cm.epoch_strides(g, bad)
