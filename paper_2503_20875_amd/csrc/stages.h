@@ -159,30 +159,45 @@ __device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, c
 
     double dfm = 0.0, dmm = 0.0;
     if (w.ok) {
+        // the window's points n = lo + q, q < L, in FP32 chunks of
+        // kLinearChunk points from lo; the staged and direct loops are
+        // separate so neither tests the source per point
         const uint32_t last = (uint32_t)(p.n_model - 1);
         uint64_t ph = w.phase;
-        int64_t n = w.lo;
-        while (n <= w.hi) {
-            const int64_t stop = min(w.hi + 1, n + kLinearChunk);
-            float sfm = 0.0f, smm = 0.0f;
-            for (; n < stop; ++n) {
-                const uint32_t k = min((uint32_t)(ph >> 32), last);
-                const float mk = s_model[k];
-                float wf, wq;
-                if (staged) {
-                    const float2 d = s_data[n - base];
-                    wf = d.x;
-                    wq = d.y;
-                } else {
-                    wq = ivar[n];
-                    wf = flux[n] * wq;
+        const int32_t L = (int32_t)(w.hi - w.lo + 1);
+        if (staged) {
+            const float2 *d = s_data + (w.lo - base);
+            for (int32_t q0 = 0; q0 < L; q0 += kLinearChunk) {
+                const int32_t q1 = min(L, q0 + kLinearChunk);
+                float sfm = 0.0f, smm = 0.0f;
+#pragma unroll 4
+                for (int32_t q = q0; q < q1; ++q) {
+                    const float mk = s_model[min((uint32_t)(ph >> 32), last)];
+                    const float2 v = d[q];
+                    sfm = fmaf(v.x, mk, sfm);
+                    smm = fmaf(v.y * mk, mk, smm);
+                    ph += p.step_fx;
                 }
-                sfm = fmaf(wf, mk, sfm);
-                smm = fmaf(wq * mk, mk, smm);
-                ph += p.step_fx;
+                dfm += (double)sfm;
+                dmm += (double)smm;
             }
-            dfm += (double)sfm;
-            dmm += (double)smm;
+        } else {
+            const float *fx = flux + w.lo;
+            const float *iv = ivar + w.lo;
+            for (int32_t q0 = 0; q0 < L; q0 += kLinearChunk) {
+                const int32_t q1 = min(L, q0 + kLinearChunk);
+                float sfm = 0.0f, smm = 0.0f;
+#pragma unroll 4
+                for (int32_t q = q0; q < q1; ++q) {
+                    const float mk = s_model[min((uint32_t)(ph >> 32), last)];
+                    const float wq = iv[q];
+                    sfm = fmaf(fx[q] * wq, mk, sfm);
+                    smm = fmaf(wq * mk, mk, smm);
+                    ph += p.step_fx;
+                }
+                dfm += (double)sfm;
+                dmm += (double)smm;
+            }
         }
     }
     __syncthreads();  // LDS may be reused by the caller's next item

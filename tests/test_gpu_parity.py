@@ -109,6 +109,20 @@ def test_tiny_linear_all_elements(tiny_pair):
     assert np.max(rel(fold[..., 0][ok], lin["depth"][ok] / lin["var"][ok], lin["aabs"][ok])) < TOL
 
 
+def test_linear_long_windows_read_from_memory(cm, ora):
+    """Windows too long to stage in LDS (46 h at 20 s: the span of 256
+    windows exceeds 64 KB) are summed from global memory: every linear
+    element and every period against the oracle."""
+    wl = W.small_random(3, n_obs=30000, cadence_s=20.0, n_dur=2, n_per=6, p_range=(3.0, 5.0), dur_h=(2.0, 38.0))
+    r, o, g = run_both(cm, ora, wl)
+    og = o["grid"]
+    span_pairs = (255 * og.t0_step + wl.durations[-1]) / og.cadence
+    assert span_pairs * 8 + 4 * wl.n_model > 64 * 1024  # the longest duration takes the direct path
+    assert ((255 * og.t0_step + wl.durations[0]) / og.cadence) * 8 + 4 * wl.n_model < 64 * 1024  # staged
+    print("linear", check_linear(*lin_arrays(r), o["linear"]))
+    print("periodic", check_periodic(g, o["periodic"], fold_at(ora, o), wl.periods))
+
+
 def test_tiny_periodic_all_periods(ora, tiny_pair, tiny_wl):
     r, o, g = tiny_pair
     res = check_periodic(g, o["periodic"], fold_at(ora, o), tiny_wl.periods)
