@@ -482,10 +482,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="time the benchmark steps only (no filter, long-baseline, network, batched, learned or "
                          "CPU measurements), e.g. for kernel traces of the headline search")
-    ap.add_argument("--mode", default="full", choices=["full", "fold", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "fold", "copy", "net"],
                     help="full: the benchmark; fold: setup once, then --steps fold launches only "
                          "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
-                         "times (calibrates the HBM byte counters)")
+                         "times (calibrates the HBM byte counters); net: the proposal network's "
+                         "convolution roofline only (for kernel traces and MFMA counters)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--batch-curves", type=int, default=32,
                     help="survey curves of the batched-search measurement (0: skip)")
@@ -515,6 +516,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
                           "launches": args.steps}), flush=True)
+        return
+    if args.mode == "net":
+        print(json.dumps({"mode": "net", **net_block()}), flush=True)
         return
     if args.fold_tuning:
         cm.set_tuning(*(int(v) for v in args.fold_tuning.split(",")))

@@ -75,9 +75,14 @@ def labels_for(pipe, injections) -> np.ndarray:
     return y
 
 
-def build_dataset(pipe, n: int, seed: int, workload: str = "learned"):
+def build_dataset(pipe, n: int, seed: int, workload: str = "learned", plain_labels: bool = False,
+                  snr_min: float = 7.0):
     """Device features [n][n_bins][16] (bf16) and labels [n][W], plus the
-    injections of every curve."""
+    injections of every curve.  With plain_labels the full periodic search
+    also runs on every curve and its best period's window is marked when its
+    SNR reaches snr_min, whether or not a planet caused it: the network then
+    learns where the full search will report its detection, noise peaks at
+    the threshold included."""
     import torch
     from .proposal import C_IN
     draw = curve_source(workload, seed)
@@ -91,6 +96,12 @@ def build_dataset(pipe, n: int, seed: int, workload: str = "learned"):
                            torch.as_tensor(s, device="cuda"))
         pipe.features(fold, out=x[i])
         y[i] = labels_for(pipe, inj)
+        if plain_labels:
+            rec = pipe.plain(fold)
+            if rec["k"] >= 0 and rec["snr"] >= snr_min:
+                w = pipe.window_of(rec["period"])
+                if w >= 0:
+                    y[i, w] = 1.0
         injs.append(inj)
         if (i + 1) % 500 == 0:
             log(f"features {i + 1}/{n} ({time.time() - t0:.1f} s)")
@@ -108,6 +119,8 @@ def main(argv=None) -> int:
     ap.add_argument("--seed", type=int, default=20250401)
     ap.add_argument("--n-trial", type=int, default=4)
     ap.add_argument("--workload", default="learned", choices=["learned", "long"])
+    ap.add_argument("--plain-labels", action="store_true",
+                    help="also label each curve's full-search best window when its SNR is at least 7")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -120,10 +133,12 @@ def main(argv=None) -> int:
     pipe = make_pipeline(workload=a.workload)
     log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
         f"bin {pipe.windows.bin_days:.5f} d")
-    x, y, _ = build_dataset(pipe, a.n_train, a.seed, a.workload)
+    x, y, _ = build_dataset(pipe, a.n_train, a.seed, a.workload, plain_labels=a.plain_labels)
+    log(f"labelled windows per curve {float(y.sum()) / a.n_train:.3f}")
     net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, n_trial=a.n_trial)
     losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)
     meta = dict(n_event=net.E, hidden=net.H, pool="fold", n_trial=net.S, workload=a.workload,
+                plain_labels=bool(a.plain_labels),
                 feature_rows=list(pipe.cfg.feature_rows), n_train=a.n_train, epochs=a.epochs,
                 batch=a.batch, lr=a.lr,
                 pos_weight=a.pos_weight, seed=a.seed, losses=losses, n_bins=pipe.cfg.n_bins,
