@@ -75,14 +75,36 @@ __global__ void downsample_kernel(const float2 *__restrict__ fold, int32_t J, in
 }
 
 // ------------------------------------------------------------ conv forward
-// Implicit GEMM with a 64 x 64 register tile per wave.  Workgroup: 256
-// positions x 64 output channels of one example; wave w owns positions
-// [64 w, 64 w + 64) (4 MFMA column tiles) and all 64 channels (4 row tiles),
-// so each k-step's 4 weight and 4 input fragments (16-byte loads) feed 16
-// MFMAs, and the next k-step's fragments are loaded while this one's MFMAs
-// issue.  Positions outside [0, L) and reduction indices past 9 cin read
-// zero.
-constexpr int kConvPos = 256;
+// Implicit GEMM with a 64 x 64 register tile per wave.  Workgroup: 512
+// positions x 64 output channels of one example (8 waves); wave w owns
+// positions [64 w, 64 w + 64) (4 MFMA column tiles) and all 16 MT rows
+// (MT row tiles).  Both operands are staged in LDS once per workgroup, so the
+// reduction loop reads no global memory:
+//   A (weights) in fragment order -- the 16-byte fragment of k-step s, row
+//     tile m and lane l at ((s MT + m) 64 + l) 16 bytes, so a wave's fragment
+//     read is 1 KB contiguous;
+//   B (inputs) as the 520 source positions [base - 4, base + 516) of the
+//     tile, channel-last with rows padded to c + 8 channels (16 lanes on 16
+//     consecutive positions then hit distinct banks); positions outside
+//     [0, L) are zero.
+// Each k-step's 4 weight and 4 input fragments feed 16 MFMAs, and the next
+// k-step's fragments are read while this one's MFMAs issue.  Reduction
+// indices past 9 c read zero.
+constexpr int kConvWaves = 8;
+constexpr int kConvThreads = 64 * kConvWaves;
+constexpr int kConvPos = 64 * kConvWaves;  // positions per workgroup
+constexpr int kConvHalo = 4;
+constexpr int kConvRows = kConvPos + 2 * kConvHalo;
+constexpr int kConvMaxK = kTaps * kWidth;  // 576
+constexpr int kConvLdsA = kWidth * kConvMaxK * 2;              // bytes: 64 rows x 576, bf16
+constexpr int kConvLdsB = kConvRows * (kWidth + 8) * 2;        // bytes: 520 rows x 72, bf16
+static_assert(kConvLdsA % 16 == 0 && kConvLdsB % 16 == 0, "16-byte LDS fragments");
+static_assert(kConvLdsA == 16 * 4 * (kConvMaxK / 32) * 64, "A holds 4 row tiles x 18 k-steps x 64 fragments");
+static_assert(kConvLdsA + kConvLdsB <= 160 * 1024, "one workgroup's LDS");
+// 16-byte staging chunks per thread, enough for the largest operands
+constexpr int kConvStageIters = 9;
+static_assert(kConvStageIters * kConvThreads * 16 >= kConvLdsA, "A chunks per thread");
+static_assert(kConvStageIters * kConvThreads >= kConvRows * kWidth / 8, "B chunks per thread");
 
 template <int MT>
 struct ConvFrags {
@@ -90,22 +112,62 @@ struct ConvFrags {
     bf16x8 b[4];
 };
 
-// Fragments of k-step k0: A rows r of `a_mat` (row stride a_ld, 16 MT rows),
-// B the inputs at source position t + shift(k) - 4 (sign +1 forward, -1 for
-// the input gradient) and channel k % c of `src` (channel-last, c channels).
-template <int MT>
-__device__ __forceinline__ void conv_load(ConvFrags<MT> &f, const __bf16 *__restrict__ a_mat, int32_t a_ld,
-                                          const __bf16 *__restrict__ src, int32_t c, int32_t k_valid, int32_t L,
-                                          int32_t t0, int sign, int32_t k0, int l) {
-    const int32_t k = k0 + 8 * (l / 16);
-    const int32_t tap = k / c, ci = k % c;
+// Stage A rows [0, 16 MT) x [0, KP) of `a_mat` (row stride a_ld) and the
+// source rows of `src` (C channels, channel-last) around `base` into LDS.
+// Every load of a thread is issued before its first store (from a clamped,
+// always valid address; out-of-range chunks are zeroed afterwards), so
+// staging waits for memory about once instead of once per chunk.
+template <int MT, int C, int KP>
+__device__ __forceinline__ void conv_stage(bf16x8 *sA, __bf16 *sB, const __bf16 *__restrict__ a_mat, int32_t a_ld,
+                                           const __bf16 *__restrict__ src, int32_t L, int32_t base) {
+    constexpr int32_t n_kk = KP / 8, n_a = 16 * MT * n_kk;
+    constexpr int32_t n_cc = C / 8, stride = C + 8, n_b = kConvRows * n_cc;
+    static_assert(n_a <= kConvStageIters * kConvThreads && n_b <= kConvStageIters * kConvThreads, "chunks");
+    bf16x8 va[kConvStageIters], vb[kConvStageIters];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) f.a[m] = load8(a_mat + (int64_t)(16 * m + (l % 16)) * a_ld + k);
+    for (int u = 0; u < kConvStageIters; ++u) {
+        const int32_t id = min((int32_t)threadIdx.x + u * kConvThreads, n_a - 1);
+        va[u] = load8(a_mat + (int64_t)(id / n_kk) * a_ld + 8 * (id % n_kk));
+    }
+#pragma unroll
+    for (int u = 0; u < kConvStageIters; ++u) {
+        const int32_t id = min((int32_t)threadIdx.x + u * kConvThreads, n_b - 1);
+        const int32_t pos = min(max(base - kConvHalo + id / n_cc, 0), L - 1);
+        vb[u] = load8(src + (int64_t)pos * C + 8 * (id % n_cc));
+    }
+#pragma unroll
+    for (int u = 0; u < kConvStageIters; ++u) {
+        const int32_t id = threadIdx.x + u * kConvThreads;
+        if (id < n_a) {
+            const int32_t r = id / n_kk, kk = id % n_kk;
+            sA[((kk / 4 * MT + r / 16) * 64) + (r % 16) + 16 * (kk % 4)] = va[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kConvStageIters; ++u) {
+        const int32_t id = threadIdx.x + u * kConvThreads;
+        const int32_t pos = base - kConvHalo + id / n_cc;
+        if (id < n_b)
+            *reinterpret_cast<bf16x8 *>(sB + (id / n_cc) * stride + 8 * (id % n_cc)) =
+                pos >= 0 && pos < L ? vb[u] : zero8();
+    }
+}
+
+// Fragments of k-step k0 from LDS: B at source position t + sign (tap - 4)
+// (sign +1 forward, -1 for the input gradient), t = tb + 16 n, tb the lane's
+// position relative to the staged origin base - 4.
+template <int MT, int C>
+__device__ __forceinline__ void conv_read(ConvFrags<MT> &f, const bf16x8 *sA, const __bf16 *sB, int32_t k_valid,
+                                          int32_t tb, int sign, int32_t k0, int l) {
+    const int32_t k = k0 + 8 * (l / 16);
+    const int32_t tap = k / C, ci = k % C;
+    constexpr int32_t stride = C + 8;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) f.a[m] = sA[((k0 / 32) * MT + m) * 64 + l];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        const int32_t t = t0 + 16 * n;
-        const int32_t s = t + sign * (tap - 4);
-        f.b[n] = (k < k_valid && s >= 0 && s < L && t < L) ? load8(src + (int64_t)s * c + ci) : zero8();
+        const int32_t rr = tb + 16 * n + sign * (tap - 4);
+        f.b[n] = k < k_valid ? *reinterpret_cast<const bf16x8 *>(sB + rr * stride + ci) : zero8();
     }
 }
 
@@ -117,36 +179,43 @@ __device__ __forceinline__ void conv_mfma(f32x4 (&acc)[MT][4], const ConvFrags<M
         for (int n = 0; n < 4; ++n) acc[m][n] = mfma16(f.a[m], f.b[n], acc[m][n]);
 }
 
-// acc[m][n] = sum over the k-steps of A rows x B columns (ping-pong over two
-// fragment sets).
-template <int MT>
-__device__ __forceinline__ void conv_gemm(f32x4 (&acc)[MT][4], const __bf16 *__restrict__ a_mat, int32_t a_ld,
-                                          const __bf16 *__restrict__ src, int32_t c, int32_t k_valid, int32_t k_end,
-                                          int32_t L, int32_t t0, int sign, int l) {
+// acc[m][n] = sum over the k-steps of A rows x B columns, from the staged
+// operands (ping-pong over two fragment sets).
+template <int MT, int C, int KP>
+__device__ __forceinline__ void conv_gemm(f32x4 (&acc)[MT][4], const bf16x8 *sA, const __bf16 *sB, int32_t k_valid,
+                                          int32_t tb, int sign, int l) {
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     ConvFrags<MT> f0, f1;
-    conv_load<MT>(f0, a_mat, a_ld, src, c, k_valid, L, t0, sign, 0, l);
-    for (int32_t k0 = 0; k0 < k_end; k0 += 64) {
-        const bool more = k0 + 32 < k_end;
-        if (more) conv_load<MT>(f1, a_mat, a_ld, src, c, k_valid, L, t0, sign, k0 + 32, l);
+    conv_read<MT, C>(f0, sA, sB, k_valid, tb, sign, 0, l);
+    for (int32_t k0 = 0; k0 < KP; k0 += 64) {
+        const bool more = k0 + 32 < KP;
+        if (more) conv_read<MT, C>(f1, sA, sB, k_valid, tb, sign, k0 + 32, l);
         conv_mfma<MT>(acc, f0);
         if (!more) break;
-        if (k0 + 64 < k_end) conv_load<MT>(f0, a_mat, a_ld, src, c, k_valid, L, t0, sign, k0 + 64, l);
+        if (k0 + 64 < KP) conv_read<MT, C>(f0, sA, sB, k_valid, tb, sign, k0 + 64, l);
         conv_mfma<MT>(acc, f1);
     }
 }
 
-__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) conv_fwd_kernel(const __bf16 *__restrict__ x, int32_t cin, int32_t L,
-                                                      const __bf16 *__restrict__ w, int32_t k32,
-                                                      const float *__restrict__ bias, __bf16 *__restrict__ y) {
+template <int CIN>
+__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(2)))
+conv_fwd_kernel(const __bf16 *__restrict__ x, int32_t L, const __bf16 *__restrict__ w,
+                const float *__restrict__ bias, __bf16 *__restrict__ y) {
+    constexpr int32_t k32 = (kTaps * CIN + 31) / 32 * 32;
+    __shared__ bf16x8 s_a[kConvLdsA / 16];
+    __shared__ bf16x8 s_b[kConvLdsB / 16];
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.y;
-    const int32_t t0 = blockIdx.x * kConvPos + wave * 64 + (l % 16);  // this lane's column of tile n: t0 + 16 n
+    const int32_t base = blockIdx.x * kConvPos;
+    conv_stage<4, CIN, k32>(s_a, reinterpret_cast<__bf16 *>(s_b), w, k32, x + b * (int64_t)L * CIN, L, base);
+    __syncthreads();
+    const int32_t tb = kConvHalo + wave * 64 + (l % 16);  // staged row of this lane's column of tile 0
     f32x4 acc[4][4];
-    conv_gemm<4>(acc, w, k32, x + b * (int64_t)L * cin, cin, kTaps * cin, k32, L, t0, +1, l);
+    conv_gemm<4, CIN, k32>(acc, s_a, reinterpret_cast<const __bf16 *>(s_b), kTaps * CIN, tb, +1, l);
+    const int32_t t0 = base + wave * 64 + (l % 16);  // this lane's column of tile n: t0 + 16 n
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int32_t t = t0 + 16 * n;
@@ -181,18 +250,24 @@ __global__ void conv_transpose_w_kernel(const __bf16 *__restrict__ w, int32_t ci
 
 // ------------------------------------------------------- conv backward-x
 // dX[b][t][ci] (FP32) = sum over tap, co of WT[ci][tap*64 + co] G[b][t - tap + 4][co],
-// the same register-tiled implicit GEMM as the forward pass with cin / 16
-// row tiles (cin in {16, 64}); workgroup: 256 positions of one example.
+// the same LDS-staged implicit GEMM as the forward pass with cin / 16 row
+// tiles (cin in {16, 64}); workgroup: 512 positions of one example.
 template <int MT>
-__global__ void __launch_bounds__(kT) conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L,
-                                                        const __bf16 *__restrict__ wt, float *__restrict__ dx) {
+__global__ void __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(2)))
+conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L, const __bf16 *__restrict__ wt, float *__restrict__ dx) {
+    __shared__ bf16x8 s_a[kConvLdsA / 16];
+    __shared__ bf16x8 s_b[kConvLdsB / 16];
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t b = blockIdx.y;
-    const int32_t t0 = blockIdx.x * kConvPos + wave * 64 + (l % 16);
+    const int32_t base = blockIdx.x * kConvPos;
     constexpr int32_t kK = kTaps * kWidth;  // 576, a multiple of 32
     constexpr int cin = 16 * MT;
+    conv_stage<MT, kWidth, kK>(s_a, reinterpret_cast<__bf16 *>(s_b), wt, kK, g + b * (int64_t)L * kWidth, L, base);
+    __syncthreads();
+    const int32_t tb = kConvHalo + wave * 64 + (l % 16);
     f32x4 acc[MT][4];
-    conv_gemm<MT>(acc, wt, kK, g + b * (int64_t)L * kWidth, kWidth, kK, kK, L, t0, -1, l);
+    conv_gemm<MT, kWidth, kK>(acc, s_a, reinterpret_cast<const __bf16 *>(s_b), kK, tb, -1, l);
+    const int32_t t0 = base + wave * 64 + (l % 16);
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int32_t t = t0 + 16 * n;
@@ -357,8 +432,13 @@ extern "C" int cetra_conv1d_fwd(void *stream, const void *x, int32_t cin, int32_
     CETRA_REQUIRE(x && w && bias && y, "conv1d_fwd: NULL pointer");
     int rc = conv_args_ok(cin, L, batch, k32);
     if (rc) return rc;
-    hipLaunchKernelGGL(conv_fwd_kernel, dim3((unsigned)ceil_div(L, kConvPos), (unsigned)batch), dim3(kT), 0,
-                       as_stream(stream), (const __bf16 *)x, cin, L, (const __bf16 *)w, k32, bias, (__bf16 *)y);
+    const dim3 gf((unsigned)ceil_div(L, kConvPos), (unsigned)batch);
+    if (cin == 16)
+        hipLaunchKernelGGL(conv_fwd_kernel<16>, gf, dim3(kConvThreads), 0, as_stream(stream), (const __bf16 *)x, L,
+                           (const __bf16 *)w, bias, (__bf16 *)y);
+    else
+        hipLaunchKernelGGL(conv_fwd_kernel<64>, gf, dim3(kConvThreads), 0, as_stream(stream), (const __bf16 *)x, L,
+                           (const __bf16 *)w, bias, (__bf16 *)y);
     return check_launch("conv1d_fwd");
 }
 
@@ -388,10 +468,10 @@ extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, co
     if ((rc = check_launch("conv1d_bwd/transpose"))) return rc;
     const dim3 gx((unsigned)ceil_div(L, kConvPos), (unsigned)batch);
     if (cin == 16)
-        hipLaunchKernelGGL(conv_bwd_x_kernel<1>, gx, dim3(kT), 0, s, (const __bf16 *)g_scratch, L,
+        hipLaunchKernelGGL(conv_bwd_x_kernel<1>, gx, dim3(kConvThreads), 0, s, (const __bf16 *)g_scratch, L,
                            (const __bf16 *)wt_scratch, dx);
     else
-        hipLaunchKernelGGL(conv_bwd_x_kernel<4>, gx, dim3(kT), 0, s, (const __bf16 *)g_scratch, L,
+        hipLaunchKernelGGL(conv_bwd_x_kernel<4>, gx, dim3(kConvThreads), 0, s, (const __bf16 *)g_scratch, L,
                            (const __bf16 *)wt_scratch, dx);
     return check_launch("conv1d_bwd/x");
 }

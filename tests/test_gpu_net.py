@@ -73,7 +73,7 @@ def packed_w(W):
     return out
 
 
-@pytest.mark.parametrize("cin,L,B", [(16, 300, 2), (64, 131, 3), (16, 1, 1), (64, 64, 1)])
+@pytest.mark.parametrize("cin,L,B", [(16, 300, 2), (64, 131, 3), (16, 1, 1), (64, 64, 1), (64, 1100, 2), (16, 1029, 1)])
 def test_conv_forward(torch, pn, cin, L, B):
     rng = np.random.default_rng(cin + L)
     x = bf16_exact(rng, (B, cin, L), 0.0, 1.0)
@@ -89,7 +89,7 @@ def test_conv_forward(torch, pn, cin, L, B):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * scale)
 
 
-@pytest.mark.parametrize("cin,L,B", [(16, 300, 2), (64, 517, 2), (64, 5, 1)])
+@pytest.mark.parametrize("cin,L,B", [(16, 300, 2), (64, 517, 2), (64, 5, 1), (64, 1100, 1), (16, 1029, 2)])
 def test_conv_backward(torch, pn, cin, L, B):
     rng = np.random.default_rng(7 * cin + L)
     x = bf16_exact(rng, (B, cin, L), 0.0, 1.0)
