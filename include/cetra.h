@@ -450,7 +450,8 @@ int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, const void *x
 int cetra_net_project_fwd(void *stream, const void *h, int64_t n_pos, const float *P, const float *p, int32_t E,
                           float *e);
 /* Backward of the projection given ge [n_pos][E]: dh [n_pos][64] FP32
- * (overwritten), dP [E][64] and dp[E] accumulate. */
+ * (overwritten; 16-byte aligned, else CETRA_ERR_INVALID), dP [E][64] and
+ * dp[E] accumulate.  n_pos <= 2^31. */
 int cetra_net_project_bwd(void *stream, const void *h, const float *ge, int64_t n_pos, const float *P, int32_t E,
                           float *dh, float *dP, float *dp);
 

@@ -41,19 +41,22 @@ __global__ void project_fwd_kernel(const __bf16 *__restrict__ h, int64_t n_pos, 
     }
 }
 
-// dh[pos][ci] = sum_c P[c][ci] ge[pos][c] (one lane per position).
+// dh[pos][ci] = sum_c P[c][ci] ge[pos][c]: a lane per (position, 4
+// consecutive channels), so consecutive lanes write consecutive 16 bytes.
 __global__ void __launch_bounds__(kT) project_bwd_dh_kernel(const float *__restrict__ ge, int64_t n_pos,
                                                             const float *__restrict__ P, int32_t E,
                                                             float *__restrict__ dh) {
-    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= n_pos) return;
-    float g[kMaxE];
-    for (int c = 0; c < E; ++c) g[c] = ge[pos * E + c];
-    for (int ci = 0; ci < kWidth; ++ci) {
-        float s = 0.0f;
-        for (int c = 0; c < E; ++c) s = fmaf(P[c * kWidth + ci], g[c], s);
-        dh[pos * kWidth + ci] = s;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_pos * (kWidth / 4)) return;
+    const int64_t pos = id / (kWidth / 4);
+    const int ci = 4 * (int)(id % (kWidth / 4));
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < E; ++c) {
+        const float g = ge[pos * E + c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s[r] = fmaf(P[c * kWidth + ci + r], g, s[r]);
     }
+    *reinterpret_cast<float4 *>(dh + pos * kWidth + ci) = make_float4(s[0], s[1], s[2], s[3]);
 }
 
 // dP[c][ci] += sum_pos ge[pos][c] h[pos][ci] and dp[c] += sum_pos ge[pos][c]
@@ -70,6 +73,9 @@ __global__ void __launch_bounds__(kT) project_bwd_dp_kernel(const __bf16 *__rest
     const int32_t n_pairs = E * kWidth;
     float acc[kPairs] = {0.0f, 0.0f, 0.0f, 0.0f};
     float accb = 0.0f;
+    // unrolled so that several positions' loads are in flight at once (the
+    // sums keep their position order)
+#pragma unroll 8
     for (int64_t pos = p0; pos < p1; ++pos) {
 #pragma unroll
         for (int k = 0; k < kPairs; ++k) {
@@ -468,10 +474,11 @@ extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *g
                                      int32_t E, float *dh, float *dP, float *dp) {
     clear_error();
     CETRA_REQUIRE(h && ge && P && dh && dP && dp, "net_project_bwd: NULL pointer");
-    CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0, "net_project_bwd: bad sizes");
+    CETRA_REQUIRE(E >= 1 && E <= kMaxE && n_pos >= 0 && n_pos <= ((int64_t)1 << 31), "net_project_bwd: bad sizes");
+    CETRA_REQUIRE(((uintptr_t)dh & 15) == 0, "net_project_bwd: dh must be 16-byte aligned");
     hipStream_t st = as_stream(stream);
-    hipLaunchKernelGGL(project_bwd_dh_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kT)), dim3(kT),
-                       0, st, ge, n_pos, P, E, dh);
+    hipLaunchKernelGGL(project_bwd_dh_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos * (kWidth / 4), 1), kT)),
+                       dim3(kT), 0, st, ge, n_pos, P, E, dh);
     int rc = check_launch("net_project_bwd/dh");
     if (rc) return rc;
     hipLaunchKernelGGL(project_bwd_dp_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kProjChunk)),
