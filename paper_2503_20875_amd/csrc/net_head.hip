@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kT) project_bwd_dh_kernel(const float *__restr
 // over a chunk of positions per workgroup: lane t accumulates the (c, ci)
 // pairs t, t + 256, ... in registers and adds them once (one atomic per pair
 // and workgroup).
-constexpr int kProjChunk = 1024;
+constexpr int kProjChunk = 256;
 __global__ void __launch_bounds__(kT) project_bwd_dp_kernel(const __bf16 *__restrict__ h,
                                                             const float *__restrict__ ge, int64_t n_pos, int32_t E,
                                                             float *__restrict__ dP, float *__restrict__ dp) {
@@ -73,9 +73,6 @@ __global__ void __launch_bounds__(kT) project_bwd_dp_kernel(const __bf16 *__rest
     const int32_t n_pairs = E * kWidth;
     float acc[kPairs] = {0.0f, 0.0f, 0.0f, 0.0f};
     float accb = 0.0f;
-    // unrolled so that several positions' loads are in flight at once (the
-    // sums keep their position order)
-#pragma unroll 8
     for (int64_t pos = p0; pos < p1; ++pos) {
 #pragma unroll
         for (int k = 0; k < kPairs; ++k) {
