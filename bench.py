@@ -447,6 +447,7 @@ def learned_block(n_curves: int, seed: int = 20250402, target: float = 0.99) -> 
     test_curves = [W.learned_curve(rng_test) for _ in range(n_curves - n_cal)]
     test_k = evaluate(pipe, net, test_curves, top_k=k_target)
     test_fb = evaluate(pipe, net, test_curves, fallback_snr=tau)
+    batched = learned_batched(pipe, net, test_curves, test_k, k_target)
 
     def point(r):
         return {"recall_at_snr7": r["recall"], "n_detections": r["n_detections"], "n_recalled": r["n_recalled"],
@@ -466,8 +467,44 @@ def learned_block(n_curves: int, seed: int = 20250402, target: float = 0.99) -> 
         "proposal_only": {"k_windows": k_target, **point(test_k)},
         "proposal_with_fallback": {"k_windows": pipe.cfg.top_k, "fallback_snr": tau if np.isfinite(tau) else None,
                                    **point(test_fb)},
+        "batched": batched,
         "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "batch", "lr", "seed")},
     }
+
+
+def learned_batched(pipe, net, curves, ref, k_target: int) -> dict:
+    """The learned and plain searches over the test curves as one batch: the
+    fold-ready arrays of all curves are resident, then the plain periodic
+    searches run back to back against `Pipeline.search_batch` (features, one
+    network forward over the batch, top-K, restricted searches) at K = 64
+    and at the calibrated K; device time over the whole batch.  Recall is
+    checked against the plain records of the same batch."""
+    import torch
+    folds = [pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
+                         torch.as_tensor(s, device="cuda")) for t, f, s, _ in curves]
+    pipe.plain(folds[0])
+    pipe.search_batch(net, folds[:2], 64)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = fn()
+        b.record()
+        b.synchronize()
+        return out, a.elapsed_time(b)
+
+    plain, ms_plain = timed(lambda: [pipe.plain(f) for f in folds])
+    out = {"n_curves": len(folds), "plain_ms": ms_plain}
+    for name, k in (("k64", 64), ("k_target", k_target)):
+        res, ms = timed(lambda: pipe.search_batch(net, folds, k))
+        det = [i for i, p in enumerate(plain) if p["k"] >= 0 and p["snr"] > 7.0]
+        hit = [i for i in det if res[i][0] is not None and res[i][0]["k"] == plain[i]["k"]]
+        out[name] = {"top_k": k, "learned_ms": ms, "speedup": ms_plain / ms, "n_detections": len(det),
+                     "n_recalled": len(hit), "recall": len(hit) / len(det) if det else None,
+                     "periods_folded_fraction": sum(r[1] for r in res) / (len(folds) * pipe.K)}
+    del folds
+    return out
 
 
 def main():

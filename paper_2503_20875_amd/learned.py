@@ -112,6 +112,22 @@ class Pipeline:
             return self.plain(fold), snr_r, True, n_sub + self.K
         return rec, snr_r, False, n_sub
 
+    def search_batch(self, net: ProposalNet, folds, top_k: int = 0):
+        """The learned search over a batch of curves: features of every curve,
+        one network forward over the batch, the top-K windows per curve, then
+        the restricted periodic searches back to back.  `folds` are the
+        curves' fold-ready arrays (this pipeline's grid).  Returns per curve
+        (host best record or None, periods folded)."""
+        import torch
+        from .proposal import C_IN
+        x = torch.empty((len(folds), self.cfg.n_bins, C_IN), dtype=torch.bfloat16, device="cuda")
+        for b, fold in enumerate(folds):
+            self.features(fold, out=x[b])
+        z = net.forward(x, self.windows)
+        self.last_scores = z
+        sel = topk_windows(z, int(top_k or self.cfg.top_k))
+        return [self.restricted(fold, sel[b]) for b, fold in enumerate(folds)]
+
     def window_of(self, period: float) -> int:
         w = int(np.searchsorted(self.windows.edges, period, side="right") - 1)
         return w if 0 <= w < self.windows.n else -1

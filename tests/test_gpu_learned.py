@@ -123,3 +123,34 @@ def test_long_baseline_proposal_finds_the_earth_analogue():
     assert not fell_back and n_sub < pipe.K // 4
     assert abs(bp["period"] / 365.25 - 1) < 0.002
     assert rec["k"] == bp["k"] and rec["epoch"] == bp["epoch"] and rec["dur"] == bp["dur"]
+
+
+def test_search_batch_matches_single_curves():
+    """The batched learned search (one network forward over the batch, then
+    the restricted searches) returns, curve by curve, the records and period
+    counts of the single-curve learned search."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_20875_amd.learned import load_weights
+    from paper_2503_20875_amd.train_proposal import make_pipeline
+    from synthlc import workloads as W
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2503_20875_amd", "weights", "proposal.npz")
+    net, _ = load_weights(path)
+    pipe = make_pipeline()
+    rng = np.random.default_rng(77)
+    print("[case] batched learned search, 5 curves", flush=True)
+    folds = []
+    for _ in range(5):
+        t, f, s, _ = W.learned_curve(rng)
+        folds.append(pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
+                                 torch.as_tensor(s, device="cuda")))
+    batch = pipe.search_batch(net, folds, 64)
+    for fold, (rec_b, n_b) in zip(folds, batch):
+        rec, _, fell_back, n_sub = pipe.search(net, fold, 64)
+        assert not fell_back and n_sub == n_b
+        assert (rec is None) == (rec_b is None)
+        if rec is not None:
+            assert (rec["k"], rec["epoch"], rec["dur"]) == (rec_b["k"], rec_b["epoch"], rec_b["dur"])
+            assert rec["snr"] == rec_b["snr"]
