@@ -125,8 +125,12 @@ __device__ __forceinline__ float fold_sum_wave(const float *s_e, int32_t L, uint
     const uint32_t ph = (uint32_t)(ph0 + lane);
     const uint32_t lim0 = uL - (uint32_t)ph0;  // ph0 < L: lane 0 is in range at transit 0
     // groups of four transits, branch-free inside: out-of-range elements read
-    // a clamped index and add zero, so the four LDS reads are in flight together
-    while ((uint32_t)(o >> 32) < lim0) {
+    // a clamped index and add zero, so the four LDS reads are in flight
+    // together; full groups while lane 0's fourth transit is inside the
+    // series, then at most three single transits into the same partial sums
+    // (transit k always goes to a[k % 4], so the sums do not depend on how
+    // the loop is split)
+    while ((uint32_t)((o + 3 * step) >> 32) < lim0) {
         uint32_t x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -142,6 +146,16 @@ __device__ __forceinline__ float fold_sum_wave(const float *s_e, int32_t L, uint
             a[u] += in ? val[u] : 0.0f;
             cnt += in ? 1 : 0;
         }
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        if ((uint32_t)(o >> 32) >= lim0) break;  // wave-uniform
+        const uint32_t x = ph + (uint32_t)(o >> 32);
+        o += step;
+        const bool in = x < uL;
+        const float val = s_e[in ? x : uL - 1];
+        a[u] += in ? val : 0.0f;
+        cnt += in ? 1 : 0;
     }
     n = cnt;
     return (a[0] + a[1]) + (a[2] + a[3]);
