@@ -828,8 +828,9 @@ __device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int
 // step's window with an explicit vmcnt that leaves the later steps' loads
 // outstanding (loads retire in issue order), and a slot is refilled only
 // after the LDS reads of the step that used it have returned (lgkmcnt(0)).
-// The loads take their LDS base from M0, which the asm sets; no other
-// instruction of the fold kernels reads M0.  Bit-identical to variants 2
+// The loads take their LDS base from M0, which the asm sets.  The compiler
+// reserves M0 (a clobber of it is ignored) and no other instruction of the
+// fold kernels reads it, so the asm need not restore it.  Bit-identical to variants 2
 // and 3 but slower on gfx950: the windows (sized for a tile's largest
 // spread) take a third fewer loads than the direct loads of variant 2, yet
 // the address unit spends about 1.25 times as many cycles on a load into
@@ -856,7 +857,7 @@ __device__ __forceinline__ void dma_window(__amdgpu_buffer_rsrc_t r, uint32_t sl
             "buffer_load_dwordx4 %1, %2, 0 offen offset:1024 lds"
             :
             : "s"(slot), "v"(voff), "s"(r)
-            : "memory", "m0");
+            : "memory");
     else
         asm volatile(
             "s_waitcnt lgkmcnt(0)\n\t"
@@ -867,7 +868,7 @@ __device__ __forceinline__ void dma_window(__amdgpu_buffer_rsrc_t r, uint32_t sl
             "buffer_load_dwordx4 %1, %2, 0 offen offset:2048 lds"
             :
             : "s"(slot), "v"(voff), "s"(r)
-            : "memory", "m0");
+            : "memory");
 }
 
 // Wait until at most N vector-memory loads of this wave are outstanding.
