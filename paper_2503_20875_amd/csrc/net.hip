@@ -323,6 +323,7 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) co
     // rows of 264 elements (528 bytes, 16 bytes past a multiple of 256): the
     // 16 rows one MFMA fragment read touches start on distinct bank groups
     constexpr int kRow = kPosChunk + 2 * kHalo;
+    static_assert(kRow % 8 == 0 && kPosChunk % 8 == 0, "8-position blocks");
     __shared__ __attribute__((aligned(16))) __bf16 s_g[kWidth][kRow];  // 33 KB
     __shared__ __attribute__((aligned(16))) __bf16 s_x[cin][kRow];     // <= 33 KB
     const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -343,22 +344,46 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) co
         const int32_t p0 = (blockIdx.x * kChunksPerWg + ch) * kPosChunk;
         if (p0 >= L) break;  // uniform over the workgroup
         __syncthreads();     // the previous chunk's reads are done
-        // transposing copies: a lane takes one position and 8 channels at a
-        // time (one 16-byte load), consecutive lanes consecutive positions,
-        // so each LDS row is written contiguously
-        for (int i = threadIdx.x; i < (kWidth / 8) * kPosChunk; i += kT) {
-            const int p = i % kPosChunk, c8 = 8 * (i / kPosChunk);
-            const bf16x8 v = (p0 + p < L) ? load8(gb + (int64_t)(p0 + p) * kWidth + c8) : zero8();
+        // transposing copies in 8 x 8 blocks: a thread loads 8 consecutive
+        // positions of 8 channels (eight 16-byte loads, from clamped and
+        // always valid positions, zeroed afterwards when outside [0, L)),
+        // transposes them in registers and writes 8 channel rows of 8
+        // positions with 16-byte LDS stores
+        for (int i = threadIdx.x; i < (kWidth / 8) * (kPosChunk / 8); i += kT) {
+            const int c8 = 8 * (i / (kPosChunk / 8)), pg = 8 * (i % (kPosChunk / 8));
+            bf16x8 v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s_g[c8 + j][p] = v[j];
+            for (int q = 0; q < 8; ++q) v[q] = load8(gb + (int64_t)min(p0 + pg + q, L - 1) * kWidth + c8);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (p0 + pg + q >= L) v[q] = zero8();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                bf16x8 r;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r[q] = v[q][j];
+                *reinterpret_cast<bf16x8 *>(&s_g[c8 + j][pg]) = r;
+            }
         }
-        // s_x[ci][pp] = X[p0 + pp - kHalo]
-        for (int i = threadIdx.x; i < (cin / 8) * kRow; i += kT) {
-            const int pp = i % kRow, c8 = 8 * (i / kRow);
-            const int32_t src = p0 + pp - kHalo;
-            const bf16x8 v = (src >= 0 && src < L) ? load8(xb + (int64_t)src * cin + c8) : zero8();
+        // s_x[ci][pp] = X[p0 + pp - kHalo], pp < kRow (= 33 blocks of 8)
+        for (int i = threadIdx.x; i < (cin / 8) * (kRow / 8); i += kT) {
+            const int c8 = 8 * (i / (kRow / 8)), pg = 8 * (i % (kRow / 8));
+            bf16x8 v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s_x[c8 + j][pp] = v[j];
+            for (int q = 0; q < 8; ++q)
+                v[q] = load8(xb + (int64_t)min(max(p0 + pg + q - kHalo, 0), L - 1) * cin + c8);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int32_t src = p0 + pg + q - kHalo;
+                if (src < 0 || src >= L) v[q] = zero8();
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                bf16x8 r;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r[q] = v[q][j];
+                *reinterpret_cast<bf16x8 *>(&s_x[c8 + j][pg]) = r;
+            }
         }
         __syncthreads();
         for (int32_t q0 = 0; q0 < kPosChunk; q0 += 32) {
