@@ -211,7 +211,7 @@ def learned_long_block(wl, top_k: int = 64) -> dict:
             "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "n_trial", "seed")}}
 
 
-def long_baseline_block(tunings=((8, 8, 4, 2), (8, 8, 4, 3)), reps: int = 2) -> dict:
+def long_baseline_block(tunings=((8, 8, 4, 2),), reps: int = 2) -> dict:
     """The Earth-analogue curve (730.5 d at 25 s: 2 524 608 points, J = 30,
     I = 1 755 200, K = 399 404): a 421 MB fold-ready array, larger than the
     256 MB Infinity Cache (the concurrent workgroups sweep one 14 MB duration

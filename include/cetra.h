@@ -120,15 +120,9 @@ typedef struct cetra_tuning {
     int32_t fold_wgs_per_cu;    /* resident workgroups per compute unit, 1..32       */
     int32_t fold_units_per_wg;  /* target work units per workgroup, 1..64            */
     int32_t fold_variant;       /* 0: register fold, lane epochs 64 apart;
-                                   1: each transit step's window staged in LDS
-                                      for the whole workgroup;
                                    2: register fold, adjacent lane epochs and
-                                      16-byte loads;
-                                   3: as 2, each wave staging its period block's
-                                      window in its own LDS buffer;
-                                   4: as 3, the windows loaded straight into a
-                                      four-slot LDS ring per wave, three steps
-                                      ahead                                    */
+                                      16-byte loads (1, 3 and 4 are retired:
+                                      LDS-staged forms that measured slower)   */
     int32_t reserved[4];
 } cetra_tuning;
 

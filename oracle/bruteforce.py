@@ -17,7 +17,8 @@ Independent of ``oracle.c`` in every step:
 
 The grid conventions follow the same readings as the oracle (window
 [t_i - D/2, t_i + D/2], null if it leaves [0, (N-1)c]; nearest cell-centred
-template sample; nearest reference time for each transit).
+template sample; nearest reference time for each transit; a period shorter
+than the reference-time step, or not finite, is not evaluated).
 """
 
 from __future__ import annotations
@@ -82,6 +83,10 @@ class BruteGrid:
             g[n] = float(model[k])
         return g
 
+    def evaluates(self, period):
+        """Whether the periodic search evaluates this period at all."""
+        return bool(np.isfinite(period)) and Fr(float(period)) >= Fr(self.dt)
+
     def transit_epochs(self, i, period):
         """Grid epochs i + round_half_up(m P / dt), m = 0, 1, ... inside the grid."""
         out = []
@@ -98,6 +103,15 @@ class BruteGrid:
         return min(self.I, math.ceil(Fr(float(period)) / Fr(self.dt)))
 
 
+def loglike(g, depth, flux, w):
+    """Gaussian log-likelihood (Eq. 1, normalisation included) of the model
+    depth * g over every resampled point with finite uncertainty
+    (sigma^2 = 1/w); null points (w = 0) carry no information."""
+    ok = w > 0
+    lnorm = -0.5 * np.log(2 * np.pi / w[ok])
+    return float(np.sum(-0.5 * w[ok] * (depth * g[ok] - flux[ok]) ** 2 + lnorm))
+
+
 def fit(g, flux, w):
     """Least-squares depth of model g on all points, its variance, and the
     full-Eq.-1 log-likelihood ratio against the zero-offset model."""
@@ -107,10 +121,7 @@ def fit(g, flux, w):
     if b <= 0:
         return None
     z = a / b
-    lnorm = -0.5 * np.log(2 * np.pi / w[ok])
-    l_model = np.sum(-0.5 * w[ok] * (z * g[ok] - flux[ok]) ** 2 + lnorm)
-    l_zero = np.sum(-0.5 * w[ok] * flux[ok] ** 2 + lnorm)
-    return z, 1.0 / b, float(l_model - l_zero)
+    return z, 1.0 / b, loglike(g, z, flux, w) - loglike(g, 0.0, flux, w)
 
 
 def linear(bg: BruteGrid, flux, w, model, elements=None):
@@ -138,6 +149,9 @@ def periodic(bg: BruteGrid, flux, w, model, periods, windows=None, stride=None):
     results = []
     for P in periods:
         best = None
+        if not bg.evaluates(P):
+            results.append(best)
+            continue
         for j, D in enumerate(bg.durations):
             if not D < P:
                 continue

@@ -172,6 +172,31 @@ def windows_for(n_windows: int, p_lo: float, p_hi: float):
     return q, edges
 
 
+def downsample(fold, n_bins: int):
+    """Network input from the linear search's fold-ready pairs (reading N1).
+
+    fold: [J, I, 2] (S_fm, S_mm) per duration and reference time.  For
+    duration j and bin b, which covers the reference times
+    [floor(b I / L), floor((b + 1) I / L)), the feature is the largest
+    single-event SNR over the bin, |S_fm| / sqrt(S_mm) = |depth| / sqrt(var)
+    (Sec. 2.2; a null element, S_mm = 0, counts as 0), clipped at 30 and
+    divided by 8.  Returns [L, J] (bin-major, the network's layout), FP64.
+    """
+    fold = np.asarray(fold, dtype=np.float64)
+    J, I = fold.shape[0], fold.shape[1]
+    out = np.zeros((n_bins, J))
+    for b in range(n_bins):
+        i0, i1 = b * I // n_bins, (b + 1) * I // n_bins
+        a = fold[:, i0:i1, 0]
+        s = fold[:, i0:i1, 1]
+        snr = np.zeros_like(a)
+        ok = s > 0
+        snr[ok] = np.abs(a[ok]) / np.sqrt(s[ok])
+        if i1 > i0:
+            out[b] = snr.max(axis=1)
+    return np.minimum(out, 30.0) / 8.0
+
+
 def bf16(x):
     """Round to the nearest bfloat16 (ties to even), returned as float64."""
     a = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)

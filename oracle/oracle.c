@@ -258,9 +258,24 @@ double ora_loglike0(const ora_grid *g, const double *flux, const double *ivar) {
  * I_P = min(I, ceil(R / 2^32)) (reference times beyond one period duplicate
  * earlier ones, Sec. 2.3).  Transit m of epoch i maps to the nearest grid
  * reference time i + o_m, o_m = (m R + 2^31) >> 32 (nearest-neighbour mapping,
- * Sec. 2.3). */
-static uint64_t period_step(const ora_grid *g, double period) {
-    return (uint64_t)llround(TWO32 * (period / g->t0_step));
+ * Sec. 2.3).
+ * Reading for the edges of the period range: a period shorter than the
+ * reference-time step, or not finite, is not evaluated (its transits would
+ * land on the same grid epoch more than once) and gets the null record; a
+ * period of at least I steps has exactly one transit per epoch inside the
+ * grid (transit 1 would fall at or beyond reference time I), so its step is
+ * taken as I * 2^32, which keeps R inside 64 bits for any such period.
+ * Returns 0 if the period is not evaluated, else 1 with *R and *IP set. */
+static int period_plan(const ora_grid *g, double period, uint64_t *R, int64_t *IP) {
+    if (!isfinite(period) || !(period >= g->t0_step)) return 0;
+    double steps = period / g->t0_step;
+    if (steps >= (double)g->n_t0)
+        *R = (uint64_t)g->n_t0 << 32;
+    else
+        *R = (uint64_t)llround(TWO32 * steps);
+    int64_t ip = (int64_t)((*R + 4294967295ULL) >> 32);
+    *IP = ip > g->n_t0 ? g->n_t0 : ip;
+    return 1;
 }
 
 static int64_t transit_offset(uint64_t R, int64_t m) {
@@ -281,6 +296,7 @@ static int fold_one(const ora_grid *g, const double *depth, const double *var, c
     const double *l = lr + (int64_t)j * I;
     const double *ab = aabs + (int64_t)j * I;
     double sw = 0.0, swd = 0.0, sab = 0.0;
+    if (R < 4294967296ULL) return 0; /* transits would not advance: not a period */
     for (int64_t m = 0;; ++m) {
         int64_t x = i + transit_offset(R, m);
         if (x >= I) break;
@@ -328,16 +344,14 @@ void ora_periodic(const ora_grid *g, const double *depth, const double *var, con
                   const double *aabs, const double *periods, const int32_t *jrange,
                   const int64_t *sel, int64_t n_sel, const int32_t *stride, double *lr_out, int32_t *i_out,
                   int32_t *j_out, double *z_out, double *zvar_out, double *aabs_out) {
-    int64_t I = g->n_t0;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < n_sel; ++s) {
         int64_t k = sel[s];
         double P = periods[k];
-        uint64_t R = period_step(g, P);
-        int64_t IP = (int64_t)((R + 4294967295ULL) >> 32);
-        if (IP > I) IP = I;
-        int jlo, jhi;
-        allowed_range(g, P, jrange, k, &jlo, &jhi);
+        uint64_t R = 0;
+        int64_t IP = 0;
+        int jlo = 0, jhi = -1;
+        if (period_plan(g, P, &R, &IP)) allowed_range(g, P, jrange, k, &jlo, &jhi);
         double best = -1.0, bz = NAN, bzv = INFINITY, bab = 0.0;
         int32_t bi = -1, bj = -1;
         for (int j = jlo; j <= jhi; ++j) {
@@ -366,7 +380,9 @@ void ora_periodic(const ora_grid *g, const double *depth, const double *var, con
 int ora_fold_at(const ora_grid *g, const double *depth, const double *var, const double *lr,
                 const double *aabs, double period, int64_t i, int32_t j,
                 double *lr_out, double *z_out, double *zvar_out, double *aabs_out) {
-    uint64_t R = period_step(g, period);
+    uint64_t R = 0;
+    int64_t IP = 0;
+    if (!period_plan(g, period, &R, &IP)) return 0;
     return fold_one(g, depth, var, lr, aabs, R, i, j, lr_out, z_out, zvar_out, aabs_out);
 }
 

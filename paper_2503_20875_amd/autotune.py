@@ -3,8 +3,7 @@
 Times the fold (``cetra_periodic_search``) on the caller's own grid,
 fold-ready array and periods under each candidate tuning -- period block,
 resident workgroups per compute unit, units per workgroup and the fold
-variant (register, workgroup LDS windows, register with 16-byte loads, wave
-LDS windows) -- and keeps
+variant (lane epochs 64 apart, or adjacent with 16-byte loads) -- and keeps
 the fastest with ``cetra_set_tuning``.
 Results do not depend on the tuning (the parity tests check that every
 variant returns identical records); only the time does.
@@ -17,7 +16,7 @@ import itertools
 from . import get_tuning, periodic_search, periodic_workspace, set_tuning
 
 DEFAULT_CANDIDATES = tuple(
-    (b, w, u, v) for b, w, u, v in itertools.product((4, 8, 16), (8,), (4, 16), (0, 1, 2, 3)))
+    (b, w, u, v) for b, w, u, v in itertools.product((4, 8, 16), (8,), (4, 16), (0, 2)))
 
 
 def tune_fold(grid, fold, periods, candidates=DEFAULT_CANDIDATES, repeats: int = 2, apply: bool = True):

@@ -100,7 +100,7 @@ extern "C" int cetra_set_tuning(const cetra_tuning *in) {
         CETRA_REQUIRE(in->fold_wgs_per_cu >= 1 && in->fold_wgs_per_cu <= 32, "set_tuning: fold_wgs_per_cu in [1, 32]");
         CETRA_REQUIRE(in->fold_units_per_wg >= 1 && in->fold_units_per_wg <= 64,
                       "set_tuning: fold_units_per_wg in [1, 64]");
-        CETRA_REQUIRE(in->fold_variant >= 0 && in->fold_variant <= 4, "set_tuning: fold_variant must be 0 to 4");
+        CETRA_REQUIRE(in->fold_variant == 0 || in->fold_variant == 2, "set_tuning: fold_variant must be 0 or 2");
         t = *in;
     }
     std::lock_guard<std::mutex> lock(g_tuning_mu);

@@ -11,11 +11,13 @@
 // Work mapping (gfx950): a persistent grid of workgroups strides over units
 // (period block of up to B periods, duration j, epoch chunk).  Every unit
 // costs about B * I element reads whatever the period, because the transits
-// of all epochs of one period tile the whole row.  A lane owns one epoch and
-// accumulates all B periods of its block in FP64 at once: the B loads of one
-// transit step are independent (memory-level parallelism) and hit nearly the
-// same addresses, since neighbouring trial periods shift the transits by a
-// few elements, so the block's periods share cache lines in L1/L2.  Units
+// of all epochs of one period tile the whole row.  A lane owns epochs and
+// sums all B periods of its block at once: the B loads of one transit step
+// are independent (memory-level parallelism) and hit nearly the same
+// addresses, since neighbouring trial periods shift the transits by a few
+// elements, so the block's periods share cache lines in L1/L2.  The sums
+// that rank candidates are FP32 chunks of 32 transits folded into FP32
+// totals; only each period's winner is recomputed in FP64 (epilogue).  Units
 // are ordered period-block fastest, so the workgroups running at once sweep
 // the same duration row, which then stays resident in each XCD's L2.
 //
@@ -109,25 +111,13 @@ __global__ void fold_setup_kernel(const double *__restrict__ periods, int64_t n_
 
 // Persistent grid over units (period block of B periods, duration j, epoch
 // chunk), ordered block-fastest; each unit is one dev::fold_unit (variant 0:
-// lane epochs 64 apart; 2: adjacent lane epochs, 16-byte loads),
-// dev::fold_unit_lds (variant 1: workgroup-wide LDS windows) or
-// dev::fold_unit_wlds (variant 3: wave-private LDS windows) or
-// dev::fold_unit_dma (variant 4: wave-private LDS ring filled by
-// direct-to-LDS loads).  kStrided: rows whose epoch stride exceeds 1 run
-// dev::fold_unit_strided on the coarser epoch grid (a separate
-// instantiation, so the plain kernels keep their register budget).
+// lane epochs 64 apart; 2: adjacent lane epochs, 16-byte loads).  kStrided:
+// rows whose epoch stride exceeds 1 run dev::fold_unit_strided on the
+// coarser epoch grid (a separate instantiation, so the plain kernels keep
+// their register budget).
 template <int B, int kVariant, bool kStrided = false>
 __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict__ fold, FoldWork w, int64_t n_eval,
                                                         int32_t I, int32_t n_chunks, int64_t n_units, Strides st) {
-    constexpr bool kLds = kVariant == 1;
-    constexpr bool kWaveLds = kVariant == 3;
-    constexpr bool kDma = kVariant == 4;
-    // float4 storage keeps every window 16-byte aligned
-    __shared__ float4 s_mem[kLds       ? cetra::dev::kFoldLdsCap
-                            : kWaveLds ? (kThreads / 64) * cetra::dev::kFoldWCap
-                            : kDma     ? (kThreads / 64) * cetra::dev::kFoldDmaSlots * cetra::dev::kFoldDmaCap / 2
-                                       : 1];
-    float2 *s_buf = reinterpret_cast<float2 *>(s_mem);
     const int64_t n_pblk = (n_eval + B - 1) / B;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pb = u % n_pblk;
@@ -165,17 +155,7 @@ __global__ void __launch_bounds__(kThreads) fold_kernel(const float2 *__restrict
         const int32_t e_lo = c * chunk;
         const int32_t e_hi = min(ipmax, e_lo + chunk);
         if (e_lo >= e_hi) continue;
-        if (kLds)
-            cetra::dev::fold_unit_lds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0, s_buf);
-        else if (kWaveLds)
-            cetra::dev::fold_unit_wlds<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0,
-                                          s_buf + (threadIdx.x >> 6) * 2 * cetra::dev::kFoldWCap);
-        else if (kDma)
-            cetra::dev::fold_unit_dma<B>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0,
-                                         s_buf + (threadIdx.x >> 6) * cetra::dev::kFoldDmaSlots *
-                                                     cetra::dev::kFoldDmaCap);
-        else
-            cetra::dev::fold_unit<B, kVariant == 2>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
+        cetra::dev::fold_unit<B, kVariant == 2>(fold + (int64_t)j * I, j, I, R, ipb, e_lo, e_hi, w.key + s0);
     }
 }
 
@@ -325,22 +305,13 @@ int periodic_search(void *stream, const cetra_grid *grid, const float *fold, con
     const int64_t n_pblk = ceil_div(n_eval, B);
     // persistent grid: no more workgroups than can be resident at once
     const void *kern = nullptr;
-    switch (tu.fold_variant * 3 + (B == 4 ? 0 : B == 8 ? 1 : 2)) {
+    switch ((tu.fold_variant == 2 ? 3 : 0) + (B == 4 ? 0 : B == 8 ? 1 : 2)) {
         case 0: kern = (const void *)fold_kernel<4, 0>; break;
         case 1: kern = (const void *)fold_kernel<8, 0>; break;
         case 2: kern = (const void *)fold_kernel<16, 0>; break;
-        case 3: kern = (const void *)fold_kernel<4, 1>; break;
-        case 4: kern = (const void *)fold_kernel<8, 1>; break;
-        case 5: kern = (const void *)fold_kernel<16, 1>; break;
-        case 6: kern = (const void *)fold_kernel<4, 2>; break;
-        case 7: kern = (const void *)fold_kernel<8, 2>; break;
-        case 8: kern = (const void *)fold_kernel<16, 2>; break;
-        case 9: kern = (const void *)fold_kernel<4, 3>; break;
-        case 10: kern = (const void *)fold_kernel<8, 3>; break;
-        case 11: kern = (const void *)fold_kernel<16, 3>; break;
-        case 12: kern = (const void *)fold_kernel<4, 4>; break;
-        case 13: kern = (const void *)fold_kernel<8, 4>; break;
-        default: kern = (const void *)fold_kernel<16, 4>; break;
+        case 3: kern = (const void *)fold_kernel<4, 2>; break;
+        case 4: kern = (const void *)fold_kernel<8, 2>; break;
+        default: kern = (const void *)fold_kernel<16, 2>; break;
     }
     if (st.any)  // a coarser epoch grid: its own instantiation, variant 2 for the rows of stride 1
         kern = B == 4 ? (const void *)fold_kernel<4, 2, true>

@@ -224,8 +224,10 @@ struct PeriodInfo {
 
 // Fixed-point step, epoch count and allowed duration range of a period:
 // D_j < P (Sec. 2.3) intersected with [jlo_cap, jhi_cap].  A period shorter
-// than the reference-time step (or not finite) is not evaluated: transit
-// offsets then advance by >= 1 per transit, which bounds every fold loop.
+// than the reference-time step (or not finite) is not evaluated, so transit
+// offsets advance by >= 1 per transit, which bounds every fold loop.  A
+// period of I or more steps has one transit per epoch inside the grid; its
+// step is taken as I * 2^32 (the same transits), which keeps R in 64 bits.
 __device__ __forceinline__ PeriodInfo period_info(double P, double t0_step, int64_t n_t0, int32_t n_dur,
                                                   const double *durations, int32_t jlo_cap, int32_t jhi_cap) {
     PeriodInfo pi;
@@ -233,8 +235,9 @@ __device__ __forceinline__ PeriodInfo period_info(double P, double t0_step, int6
     pi.n_ep = 0;
     pi.jlo = 0;
     pi.jhi = -1;
-    if (!isfinite(P) || !(P >= t0_step) || !(P / t0_step < 2.0e9)) return pi;
-    const uint64_t R = (uint64_t)llround(4294967296.0 * (P / t0_step));
+    if (!isfinite(P) || !(P >= t0_step)) return pi;
+    const double x = P / t0_step;
+    const uint64_t R = x >= (double)n_t0 ? (uint64_t)n_t0 << 32 : (uint64_t)llround(4294967296.0 * x);
     int64_t ip = (int64_t)((R + 4294967295ull) >> 32);
     if (ip > n_t0) ip = n_t0;
     int lo = max(0, jlo_cap), hi = min(n_dur - 1, jhi_cap);
@@ -579,673 +582,6 @@ __device__ __forceinline__ void fold_unit_strided(const float2 *row, int32_t j, 
                 const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
                 const uint32_t fine = h ? f1 : f0;
                 const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + fine);
-                best[b] = ok && key > best[b] ? key : best[b];
-            }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const uint64_t m = wave_max_u64(best[b]);
-        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
-    }
-}
-
-// Wave-private LDS fold unit (variant 3).  At transit step m the B periods
-// of the block read windows of 128 epochs at offsets o_b(m) that lie in
-// [o_slow(m), o_slow(m) + spread], o_slow being the offset of the period with
-// the smallest step (offsets grow with the step).  Over a tile the spread is
-// largest at the last step and is bounded before the tile starts; when the
-// bound leaves room in a kFoldWCap-pair buffer the whole tile runs from LDS:
-// per step the wave loads the union window once with 16-byte loads
-// (out-of-row pairs read zero, which also serves periods already past the
-// row end) into its half of a private double buffer, the next step's window
-// is loaded into registers while this step is summed, and every period reads
-// its window from LDS at o_b - o_slow.  Lane l owns epochs e_wave + l and
-// e_wave + 64 + l, so each half of a period's LDS read is 512 contiguous
-// bytes (no bank conflicts).  The buffer is private to the wave and LDS
-// operations of one wave complete in issue order, so no barrier is needed.
-// A tile whose bound is too wide is summed with direct loads.  Every epoch
-// receives the same values in the same order as in fold_unit, so the sums,
-// the keys and the records are bit-identical to variants 0 and 2.
-constexpr int kFoldWCap = 384;             // pairs per half of a wave's double buffer (3 KB)
-constexpr int kFoldWLd = kFoldWCap / 128;  // 16-byte loads per lane for a full window
-
-template <int B>
-__device__ __forceinline__ void fold_unit_wlds(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
-                                               const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
-                                               float2 *s_wave) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
-    const uint32_t uI = (uint32_t)I;
-    uint64_t r_min = ~0ull, r_max = 0;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        r_min = ipb[b] > 0 && R[b] < r_min ? R[b] : r_min;
-        r_max = ipb[b] > 0 && R[b] > r_max ? R[b] : r_max;
-    }
-    if (r_min == ~0ull) return;  // no period of the block is evaluated on this row
-    // a period not evaluated on this row follows the slowest one (its sums
-    // are discarded), so every offset lies between the slowest and the fastest
-    uint32_t Rh[B], Rl[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const uint64_t r = ipb[b] > 0 ? R[b] : r_min;
-        Rh[b] = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
-        Rl[b] = __builtin_amdgcn_readfirstlane((uint32_t)r);
-    }
-    const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
-    const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
-    // o_b(m) - o_slow(m) <= m (R_max - R_min) / 2^32 + 1, and a tile's steps
-    // m satisfy o_slow(m) < lim, i.e. m < (lim + 1/2) 2^32 / R_min
-    const double steps_per_epoch = 4294967296.0 / (double)r_min;
-    const double spread_per_step = (double)(r_max - r_min) / 4294967296.0;
-    uint64_t best[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) best[b] = 0;
-
-    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
-        const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
-        if (e_wave >= e_hi) break;
-        const int32_t e = e_wave + lane;  // epochs e and e + 64
-        const uint32_t e_bytes = (uint32_t)e * 8u;
-        const uint32_t lim = uI - (uint32_t)e_wave;
-        // steps m < m_lds run from LDS: there the spread bound leaves room in
-        // the buffer; later steps (if any) use direct loads
-        const double m_max = ((double)lim + 0.5) * steps_per_epoch;
-        const double m_fit = spread_per_step > 0.0 ? ((double)(kFoldWCap - 128) - 2.0) / spread_per_step : m_max;
-        const double m_cut = fmin(m_max, fmax(m_fit, 0.0));
-        const int32_t m_lds = (int32_t)fmin(m_cut, 2.0e9);                       // wave-uniform
-        const double spread = (double)m_lds * spread_per_step + 2.0;
-        const int n_ld = (int)((spread + 128.0 + 127.0) / 128.0);                // window loads per step
-        const bool in_lds = m_lds > 1;
-        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
-        uint32_t hi[B], lo[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
-            hi[b] = 0;
-            lo[b] = 0x80000000u;  // + 1/2: round half up
-        }
-        uint32_t h_min = 0, l_min = 0x80000000u;
-        {
-            // transit 0 sits at offset 0 for every period: one load serves the block
-            const float2 v0 = load_pair(rsrc, e_bytes, 0);
-            const float2 v1 = load_pair(rsrc, e_bytes, 64 * 8);
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                hi[b] = min(hi[b], uI);
-            }
-            acc_add(l_min, h_min, Rl_min, Rh_min);
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                a0[b] += v0.x;
-                s0[b] += v0.y;
-                a1[b] += v1.x;
-                s1[b] += v1.y;
-            }
-        }
-        int n_in_chunk = 1;
-        int32_t m = 1;  // the next step
-        if (in_lds) {
-            const uint32_t w_bytes = (uint32_t)(e_wave + 2 * lane) * 8u;  // this lane's 16 bytes of a window
-            float4 pf[kFoldWLd];
-            bool have = h_min < lim && m < m_lds;
-            if (have) {
-#pragma unroll
-                for (int k = 0; k < kFoldWLd; ++k)
-                    if (k < n_ld) pf[k] = load_quad(rsrc, w_bytes + (h_min + 128u * k) * 8u);
-                float4 *dst = reinterpret_cast<float4 *>(s_wave);
-#pragma unroll
-                for (int k = 0; k < kFoldWLd; ++k)
-                    if (k < n_ld) dst[64 * k + lane] = pf[k];
-            }
-            int half = 0;
-            while (have) {
-                uint32_t q[B];  // this step's window positions; the buffer covers them
-#pragma unroll
-                for (int b = 0; b < B; ++b) q[b] = hi[b] - h_min;
-                // advance to the next step and start loading its window
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                    hi[b] = min(hi[b], uI);
-                }
-                acc_add(l_min, h_min, Rl_min, Rh_min);
-                ++m;
-                have = h_min < lim && m < m_lds;
-                if (have) {
-#pragma unroll
-                    for (int k = 0; k < kFoldWLd; ++k)
-                        if (k < n_ld) pf[k] = load_quad(rsrc, w_bytes + (h_min + 128u * k) * 8u);
-                }
-                const float2 *buf = s_wave + half * kFoldWCap + lane;
-                float2 v0[B], v1[B];
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    v0[b] = buf[q[b]];
-                    v1[b] = buf[q[b] + 64];
-                }
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    a0[b] += v0[b].x;
-                    s0[b] += v0[b].y;
-                    a1[b] += v1[b].x;
-                    s1[b] += v1[b].y;
-                }
-                if (++n_in_chunk == kFoldChunk) {
-                    n_in_chunk = 0;
-#pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        ta0[b] += a0[b];
-                        ts0[b] += s0[b];
-                        ta1[b] += a1[b];
-                        ts1[b] += s1[b];
-                        a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-                    }
-                }
-                if (have) {
-                    float4 *dst = reinterpret_cast<float4 *>(s_wave + (half ^ 1) * kFoldWCap);
-#pragma unroll
-                    for (int k = 0; k < kFoldWLd; ++k)
-                        if (k < n_ld) dst[64 * k + lane] = pf[k];
-                }
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);  // keep the next reads after these writes
-                half ^= 1;
-            }
-        }
-        {
-            while (h_min < lim) {
-                float2 v0[B], v1[B];
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    v0[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 0);
-                    v1[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 64 * 8);
-                }
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                    hi[b] = min(hi[b], uI);
-                }
-                acc_add(l_min, h_min, Rl_min, Rh_min);
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    a0[b] += v0[b].x;
-                    s0[b] += v0[b].y;
-                    a1[b] += v1[b].x;
-                    s1[b] += v1[b].y;
-                }
-                if (++n_in_chunk == kFoldChunk) {
-                    n_in_chunk = 0;
-#pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        ta0[b] += a0[b];
-                        ts0[b] += s0[b];
-                        ta1[b] += a1[b];
-                        ts1[b] += s1[b];
-                        a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            ta0[b] += a0[b];
-            ts0[b] += s0[b];
-            ta1[b] += a1[b];
-            ts1[b] += s1[b];
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int32_t eh = e + 64 * h;
-                const float A = h ? ta1[b] : ta0[b];
-                const float S = h ? ts1[b] : ts0[b];
-                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
-                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
-                best[b] = ok && key > best[b] ? key : best[b];
-            }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const uint64_t m = wave_max_u64(best[b]);
-        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
-    }
-}
-
-// Wave-private LDS ring filled by direct-to-LDS loads (variant 4).  The
-// windows, their bound and the summation are those of fold_unit_wlds, but a
-// step's union window goes from memory straight into LDS: with
-// buffer_load_dwordx4 ... lds, lane l's 16 bytes land at M0 + offset + 16 l
-// and dwords past the row end are written as zero.  No registers stage the
-// window, so the wave keeps the windows of up to kFoldDmaSlots - 1 later
-// steps in flight in a ring of kFoldDmaSlots slots while it sums the current
-// one.  The compiler does not track these loads: the wave waits for a
-// step's window with an explicit vmcnt that leaves the later steps' loads
-// outstanding (loads retire in issue order), and a slot is refilled only
-// after the LDS reads of the step that used it have returned (lgkmcnt(0)).
-// The loads take their LDS base from M0, which the asm sets.  The compiler
-// reserves M0 (a clobber of it is ignored) and no other instruction of the
-// fold kernels reads it, so the asm need not restore it.  Bit-identical to variants 2
-// and 3 but slower on gfx950: the windows (sized for a tile's largest
-// spread) take a third fewer loads than the direct loads of variant 2, yet
-// the address unit spends about 1.25 times as many cycles on a load into
-// LDS as on the same load into registers (variant 3), so it stays the
-// busiest unit.
-constexpr int kFoldDmaSlots = 4;
-constexpr int kFoldDmaCap = 384;  // pairs per slot (3 KB): up to three 1 KB wave loads
-
-__device__ __forceinline__ uint32_t lds_address(const void *p) {
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
-}
-
-// One step's window: NLD wave loads of 1 KB into the slot at LDS byte
-// address `slot` (wave-uniform); `voff` is the lane's byte offset in the row.
-template <int NLD>
-__device__ __forceinline__ void dma_window(__amdgpu_buffer_rsrc_t r, uint32_t slot, uint32_t voff) {
-    static_assert(NLD == 2 || NLD == 3, "a window spans two or three wave loads");
-    if constexpr (NLD == 2)
-        asm volatile(
-            "s_waitcnt lgkmcnt(0)\n\t"
-            "s_mov_b32 m0, %0\n\t"
-            "s_nop 0\n\t"
-            "buffer_load_dwordx4 %1, %2, 0 offen lds\n\t"
-            "buffer_load_dwordx4 %1, %2, 0 offen offset:1024 lds"
-            :
-            : "s"(slot), "v"(voff), "s"(r)
-            : "memory");
-    else
-        asm volatile(
-            "s_waitcnt lgkmcnt(0)\n\t"
-            "s_mov_b32 m0, %0\n\t"
-            "s_nop 0\n\t"
-            "buffer_load_dwordx4 %1, %2, 0 offen lds\n\t"
-            "buffer_load_dwordx4 %1, %2, 0 offen offset:1024 lds\n\t"
-            "buffer_load_dwordx4 %1, %2, 0 offen offset:2048 lds"
-            :
-            : "s"(slot), "v"(voff), "s"(r)
-            : "memory");
-}
-
-// Wait until at most N vector-memory loads of this wave are outstanding.
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-    asm volatile("s_waitcnt vmcnt(%0)" : : "n"(N) : "memory");
-}
-
-template <int B>
-__device__ __forceinline__ void fold_unit_dma(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
-                                              const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
-                                              float2 *s_wave) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
-    const uint32_t uI = (uint32_t)I;
-    uint64_t r_min = ~0ull, r_max = 0;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        r_min = ipb[b] > 0 && R[b] < r_min ? R[b] : r_min;
-        r_max = ipb[b] > 0 && R[b] > r_max ? R[b] : r_max;
-    }
-    if (r_min == ~0ull) return;  // no period of the block is evaluated on this row
-    // a period not evaluated on this row follows the slowest one (its sums
-    // are discarded), so every offset lies between the slowest and the fastest
-    uint32_t Rh[B], Rl[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const uint64_t r = ipb[b] > 0 ? R[b] : r_min;
-        Rh[b] = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
-        Rl[b] = __builtin_amdgcn_readfirstlane((uint32_t)r);
-    }
-    const uint32_t Rh_min = __builtin_amdgcn_readfirstlane((uint32_t)(r_min >> 32));
-    const uint32_t Rl_min = __builtin_amdgcn_readfirstlane((uint32_t)r_min);
-    const double steps_per_epoch = 4294967296.0 / (double)r_min;
-    const double spread_per_step = (double)(r_max - r_min) / 4294967296.0;
-    const uint32_t ring = __builtin_amdgcn_readfirstlane(lds_address(s_wave));
-    const uint32_t lane_bytes = (uint32_t)lane * 16u;
-    uint64_t best[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) best[b] = 0;
-
-    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldTileEpochs) {
-        const int32_t e_wave = e0 + wave * kFoldWaveEpochs;  // wave-uniform
-        if (e_wave >= e_hi) break;
-        const int32_t e = e_wave + lane;  // epochs e and e + 64
-        const uint32_t e_bytes = (uint32_t)e * 8u;
-        const uint32_t lim = uI - (uint32_t)e_wave;
-        // steps m < m_lds run from the ring (the spread bound leaves room in
-        // a slot); later steps (if any) use direct loads
-        const double m_max = ((double)lim + 0.5) * steps_per_epoch;
-        const double m_fit =
-            spread_per_step > 0.0 ? ((double)(kFoldDmaCap - 128) - 2.0) / spread_per_step : m_max;
-        const int32_t m_lds =
-            __builtin_amdgcn_readfirstlane((int32_t)fmin(fmin(m_max, fmax(m_fit, 0.0)), 2.0e9));  // wave-uniform
-        const double spread = (double)m_lds * spread_per_step + 2.0;
-        const int n_ld = __builtin_amdgcn_readfirstlane((int)((spread + 128.0 + 127.0) / 128.0));  // 2 or 3
-        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
-        uint32_t hi[B], lo[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
-            hi[b] = 0;
-            lo[b] = 0x80000000u;  // + 1/2: round half up
-        }
-        uint32_t h_min = 0, l_min = 0x80000000u;
-        {
-            // transit 0 sits at offset 0 for every period: one load serves the block
-            const float2 v0 = load_pair(rsrc, e_bytes, 0);
-            const float2 v1 = load_pair(rsrc, e_bytes, 64 * 8);
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                hi[b] = min(hi[b], uI);
-            }
-            acc_add(l_min, h_min, Rl_min, Rh_min);
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                a0[b] += v0.x;
-                s0[b] += v0.y;
-                a1[b] += v1.x;
-                s1[b] += v1.y;
-            }
-        }
-        int n_in_chunk = 1;
-        int32_t m = 1;  // the next step
-        auto ring_steps = [&](auto nld) {
-            constexpr int NLD = decltype(nld)::value;
-            // the lead: the slowest period's offset at the next step to load
-            uint32_t h_lead = h_min, l_lead = l_min;
-            int32_t m_lead = m;
-            auto lead_ok = [&]() { return m_lead < m_lds && h_lead < lim; };
-            auto issue = [&]() {  // the slot of step m_lead is the one step m_lead - 4 used
-                dma_window<NLD>(rsrc, ring + (uint32_t)(m_lead & (kFoldDmaSlots - 1)) * (kFoldDmaCap * 8u),
-                                lane_bytes + ((uint32_t)e_wave + h_lead) * 8u);
-                acc_add(l_lead, h_lead, Rl_min, Rh_min);
-                ++m_lead;
-            };
-            // sum step m from its slot; inside the window the transit offsets
-            // need no clamp (pairs past the row end were loaded as zero)
-            auto consume = [&]() {
-                const float2 *buf = s_wave + (m & (kFoldDmaSlots - 1)) * kFoldDmaCap + lane;
-                float2 v0[B], v1[B];
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const uint32_t q = hi[b] - h_min;  // inside the window by the spread bound
-                    v0[b] = buf[q];
-                    v1[b] = buf[q + 64];
-                }
-#pragma unroll
-                for (int b = 0; b < B; ++b) acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                acc_add(l_min, h_min, Rl_min, Rh_min);
-                ++m;
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    a0[b] += v0[b].x;
-                    s0[b] += v0[b].y;
-                    a1[b] += v1[b].x;
-                    s1[b] += v1[b].y;
-                }
-                if (++n_in_chunk == kFoldChunk) {
-                    n_in_chunk = 0;
-#pragma unroll
-                    for (int b = 0; b < B; ++b) {
-                        ta0[b] += a0[b];
-                        ts0[b] += s0[b];
-                        ta1[b] += a1[b];
-                        ts1[b] += s1[b];
-                        a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-                    }
-                }
-            };
-#pragma unroll
-            for (int d = 0; d < kFoldDmaSlots - 1; ++d)
-                if (lead_ok()) issue();
-            // steady state: three later windows stay in flight while step m is summed
-            while (lead_ok()) {
-                issue();
-                wait_vm<(kFoldDmaSlots - 1) * NLD>();
-                consume();
-            }
-            if (m < m_lead) {
-                wait_vm<0>();
-                do consume();
-                while (m < m_lead);
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) hi[b] = min(hi[b], uI);  // the direct loads rely on the clamp
-        };
-        if (m < m_lds && h_min < lim) {
-            if (n_ld <= 2)
-                ring_steps(std::integral_constant<int, 2>());
-            else
-                ring_steps(std::integral_constant<int, 3>());
-        }
-        while (h_min < lim) {
-            float2 v0[B], v1[B];
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                v0[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 0);
-                v1[b] = load_pair(rsrc, e_bytes + hi[b] * 8u, 64 * 8);
-            }
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                acc_add(lo[b], hi[b], Rl[b], Rh[b]);
-                hi[b] = min(hi[b], uI);
-            }
-            acc_add(l_min, h_min, Rl_min, Rh_min);
-#pragma unroll
-            for (int b = 0; b < B; ++b) {
-                a0[b] += v0[b].x;
-                s0[b] += v0[b].y;
-                a1[b] += v1[b].x;
-                s1[b] += v1[b].y;
-            }
-            if (++n_in_chunk == kFoldChunk) {
-                n_in_chunk = 0;
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    ta0[b] += a0[b];
-                    ts0[b] += s0[b];
-                    ta1[b] += a1[b];
-                    ts1[b] += s1[b];
-                    a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-                }
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            ta0[b] += a0[b];
-            ts0[b] += s0[b];
-            ta1[b] += a1[b];
-            ts1[b] += s1[b];
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int32_t eh = e + 64 * h;
-                const float A = h ? ta1[b] : ta0[b];
-                const float S = h ? ts1[b] : ts0[b];
-                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
-                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
-                best[b] = ok && key > best[b] ? key : best[b];
-            }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const uint64_t m = wave_max_u64(best[b]);
-        if (lane == 0 && m != 0) atomicMax((unsigned long long *)&keys[b], (unsigned long long)m);
-    }
-}
-
-// LDS-staged fold unit.  The workgroup owns 512 consecutive epochs of B
-// periods: lane t accumulates epochs e0 + t and e0 + t + 256.  For every
-// transit step the union of the B periods' element windows, [e0 + o_min,
-// e0 + o_max + 512), a few hundred elements more than the tile when the
-// periods are close, is loaded once with coalesced buffer loads (out-of-row
-// elements read as zero) and every lane then reads its 2B elements from LDS,
-// consecutive lanes on consecutive elements.  The loads are software
-// pipelined: step m + 1's window is loaded into registers while step m is
-// summed from the other half of the double buffer, so each step costs one
-// barrier and the load latency is hidden behind the sums.  A step whose
-// window exceeds kFoldLdsCap is summed with direct loads instead.  Partial
-// sums, their order and the argmax keys are those of fold_unit.
-constexpr int kFoldLdsTile = 2 * kThreads;
-constexpr int kFoldLdsCap = 2048;                      // float pairs per buffer half (16 KB)
-constexpr int kFoldLdsPf = kFoldLdsCap / kThreads;     // prefetch registers (pairs) per lane
-
-template <int B>
-struct FoldStep {
-    uint32_t o[B];
-    uint32_t use;    // bit b: period b has a transit inside the row
-    uint32_t omin;   // window start offset (valid when use != 0)
-    uint32_t span;   // window length in pairs
-};
-
-template <int B>
-__device__ __forceinline__ FoldStep<B> fold_next_step(uint64_t (&acc)[B], const uint64_t (&R)[B],
-                                                      const int32_t (&ipb)[B], uint32_t e0, uint32_t I) {
-    FoldStep<B> st;
-    st.use = 0;
-    uint32_t omin = 0xFFFFFFFFu, omax = 0;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const uint32_t hi = (uint32_t)(acc[b] >> 32);
-        const bool live = hi < I;
-        st.o[b] = live ? hi : I;
-        acc[b] += live ? R[b] : 0ull;
-        const bool u = ipb[b] > 0 && e0 + st.o[b] < I;
-        st.use |= u ? (1u << b) : 0u;
-        omin = u ? min(omin, st.o[b]) : omin;
-        omax = u ? max(omax, st.o[b]) : omax;
-    }
-    st.omin = omin;
-    st.span = st.use ? omax - omin + (uint32_t)kFoldLdsTile : 0u;
-    return st;
-}
-
-template <int B>
-__device__ __forceinline__ void fold_unit_lds(const float2 *row, int32_t j, int32_t I, const uint64_t (&R)[B],
-                                              const int32_t (&ipb)[B], int32_t e_lo, int32_t e_hi, uint64_t *keys,
-                                              float2 *s_buf) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const __amdgpu_buffer_rsrc_t rsrc = row_resource(row, I);
-    const uint32_t uI = (uint32_t)I;
-    uint64_t best[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) best[b] = 0;
-
-    for (int32_t e0 = e_lo; e0 < e_hi; e0 += kFoldLdsTile) {
-        float a0[B], s0[B], a1[B], s1[B], ta0[B], ts0[B], ta1[B], ts1[B];
-        uint64_t acc[B];
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-            ta0[b] = ts0[b] = ta1[b] = ts1[b] = 0.0f;
-            acc[b] = 2147483648ull;  // + 1/2: round half up
-        }
-        // prologue: stage step 0 into buffer half 0
-        FoldStep<B> cur = fold_next_step<B>(acc, R, ipb, (uint32_t)e0, uI);
-        if (cur.use && cur.span <= (uint32_t)kFoldLdsCap) {
-            const uint32_t ws = (uint32_t)e0 + cur.omin;
-            for (uint32_t q = tid; q < cur.span; q += kThreads) s_buf[q] = load_pair(rsrc, (ws + q) * 8u, 0);
-        }
-        __syncthreads();
-        int half = 0;
-        int n_in_chunk = 0;
-        while (cur.use) {
-            // issue the loads of the next step before summing this one
-            FoldStep<B> nxt = fold_next_step<B>(acc, R, ipb, (uint32_t)e0, uI);
-            const bool nxt_lds = nxt.use && nxt.span <= (uint32_t)kFoldLdsCap;
-            float2 pf[kFoldLdsPf];
-            if (nxt_lds) {
-                const uint32_t ws = (uint32_t)e0 + nxt.omin;
-#pragma unroll
-                for (int k = 0; k < kFoldLdsPf; ++k) {
-                    const uint32_t q = (uint32_t)tid + (uint32_t)(k * kThreads);
-                    if (q < nxt.span) pf[k] = load_pair(rsrc, (ws + q) * 8u, 0);
-                }
-            }
-            if (cur.span <= (uint32_t)kFoldLdsCap) {
-                // every period reads (an unused one at offset 0 and adds
-                // zero), so the 2B LDS reads issue back to back
-                const float2 *buf = s_buf + half * kFoldLdsCap;
-                float2 v0[B], v1[B];
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool u = (cur.use >> b) & 1u;
-                    const uint32_t x = (uint32_t)tid + (u ? cur.o[b] - cur.omin : 0u);
-                    v0[b] = buf[x];
-                    v1[b] = buf[x + kThreads];
-                }
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    const bool u = (cur.use >> b) & 1u;
-                    a0[b] += u ? v0[b].x : 0.0f;
-                    s0[b] += u ? v0[b].y : 0.0f;
-                    a1[b] += u ? v1[b].x : 0.0f;
-                    s1[b] += u ? v1[b].y : 0.0f;
-                }
-            } else {
-                const uint32_t e_bytes = ((uint32_t)e0 + (uint32_t)tid) * 8u;
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    if (!(cur.use & (1u << b))) continue;
-                    const uint32_t off = e_bytes + cur.o[b] * 8u;
-                    const float2 v0 = load_pair(rsrc, off, 0);
-                    const float2 v1 = load_pair(rsrc, off, kThreads * 8);
-                    a0[b] += v0.x;
-                    s0[b] += v0.y;
-                    a1[b] += v1.x;
-                    s1[b] += v1.y;
-                }
-            }
-            if (++n_in_chunk == kFoldChunk) {
-                n_in_chunk = 0;
-#pragma unroll
-                for (int b = 0; b < B; ++b) {
-                    ta0[b] += a0[b];
-                    ts0[b] += s0[b];
-                    ta1[b] += a1[b];
-                    ts1[b] += s1[b];
-                    a0[b] = s0[b] = a1[b] = s1[b] = 0.0f;
-                }
-            }
-            if (nxt_lds) {
-                float2 *dst = s_buf + (half ^ 1) * kFoldLdsCap;
-#pragma unroll
-                for (int k = 0; k < kFoldLdsPf; ++k) {
-                    const uint32_t q = (uint32_t)tid + (uint32_t)(k * kThreads);
-                    if (q < nxt.span) dst[q] = pf[k];
-                }
-            }
-            __syncthreads();  // the next half is written; this half's reads are done
-            half ^= 1;
-            cur = nxt;
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            ta0[b] += a0[b];
-            ts0[b] += s0[b];
-            ta1[b] += a1[b];
-            ts1[b] += s1[b];
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int32_t eh = e0 + tid + kThreads * h;
-                const float A = h ? ta1[b] : ta0[b];
-                const float S = h ? ts1[b] : ts0[b];
-                const bool ok = eh < ipb[b] && eh < e_hi && S > 0.0f;
-                const uint64_t key = fold_key(fold_rank_lr(A, S), (uint32_t)j * (uint32_t)I + (uint32_t)eh);
                 best[b] = ok && key > best[b] ? key : best[b];
             }
         }

@@ -7,7 +7,11 @@ The floors come from the absolute-value sums the oracle also returns
   LR     s = |depth| * aabs / 2
   var    no floor (a sum of positive terms)
 Plain relative error is ill-conditioned where S_fm is close to zero, i.e. in
-pure-noise windows, which is why the floors exist.
+pure-noise windows, which is why the floors exist.  The floors only bind
+where the sum cancels: every element whose signed sum keeps at least half of
+its absolute sum (|S_fm| >= aabs / 2, a cancellation factor of at most 2) is
+also held to the plain relative error |x_gpu - x_ora| / |x_ora| <= TOL for
+the depth and the LR (``well`` in the returned summaries counts them).
 
 Near-ties: an argmax index mismatch is accepted only if the oracle's own
 likelihood ratio at the GPU's choice is within TOL * max(LR*, floor) of the
@@ -37,9 +41,15 @@ def check_linear(depth, var, lr, ora: dict, tol: float = TOL) -> dict:
     e_d = rel(np.asarray(depth)[ok], d, a * v)
     e_v = rel(np.asarray(var)[ok], v)
     e_l = rel(np.asarray(lr)[ok], l, 0.5 * np.abs(d) * a)
+    well = np.abs(d) / v >= 0.5 * a
+    p_d = rel(np.asarray(depth)[ok][well], d[well])
+    p_l = rel(np.asarray(lr)[ok][well], l[well])
     out = dict(depth=float(e_d.max(initial=0)), var=float(e_v.max(initial=0)), lr=float(e_l.max(initial=0)),
-               n=int(ok.sum()), unfloored_frac=float(np.mean(rel(np.asarray(lr)[ok], l) <= tol)) if ok.any() else 1.0)
+               n=int(ok.sum()), well=int(well.sum()), plain_depth=float(p_d.max(initial=0)),
+               plain_lr=float(p_l.max(initial=0)),
+               unfloored_frac=float(np.mean(rel(np.asarray(lr)[ok], l) <= tol)) if ok.any() else 1.0)
     assert out["depth"] <= tol and out["var"] <= tol and out["lr"] <= tol, out
+    assert out["plain_depth"] <= tol and out["plain_lr"] <= tol, out
     return out
 
 
@@ -51,7 +61,9 @@ def check_periodic(gpu: dict, ora: dict, fold_at, periods, sel=None, tol: float 
     K = len(ora["lr"])
     sel = np.arange(K) if sel is None else np.asarray(sel)
     worst = dict(lr=0.0, depth=0.0, var=0.0)
+    plain = dict(lr=0.0, depth=0.0)
     near_ties = 0
+    well = 0
     for s in range(K):
         k = sel[s]
         oi, oj = int(ora["i"][s]), int(ora["j"][s])
@@ -73,6 +85,13 @@ def check_periodic(gpu: dict, ora: dict, fold_at, periods, sel=None, tol: float 
         worst["lr"] = max(worst["lr"], float(rel(g["lr"][k], lr_o, floor_l)))
         worst["depth"] = max(worst["depth"], float(rel(g["depth"][k], z_o, ab_o * zv_o)))
         worst["var"] = max(worst["var"], float(rel(g["depth_var"][k], zv_o)))
+        if abs(z_o) / zv_o >= 0.5 * ab_o:  # well conditioned: plain relative error
+            well += 1
+            plain["lr"] = max(plain["lr"], float(rel(g["lr"][k], lr_o)))
+            plain["depth"] = max(plain["depth"], float(rel(g["depth"][k], z_o)))
     assert max(worst.values()) <= tol, worst
+    assert max(plain.values()) <= tol, plain
     worst["near_ties"] = near_ties
+    worst["well"] = well
+    worst["plain_lr"], worst["plain_depth"] = plain["lr"], plain["depth"]
     return worst

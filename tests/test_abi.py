@@ -90,12 +90,12 @@ def test_tuning_roundtrip_and_validation(lib):
     import paper_2503_20875_amd as cm
     cm.reset_tuning()
     assert cm.get_tuning() == dict(fold_period_block=8, fold_wgs_per_cu=8, fold_units_per_wg=4, fold_variant=2)
-    cm.set_tuning(4, 6, 2, 1)
-    assert cm.get_tuning() == dict(fold_period_block=4, fold_wgs_per_cu=6, fold_units_per_wg=2, fold_variant=1)
+    cm.set_tuning(4, 6, 2, 0)
+    assert cm.get_tuning() == dict(fold_period_block=4, fold_wgs_per_cu=6, fold_units_per_wg=2, fold_variant=0)
     with pytest.raises(cm.CetraError, match="fold_period_block"):
         cm.set_tuning(5, 6, 2)
     with pytest.raises(cm.CetraError, match="fold_variant"):
-        cm.set_tuning(4, 6, 2, 5)
+        cm.set_tuning(4, 6, 2, 1)
     assert cm.get_tuning()["fold_period_block"] == 4  # unchanged after a rejected call
     cm.reset_tuning()
     assert cm.get_tuning()["fold_period_block"] == 8

@@ -23,7 +23,7 @@ def test_tune_fold_applies_a_candidate():
     per = torch.as_tensor(wl.periods, device="cuda")
     cm.reset_tuning()
     ref = {k: v.cpu().numpy() for k, v in cm.periodic_search(grid, fold, per).items()}
-    cands = [(4, 8, 4, 0), (8, 8, 4, 0), (4, 8, 16, 1), (4, 8, 4, 2)]
+    cands = [(4, 8, 4, 0), (8, 8, 4, 0), (4, 8, 16, 2), (4, 8, 4, 2)]
     print("[autotune] tiny workload", flush=True)
     try:
         cfg, times = tune_fold(grid, fold, per, candidates=cands, repeats=1)

@@ -131,3 +131,40 @@ def test_batch_graph_replay(cm, setup):
         assert int(o["status"].item()) == 0
         compare(cm, o, single, per_off)
         _ = (torch.randn(1000, device="cuda") ** 2).sum().item()  # eager work between replays
+
+
+def test_batch_matches_oracle(cm, ora, setup):
+    """Every curve of the batch, edge cases included, against the FP64
+    oracle run on that curve alone: per-period records to the parity bar
+    (floored 1e-5, argmax identical outside near-ties) and the best period."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from parity import TOL, check_periodic
+    curves, model, packed, _ = setup
+    grids, obs_off, per_off = packed[:3]
+    plan = cm.batch_plan(grids, obs_off, per_off)
+    o = batch_results(cm, plan, curves, packed, model)
+    assert int(o["status"].item()) == 0
+    h = {k: v.cpu().numpy() for k, v in o.items() if k not in ("best", "status")}
+    bests = cm.best_records(o["best"])
+    for ci, c in enumerate(curves):
+        print(f"[oracle] curve {ci}: n_obs={c.n_obs} K={len(c.periods)}", flush=True)
+        ref = ora.search(c)
+        sl = slice(per_off[ci], per_off[ci + 1])
+        if len(c.periods) == 0:
+            assert bests[ci]["k"] == -1
+            continue
+        g = {k: h[k][sl] for k in ("lr", "epoch", "dur", "depth", "depth_var")}
+        res = check_periodic(g, ref["periodic"], lambda P, i, j: ora.fold_at(ref["grid"], ref["linear"], P, i, j),
+                             c.periods)
+        b = bests[ci]
+        if ref["best"] < 0:
+            assert b["k"] == -1
+            continue
+        if b["k"] != ref["best"]:  # near-tie across periods
+            lr_o = ref["periodic"]["lr"]
+            gap = (lr_o[ref["best"]] - lr_o[b["k"]]) / lr_o[ref["best"]]
+            assert gap <= TOL, (ci, b["k"], ref["best"], gap)
+        assert b["lr"] == pytest.approx(ref["periodic"]["lr"][b["k"]], rel=TOL)
+        print(f"[oracle] curve {ci}: {res}", flush=True)

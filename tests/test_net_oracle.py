@@ -164,3 +164,42 @@ def test_parameter_count():
     conv = 64 * 16 * 9 + 64 + 4 * (64 * 64 * 9 + 64)
     head = 8 * 64 + 8 + 64 * 9 + 64 + 64 + 1
     assert net.n_params(net.init_params()) == conv + head
+
+
+def test_downsample_is_binned_single_event_snr(ora):
+    """The network input (reading N1) pinned against the linear search: on a
+    small curve the oracle's own depth and variance give the single-event SNR
+    |depth| / sqrt(var) of every element; the maximum over each bin, clipped at
+    30 and divided by 8, equals net.downsample of the (S_fm, S_mm) pairs
+    (S_fm = depth / var, S_mm = 1 / var).  Bins follow floor(b I / L), so a
+    bin count that does not divide I leaves ragged bins."""
+    from synthlc import workloads as W
+    wl = W.small_random(3, n_obs=400, n_dur=3)
+    g = ora.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 128, t0_step=0.05 * wl.durations[0])
+    flux, ivar = ora.resample(g, wl.t, wl.f, wl.sigma)
+    lin = ora.linear(g, flux, ivar, ora.template(wl.dense, 128))
+    ok = np.isfinite(lin["var"])
+    assert 0 < ok.sum() < ok.size
+    pairs = np.zeros((g.n_dur, g.n_t0, 2))
+    pairs[..., 0][ok] = lin["depth"][ok] / lin["var"][ok]
+    pairs[..., 1][ok] = 1.0 / lin["var"][ok]
+    for L in (7, 64, g.n_t0):
+        got = net.downsample(pairs, L)
+        for j in range(g.n_dur):
+            for b in range(L):
+                i0, i1 = (b * g.n_t0) // L, ((b + 1) * g.n_t0) // L
+                vals = [abs(lin["depth"][j, i]) / np.sqrt(lin["var"][j, i]) for i in range(i0, i1) if ok[j, i]]
+                expect = min(max(vals, default=0.0), 30.0) / 8.0
+                assert got[b, j] == pytest.approx(expect, rel=1e-12, abs=1e-300)
+
+
+def test_downsample_saturation_and_nulls():
+    """A huge SNR saturates at 30 / 8 = 3.75; an all-null bin is 0; the sign
+    of S_fm does not matter (a brightening is as strong as a dip)."""
+    fold = np.zeros((2, 10, 2))
+    fold[0, :, 0] = 1e6
+    fold[0, :, 1] = 1.0
+    fold[1, 5, :] = (-3.0, 1.0)   # SNR 3 in the second bin of duration 1
+    out = net.downsample(fold, 2)
+    assert np.array_equal(out[:, 0], [3.75, 3.75])
+    assert out[0, 1] == 0.0 and out[1, 1] == pytest.approx(3.0 / 8.0)

@@ -340,3 +340,101 @@ def test_paper_worked_example_period_and_aliases(ora):
         # and it is a local peak: clearly above the periodogram 12% either side
         side = [lr[np.argmin(np.abs(periods - alias * f))] for f in (0.88, 1.12)]
         assert peak > 1.3 * max(side)
+
+
+# ------------------------------------------------- zero-offset log-likelihood
+def test_loglike0_matches_bruteforce_and_gaussian_density(ora):
+    """l0 (Eq. 1 at zero depth over the non-null resampled points) equals the
+    brute force's full Eq. 1 at depth 0, the sum of scipy's normal log
+    densities N(flux; 0, w^-1/2), and l0 + LR of a window equals the full
+    log-likelihood of that window's fitted model (Sec. 2.2: the LR is the
+    difference of the two log-likelihoods)."""
+    from scipy.stats import norm
+    wl = W.small_random(2, n_obs=300, n_dur=2, n_per=3, dur_h=(1.0, 3.0))
+    step = 0.0913 * wl.durations[0]
+    M = 128
+    g = ora.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, M, t0_step=step)
+    bg = bf.BruteGrid(wl.t[0], wl.t[-1], wl.cadence, wl.durations, M, t0_step=step)
+    flux, ivar = ora.resample(g, wl.t, wl.f, wl.sigma)
+    bflux, bw = bg.resample(wl.t, wl.f, wl.sigma)
+    l0 = ora.loglike0(g, flux, ivar)
+    zero = np.zeros(bg.N)
+    assert l0 == pytest.approx(bf.loglike(zero, 0.0, bflux, bw), rel=1e-13)
+    ok = ivar > 0
+    assert ok.sum() < ok.size  # the padding and the gap are null points
+    dens = float(np.sum(norm.logpdf(flux[ok], loc=0.0, scale=1.0 / np.sqrt(ivar[ok]))))
+    assert l0 == pytest.approx(dens, rel=1e-13)
+    model = ora.template(wl.dense, M)
+    lin = ora.linear(g, flux, ivar, model)
+    rng = np.random.default_rng(0)
+    done = 0
+    for _ in range(400):
+        j, i = int(rng.integers(0, g.n_dur)), int(rng.integers(0, g.n_t0))
+        gv = bg.window_model(i, j, model)
+        if gv is None or not np.isfinite(lin["var"][j, i]):
+            continue
+        full = bf.loglike(gv, lin["depth"][j, i], bflux, bw)
+        assert l0 + lin["lr"][j, i] == pytest.approx(full, rel=1e-12, abs=1e-9 * abs(l0))
+        done += 1
+    assert done > 100
+
+
+def test_loglike0_uniform_sigma_closed_form(ora):
+    """Uniform sigma, n non-null points: l0 = -sum f^2 / (2 sigma^2)
+    - (n/2) ln(2 pi sigma^2)."""
+    rng = np.random.default_rng(8)
+    c = 120.0 / 86400.0
+    t = np.arange(3000) * c + 1000.0
+    t = np.delete(t, np.arange(700, 1100))  # a gap of null points
+    sigma = 4e-4
+    f = (rng.normal(0, sigma, t.size) + 1e-4).astype(np.float32)
+    s = np.full(t.size, sigma, dtype=np.float32)
+    g = ora.grid_plan(t[0], t[-1], c, [0.05, 0.1], 64)
+    flux, ivar = ora.resample(g, t, f, s)
+    s64 = float(np.float32(sigma))
+    ff = f.astype(np.float64)
+    expect = -0.5 * np.sum(ff ** 2) / s64 ** 2 - 0.5 * t.size * math.log(2 * math.pi * s64 ** 2)
+    assert np.count_nonzero(ivar > 0) == t.size
+    assert ora.loglike0(g, flux, ivar) == pytest.approx(expect, rel=1e-12)
+
+
+# ------------------------------------------------------- edges of the period range
+def test_period_range_edges(ora):
+    """Reading for the period range: a period shorter than the reference-time
+    step, or not finite, is not evaluated and gets the null record, even when
+    some durations are shorter than it; a period of at least I steps has one
+    transit per epoch, so its record is the best single window of the allowed
+    durations; the brute force agrees on every evaluated period."""
+    wl = W.small_random(5, n_obs=200, n_dur=3, n_per=4, p_range=(0.5, 1.0), dur_h=(0.6, 2.0))
+    M = 64
+    step = 1.7 * wl.durations[0]  # a step longer than the shortest duration
+    g = ora.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, M, t0_step=step)
+    bg = bf.BruteGrid(wl.t[0], wl.t[-1], wl.cadence, wl.durations, M, t0_step=step)
+    model = ora.template(wl.dense, M)
+    flux, ivar = ora.resample(g, wl.t, wl.f, wl.sigma)
+    lin = ora.linear(g, flux, ivar, model)
+    span = g.n_t0 * g.t0_step
+    short = [0.5 * step, step * (1 - 1e-9), 1.2 * wl.durations[0]]
+    assert all(wl.durations[0] < p < step for p in short[1:])
+    bad = [float("nan"), float("inf"), -1.0, 0.0]
+    longp = [span * 1.0000001, span * 4.0, 1e30]
+    periods = np.array(short + bad + [step] + longp)
+    per = ora.periodic(g, lin, periods)
+    for k in range(len(short) + len(bad)):
+        assert per["i"][k] == -1 and per["j"][k] == -1 and per["lr"][k] == 0, periods[k]
+        assert np.isnan(per["z"][k]) and per["zvar"][k] == np.inf
+        assert ora.fold_at(g, lin, periods[k], 0, 0) is None
+    n0 = len(short) + len(bad)
+    # P = dt with D_0 < P: evaluated (one epoch, a transit at every reference time)
+    assert per["i"][n0] == 0 and per["j"][n0] == 0
+    # P >= I dt: the best single window among the durations shorter than P
+    flat = lin["lr"].reshape(-1)
+    jb, ib = divmod(int(np.argmax(flat)), g.n_t0)
+    for k in range(n0 + 1, len(periods)):
+        assert (per["i"][k], per["j"][k]) == (ib, jb)
+        assert per["lr"][k] == pytest.approx(flat.max(), rel=1e-12)
+    brute = bf.periodic(bg, *bg.resample(wl.t, wl.f, wl.sigma), model, periods[n0 + 1:n0 + 3])
+    for k, b in enumerate(brute):
+        assert (per["i"][n0 + 1 + k], per["j"][n0 + 1 + k]) == (b[1], b[2])
+        assert per["lr"][n0 + 1 + k] == pytest.approx(b[0], rel=1e-8)
+    assert bf.periodic(bg, *bg.resample(wl.t, wl.f, wl.sigma), model, periods[:2]) == [None, None]
