@@ -20,7 +20,9 @@
  *            "host" pointers are ordinary host memory.  The caller allocates
  *            and owns every buffer, including workspaces; the library never
  *            allocates device memory and keeps no pointer after a call
- *            returns.
+ *            returns.  The one exception is the fixed scratch array of
+ *            cetra_periodic_search_noalloc, a static device array of the
+ *            library's own code object.
  * Streams    `stream` is a hipStream_t passed as void* (NULL = the default
  *            stream).  Device work is only enqueued: no entry point
  *            synchronises, so results are ready when the stream is.  No entry
@@ -263,6 +265,28 @@ int cetra_periodic_search(void *stream, const cetra_grid *grid, const float *fol
                           const double *periods, int64_t n_periods, const int32_t *jrange,
                           const int64_t *subset, int64_t n_subset, void *work, size_t work_bytes,
                           float *lr, int32_t *epoch, int32_t *dur, float *depth, float *depth_var);
+
+/* Periodic search without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, outputs, kernels and
+ * results as cetra_periodic_search, except that the fold workspace is a
+ * fixed 16 MiB device array inside the library (one per device, kept until
+ * the process ends; its address is resolved once per device at the first
+ * call).  Nothing is allocated or freed.  Every evaluated period's argmax key
+ * and table entry is rewritten by each call, so nothing carries over from
+ * the previous call; but all calls on one device share the array, so calls
+ * that overlap on one device (concurrent streams or host threads) race and
+ * must be serialised by the caller.  More evaluated periods than
+ * cetra_periodic_search_noalloc_limit reports returns CETRA_ERR_RANGE with
+ * nothing enqueued. */
+int cetra_periodic_search_noalloc(void *stream, const cetra_grid *grid, const float *fold,
+                                  const double *periods, int64_t n_periods, const int32_t *jrange,
+                                  const int64_t *subset, int64_t n_subset, float *lr, int32_t *epoch,
+                                  int32_t *dur, float *depth, float *depth_var);
+
+/* Largest number of evaluated periods cetra_periodic_search_noalloc accepts
+ * (host only; *max_eval out). */
+int cetra_periodic_search_noalloc_limit(const cetra_grid *grid, int64_t *max_eval);
 
 /* Fold epoch strides for a reference-time step that grows with the duration,
  * the TLS grid that Sec. 2.1.3 mentions adopting (the paper itself keeps one

@@ -228,6 +228,38 @@ def periodic_search(grid: Grid, fold, periods, jrange=None, subset=None, work=No
     return out
 
 
+def periodic_search_noalloc(grid: Grid, fold, periods, jrange=None, subset=None, out=None,
+                            stream=None) -> dict:
+    """periodic_search with the library's fixed device scratch as the fold
+    workspace (the C call allocates nothing; `out` may be passed in so this
+    wrapper allocates nothing either).  Calls that overlap on one device
+    share the scratch and race."""
+    torch = _torch()
+    dev = fold.device
+    periods = _dev(periods, torch.float64)
+    K = periods.numel()
+    jr = None if jrange is None else _dev(jrange, torch.int32)
+    sub = None if subset is None else _dev(subset, torch.int64)
+    if out is None:
+        out = dict(lr=torch.empty(K, dtype=torch.float32, device=dev),
+                   epoch=torch.empty(K, dtype=torch.int32, device=dev),
+                   dur=torch.empty(K, dtype=torch.int32, device=dev),
+                   depth=torch.empty(K, dtype=torch.float32, device=dev),
+                   depth_var=torch.empty(K, dtype=torch.float32, device=dev))
+    _abi.check(_abi.load().cetra_periodic_search_noalloc(
+        _stream(stream), ctypes.byref(grid), _ptr(fold), _ptr(periods), K, _ptr(jr), _ptr(sub),
+        0 if sub is None else sub.numel(), _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]),
+        _ptr(out["depth"]), _ptr(out["depth_var"])))
+    return out
+
+
+def periodic_search_noalloc_limit(grid: Grid) -> int:
+    """Most evaluated periods periodic_search_noalloc accepts."""
+    n = ctypes.c_int64()
+    _abi.check(_abi.load().cetra_periodic_search_noalloc_limit(ctypes.byref(grid), ctypes.byref(n)))
+    return int(n.value)
+
+
 def best(grid: Grid, periods, per: dict, out=None, stream=None):
     """Best period; returns a uint8 device tensor holding one cetra_best_record
     (use ``best_record`` to read it on the host)."""

@@ -138,6 +138,9 @@ SIGNATURES = {
     "cetra_periodic_search_strided": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _i64, _P, _P, _i64, _P,
                                                      _P, _sz, _P, _P, _P, _P, _P]),
     "cetra_epoch_strides": (ctypes.c_int, [ctypes.POINTER(Grid), _d, _P]),
+    "cetra_periodic_search_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _P, _i64, _P, _P, _i64, _P, _P,
+                                                     _P, _P, _P]),
+    "cetra_periodic_search_noalloc_limit": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(_i64)]),
     "cetra_best": (ctypes.c_int, [_P, ctypes.POINTER(Grid), _P, _i64, _P, _P, _P, _P, _P, _P]),
     "cetra_batch_plan_create": (ctypes.c_int, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P)]),
     "cetra_batch_plan_destroy": (ctypes.c_int, [_P]),

@@ -27,6 +27,8 @@
 // winner's sums in the same order to emit LR, Z and var_Z.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 #include "stages.h"
@@ -34,6 +36,13 @@
 namespace {
 
 using cetra::dev::kThreads;
+
+// Fold workspace of cetra_periodic_search_noalloc: one copy per device, held
+// until the process ends.  Host code never passes this name to a kernel (on
+// the host it is a stand-in, not a device address); it uses the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct FoldWork {
     uint64_t *key;     // [n_eval] argmax keys
@@ -355,6 +364,70 @@ extern "C" int cetra_periodic_search_strided(void *stream, const cetra_grid *gri
                                              float *depth, float *depth_var) {
     return periodic_search(stream, grid, fold, periods, n_periods, jrange, subset, n_subset, stride, work,
                            work_bytes, lr, epoch, dur, depth, depth_var);
+}
+
+namespace {
+
+// Device address of `scratch` on the current device, resolved once per device
+// (each GPU holds its own copy of the array at its own address).
+int scratch_address(void **out) {
+    static std::mutex mu;
+    static std::vector<void *> addr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(CETRA_ERR_HIP, "periodic_search_noalloc: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)dev >= addr.size()) addr.resize((size_t)dev + 1, nullptr);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(CETRA_ERR_HIP, "periodic_search_noalloc: scratch address: %s", hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return CETRA_OK;
+}
+
+}  // namespace
+
+extern "C" int cetra_periodic_search_noalloc_limit(const cetra_grid *grid, int64_t *max_eval) {
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    CETRA_REQUIRE(max_eval != nullptr, "periodic_search_noalloc_limit: NULL output");
+    int64_t lo = 0, hi = (int64_t)(kScratchBytes / 8);  // workspace_bytes grows with n_eval
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (workspace_bytes(mid) <= kScratchBytes)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    *max_eval = lo;
+    return CETRA_OK;
+}
+
+extern "C" int cetra_periodic_search_noalloc(void *stream, const cetra_grid *grid, const float *fold,
+                                             const double *periods, int64_t n_periods, const int32_t *jrange,
+                                             const int64_t *subset, int64_t n_subset, float *lr, int32_t *epoch,
+                                             int32_t *dur, float *depth, float *depth_var) {
+    clear_error();
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    CETRA_REQUIRE(n_periods >= 0 && (!subset || n_subset >= 0), "periodic_search_noalloc: negative size");
+    const int64_t n_eval = subset ? n_subset : n_periods;
+    if (workspace_bytes(n_eval) > kScratchBytes) {
+        int64_t lim = 0;
+        cetra_periodic_search_noalloc_limit(grid, &lim);
+        return set_error(CETRA_ERR_RANGE,
+                         "periodic_search_noalloc: %lld evaluated periods exceed the fixed scratch of %zu bytes "
+                         "(at most %lld periods)", (long long)n_eval, kScratchBytes, (long long)lim);
+    }
+    void *work = nullptr;
+    if ((rc = scratch_address(&work))) return rc;
+    return periodic_search(stream, grid, fold, periods, n_periods, jrange, subset, n_subset, nullptr, work,
+                           kScratchBytes, lr, epoch, dur, depth, depth_var);
 }
 
 extern "C" int cetra_best(void *stream, const cetra_grid *grid, const double *periods, int64_t n_periods,

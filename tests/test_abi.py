@@ -135,3 +135,21 @@ def test_batch_plan_host_only(lib):
         cm.batch_plan(grids, oo[::-1].copy(), po)
     with pytest.raises(ValueError):
         cm.batch_plan(grids, oo[:-1], po)
+
+
+def test_noalloc_limit_and_range_error_without_a_gpu(lib):
+    """The allocation-free periodic search reports its period limit and
+    rejects a larger request on the host, before touching the device."""
+    import paper_2503_20875_amd as cm
+    from paper_2503_20875_amd import _abi
+    grid = cm.grid_plan(0.0, 1.0, 0.01, [0.05, 0.1])
+    lim = cm.periodic_search_noalloc_limit(grid)
+    assert cm.periodic_workspace(grid, lim) <= 16 << 20 < cm.periodic_workspace(grid, lim + 1)
+    assert lim >= 400_000  # the two-year, 400 000-period search fits
+    rc = lib.cetra_periodic_search_noalloc(None, ctypes.byref(grid), None, None, lim + 1, None, None, 0,
+                                           None, None, None, None, None)
+    assert rc == -2 and b"scratch" in lib.cetra_last_error()
+    rc = lib.cetra_periodic_search_noalloc(None, ctypes.byref(grid), None, None, -1, None, None, 0,
+                                           None, None, None, None, None)
+    assert rc == -1
+    assert _abi.SIGNATURES["cetra_periodic_search_noalloc"][0] is ctypes.c_int
