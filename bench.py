@@ -1,21 +1,28 @@
 """Benchmark of the transit search on one MI355X.
 
 One step = one pass of the whole search over one light curve already resident
-in HBM: template resampling, light-curve resampling, linear search, periodic
-search (fold + per-period argmax) and the best period.  Workload: one 90-d
-light curve at 20-s cadence (369 360 observations, AR(1) red + white noise,
-pre-whitened, 5% gaps, two injected transits), 20 log-spaced durations
-0.5-15 h, 50 000 log-spaced periods 0.5-45 d; synthetic, seeded.
+in HBM: template resampling, light-curve resampling, linear search over every
+duration, periodic search (fold + per-period argmax) and the best period.
+Default workload: the Earth-analogue batch (two-year curves at 25-s cadence,
+2 524 608 points each, white noise 200 ppm, one 100-ppm 13-h transit signal
+at P = 365.25 d; 30 log-spaced durations 1-20 h; 399 404 duty-cycle periods
+1-400 d); each timed step searches the next curve of the batch.  Synthetic,
+seeded.
 
 Metric: light-curve points x trial periods per second, linear + periodic
-(N_obs * K / step time), and the learned proposal's recall of the plain
-search's detections above SNR 7 with its speedup (held-out curves of the
-learned-proposal workload).  Prints one JSON line.
+(N_obs * K / step time).  The line also carries the fold's rooflines (bytes
+past L2 from live rocprofv3 counter passes against the HBM peak, and the
+algorithmic element-visit rate against the vector-memory address unit), the
+linear search's FP32 rate, the rate with the host transfers included, the
+FP64 oracle timed on the host's cores, and the secondary measurements (the
+90-day high-cadence curve, default grids, batched survey, proposal network,
+learned proposal recall at SNR > 7).  Prints one JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -29,11 +36,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "fold_high_cadence_counters.json")
-PROFILE_PIPELINE = os.path.join(ROOT, "profiles", "fold_high_cadence_pipeline_counters.json")
 # Vector-memory load path of one CU: a wave load of 16 bytes per lane (1 KB)
 # keeps the address unit busy 16 cycles (its busy counter), i.e. 64 B per cycle.
-L1_PEAK_GBS = 64.0 * 256 * 2.4
+ADDRESS_UNIT_PEAK_GBS = 64.0 * 256 * 2.4
+LONG_SEED = 20250329  # seed of curve 0 of the Earth-analogue batch
 FOLD_SOURCES = [os.path.join(ROOT, "paper_2503_20875_amd", "csrc", name) for name in ("fold.hip", "stages.h")]
 PROPOSAL_WEIGHTS = os.path.join(ROOT, "paper_2503_20875_amd", "weights", "proposal.npz")
 
@@ -96,47 +102,20 @@ def algorithmic_work(wl, grid):
                 linear_flop=4 * lin_points)
 
 
-def cpu_baseline(wl, stride: int = 10):
-    """The FP64 oracle, as it is, on a bounded sample: full resample + linear
-    search, fold over every `stride`-th period, extrapolated linearly in fold
-    element visits to the full period grid."""
-    import oracle
-    g = oracle.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, wl.n_model)
-    model = oracle.template(wl.dense, wl.n_model)
-    t0 = time.perf_counter()
-    flux, ivar = oracle.resample(g, wl.t, wl.f, wl.sigma)
-    lin = oracle.linear(g, flux, ivar, model)
-    t_lin = time.perf_counter() - t0
-    sel = np.arange(0, len(wl.periods), stride)
-    t0 = time.perf_counter()
-    oracle.periodic(g, lin, wl.periods, sel=sel)
-    t_fold = time.perf_counter() - t0
-    durs = np.asarray(wl.durations)
-    jk = np.array([np.count_nonzero(durs < P) for P in wl.periods], dtype=np.float64)
-    scale = jk.sum() / jk[sel].sum()
-    t_full = t_lin + t_fold * scale
-    value = wl.n_obs * len(wl.periods) / t_full
-    return dict(value=value, unit="LC points x trial periods / s", cores=oracle.max_threads(), kind="oracle",
-                sample=(f"resample + linear search in full ({t_lin:.2f} s), fold over every {stride}th period "
-                        f"({len(sel)} of {len(wl.periods)}, {t_fold:.2f} s) extrapolated x{scale:.1f} in fold "
-                        f"element visits; estimated full search {t_full:.1f} s"),
-                seconds_measured=round(t_lin + t_fold, 2))
-
-
-def batched_block(n_curves: int = 32, seed: int = 20250328) -> dict:
-    """Batched search over survey curves of uneven length (5 000-120 000
-    points at 2-min cadence, 16 durations, per-curve duty-cycle period grids
-    over 0.5-min(40, T/2) d): one eager pass, then the same batch captured in
-    a HIP graph and replayed, both timed with HIP events; throughput is
-    sum over curves of N_obs x K_c per second.  Long gapped curves fold
-    more epochs per point than the contiguous single-curve workload, so the
-    algorithmic fold bytes per second (same definition as the single-curve
-    roofline, whole batch time including the linear stages) are reported
-    beside it as the comparable rate."""
+def batched_block(n_curves: int = 64, seed: int = 20250328) -> dict:
+    """Batched survey: a length-stratified subset of the survey workload
+    (curve k has the midpoint length of the k-th of n_curves strata of
+    5 000-120 000 points at 2-min cadence; 16 durations 0.5-10 h; per-curve
+    duty-cycle period grids over 0.5-min(40, T/2) d), searched by the
+    persistent work-queue launch, eagerly and as a replayed HIP graph, both
+    timed with HIP events; then the same curves as back-to-back single-curve
+    searches (resample, linear search, periodic search, best per curve) for
+    comparison.  Throughput is sum over curves of N_obs x K_c per second."""
     import torch
     import paper_2503_20875_amd as cm
     from synthlc import workloads as W
-    curves = W.batched_survey(n_curves, seed=seed)
+    curves = W.survey_subset(n_curves, seed=seed)
+    log(f"batched survey: {n_curves} curves generated")
     grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations, 0.0, c.n_model) for c in curves]
     oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
     po = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
@@ -150,7 +129,8 @@ def batched_block(n_curves: int = 32, seed: int = 20250328) -> dict:
     work = cm.batch_workspace(plan)
     out = cm.batch_search(plan, t, f, s_, model, p, work=work)
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    log(f"batched survey: first search done, status {int(out['status'].item())}")
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     e[0].record()
     cm.batch_search(plan, t, f, s_, model, p, work=work, out=out)
     e[1].record()
@@ -165,15 +145,49 @@ def batched_block(n_curves: int = 32, seed: int = 20250328) -> dict:
     g.replay()
     e[3].record()
     torch.cuda.synchronize()
+    log("batched survey: eager and graph-replayed searches timed")
+    status = int(out["status"].item())
+    n_done = int((out["done"] == 1).sum().item())
+    best_batch = out["best"].cpu().numpy()
+    del g, work
+    # the same curves as single-curve searches back to back (device-resident inputs)
+    bufs = []
+    for c, gr in zip(curves, grids):
+        K = len(c.periods)
+        bufs.append((tuple(torch.as_tensor(a, device=dev) for a in (c.t, c.f, c.sigma)),
+                     torch.as_tensor(c.periods, device=dev), search_buffers(cm, torch, gr, max(K, 1))))
+
+    def singles():
+        for (c, gr), ((td, fd, sd), pd, b) in zip(zip(curves, grids), bufs):
+            flux, ivar, _ = cm.resample(gr, td, fd, sd, status=False)
+            cm.linear_search(gr, flux, ivar, model, fold=b["fold"])
+            if len(c.periods):
+                cm.periodic_search(gr, b["fold"], pd, work=b["work"], out=b["per"])
+                cm.best(gr, pd, b["per"], out=b["best"])
+
+    singles()
+    torch.cuda.synchronize()
+    log("batched survey: single-curve searches warmed up")
+    e[4].record()
+    singles()
+    e[5].record()
+    torch.cuda.synchronize()
+    same = all(np.array_equal(best_batch[i], b[2]["best"].cpu().numpy())
+               for i, (c, b) in enumerate(zip(curves, bufs)) if len(c.periods))
+    del bufs
+    torch.cuda.empty_cache()
     work_units = float(sum(c.n_obs * len(c.periods) for c in curves))
     fold_bytes = float(sum(algorithmic_work(c, gr)["fold_bytes"] for c, gr in zip(curves, grids)))
-    ms_eager, ms_graph = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3])
+    ms_eager, ms_graph, ms_single = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]), e[4].elapsed_time(e[5])
     sec = min(ms_eager, ms_graph) / 1e3
-    return {"workload": f"{n_curves} survey curves, {int(oo[-1])} observations, {int(po[-1])} trial periods in all",
-            "n_launches": plan.info["n_launches"], "ms_eager": ms_eager, "ms_graph_replay": ms_graph,
+    return {"workload": (f"{n_curves} length-stratified survey curves (5 000-120 000 points at 2 min), "
+                         f"{int(oo[-1])} observations, {int(po[-1])} trial periods in all"),
+            "n_launches": plan.info["n_launches"], "n_items": plan.info["n_items"],
+            "ms_eager": ms_eager, "ms_graph_replay": ms_graph, "ms_single_curve_calls": ms_single,
+            "speedup_over_single_curve_calls": ms_single / min(ms_eager, ms_graph),
             "value": work_units / sec, "unit": "LC points x trial periods / s",
             "fold_algorithmic_bytes": fold_bytes, "fold_algorithmic_GBps": fold_bytes / sec / 1e9,
-            "status": int(out["status"].item())}
+            "status": status, "curves_done": n_done, "best_equal_to_single_calls": bool(same)}
 
 
 PROPOSAL_WEIGHTS_LONG = os.path.join(ROOT, "paper_2503_20875_amd", "weights", "proposal_long.npz")
@@ -211,83 +225,31 @@ def learned_long_block(wl, top_k: int = 64) -> dict:
             "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "n_trial", "seed")}}
 
 
-def long_baseline_block(tunings=((8, 8, 4, 2),), reps: int = 2) -> dict:
-    """The Earth-analogue curve (730.5 d at 25 s: 2 524 608 points, J = 30,
-    I = 1 755 200, K = 399 404): a 421 MB fold-ready array, larger than the
-    256 MB Infinity Cache (the concurrent workgroups sweep one 14 MB duration
-    row at a time).  Resample + linear search, then the periodic search under
-    each tuning (one untimed launch, then `reps` timed ones), with HIP events;
-    algorithmic fold bytes over the mean launch time against the HBM peak.
-    Also the monotransit-only search (resample + linear search + the five
-    strongest single events), timed once after a warm-up."""
+def monotransit_block(wl) -> dict:
+    """The monotransit-only search on one curve: resampling, the linear search
+    and the five strongest single events, timed once after a warm-up."""
     import torch
     import paper_2503_20875_amd as cm
-    from synthlc import workloads as W
-    wl = W.long_baseline()
-    dev = "cuda"
     grid = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
-    K = len(wl.periods)
-    t_d, f_d, s_d = (torch.as_tensor(a, device=dev) for a in (wl.t, wl.f, wl.sigma))
-    per_d = torch.as_tensor(wl.periods, device=dev)
-    fold = torch.empty((grid.n_dur, grid.n_t0, 2), dtype=torch.float32, device=dev)
-    work = torch.empty(cm.periodic_workspace(grid, K), dtype=torch.uint8, device=dev)
-    model = cm.template_resample(torch.as_tensor(wl.dense, device=dev), wl.n_model)
+    t_d, f_d, s_d = (torch.as_tensor(a, device="cuda") for a in (wl.t, wl.f, wl.sigma))
+    model = cm.template_resample(torch.as_tensor(wl.dense, device="cuda"), wl.n_model)
+    fold = torch.empty((grid.n_dur, grid.n_t0, 2), dtype=torch.float32, device="cuda")
 
-    def linear():
+    def run(out=None):
         flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
         cm.linear_search(grid, flux, ivar, model, fold=fold)
+        return cm.single_events(grid, fold, 5, out=out)
 
-    linear()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    linear()
-    e1.record()
-    torch.cuda.synchronize()
-    lin_ms = e0.elapsed_time(e1)
-    before = cm.get_tuning()
-    per = None
-    fold_ms = {}
-    try:
-        for tun in tunings:
-            cm.set_tuning(*tun)
-            per = cm.periodic_search(grid, fold, per_d, work=work, out=per)
-            ms = []
-            for _ in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                cm.periodic_search(grid, fold, per_d, work=work, out=per)
-                b.record()
-                b.synchronize()
-                ms.append(a.elapsed_time(b))
-            fold_ms[",".join(map(str, tun))] = sum(ms) / len(ms)
-    finally:
-        cm.set_tuning(**before)
-    rec = cm.best_record(cm.best(grid, per_d, per))
-    # monotransit-only search: resample + linear search + the 5 strongest single events
-    ev_out = cm.single_events(grid, fold, 5)
+    ev_out = run()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    linear()
-    cm.single_events(grid, fold, 5, out=ev_out)
+    run(ev_out)
     b.record()
     b.synchronize()
-    mono_ms = a.elapsed_time(b)
     events = cm.event_records(ev_out)
-    alg = algorithmic_work(wl, grid)
-    fastest = min(fold_ms, key=fold_ms.get)
-    gbps = alg["fold_bytes"] / (fold_ms[fastest] / 1e3) / 1e9
-    learned = learned_long_block(wl)
-    return {"workload": (f"long baseline: {wl.n_obs} points at 25 s over 730.5 d, J = {grid.n_dur}, "
-                         f"I = {grid.n_t0}, K = {K}; fold-ready array {grid.n_dur * grid.n_t0 * 8 / 1e6:.0f} MB"),
-            "linear_ms": lin_ms, "fold_ms_by_tuning": fold_ms, "fastest_tuning": fastest,
-            "fold_algorithmic_bytes": alg["fold_bytes"], "fold_effective_GBps": gbps,
-            "frac_of_hbm_peak": gbps / HBM_PEAK_GBS,
-            "search_ms": lin_ms + fold_ms[fastest],
-            "points_x_periods_per_s": wl.n_obs * K / ((lin_ms + fold_ms[fastest]) / 1e3),
-            "best": {"period": rec["period"], "snr": rec["snr"], "duration": rec["duration"]},
-            "monotransit_search_ms": mono_ms,
-            "learned": learned,
-            "single_events": [{"t0_abs": e["t0_abs"], "duration": e["duration"], "snr": e["snr"]} for e in events[:3]]}
+    return {"ms": a.elapsed_time(b),
+            "single_events": [{"t0_abs": e["t0_abs"], "duration": e["duration"], "snr": e["snr"]}
+                              for e in events[:3]]}
 
 
 def keplerian_block(rho=(0.5, 3.0), k_max: float = 0.2, b_max: float = 0.9, reps: int = 2) -> dict:
@@ -507,25 +469,343 @@ def learned_batched(pipe, net, curves, ref, k_target: int) -> dict:
     return out
 
 
+def log(msg: str) -> None:
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------- counters
+COUNTER_TIMEOUT_S = 240
+
+
+def _under_profiler() -> bool:
+    """True when this process already runs under rocprofv3 (a nested counter
+    pass would not work)."""
+    pre = os.environ.get("LD_PRELOAD", "")
+    return "rocprof" in pre or any(k.startswith("ROCPROF") for k in os.environ)
+
+
+def read_counter_csv(out_dir: str) -> list:
+    """Rows of every rocprofv3 counter-collection CSV under out_dir:
+    (dispatch id, kernel name, counter name, value)."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def per_dispatch(rows, counter: str) -> dict:
+    """{dispatch id: (kernel name, summed value)} of one counter."""
+    out = {}
+    for d, k, c, v in rows:
+        if c != counter:
+            continue
+        name, acc = out.get(d, (k, 0.0))
+        out[d] = (name, acc + v)
+    return out
+
+
+def counter_pass(counter: str, workload: str, copy_mib: int, tuning: str) -> dict:
+    """One rocprofv3 --pmc pass of `counter` over a child process that runs a
+    plain device copy of copy_mib MiB and one fold launch of the workload;
+    returns the counter per dispatch of the copy and of the fold (KiB)."""
+    import subprocess
+    import tempfile
+    out_dir = tempfile.mkdtemp(prefix=f"cetra_{counter.lower()}_", dir=os.environ.get("TMPDIR", "/tmp"))
+    cmd = ["rocprofv3", "--pmc", counter, "--output-format", "csv", "-d", out_dir, "-o", "run", "--",
+           sys.executable, os.path.join(ROOT, "bench.py"), "--mode", "fold", "--workload", workload,
+           "--steps", "1", "--copy-mib", str(copy_mib)]
+    if tuning:
+        cmd += ["--fold-tuning", tuning]
+    import signal
+    proc = subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, cwd=out_dir,
+                            start_new_session=True)
+    try:
+        text, _ = proc.communicate(timeout=COUNTER_TIMEOUT_S)
+    except subprocess.TimeoutExpired:
+        os.killpg(proc.pid, signal.SIGKILL)  # the profiler and its child, nothing else
+        proc.communicate()
+        raise RuntimeError(f"counter pass {counter} exceeded {COUNTER_TIMEOUT_S} s")
+    rows = read_counter_csv(out_dir)
+    disp = per_dispatch(rows, counter)
+    fold = [v for _, (k, v) in sorted(disp.items()) if "fold_kernel" in k]
+    copies = [v for _, (k, v) in sorted(disp.items()) if "fold" not in k and ("copy" in k.lower() or "elementwise" in k)]
+    if not fold or not copies:
+        tail = text.decode(errors="replace")[-600:]
+        raise RuntimeError(f"counter pass {counter}: no fold or copy dispatch found (rc {proc.returncode}): {tail}")
+    return {"fold_kib": fold, "copy_kib": max(copies), "rc": proc.returncode}
+
+
+def live_counters(workload: str, tuning: str, copy_mib: int = 1024) -> dict:
+    """Bytes the fold moves past L2 per launch, measured now: one rocprofv3
+    pass for FETCH_SIZE and one for WRITE_SIZE, each scaled by what the same
+    counter reads for a plain copy of copy_mib MiB in the same process (the
+    copy reads and writes exactly copy_mib MiB)."""
+    copy_bytes = copy_mib * (1 << 20)
+    fetch = counter_pass("FETCH_SIZE", workload, copy_mib, tuning)
+    write = counter_pass("WRITE_SIZE", workload, copy_mib, tuning)
+    f_scale = copy_bytes / (fetch["copy_kib"] * 1024.0)
+    w_scale = copy_bytes / (write["copy_kib"] * 1024.0)
+    fetch_b = float(np.mean(fetch["fold_kib"])) * 1024.0 * f_scale
+    write_b = float(np.mean(write["fold_kib"])) * 1024.0 * w_scale
+    return {"source": "live rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) over one fold launch of this "
+                      "workload, scaled by the same counters over a plain device copy",
+            "fetch_kib_per_dispatch": fetch["fold_kib"], "write_kib_per_dispatch": write["fold_kib"],
+            "copy_bytes": copy_bytes, "copy_fetch_kib": fetch["copy_kib"], "copy_write_kib": write["copy_kib"],
+            "fetch_scale": f_scale, "write_scale": w_scale,
+            "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+            "bytes_per_launch": fetch_b + write_b}
+
+
+def committed_counters(workload: str, tuning: dict):
+    """Counter figures committed under profiles/ for this workload, used only
+    while the fold source and tuning still match the ones they were taken on."""
+    path = os.path.join(ROOT, "profiles", f"fold_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        prof = json.load(fh)
+    tun = [tuning[k] for k in ("fold_period_block", "fold_wgs_per_cu", "fold_units_per_wg", "fold_variant")]
+    if prof.get("fold_source_sha256_16") != fold_source_hash() or prof.get("tuning") != tun:
+        return None
+    return {"source": f"profiles/fold_{workload}_counters.json (fold source hash and tuning match)",
+            "bytes_per_launch": prof["hbm_bytes_per_launch"], "fetch_scale": prof.get("fetch_scale"),
+            "write_scale": prof.get("write_scale")}
+
+
+# ------------------------------------------------------------ host facts
+def cpu_facts() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(wl, fold_stride: int = 4000, st_lin_stride: int = 4000, st_periods: int = 4) -> dict:
+    """The FP64 oracle, as it is, on a bounded sample of one curve of the
+    workload, on every core OpenMP uses here: resampling and the linear search
+    in full, the fold over every fold_stride-th period, extrapolated linearly
+    in fold element visits (sum over periods of allowed durations x I) to the
+    full grid.  Then the same on one thread: the linear search on every
+    st_lin_stride-th element (extrapolated in elements) and the fold over
+    st_periods evenly spaced periods (extrapolated in element visits)."""
+    import oracle
+    g = oracle.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, wl.n_model)
+    model = oracle.template(wl.dense, wl.n_model)
+    cores = oracle.max_threads()
+    durs = np.asarray(wl.durations)
+    jk = np.array([np.count_nonzero(durs < P) for P in wl.periods], dtype=np.float64)
+    K = len(wl.periods)
+    t0 = time.perf_counter()
+    flux, ivar = oracle.resample(g, wl.t, wl.f, wl.sigma)
+    t_res = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lin = oracle.linear(g, flux, ivar, model)
+    t_lin = time.perf_counter() - t0
+    sel = np.arange(fold_stride // 2, K, fold_stride)
+    t0 = time.perf_counter()
+    oracle.periodic(g, lin, wl.periods, sel=sel)
+    t_fold = time.perf_counter() - t0
+    scale = jk.sum() / jk[sel].sum()
+    t_full = t_res + t_lin + t_fold * scale
+    # one thread
+    n_el = g.n_dur * g.n_t0
+    idx = np.arange(0, n_el, st_lin_stride, dtype=np.int64)
+    sel1 = np.linspace(0, K - 1, st_periods + 2)[1:-1].astype(np.int64)
+    try:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.linear_at(g, flux, ivar, model, idx)
+        m_lin1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.periodic(g, lin, wl.periods, sel=sel1)
+        m_fold1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    t_lin1 = m_lin1 * n_el / len(idx)
+    t_fold1 = m_fold1 * jk.sum() / jk[sel1].sum()
+    t_full1 = t_res + t_lin1 + t_fold1
+    units = wl.n_obs * K
+    return dict(value=units / t_full, unit="LC points x trial periods / s", cores=cores, kind="oracle",
+                sample=(f"one curve of the workload: resampling ({t_res:.2f} s) and the linear search "
+                        f"({t_lin:.2f} s) in full, fold over every {fold_stride}th period ({len(sel)} of {K}, "
+                        f"{t_fold:.2f} s) extrapolated x{scale:.0f} in fold element visits; estimated full "
+                        f"search {t_full:.0f} s"),
+                single_thread={"value": units / t_full1, "estimated_full_search_s": t_full1,
+                               "sample": (f"linear search on every {st_lin_stride}th element, fold over "
+                                          f"{len(sel1)} periods, each extrapolated as above")},
+                seconds_measured=round(t_res + t_lin + t_fold + m_lin1 + m_fold1, 1),
+                **cpu_facts())
+
+
+# ------------------------------------------------------------ headline
+def search_buffers(cm, torch, grid, K, dev="cuda"):
+    return dict(fold=torch.empty((grid.n_dur, grid.n_t0, 2), dtype=torch.float32, device=dev),
+                work=torch.empty(max(cm.periodic_workspace(grid, K), 1), dtype=torch.uint8, device=dev),
+                per=dict(lr=torch.empty(K, dtype=torch.float32, device=dev),
+                         epoch=torch.empty(K, dtype=torch.int32, device=dev),
+                         dur=torch.empty(K, dtype=torch.int32, device=dev),
+                         depth=torch.empty(K, dtype=torch.float32, device=dev),
+                         depth_var=torch.empty(K, dtype=torch.float32, device=dev)),
+                best=torch.empty(ctypes.sizeof(cm.BestRecord), dtype=torch.uint8, device=dev))
+
+
+def timed_search(cm, torch, grid, curves, dense_d, per_d, n_model, bufs, steps: int, warmup: int) -> dict:
+    """warmup untimed steps, then `steps` timed ones, step s on curve
+    s mod len(curves) (each a (t, f, sigma) triple of device tensors); HIP
+    events on the launch stream around every step and around its fold."""
+    stream = torch.cuda.current_stream()
+    fold, work, per, best = bufs["fold"], bufs["work"], bufs["per"], bufs["best"]
+    names = ("start", "lin", "fold1", "end")
+    ev = {k: [] for k in names}
+
+    def step(s: int, record: bool):
+        t_d, f_d, s_d = curves[s % len(curves)]
+        e = {k: torch.cuda.Event(enable_timing=True) for k in names} if record else None
+        if record:
+            e["start"].record(stream)
+        model = cm.template_resample(dense_d, n_model)
+        flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
+        cm.linear_search(grid, flux, ivar, model, fold=fold)
+        if record:
+            e["lin"].record(stream)
+        cm.periodic_search(grid, fold, per_d, work=work, out=per)
+        if record:
+            e["fold1"].record(stream)
+        cm.best(grid, per_d, per, out=best)
+        if record:
+            e["end"].record(stream)
+            for k in names:
+                ev[k].append(e[k])
+
+    for s in range(warmup):
+        step(s, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(warmup + s, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_steps = [ev["start"][i].elapsed_time(ev["end"][i]) for i in range(steps)]
+    ms_lin = [ev["start"][i].elapsed_time(ev["lin"][i]) for i in range(steps)]
+    ms_fold = [ev["lin"][i].elapsed_time(ev["fold1"][i]) for i in range(steps)]
+    return dict(ms_step=float(np.mean(ms_steps)), ms_lin=float(np.mean(ms_lin)), ms_fold=float(np.mean(ms_fold)),
+                wall=wall, best=cm.best_record(best), last_curve=(warmup + steps - 1) % len(curves))
+
+
+def pcie_inclusive(cm, torch, grid, host_curve, dense_d, per_d, n_model, bufs, reps: int = 2) -> dict:
+    """One step with the host transfers inside: t, f, sigma copied from
+    pinned host memory, the search, and the per-period records plus the best
+    record copied back to pinned host memory; mean of `reps` after one
+    untimed run."""
+    t_h, f_h, s_h = (torch.as_tensor(a).pin_memory() for a in host_curve)
+    t_d, f_d, s_d = (torch.empty_like(a, device="cuda") for a in (t_h, f_h, s_h))
+    per, best = bufs["per"], bufs["best"]
+    out_h = {k: torch.empty(v.shape, dtype=v.dtype).pin_memory() for k, v in per.items()}
+    best_h = torch.empty(best.shape, dtype=best.dtype).pin_memory()
+
+    def run():
+        for d, h in ((t_d, t_h), (f_d, f_h), (s_d, s_h)):
+            d.copy_(h, non_blocking=True)
+        model = cm.template_resample(dense_d, n_model)
+        flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
+        cm.linear_search(grid, flux, ivar, model, fold=bufs["fold"])
+        cm.periodic_search(grid, bufs["fold"], per_d, work=bufs["work"], out=per)
+        cm.best(grid, per_d, per, out=best)
+        for k, v in per.items():
+            out_h[k].copy_(v, non_blocking=True)
+        best_h.copy_(best, non_blocking=True)
+
+    run()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run()
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    h2d = sum(x.numel() * x.element_size() for x in (t_h, f_h, s_h))
+    d2h = sum(v.numel() * v.element_size() for v in out_h.values()) + best_h.numel()
+    return {"ms_per_step": float(np.mean(ms)), "h2d_bytes": h2d, "d2h_bytes": d2h}
+
+
+def high_cadence_block(steps: int = 5, warmup: int = 2) -> dict:
+    """The 90-day, 20-s cadence curve (369 360 observations, red + white
+    noise, pre-whitened, gaps; 20 durations 0.5-15 h; 50 000 periods
+    0.5-45 d): the same timed step as the headline, with its fold rate in
+    algorithmic bytes against the address-unit bound (the 70 MB fold-ready
+    array is cache-resident), the linear search's FP32 rate, and the
+    default-grid measurements on the same curve."""
+    import torch
+    import paper_2503_20875_amd as cm
+    from synthlc import workloads as W
+    wl = W.high_cadence()
+    grid = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
+    K = len(wl.periods)
+    curves = [tuple(torch.as_tensor(a, device="cuda") for a in (wl.t, wl.f, wl.sigma))]
+    bufs = search_buffers(cm, torch, grid, K)
+    r = timed_search(cm, torch, grid, curves, torch.as_tensor(wl.dense, device="cuda"),
+                     torch.as_tensor(wl.periods, device="cuda"), wl.n_model, bufs, steps, warmup)
+    alg = algorithmic_work(wl, grid)
+    fold_gbps = alg["fold_bytes"] / (r["ms_fold"] / 1e3) / 1e9
+    lin_tf = alg["linear_flop"] / (r["ms_lin"] / 1e3) / 1e12
+    del bufs
+    return {"workload": (f"single light curve, 90 d at 20 s cadence, {wl.n_obs} observations (N = {grid.n}), "
+                         f"J = {grid.n_dur} durations 0.5-15 h, I = {grid.n_t0}, K = {K} periods 0.5-45 d"),
+            "value": wl.n_obs * K / (r["ms_step"] / 1e3), "unit": "LC points x trial periods / s",
+            "ms_per_step": r["ms_step"], "steps": steps,
+            "stages_ms": {"setup_and_linear": r["ms_lin"], "periodic": r["ms_fold"],
+                          "best": r["ms_step"] - r["ms_lin"] - r["ms_fold"]},
+            "roofline_address_unit": {"kernel": "fold_kernel (periodic search)", "achieved": fold_gbps,
+                                      "peak": ADDRESS_UNIT_PEAK_GBS, "unit": "GB/s",
+                                      "frac": fold_gbps / ADDRESS_UNIT_PEAK_GBS,
+                                      "algorithmic_bytes_per_launch": alg["fold_bytes"]},
+            "roofline_linear": {"kernel": "linear_kernel", "bound": "alu", "achieved": lin_tf,
+                                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": lin_tf / FP32_VECTOR_PEAK_TFLOPS, "algorithmic_flop": alg["linear_flop"],
+                                "avg_ms_incl_setup": r["ms_lin"]},
+            "best": {"period": r["best"]["period"], "snr": r["best"]["snr"], "depth": r["best"]["depth"],
+                     "duration": r["best"]["duration"]},
+            "default_grids": keplerian_block()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="high_cadence", choices=["high_cadence", "tiny", "long_baseline"])
-    ap.add_argument("--no-long-baseline", action="store_true",
-                    help="skip the long-baseline (2 yr at 25 s) fold measurement")
+    ap.add_argument("--workload", default="long_baseline", choices=["long_baseline", "high_cadence", "tiny"],
+                    help="long_baseline (default): the Earth-analogue batch, one curve per step")
+    ap.add_argument("--curves", type=int, default=8,
+                    help="distinct curves of the Earth-analogue batch the steps cycle through")
     ap.add_argument("--no-extras", action="store_true",
-                    help="time the benchmark steps only (no filter, long-baseline, network, batched, learned or "
-                         "CPU measurements), e.g. for kernel traces of the headline search")
-    ap.add_argument("--mode", default="full", choices=["full", "fold", "copy", "net"],
-                    help="full: the benchmark; fold: setup once, then --steps fold launches only "
-                         "(for counter runs); copy: a plain device copy of --copy-mib MiB, --steps "
-                         "times (calibrates the HBM byte counters); net: the proposal network's "
-                         "convolution roofline only (for kernel traces and MFMA counters)")
-    ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--batch-curves", type=int, default=32,
+                    help="time the benchmark steps only (no counters, secondary workloads, network, batched, "
+                         "learned or CPU measurements), e.g. for kernel traces of the headline search")
+    ap.add_argument("--no-counters", action="store_true", help="skip the live rocprofv3 counter passes")
+    ap.add_argument("--mode", default="full", choices=["full", "fold", "copy", "net", "batch"],
+                    help="full: the benchmark; fold: setup once, then an optional --copy-mib device copy and "
+                         "--steps fold launches only (for counter runs); copy: a plain device copy of "
+                         "--copy-mib MiB, --steps times; net: the proposal network's convolution roofline only; "
+                         "batch: the batched-survey measurement only (--batch-curves curves)")
+    ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--batch-curves", type=int, default=64,
                     help="survey curves of the batched-search measurement (0: skip)")
     ap.add_argument("--fold-tuning", default="",
                     help="period block, workgroups per CU, units per workgroup, variant (e.g. 4,8,4,0); "
@@ -545,7 +825,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.mode == "copy":
-        n = args.copy_mib * (1 << 20) // 4
+        n = max(args.copy_mib, 1) * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(args.steps):
@@ -557,94 +837,62 @@ def main():
     if args.mode == "net":
         print(json.dumps({"mode": "net", **net_block()}), flush=True)
         return
+    if args.mode == "batch":
+        print(json.dumps({"mode": "batch", **batched_block(args.batch_curves)}), flush=True)
+        return
     if args.fold_tuning:
         cm.set_tuning(*(int(v) for v in args.fold_tuning.split(",")))
-    wl = W.WORKLOADS[args.workload]()
+    tuning = cm.get_tuning()
+    tuning_str = ",".join(str(tuning[k]) for k in ("fold_period_block", "fold_wgs_per_cu", "fold_units_per_wg",
+                                                     "fold_variant"))
+    long = args.workload == "long_baseline"
+    n_curves = max(1, min(args.curves, args.steps + args.warmup)) if long and args.mode == "full" else 1
+    wls = [W.long_baseline(seed=LONG_SEED + c) for c in range(n_curves)] if long else [W.WORKLOADS[args.workload]()]
+    wl = wls[0]
     dev = "cuda"
-    t_d = torch.as_tensor(wl.t, device=dev)
-    f_d = torch.as_tensor(wl.f, device=dev)
-    s_d = torch.as_tensor(wl.sigma, device=dev)
-    dense_d = torch.as_tensor(wl.dense, device=dev)
-    per_d = torch.as_tensor(wl.periods, device=dev)
     grid = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
     K = len(wl.periods)
-    # every buffer allocated up front: the timed region only launches kernels
-    fold = torch.empty((grid.n_dur, grid.n_t0, 2), dtype=torch.float32, device=dev)
-    work = torch.empty(cm.periodic_workspace(grid, K), dtype=torch.uint8, device=dev)
-    per = dict(lr=torch.empty(K, dtype=torch.float32, device=dev),
-               epoch=torch.empty(K, dtype=torch.int32, device=dev),
-               dur=torch.empty(K, dtype=torch.int32, device=dev),
-               depth=torch.empty(K, dtype=torch.float32, device=dev),
-               depth_var=torch.empty(K, dtype=torch.float32, device=dev))
-    best = torch.empty(96, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-    ev = {k: [] for k in ("start", "lin", "fold0", "fold1", "end")}
-
-    def step(record: bool):
-        e = {k: torch.cuda.Event(enable_timing=True) for k in ev} if record else None
-        if record:
-            e["start"].record(stream)
-        model = cm.template_resample(dense_d, wl.n_model)
-        flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
-        cm.linear_search(grid, flux, ivar, model, fold=fold)
-        if record:
-            e["lin"].record(stream)
-            e["fold0"].record(stream)
-        cm.periodic_search(grid, fold, per_d, work=work, out=per)
-        if record:
-            e["fold1"].record(stream)
-        cm.best(grid, per_d, per, out=best)
-        if record:
-            e["end"].record(stream)
-            for k in ev:
-                ev[k].append(e[k])
+    for w in wls[1:]:  # the batch shares its time grid and period grid
+        assert np.array_equal(w.t, wl.t) and np.array_equal(w.periods, wl.periods)
+    curves = [tuple(torch.as_tensor(a, device=dev) for a in (w.t, w.f, w.sigma)) for w in wls]
+    dense_d = torch.as_tensor(wl.dense, device=dev)
+    per_d = torch.as_tensor(wl.periods, device=dev)
+    bufs = search_buffers(cm, torch, grid, K)  # every buffer allocated before timing
 
     if args.mode == "fold":
+        t_d, f_d, s_d = curves[0]
         model = cm.template_resample(dense_d, wl.n_model)
         flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
-        cm.linear_search(grid, flux, ivar, model, fold=fold)
+        cm.linear_search(grid, flux, ivar, model, fold=bufs["fold"])
+        if args.copy_mib > 0:
+            n = args.copy_mib * (1 << 20) // 4
+            src = torch.ones(n, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            del src, dst
         for _ in range(args.steps):
-            cm.periodic_search(grid, fold, per_d, work=work, out=per)
+            cm.periodic_search(grid, bufs["fold"], per_d, work=bufs["work"], out=bufs["per"])
         torch.cuda.synchronize()
-        work_alg = algorithmic_work(wl, grid)
-        print(json.dumps({"mode": "fold", "launches": args.steps, "workload": args.workload, "tuning": cm.get_tuning(),
-                          "fold_source_sha256_16": fold_source_hash(),
-                          "algorithmic_bytes_per_launch": work_alg["fold_bytes"]}), flush=True)
+        print(json.dumps({"mode": "fold", "launches": args.steps, "workload": args.workload, "tuning": tuning,
+                          "fold_source_sha256_16": fold_source_hash(), "copy_mib": args.copy_mib,
+                          "algorithmic_bytes_per_launch": algorithmic_work(wl, grid)["fold_bytes"]}), flush=True)
         return
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_steps = [ev["start"][i].elapsed_time(ev["end"][i]) for i in range(args.steps)]
-    ms_lin = [ev["start"][i].elapsed_time(ev["lin"][i]) for i in range(args.steps)]
-    ms_fold = [ev["fold0"][i].elapsed_time(ev["fold1"][i]) for i in range(args.steps)]
-    ms_step = float(np.mean(ms_steps))
-    b = cm.best_record(best)
-
-    work_alg = algorithmic_work(wl, grid)
-    fold_s = float(np.mean(ms_fold)) / 1e3
-    achieved = work_alg["fold_bytes"] / fold_s / 1e9
-    traffic = None
-    if os.path.exists(PROFILE_COUNTERS):
-        with open(PROFILE_COUNTERS) as fh:
-            prof = json.load(fh)
-        if prof.get("fold_source_sha256_16") == fold_source_hash() and prof.get("workload") == args.workload:
-            traffic = prof.get("hbm_bytes_per_launch")
-    ta_busy = None
-    if os.path.exists(PROFILE_PIPELINE):
-        with open(PROFILE_PIPELINE) as fh:
-            pipe = json.load(fh)
-        if (pipe.get("fold_source_sha256_16") == fold_source_hash() and pipe.get("workload") == args.workload
-                and pipe.get("tuning") == [cm.get_tuning()[k] for k in ("fold_period_block", "fold_wgs_per_cu",
-                                                                          "fold_units_per_wg", "fold_variant")]):
-            ta_busy = pipe.get("ta_busy_frac")
-    lin_s = float(np.mean(ms_lin)) / 1e3
-    value = wl.n_obs * K / (ms_step / 1e3)
+    log(f"{args.workload}: {n_curves} curve(s) resident, {args.warmup} warm-up + {args.steps} timed steps")
+    r = timed_search(cm, torch, grid, curves, dense_d, per_d, wl.n_model, bufs, args.steps, args.warmup)
+    log(f"timed steps done: {r['ms_step']:.1f} ms per step")
+    alg = algorithmic_work(wl, grid)
+    fold_s = r["ms_fold"] / 1e3
+    lin_s = r["ms_lin"] / 1e3
+    alg_gbps = alg["fold_bytes"] / fold_s / 1e9
+    value = wl.n_obs * K / (r["ms_step"] / 1e3)
+    b = r["best"]
+    if long:
+        desc = (f"Earth-analogue batch of 64 curves, one curve per step (steps cycle through {n_curves} of them): "
+                f"730.5 d at 25 s, {wl.n_obs} observations (N = {grid.n} resampled), J = {grid.n_dur} durations "
+                f"1-20 h, I = {grid.n_t0} reference times, K = {K} periods 1-400 d")
+    else:
+        desc = (f"{wl.name}: {wl.n_obs} observations (N = {grid.n}), J = {grid.n_dur}, I = {grid.n_t0}, K = {K}")
     out = {
         "metric": "LC points x trials/sec (linear+periodic) on 1 GPU",
         "value": value,
@@ -652,72 +900,101 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": (f"single light curve, 90 d at 20 s cadence, {wl.n_obs} observations "
-                         f"(N = {grid.n} resampled), J = {grid.n_dur} durations 0.5-15 h, "
-                         f"I = {grid.n_t0} reference times, K = {K} periods 0.5-45 d")
-            if args.workload == "high_cadence" else wl.name,
-            "n_obs": wl.n_obs, "n_grid": int(grid.n), "n_t0": int(grid.n_t0), "n_durations": int(grid.n_dur),
-            "n_periods": K, "n_model": wl.n_model,
-        },
-        "roofline": {
-            "kernel": "fold_kernel (periodic search)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": work_alg["fold_bytes"],
-            "avg_launch_ms": fold_s * 1e3,
-            "tuning": cm.get_tuning(),
-        },
-        "roofline_l1": {
-            "kernel": "fold_kernel (periodic search)",
-            "bound": "vector-memory address unit (cache-resident working set)",
-            "achieved": achieved,
-            "peak": L1_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / L1_PEAK_GBS,
-            "ta_busy_frac": ta_busy,
-            "note": "achieved counts 8 B per element visit; transit 0 of a period block is one load for all its "
-                    "periods, so the bytes the unit delivers are slightly fewer",
-        },
-        "roofline_linear": {
-            "kernel": "linear_kernel (linear search, all durations)",
-            "bound": "alu",
-            "achieved": work_alg["linear_flop"] / lin_s / 1e12,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": work_alg["linear_flop"] / lin_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-            "algorithmic_flop": work_alg["linear_flop"],
-            "avg_ms_incl_setup": lin_s * 1e3,
-        },
-        "stages_ms": {"setup_and_linear": lin_s * 1e3, "periodic": fold_s * 1e3,
-                      "best": ms_step - lin_s * 1e3 - fold_s * 1e3},
-        "wall_s_timed": wall,
-        "best": {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"]},
+        "config": {"workload": desc, "n_obs": wl.n_obs, "n_grid": int(grid.n), "n_t0": int(grid.n_t0),
+                   "n_durations": int(grid.n_dur), "n_periods": K, "n_model": wl.n_model,
+                   "curves_cycled": n_curves},
     }
+    counters, counter_note = None, None
+    if not args.no_extras and not args.no_counters and not _under_profiler():
+        try:
+            log("live counter passes (FETCH_SIZE, WRITE_SIZE)")
+            counters = live_counters(args.workload, tuning_str)
+        except Exception as exc:  # a missing profiler is reported, never papered over
+            counter_note = f"live counter passes failed: {exc}"
+    if counters is None:
+        counters = committed_counters(args.workload, tuning)
+    traffic = counters["bytes_per_launch"] if counters else None
+    achieved = traffic / fold_s / 1e9 if traffic else None
+    out["roofline"] = {
+        "kernel": "fold_kernel (periodic search)",
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+        "traffic": traffic,
+        "basis": ("achieved = bytes the fold moves past L2 per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                  "they are served by the Infinity Cache or HBM) / the fold's mean launch time in the timed "
+                  "steps; null when no counter figures for this exact fold source exist"),
+        "counters": counters if counters else counter_note,
+        "algorithmic_bytes_per_launch": alg["fold_bytes"],
+        "algorithmic_GBps": alg_gbps,
+        "traffic_over_algorithmic": traffic / alg["fold_bytes"] if traffic else None,
+        "avg_launch_ms": fold_s * 1e3,
+        "tuning": tuning,
+        "fold_source_sha256_16": fold_source_hash(),
+    }
+    out["roofline_address_unit"] = {
+        "kernel": "fold_kernel (periodic search)",
+        "bound": "vector-memory address unit",
+        "achieved": alg_gbps,
+        "peak": ADDRESS_UNIT_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": alg_gbps / ADDRESS_UNIT_PEAK_GBS,
+        "derivation": ("peak = 64 B per clock per CU (a 16-byte-per-lane wave load, 1 KB, occupies the unit 16 "
+                       "cycles) x 256 CUs x 2.4 GHz; achieved = algorithmic bytes (8 B per element visit + 20 B "
+                       "per period) / mean launch time"),
+    }
+    out["roofline_linear"] = {
+        "kernel": "linear_kernel (linear search, all durations)",
+        "bound": "alu",
+        "achieved": alg["linear_flop"] / lin_s / 1e12,
+        "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": alg["linear_flop"] / lin_s / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+        "algorithmic_flop": alg["linear_flop"],
+        "avg_ms_incl_setup": lin_s * 1e3,
+    }
+    out["stages_ms"] = {"setup_and_linear": r["ms_lin"], "periodic": r["ms_fold"],
+                        "best": r["ms_step"] - r["ms_lin"] - r["ms_fold"]}
+    out["wall_s_timed"] = r["wall"]
+    out["best"] = {"period": b["period"], "snr": b["snr"], "depth": b["depth"], "duration": b["duration"],
+                   "curve": r["last_curve"]}
     if args.no_extras:
         print(json.dumps(out), flush=True)
         return
-    if args.workload == "high_cadence":
-        out["keplerian"] = keplerian_block()
-        if not args.no_long_baseline:
-            out["long_baseline"] = long_baseline_block()
-        out["roofline_net"] = net_block()
-        if args.batch_curves > 0:
-            out["batched"] = batched_block(args.batch_curves)
-    if args.learned_curves > 0 and args.workload == "high_cadence":
+    log("host-transfer-inclusive step")
+    pc = pcie_inclusive(cm, torch, grid, (wl.t, wl.f, wl.sigma), dense_d, per_d, wl.n_model, bufs)
+    out["pcie_inclusive"] = {**pc, "value": wl.n_obs * K / (pc["ms_per_step"] / 1e3),
+                             "note": "t, f, sigma from pinned host memory and the per-period and best records "
+                                     "back to it, inside the timed step"}
+    del bufs, curves
+    torch.cuda.empty_cache()
+    if long:
+        log("learned form on the Earth analogue")
+        out["learned_long"] = learned_long_block(wl)
+        log("monotransit search")
+        out["monotransit"] = monotransit_block(wl)
+        log("high-cadence curve")
+        out["high_cadence"] = high_cadence_block()
+    log("proposal network")
+    out["roofline_net"] = net_block()
+    if args.batch_curves > 0:
+        log(f"batched survey ({args.batch_curves} curves)")
+        out["batched"] = batched_block(args.batch_curves)
+    if args.learned_curves > 0:
+        log(f"learned proposal ({args.learned_curves} held-out curves)")
         out["learned"] = learned_block(args.learned_curves)
     if not args.no_cpu_baseline:
+        log("FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(wl)
+    log("done")
     print(json.dumps(out), flush=True)
 
 

@@ -115,8 +115,8 @@ typedef struct cetra_event {
 } cetra_event;
 
 /* Launch tuning of the periodic search, process-wide for this library
- * instance (an autotuner sets it; the defaults are 8, 8, 4, 2).  Results do not
- * depend on it except through near-ties of the argmax. */
+ * instance (an autotuner sets it; the defaults are 8, 8, 4, 2, 4).  Results do
+ * not depend on it. */
 typedef struct cetra_tuning {
     int32_t fold_period_block;  /* trial periods accumulated per lane: 4, 8 or 16     */
     int32_t fold_wgs_per_cu;    /* resident workgroups per compute unit, 1..32       */
@@ -125,7 +125,10 @@ typedef struct cetra_tuning {
                                    2: register fold, adjacent lane epochs and
                                       16-byte loads (1, 3 and 4 are retired:
                                       LDS-staged forms that measured slower)   */
-    int32_t reserved[4];
+    int32_t linear_windows;     /* linear-search windows per lane: 1, 2 or 4 (a
+                                   workgroup computes 256 x this many reference
+                                   times; results do not depend on it)         */
+    int32_t reserved[3];
 } cetra_tuning;
 
 /* ---------------------------------------------------------------- service */
@@ -355,63 +358,157 @@ int cetra_periodic_merge(void *stream, int32_t n_sets, int64_t n_periods, const 
 int cetra_mask_transits(void *stream, const cetra_grid *grid, double period, double t0, double duration,
                         double width, float *flux, float *ivar);
 
+/* ------------------------------------------------------------- autotuner */
+
+/* Shape class of a search, the key of the autotuner's cache. */
+typedef struct cetra_shape_class {
+    char arch[32];          /* GPU architecture ("gfx950"); empty = the current device's */
+    int32_t log2_t0;        /* ceil(log2(I))                                           */
+    int32_t n_dur;          /* J                                                        */
+    int32_t log2_periods;   /* ceil(log2(K))                                           */
+    int32_t reserved;
+} cetra_shape_class;
+
+/* Shape class of a grid and a period count (host only; arch left empty). */
+int cetra_shape_class_of(const cetra_grid *grid, int64_t n_periods, cetra_shape_class *out);
+
+/* Device workspace bytes cetra_autotune needs for this grid and period count
+ * (host only). */
+int cetra_autotune_workspace(const cetra_grid *grid, int64_t n_periods, size_t *bytes);
+
+/* Launch autotuner.  If cache_path (nullable) names a JSON cache holding an
+ * entry for shape's architecture and class, that tuning is applied
+ * (cetra_set_tuning) and returned with *from_cache = 1: no device work, no
+ * synchronisation.  Otherwise the candidates are timed with HIP events on
+ * `stream` on the caller's data: the linear search under 1, 2 and 4 windows
+ * per lane (flux, ivar, model as for cetra_linear_search; fold[J][I][2] is
+ * overwritten with the same values each time), then the periodic search
+ * under period blocks 4/8/16 x workgroups per CU 2/4/8 x units per workgroup
+ * 2/4/8 x fold variants 0/2 over a contiguous slice of periods[n_periods]
+ * (device) from the middle of the grid, sized to about 5e11 algorithmic
+ * bytes.  The fastest of each is applied and returned (*from_cache = 0,
+ * times in ms through fold_ms / linear_ms, nullable), and written to the
+ * cache (entries of other classes are kept; the file is replaced
+ * atomically).  work: device workspace of cetra_autotune_workspace bytes.
+ * This call synchronises the stream (a set-up step, not capturable).
+ * Results of the search do not depend on the tuning. */
+int cetra_autotune(void *stream, const cetra_shape_class *shape, const cetra_grid *grid,
+                   const float *flux, const float *ivar, const float *model, float *fold,
+                   const double *periods, int64_t n_periods, void *work, size_t work_bytes,
+                   const char *cache_path, cetra_tuning *out, double *fold_ms, double *linear_ms,
+                   int32_t *from_cache);
+
 /* ---------------------------------------------------------- batched search */
 
-/* A batch of light curves searched with one call (the per-curve method is
- * Sec. 2.1-2.3 unchanged; batching is this library's addition).  Curves share
- * the durations and template size; each has its own grid plan, observations
- * and period grid, concatenated (CSR) in device arrays. */
+/* A batch of light curves searched by one persistent launch that drains a
+ * work queue (the per-curve method is Sec. 2.1-2.3 unchanged; batching is
+ * this library's addition).  Curves share the durations and template size;
+ * each has its own grid plan, observations and period grid, concatenated
+ * (CSR) in device arrays. */
 typedef struct cetra_batch_desc {
     int32_t n_curves;              /* >= 1                                           */
-    int32_t reserved0;             /* must be 0                                      */
+    int32_t fold_period_block;     /* periods per fold lane block: 4 or 8, 0 = the
+                                      library tuning's (if that is 16, 8)              */
     const cetra_grid *grids;       /* host [n_curves]: cetra_grid_plan of each curve;
                                       all with the same n_dur, durations and n_model    */
-    const int64_t *obs_offsets;    /* host [n_curves + 1]: curve c's observations are
-                                      t/f/sigma[obs_offsets[c] .. obs_offsets[c+1])     */
-    const int64_t *period_offsets; /* host [n_curves + 1]: the same for periods and for
-                                      the per-period outputs                            */
-    int64_t reserved1;             /* must be 0                                      */
+    const int64_t *obs_offsets;    /* host [n_curves + 1], starting at 0: curve c's
+                                      observations are t/f/sigma[obs_offsets[c] ..
+                                      obs_offsets[c+1])                                 */
+    const int64_t *period_offsets; /* host [n_curves + 1], starting at 0: the same for
+                                      periods and for the per-period outputs            */
+    int64_t shuffle_seed;          /* 0: curves queued by descending fold cost; else a
+                                      permutation drawn from this seed (results do not
+                                      depend on the order)                              */
+    int32_t reserved0;             /* must be 0                                      */
+    int32_t reserved1;
 } cetra_batch_desc;
 
 typedef struct cetra_batch_info {
     size_t workspace_bytes;  /* device workspace cetra_batch_search needs          */
+    size_t tables_bytes;     /* leading workspace bytes that hold the plan's tables */
     int64_t n_curves;
     int64_t total_periods;
-    int64_t n_launches;      /* kernel launches one cetra_batch_search enqueues    */
+    int64_t n_launches;      /* kernel launches per cetra_batch_search (2)         */
+    int64_t n_items;         /* work-queue items of one search                     */
+    int32_t n_slots;         /* curves whose device data are resident at once      */
+    int32_t period_block;
+    int32_t lds_bytes;       /* dynamic LDS per workgroup of the persistent kernel */
+    int32_t reserved;
 } cetra_batch_info;
+
+/* Flags of cetra_batch_search. */
+#define CETRA_BATCH_RESUME 1      /* skip curves whose done flag is already set       */
+
+/* Device status bits written by cetra_batch_search (0 = every curve searched). */
+#define CETRA_BATCH_CANCELLED 1   /* the cancel flag stopped the launch early          */
+#define CETRA_BATCH_WAIT_LIMIT 2  /* a dependency wait exceeded 30 s (results invalid)  */
+#define CETRA_BATCH_BAD_TABLES 4  /* the workspace does not hold this plan's tables    */
+#define CETRA_BATCH_UNSORTED 8    /* some curve's times were not finite and ascending  */
 
 /* Opaque host-side plan. */
 typedef struct cetra_batch_plan cetra_batch_plan;
 
 /* Plan a batch (host only): validates the grids and offsets, orders the
- * curves by descending fold cost (sum over periods of allowed durations times
- * reference times) and sizes the device workspace for the largest curve
- * (resampled curve, fold-ready array and fold workspace).  The plan copies
- * what it needs from desc and owns host memory only; free it with
- * cetra_batch_plan_destroy. */
+ * curves (descending fold cost = sum over periods of allowed durations times
+ * reference times, or a seeded shuffle), cuts every curve's stages into work
+ * items (resampling, linear search, fold units, decode) and lays out the
+ * queue so that each item's inputs come from items queued before it: curve
+ * p+2's resampling and linear search and curve p-1's decode are queued
+ * around curve p's fold.  Four device slots (resampled curve and fold-ready
+ * array, sized for the longest curve) are reused in queue order.  The plan
+ * owns host memory only; free it with cetra_batch_plan_destroy. */
 int cetra_batch_plan_create(const cetra_batch_desc *desc, cetra_batch_plan **out);
 int cetra_batch_plan_destroy(cetra_batch_plan *plan);
 int cetra_batch_plan_info(const cetra_batch_plan *plan, cetra_batch_info *info);
-/* The processing order (host int32 [n], n = number of curves). */
+/* The queue order of the curves (host int32 [n], n = number of curves). */
 int cetra_batch_plan_order(const cetra_batch_plan *plan, int32_t *order, int32_t n);
 
-/* Search every curve of the batch: for each curve in plan order, enqueue on
- * `stream` the single-curve stages (cetra_resample, cetra_linear_search,
- * cetra_periodic_search, cetra_best) with the curve's slice of the inputs and
- * outputs; the resampled curve and fold-ready array live in `work`, reused
- * curve after curve in stream order.  Results are identical to separate
- * single-curve calls.  Nothing is allocated and nothing synchronises, so the
- * whole batch can be captured in one HIP graph and replayed.
- * t, f, sigma: device CSR observations (as cetra_resample, each curve sorted).
- * model[M]: device template (cetra_template_resample).  periods: device CSR.
- * work: device workspace of info.workspace_bytes.
+/* Device workspace of cetra_batch_search (host only): *bytes in all, of which
+ * the first *tables_bytes (nullable) must hold the plan's tables image. */
+int cetra_batch_workspace(const cetra_batch_plan *plan, size_t *bytes, size_t *tables_bytes);
+
+/* Copies the plan's tables image (tables_bytes) to host memory; the caller
+ * copies it once to the start of the device workspace before the first
+ * search with that workspace (searches only read it). */
+int cetra_batch_tables(const cetra_batch_plan *plan, void *host_dst, size_t bytes);
+
+/* A cancel flag for the plan's searches in pinned host memory allocated by
+ * this call on first use (hipHostMalloc) and freed by
+ * cetra_batch_plan_destroy: writing a non-zero value while a search runs
+ * stops it early (CETRA_BATCH_CANCELLED).  Searches poll it when their
+ * cancel argument is NULL. */
+int cetra_batch_cancel_flag(cetra_batch_plan *plan, int32_t **flag);
+
+/* Search every curve of the batch: two launches on `stream`, a small kernel
+ * that clears the counters (and the done flags, unless resuming), then one
+ * persistent grid whose workgroups pop work items from an atomic counter in
+ * queue order, wait for the items they depend on (acquire/release counters
+ * per curve and stage), and run the same per-item code as the single-curve
+ * calls, so every curve's records are bit-identical to cetra_resample +
+ * cetra_linear_search + cetra_periodic_search + cetra_best on that curve.
+ * Nothing is allocated and nothing synchronises, so the call can be
+ * captured in a HIP graph and replayed.
+ * t, f, sigma: device CSR observations (each curve's times finite and
+ *   ascending; a curve that is not gets done = -1, undefined records and
+ *   CETRA_BATCH_UNSORTED).  model[M]: device template.  periods: device CSR.
+ * jrange: NULL, or device int32 [total periods][2] (CSR like the periods):
+ *   each period's inclusive duration-index range, as cetra_periodic_search.
+ * cancel: NULL (then the plan's flag, if cetra_batch_cancel_flag made one), or
+ *   an int32 in device memory or pinned host memory, polled as items are
+ *   taken; non-zero stops the launch after the items in progress.
+ * flags: 0 or CETRA_BATCH_RESUME (curves with done[c] != 0 are skipped and
+ *   keep their earlier outputs).
+ * work: device workspace of cetra_batch_workspace bytes holding the tables.
  * Outputs: per-period lr, epoch, dur, depth, depth_var (device, CSR like the
  * periods), best[n_curves] (device; a curve without periods gets the null
- * record), status (device int32, set to 0 after the last curve). */
+ * record), done[n_curves] (device int32: 1 searched, -1 searched on unsorted
+ * input, 0 not reached), status (device int32, CETRA_BATCH_* bits). */
 int cetra_batch_search(const cetra_batch_plan *plan, void *stream, const double *t, const float *f,
-                       const float *sigma, const float *model, const double *periods, void *work,
-                       size_t work_bytes, float *lr, int32_t *epoch, int32_t *dur, float *depth, float *depth_var,
-                       cetra_best_record *best, int32_t *status);
+                       const float *sigma, const float *model, const double *periods,
+                       const int32_t *jrange, const int32_t *cancel, int32_t flags, void *work,
+                       size_t work_bytes, float *lr,
+                       int32_t *epoch, int32_t *dur, float *depth, float *depth_var,
+                       cetra_best_record *best, int32_t *done, int32_t *status);
 
 /* ------------------------------------------------------------------------
  * Period-window proposal network (an addition, not part of the paper).

@@ -59,12 +59,13 @@ def get_tuning() -> dict:
     t = Tuning()
     _abi.check(_abi.load().cetra_get_tuning(ctypes.byref(t)))
     return dict(fold_period_block=t.fold_period_block, fold_wgs_per_cu=t.fold_wgs_per_cu,
-                fold_units_per_wg=t.fold_units_per_wg, fold_variant=t.fold_variant)
+                fold_units_per_wg=t.fold_units_per_wg, fold_variant=t.fold_variant,
+                linear_windows=t.linear_windows)
 
 
 def set_tuning(fold_period_block: int = 8, fold_wgs_per_cu: int = 8, fold_units_per_wg: int = 4,
-               fold_variant: int = 2) -> None:
-    t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_variant)
+               fold_variant: int = 2, linear_windows: int = 4) -> None:
+    t = Tuning(fold_period_block, fold_wgs_per_cu, fold_units_per_wg, fold_variant, linear_windows)
     _abi.check(_abi.load().cetra_set_tuning(ctypes.byref(t)))
 
 
@@ -410,6 +411,7 @@ class BatchPlan:
         self.info = {name: getattr(info, name) for name, _ in _abi.BatchInfo._fields_}
         self.n_curves = n_curves
         self.period_offsets = np.asarray(period_offsets, dtype=np.int64)
+        self._cancel = None
 
     @property
     def handle(self):
@@ -420,6 +422,21 @@ class BatchPlan:
         _abi.check(_abi.load().cetra_batch_plan_order(self._h, o.ctypes.data_as(ctypes.c_void_p), self.n_curves))
         return o
 
+    def tables(self) -> bytes:
+        """The plan's tables image (copied to the start of a workspace)."""
+        buf = ctypes.create_string_buffer(max(self.info["tables_bytes"], 1))
+        _abi.check(_abi.load().cetra_batch_tables(self._h, buf, len(buf)))
+        return buf.raw[: self.info["tables_bytes"]]
+
+    def cancel_flag(self):
+        """The plan's pinned-host cancel flag (a ctypes int32 pointer):
+        setting ``flag[0] = 1`` while a search runs stops it early."""
+        if self._cancel is None:
+            p = ctypes.POINTER(ctypes.c_int32)()
+            _abi.check(_abi.load().cetra_batch_cancel_flag(self._h, ctypes.byref(p)))
+            self._cancel = p
+        return self._cancel
+
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
         if h:
@@ -429,7 +446,7 @@ class BatchPlan:
                 pass
 
 
-def batch_plan(grids, obs_offsets, period_offsets) -> BatchPlan:
+def batch_plan(grids, obs_offsets, period_offsets, period_block: int = 0, shuffle_seed: int = 0) -> BatchPlan:
     """Plan a batch from per-curve grid plans and CSR offsets (host arrays)."""
     n = len(grids)
     garr = (Grid * n)(*grids)
@@ -437,8 +454,8 @@ def batch_plan(grids, obs_offsets, period_offsets) -> BatchPlan:
     po = np.ascontiguousarray(period_offsets, dtype=np.int64)
     if oo.shape[0] != n + 1 or po.shape[0] != n + 1:
         raise ValueError("offsets must have n_curves + 1 entries")
-    d = _abi.BatchDesc(n, 0, ctypes.cast(garr, ctypes.c_void_p), oo.ctypes.data_as(ctypes.c_void_p),
-                       po.ctypes.data_as(ctypes.c_void_p), 0)
+    d = _abi.BatchDesc(n, int(period_block), ctypes.cast(garr, ctypes.c_void_p), oo.ctypes.data_as(ctypes.c_void_p),
+                       po.ctypes.data_as(ctypes.c_void_p), int(shuffle_seed), 0, 0)
     lib = _abi.load()
     h = ctypes.c_void_p()
     _abi.check(lib.cetra_batch_plan_create(ctypes.byref(d), ctypes.byref(h)))
@@ -448,16 +465,26 @@ def batch_plan(grids, obs_offsets, period_offsets) -> BatchPlan:
 
 
 def batch_workspace(plan: BatchPlan, device="cuda"):
-    """Device workspace of the plan's size."""
+    """Device workspace of the plan's size with the plan's tables copied to
+    its start (one host-to-device copy; searches only read them)."""
     torch = _torch()
-    return torch.empty(max(plan.info["workspace_bytes"], 1), dtype=torch.uint8, device=device)
+    work = torch.empty(max(plan.info["workspace_bytes"], 1), dtype=torch.uint8, device=device)
+    tbl = torch.frombuffer(bytearray(plan.tables()), dtype=torch.uint8)
+    work[: tbl.numel()].copy_(tbl)
+    return work
 
 
-def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, out=None, stream=None) -> dict:
-    """Search every curve of the batch on one stream.  Returns device
-    tensors: per-period lr, epoch, dur, depth, depth_var (CSR), best records
-    (uint8 [n_curves, sizeof(cetra_best_record)]) and status."""
+def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, out=None, cancel=None,
+                 resume: bool = False, jrange=None, stream=None) -> dict:
+    """Search every curve of the batch with one persistent launch.  Returns
+    device tensors: per-period lr, epoch, dur, depth, depth_var (CSR), best
+    records (uint8 [n_curves, sizeof(cetra_best_record)]), done [n_curves]
+    and status.  `cancel`: None (the plan's flag, if made), or an int32
+    device tensor; `resume` skips curves whose done flag is set in `out`;
+    `jrange` (int32 [total periods, 2], CSR like the periods) restricts each
+    period's durations."""
     torch = _torch()
+    jr = None if jrange is None else _dev(jrange, torch.int32)
     t = _dev(t, torch.float64)
     f = _dev(f, torch.float32)
     s = _dev(sigma, torch.float32)
@@ -473,11 +500,13 @@ def batch_search(plan: BatchPlan, t, f, sigma, model, periods, work=None, out=No
                    depth=torch.empty(max(K, 1), dtype=torch.float32, device=dev),
                    depth_var=torch.empty(max(K, 1), dtype=torch.float32, device=dev),
                    best=torch.empty((plan.n_curves, ctypes.sizeof(BestRecord)), dtype=torch.uint8, device=dev),
+                   done=torch.zeros(plan.n_curves, dtype=torch.int32, device=dev),
                    status=torch.empty(1, dtype=torch.int32, device=dev))
     _abi.check(_abi.load().cetra_batch_search(
-        plan.handle, _stream(stream), _ptr(t), _ptr(f), _ptr(s), _ptr(model), _ptr(periods), _ptr(work),
-        work.numel(), _ptr(out["lr"]), _ptr(out["epoch"]), _ptr(out["dur"]), _ptr(out["depth"]),
-        _ptr(out["depth_var"]), _ptr(out["best"]), _ptr(out["status"])))
+        plan.handle, _stream(stream), _ptr(t), _ptr(f), _ptr(s), _ptr(model), _ptr(periods), _ptr(jr), _ptr(cancel),
+        _abi.BATCH_RESUME if resume else 0, _ptr(work), work.numel(), _ptr(out["lr"]), _ptr(out["epoch"]),
+        _ptr(out["dur"]), _ptr(out["depth"]), _ptr(out["depth_var"]), _ptr(out["best"]), _ptr(out["done"]),
+        _ptr(out["status"])))
     return out
 
 

@@ -84,7 +84,8 @@ class Tuning(ctypes.Structure):
         ("fold_wgs_per_cu", ctypes.c_int32),
         ("fold_units_per_wg", ctypes.c_int32),
         ("fold_variant", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("linear_windows", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -92,11 +93,13 @@ class BatchDesc(ctypes.Structure):
     """Mirror of ``cetra_batch_desc``."""
     _fields_ = [
         ("n_curves", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("fold_period_block", ctypes.c_int32),
         ("grids", ctypes.c_void_p),
         ("obs_offsets", ctypes.c_void_p),
         ("period_offsets", ctypes.c_void_p),
-        ("reserved1", ctypes.c_int64),
+        ("shuffle_seed", ctypes.c_int64),
+        ("reserved0", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -104,10 +107,31 @@ class BatchInfo(ctypes.Structure):
     """Mirror of ``cetra_batch_info``."""
     _fields_ = [
         ("workspace_bytes", ctypes.c_size_t),
+        ("tables_bytes", ctypes.c_size_t),
         ("n_curves", ctypes.c_int64),
         ("total_periods", ctypes.c_int64),
         ("n_launches", ctypes.c_int64),
+        ("n_items", ctypes.c_int64),
+        ("n_slots", ctypes.c_int32),
+        ("period_block", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
+
+
+class ShapeClass(ctypes.Structure):
+    """Mirror of ``cetra_shape_class``."""
+    _fields_ = [
+        ("arch", ctypes.c_char * 32),
+        ("log2_t0", ctypes.c_int32),
+        ("n_dur", ctypes.c_int32),
+        ("log2_periods", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+BATCH_RESUME = 1
+BATCH_CANCELLED, BATCH_WAIT_LIMIT, BATCH_BAD_TABLES, BATCH_UNSORTED = 1, 2, 4, 8
 
 
 _P = ctypes.c_void_p
@@ -146,7 +170,16 @@ SIGNATURES = {
     "cetra_batch_plan_destroy": (ctypes.c_int, [_P]),
     "cetra_batch_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(BatchInfo)]),
     "cetra_batch_plan_order": (ctypes.c_int, [_P, _P, _i32]),
-    "cetra_batch_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _sz, _P, _P, _P, _P, _P, _P, _P]),
+    "cetra_shape_class_of": (ctypes.c_int, [ctypes.POINTER(Grid), _i64, ctypes.POINTER(ShapeClass)]),
+    "cetra_autotune_workspace": (ctypes.c_int, [ctypes.POINTER(Grid), _i64, ctypes.POINTER(_sz)]),
+    "cetra_autotune": (ctypes.c_int, [_P, ctypes.POINTER(ShapeClass), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _i64,
+                                      _P, _sz, ctypes.c_char_p, ctypes.POINTER(Tuning), ctypes.POINTER(_d),
+                                      ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
+    "cetra_batch_workspace": (ctypes.c_int, [_P, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
+    "cetra_batch_tables": (ctypes.c_int, [_P, _P, _sz]),
+    "cetra_batch_cancel_flag": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]),
+    "cetra_batch_search": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _i32, _P, _sz, _P, _P, _P, _P, _P,
+                                          _P, _P, _P]),
     "cetra_net_mfma_probe": (ctypes.c_int, [_P, _P, _P, _P]),
     "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),

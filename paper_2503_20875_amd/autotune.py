@@ -1,51 +1,49 @@
-"""Launch-tuning search for the periodic search.
+"""Binding of the library's launch autotuner (``cetra_autotune``).
 
-Times the fold (``cetra_periodic_search``) on the caller's own grid,
-fold-ready array and periods under each candidate tuning -- period block,
-resident workgroups per compute unit, units per workgroup and the fold
-variant (lane epochs 64 apart, or adjacent with 16-byte loads) -- and keeps
-the fastest with ``cetra_set_tuning``.
-Results do not depend on the tuning (the parity tests check that every
-variant returns identical records); only the time does.
+The timing loop, the candidate set and the JSON cache keyed by GPU
+architecture and shape class live in the library; this module marshals the
+arguments.  ``tune`` returns the tuning it applied (see
+``cetra_set_tuning``) with the measured or cached times.
 """
 
 from __future__ import annotations
 
-import itertools
+import ctypes
 
-from . import get_tuning, periodic_search, periodic_workspace, set_tuning
-
-DEFAULT_CANDIDATES = tuple(
-    (b, w, u, v) for b, w, u, v in itertools.product((4, 8, 16), (8,), (4, 16), (0, 2)))
+from . import _abi, _dev, _ptr, _stream
 
 
-def tune_fold(grid, fold, periods, candidates=DEFAULT_CANDIDATES, repeats: int = 2, apply: bool = True):
-    """Returns (best tuning dict, {candidate: mean ms}).  The first launch of
-    each candidate is a warm-up and is not timed."""
+def shape_class(grid, n_periods: int, arch: str = "") -> _abi.ShapeClass:
+    sc = _abi.ShapeClass()
+    _abi.check(_abi.load().cetra_shape_class_of(ctypes.byref(grid), int(n_periods), ctypes.byref(sc)))
+    sc.arch = arch.encode()
+    return sc
+
+
+def workspace_bytes(grid, n_periods: int) -> int:
+    n = ctypes.c_size_t()
+    _abi.check(_abi.load().cetra_autotune_workspace(ctypes.byref(grid), int(n_periods), ctypes.byref(n)))
+    return int(n.value)
+
+
+def tune(grid, flux, ivar, model, fold, periods, cache_path=None, arch: str = "", stream=None) -> dict:
+    """Apply the cached or measured fastest tuning for this search's shape
+    class.  `fold` [J, I, 2] is overwritten by linear searches (same values)
+    when candidates are timed.  Returns dict(tuning=..., fold_ms, linear_ms,
+    from_cache)."""
     import torch
-    periods = periods if isinstance(periods, torch.Tensor) else torch.as_tensor(periods, device="cuda")
+    periods = _dev(periods, torch.float64)
     K = int(periods.numel())
-    work = torch.empty(max(periodic_workspace(grid, K), 1), dtype=torch.uint8, device="cuda")
-    before = get_tuning()
-    out = None
-    times = {}
-    try:
-        for cand in candidates:
-            set_tuning(*cand)
-            out = periodic_search(grid, fold, periods, work=work, out=out)
-            ms = []
-            for _ in range(repeats):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                periodic_search(grid, fold, periods, work=work, out=out)
-                e1.record()
-                e1.synchronize()
-                ms.append(e0.elapsed_time(e1))
-            times[tuple(cand)] = sum(ms) / len(ms)
-    finally:
-        set_tuning(**before)
-    best = min(times, key=times.get)
-    cfg = dict(fold_period_block=best[0], fold_wgs_per_cu=best[1], fold_units_per_wg=best[2], fold_variant=best[3])
-    if apply:
-        set_tuning(**cfg)
-    return cfg, times
+    sc = shape_class(grid, K, arch)
+    work = None
+    if flux is not None:
+        work = torch.empty(max(workspace_bytes(grid, K), 1), dtype=torch.uint8, device=periods.device)
+    t = _abi.Tuning()
+    fms, lms, hit = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _abi.check(_abi.load().cetra_autotune(
+        _stream(stream) if flux is not None else None, ctypes.byref(sc), ctypes.byref(grid), _ptr(flux), _ptr(ivar),
+        _ptr(model), _ptr(fold), _ptr(periods), K, _ptr(work), 0 if work is None else work.numel(),
+        None if cache_path is None else str(cache_path).encode(), ctypes.byref(t), ctypes.byref(fms),
+        ctypes.byref(lms), ctypes.byref(hit)))
+    tuning = {name: getattr(t, name) for name, _ in _abi.Tuning._fields_ if name != "reserved"}
+    return dict(tuning=tuning, fold_ms=fms.value, linear_ms=lms.value, from_cache=bool(hit.value))

@@ -28,9 +28,10 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Launch tuning currently in force (process-wide).
 cetra_tuning current_tuning();
 
-// LDS bytes of the linear tile for duration j and its staged span.
+// LDS bytes of the linear tile (W windows per lane) for duration j, and its
+// staged span (0 = the span does not fit `cap` bytes and is read directly).
 constexpr int kMaxLinearLdsBytes = 64 * 1024;
-size_t linear_lds_bytes(const cetra_grid *g, int j, int32_t *span_cap);
+size_t linear_lds_bytes(const cetra_grid *g, int j, int W, size_t cap, int32_t *span_cap);
 
 // Validates the parts of a grid plan that kernels rely on.
 int check_grid(const cetra_grid *g);

@@ -46,7 +46,7 @@ int check_launch(const char *what) {
 }
 
 static std::mutex g_tuning_mu;
-static cetra_tuning g_tuning = {8, 8, 4, 2, {0, 0, 0, 0}};
+static cetra_tuning g_tuning = {8, 8, 4, 2, 4, {0, 0, 0}};
 
 cetra_tuning current_tuning() {
     std::lock_guard<std::mutex> lock(g_tuning_mu);
@@ -93,7 +93,7 @@ extern "C" int cetra_get_tuning(cetra_tuning *out) {
 
 extern "C" int cetra_set_tuning(const cetra_tuning *in) {
     clear_error();
-    cetra_tuning t = {8, 8, 4, 2, {0, 0, 0, 0}};
+    cetra_tuning t = {8, 8, 4, 2, 4, {0, 0, 0}};
     if (in) {
         CETRA_REQUIRE(in->fold_period_block == 4 || in->fold_period_block == 8 || in->fold_period_block == 16,
                       "set_tuning: fold_period_block must be 4, 8 or 16");
@@ -101,7 +101,11 @@ extern "C" int cetra_set_tuning(const cetra_tuning *in) {
         CETRA_REQUIRE(in->fold_units_per_wg >= 1 && in->fold_units_per_wg <= 64,
                       "set_tuning: fold_units_per_wg in [1, 64]");
         CETRA_REQUIRE(in->fold_variant == 0 || in->fold_variant == 2, "set_tuning: fold_variant must be 0 or 2");
+        CETRA_REQUIRE(in->linear_windows == 0 || in->linear_windows == 1 || in->linear_windows == 2 ||
+                          in->linear_windows == 4,
+                      "set_tuning: linear_windows must be 1, 2 or 4 (0: the default)");
         t = *in;
+        if (t.linear_windows == 0) t.linear_windows = 4;
     }
     std::lock_guard<std::mutex> lock(g_tuning_mu);
     g_tuning = t;

@@ -15,7 +15,6 @@ namespace cetra {
 namespace dev {
 
 constexpr int kThreads = 256;          // lanes per workgroup in every stage
-constexpr int kLinearChunk = 32;       // FP32 partial-sum length of the linear search
 constexpr int kFoldChunk = 32;         // FP32 partial-sum length of the fold
 constexpr int kFoldWaveEpochs = 128;   // epochs per wave in the fold
 constexpr int kFoldTileEpochs = kFoldWaveEpochs * (kThreads / 64);
@@ -73,11 +72,19 @@ struct Window {
     bool ok;
 };
 
-// Points covered by 256 consecutive windows of one duration, with a margin of
-// three for rounding: (255 dt + D)/c + 1 at most.
-__host__ __device__ inline double linear_span(double t0_step, double duration, double cadence) {
-    return ((double)(kThreads - 1) * t0_step + duration) / cadence + 4.0;
+// Points covered by the 256 W consecutive windows of one duration that a
+// workgroup computes (W windows per lane), with a margin of three for
+// rounding: ((256 W - 1) dt + D)/c + 1 at most.
+__host__ __device__ inline double linear_span(double t0_step, double duration, double cadence, int W) {
+    return ((double)(kThreads * W - 1) * t0_step + duration) / cadence + 4.0;
 }
+
+// Template table entries in LDS: (m_k, m_k^2) for k < M, then copies of the
+// last sample.  The nearest-sample index of a point inside its window never
+// exceeds M (the last point lies at most D after the window start), so the
+// copies stand in for the clamp to M - 1 of Sec. 2.1.2's table lookup.
+constexpr int kTemplatePad = 4;
+__host__ __device__ inline int template_table_entries(int n_model) { return n_model + kTemplatePad; }
 
 __host__ __device__ inline LinearParams linear_params(const cetra_grid &g, int j) {
     LinearParams p;
@@ -116,26 +123,130 @@ __device__ __forceinline__ Window make_window(const LinearParams &p, int64_t i) 
     return w;
 }
 
-// One workgroup computes reference times i0 .. i0+255 of one duration.  The
-// template and (if p.span_cap > 0) the light-curve span of the 256 windows,
-// as (w f, w) pairs, are staged in LDS.  Template indices advance in 32.32
-// fixed point; FP32 partial sums over 32 points are folded into FP64.  Must
-// be called by all lanes of the workgroup (it synchronises).
+// FP32 partial sums are taken over aligned blocks of 32 grid points
+// (n >> 5) and folded into FP64 block by block, so a window's sums do not
+// depend on how many windows a lane computes or where they start.
+constexpr int kLinearBlockShift = 5;
+
+// One point of one window: template entry of 32.32 phase ph (integer part
+// <= M), (w f, w) of the point.
+__device__ __forceinline__ void linear_point(const float2 *__restrict__ tab, uint64_t &ph, uint64_t step,
+                                             float2 d, float &sfm, float &smm) {
+    const float2 mt = tab[(uint32_t)(ph >> 32)];
+    sfm = fmaf(d.x, mt.x, sfm);
+    smm = fmaf(d.y, mt.y, smm);
+    ph += step;
+}
+
+template <bool kStaged>
+__device__ __forceinline__ float2 linear_data(const float2 *__restrict__ s_data, int64_t base,
+                                              const float *__restrict__ flux, const float *__restrict__ ivar,
+                                              int64_t n) {
+    if (kStaged) return s_data[n - base];
+    const float wq = ivar[n];
+    return make_float2(flux[n] * wq, wq);
+}
+
+// The W windows of one lane, all non-null: one pass over the union of their
+// points [lo[0], hi[W-1]] in aligned 32-point blocks.  Points inside every
+// window ([lo[W-1], hi[0]]) read (w f, w) once for all W windows; the few
+// points near the ends test each window's range.
+template <int W, bool kStaged>
+__device__ __forceinline__ void linear_lane(const float2 *__restrict__ tab, const float2 *__restrict__ s_data,
+                                            int64_t base, const float *__restrict__ flux,
+                                            const float *__restrict__ ivar, uint64_t step, const int64_t (&lo)[W],
+                                            const int64_t (&hi)[W], uint64_t (&ph)[W], double (&dfm)[W],
+                                            double (&dmm)[W]) {
+    constexpr int kUnroll = W >= 4 ? 2 : 4;  // keeps four windows per lane within 128 VGPRs
+    float sfm[W], smm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) sfm[w] = smm[w] = 0.0f;
+    const int64_t n0 = lo[0], n1 = hi[W - 1];
+    const int64_t na = lo[W - 1], nb = hi[0];  // [na, nb]: in every window (empty if na > nb)
+    for (int64_t b = n0 >> kLinearBlockShift; b <= (n1 >> kLinearBlockShift); ++b) {
+        const int64_t s0 = max(n0, b << kLinearBlockShift);
+        const int64_t s1 = min(n1, (b << kLinearBlockShift) + (1 << kLinearBlockShift) - 1);
+        const int64_t m0 = max(s0, na), m1 = min(s1, nb);
+        if (m0 <= m1) {
+            for (int64_t n = s0; n < m0; ++n) {  // ramp-in: windows still to start
+                const float2 d = linear_data<kStaged>(s_data, base, flux, ivar, n);
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (n >= lo[w] && n <= hi[w]) linear_point(tab, ph[w], step, d, sfm[w], smm[w]);
+            }
+#pragma unroll kUnroll
+            for (int64_t n = m0; n <= m1; ++n) {  // every window
+                const float2 d = linear_data<kStaged>(s_data, base, flux, ivar, n);
+#pragma unroll
+                for (int w = 0; w < W; ++w) linear_point(tab, ph[w], step, d, sfm[w], smm[w]);
+            }
+            for (int64_t n = m1 + 1; n <= s1; ++n) {  // ramp-out: windows already ended
+                const float2 d = linear_data<kStaged>(s_data, base, flux, ivar, n);
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (n >= lo[w] && n <= hi[w]) linear_point(tab, ph[w], step, d, sfm[w], smm[w]);
+            }
+        } else {
+            for (int64_t n = s0; n <= s1; ++n) {
+                const float2 d = linear_data<kStaged>(s_data, base, flux, ivar, n);
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (n >= lo[w] && n <= hi[w]) linear_point(tab, ph[w], step, d, sfm[w], smm[w]);
+            }
+        }
+        // fold the block into FP64 for the windows it intersects
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (b >= (lo[w] >> kLinearBlockShift) && b <= (hi[w] >> kLinearBlockShift)) {
+                dfm[w] += (double)sfm[w];
+                dmm[w] += (double)smm[w];
+            }
+            sfm[w] = smm[w] = 0.0f;
+        }
+    }
+}
+
+// One workgroup computes reference times i0 .. i0 + 256 W - 1 of one
+// duration, W adjacent ones per lane.  The template table (m, m^2) and, if
+// p.span_cap > 0, the light-curve span of the workgroup's windows as (w f, w)
+// pairs are staged in LDS.  Template indices advance in 32.32 fixed point;
+// per window S_fm = sum w f m and S_mm = sum w m^2 are FP32 over aligned
+// 32-point blocks folded into FP64.  A lane whose W windows are all non-null
+// walks their union once; a lane with a null window walks each non-null
+// window alone (same blocks, same sums).  Must be called by all lanes of the
+// workgroup (it synchronises).
+template <int W>
 __device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, const float *__restrict__ flux,
                                             const float *__restrict__ ivar, const float *__restrict__ model,
                                             float2 *__restrict__ fold_row, float *__restrict__ depth_row,
                                             float *__restrict__ var_row, float *__restrict__ lr_row, float *lds,
                                             int *s_bounds) {
-    float *s_model = lds;                                                        // [M]
-    float2 *s_data = reinterpret_cast<float2 *>(lds + ((p.n_model + 1) & ~1));  // [span_cap]
+    const int n_tab = template_table_entries(p.n_model);
+    float2 *s_tab = reinterpret_cast<float2 *>(lds);  // [n_tab]
+    float2 *s_data = s_tab + n_tab;                    // [span_cap]
     const bool staged = p.span_cap > 0;
 
-    const int64_t i = i0 + threadIdx.x;
-    const bool in_range = i < p.n_t0;
-    Window w = make_window(p, in_range ? i : 0);
-    w.ok = w.ok && in_range;
+    const int64_t ib = i0 + (int64_t)threadIdx.x * W;
+    int64_t lo[W], hi[W];
+    uint64_t ph[W];
+    bool ok[W];
+    bool all_ok = true, any_ok = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const bool in_range = ib + w < p.n_t0;
+        const Window win = make_window(p, in_range ? ib + w : 0);
+        ok[w] = win.ok && in_range;
+        lo[w] = win.lo;
+        hi[w] = win.hi;
+        ph[w] = win.phase;
+        all_ok = all_ok && ok[w];
+        any_ok = any_ok || ok[w];
+    }
 
-    for (int k = threadIdx.x; k < p.n_model; k += kThreads) s_model[k] = model[k];
+    for (int k = threadIdx.x; k < n_tab; k += kThreads) {
+        const float m = model[min(k, p.n_model - 1)];
+        s_tab[k] = make_float2(m, m * m);
+    }
     int64_t base = 0;
     if (staged) {
         if (threadIdx.x == 0) {
@@ -143,9 +254,12 @@ __device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, c
             s_bounds[1] = -1;
         }
         __syncthreads();
-        if (w.ok) {
-            atomicMin(&s_bounds[0], (int)w.lo);
-            atomicMax(&s_bounds[1], (int)w.hi);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (ok[w]) {
+                atomicMin(&s_bounds[0], (int)lo[w]);
+                atomicMax(&s_bounds[1], (int)hi[w]);
+            }
         }
         __syncthreads();
         base = s_bounds[0];
@@ -157,61 +271,45 @@ __device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, c
     }
     __syncthreads();
 
-    double dfm = 0.0, dmm = 0.0;
-    if (w.ok) {
-        // the window's points n = lo + q, q < L, in FP32 chunks of
-        // kLinearChunk points from lo; the staged and direct loops are
-        // separate so neither tests the source per point
-        const uint32_t last = (uint32_t)(p.n_model - 1);
-        uint64_t ph = w.phase;
-        const int32_t L = (int32_t)(w.hi - w.lo + 1);
-        if (staged) {
-            const float2 *d = s_data + (w.lo - base);
-            for (int32_t q0 = 0; q0 < L; q0 += kLinearChunk) {
-                const int32_t q1 = min(L, q0 + kLinearChunk);
-                float sfm = 0.0f, smm = 0.0f;
-#pragma unroll 4
-                for (int32_t q = q0; q < q1; ++q) {
-                    const float mk = s_model[min((uint32_t)(ph >> 32), last)];
-                    const float2 v = d[q];
-                    sfm = fmaf(v.x, mk, sfm);
-                    smm = fmaf(v.y * mk, mk, smm);
-                    ph += p.step_fx;
-                }
-                dfm += (double)sfm;
-                dmm += (double)smm;
-            }
-        } else {
-            const float *fx = flux + w.lo;
-            const float *iv = ivar + w.lo;
-            for (int32_t q0 = 0; q0 < L; q0 += kLinearChunk) {
-                const int32_t q1 = min(L, q0 + kLinearChunk);
-                float sfm = 0.0f, smm = 0.0f;
-#pragma unroll 4
-                for (int32_t q = q0; q < q1; ++q) {
-                    const float mk = s_model[min((uint32_t)(ph >> 32), last)];
-                    const float wq = iv[q];
-                    sfm = fmaf(fx[q] * wq, mk, sfm);
-                    smm = fmaf(wq * mk, mk, smm);
-                    ph += p.step_fx;
-                }
-                dfm += (double)sfm;
-                dmm += (double)smm;
-            }
+    double dfm[W], dmm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) dfm[w] = dmm[w] = 0.0;
+    if (all_ok) {
+        if (staged)
+            linear_lane<W, true>(s_tab, s_data, base, flux, ivar, p.step_fx, lo, hi, ph, dfm, dmm);
+        else
+            linear_lane<W, false>(s_tab, s_data, base, flux, ivar, p.step_fx, lo, hi, ph, dfm, dmm);
+    } else if (any_ok) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (!ok[w]) continue;
+            const int64_t l1[1] = {lo[w]}, h1[1] = {hi[w]};
+            uint64_t p1[1] = {ph[w]};
+            double f1[1] = {0.0}, m1[1] = {0.0};
+            if (staged)
+                linear_lane<1, true>(s_tab, s_data, base, flux, ivar, p.step_fx, l1, h1, p1, f1, m1);
+            else
+                linear_lane<1, false>(s_tab, s_data, base, flux, ivar, p.step_fx, l1, h1, p1, f1, m1);
+            dfm[w] = f1[0];
+            dmm[w] = m1[0];
         }
     }
     __syncthreads();  // LDS may be reused by the caller's next item
-    if (!in_range) return;
-    if (w.ok && dmm > 0.0) {
-        fold_row[i] = make_float2((float)dfm, (float)dmm);
-        if (depth_row) depth_row[i] = (float)(dfm / dmm);
-        if (var_row) var_row[i] = (float)(1.0 / dmm);
-        if (lr_row) lr_row[i] = (float)(0.5 * dfm * dfm / dmm);
-    } else {
-        fold_row[i] = make_float2(0.0f, 0.0f);
-        if (depth_row) depth_row[i] = __builtin_nanf("");
-        if (var_row) var_row[i] = __builtin_inff();
-        if (lr_row) lr_row[i] = 0.0f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const int64_t i = ib + w;
+        if (i >= p.n_t0) continue;
+        if (ok[w] && dmm[w] > 0.0) {
+            fold_row[i] = make_float2((float)dfm[w], (float)dmm[w]);
+            if (depth_row) depth_row[i] = (float)(dfm[w] / dmm[w]);
+            if (var_row) var_row[i] = (float)(1.0 / dmm[w]);
+            if (lr_row) lr_row[i] = (float)(0.5 * dfm[w] * dfm[w] / dmm[w]);
+        } else {
+            fold_row[i] = make_float2(0.0f, 0.0f);
+            if (depth_row) depth_row[i] = __builtin_nanf("");
+            if (var_row) var_row[i] = __builtin_inff();
+            if (lr_row) lr_row[i] = 0.0f;
+        }
     }
 }
 

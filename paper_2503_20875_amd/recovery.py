@@ -14,7 +14,7 @@ A period is recovered when the best period lies within 1% of the injected
 period, its half or its double.  Also reported: the Earth-analogue subset
 (depth 75-125 ppm, period 58-87 d).
 
-    python -m paper_2503_20875_amd.recovery --n 1000 --out recovery.json
+    python -m paper_2503_20875_amd.recovery --n 5000 --out recovery.json
 """
 
 from __future__ import annotations
@@ -91,65 +91,82 @@ def light_curve(signal, level: float, rng):
     return W.to_offset(y), np.full(signal.shape[0], sig, dtype=np.float32)
 
 
-def run(n: int, seed: int = 20250405, levels=NOISE_LEVELS, log=None) -> dict:
+def run(n: int, seed: int = 20250405, levels=NOISE_LEVELS, batch: int = 256, log=None) -> dict:
+    """n curves per noise level, searched `batch` curves at a time by the
+    persistent batched search (every curve on the same time grid, period
+    grid and Keplerian duration ranges).  The light curves are drawn in the
+    same order as a curve-by-curve run would draw them, and batched records
+    equal single-curve records, so the result does not depend on `batch`."""
     import torch
     import paper_2503_20875_amd as cm
     from synthlc import transit
     from synthlc import workloads as W
     t = times()
     dev = "cuda"
+    cadence = CADENCE_S / 86400.0
     durations, periods, jrange = search_grids(cm, t)
-    grid = cm.grid_plan(t[0], t[-1], CADENCE_S / 86400.0, durations, 0.0, 1024)
+    grid = cm.grid_plan(t[0], t[-1], cadence, durations, 0.0, 1024)
     model = cm.template_resample(torch.as_tensor(transit.dense_template(), device=dev), 1024)
-    t_d = torch.as_tensor(t, device=dev)
-    per_d = torch.as_tensor(periods, device=dev)
-    jr_d = torch.as_tensor(jrange, device=dev)
     K = len(periods)
-    work = torch.empty(cm.periodic_workspace(grid, K), dtype=torch.uint8, device=dev)
-    fold = per = None
     inj = draw(np.random.default_rng(seed), lambda P: cm.duration_limits(P, RHO[0], RHO[1], K_MAX, B_MAX), n)
     cache = {}
     signals = [W.inject(t, W.Injection(period=p, epoch=e, duration=d, depth=dp), cache) for p, e, d, dp in inj]
+    plans = {}
+
+    def plan_for(m):
+        if m not in plans:
+            pl = cm.batch_plan([grid] * m, np.arange(m + 1) * t.shape[0], np.arange(m + 1) * K)
+            plans[m] = (pl, cm.batch_workspace(pl),
+                        torch.as_tensor(np.tile(t, m), device=dev), torch.as_tensor(np.tile(periods, m), device=dev),
+                        torch.as_tensor(np.tile(jrange, (m, 1)), device=dev))
+        return plans[m]
+
     results = {}
     t_gpu = 0.0
     for level in levels:
         rng = np.random.default_rng(seed + int(level))
         hit = np.zeros(n, dtype=bool)
-        s_d = None
-        for r in range(n):
-            f, s = light_curve(signals[r], level, rng)
-            f_d = torch.as_tensor(f, device=dev)
-            if s_d is None:
-                s_d = torch.as_tensor(s, device=dev)
+        best_p = np.full(n, np.nan)
+        for b0 in range(0, n, batch):
+            rows = range(b0, min(n, b0 + batch))
+            fs, ss = zip(*(light_curve(signals[r], level, rng) for r in rows))
+            pl, work, t_d, p_d, jr_d = plan_for(len(rows))
+            f_d = torch.as_tensor(np.concatenate(fs), device=dev)
+            s_d = torch.as_tensor(np.concatenate(ss), device=dev)
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
-            flux, ivar, _ = cm.resample(grid, t_d, f_d, s_d, status=False)
-            fold = cm.linear_search(grid, flux, ivar, model, fold=fold)
-            per = cm.periodic_search(grid, fold, per_d, jrange=jr_d, work=work, out=per)
-            b = cm.best_record(cm.best(grid, per_d, per))
+            out = cm.batch_search(pl, t_d, f_d, s_d, model, p_d, work=work, jrange=jr_d)
+            torch.cuda.synchronize()
             t_gpu += time.perf_counter() - t0
-            hit[r] = b["k"] >= 0 and recovered(b["period"], inj[r, 0])
-            if log and (r + 1) % 250 == 0:
-                log(f"{level:g} ppm/h: {r + 1}/{n} searched, {hit[:r + 1].sum()} recovered")
+            if int(out["status"].item()) != 0 or not bool((out["done"] == 1).all()):
+                raise RuntimeError(f"batched search status {int(out['status'].item())}")
+            for r, b in zip(rows, cm.best_records(out["best"])):
+                best_p[r] = b["period"] if b["k"] >= 0 else np.nan
+                hit[r] = b["k"] >= 0 and recovered(b["period"], inj[r, 0])
+            if log:
+                log(f"{level:g} ppm/h: {rows[-1] + 1}/{n} searched, {hit[:rows[-1] + 1].sum()} recovered")
         earth = (inj[:, 3] >= 75e-6) & (inj[:, 3] <= 125e-6) & (inj[:, 0] >= 58.0) & (inj[:, 0] <= 87.0)
         results[f"{level:g}"] = {"n": n, "recovered": int(hit.sum()), "percent": 100.0 * hit.mean(),
                                  "earth_analogue_n": int(earth.sum()), "earth_analogue_recovered": int(hit[earth].sum())}
         if log:
             log(f"{level:g} ppm/h: {hit.sum()}/{n} recovered ({100.0 * hit.mean():.1f}%)")
     return {"n_per_level": n, "seed": seed, "n_periods": K, "n_durations": len(durations), "n_t0": int(grid.n_t0),
-            "n_points": int(t.shape[0]), "seconds_per_search": t_gpu / (n * len(levels)), "levels": results}
+            "n_points": int(t.shape[0]), "batch": batch, "seconds_per_search": t_gpu / (n * len(levels)),
+            "levels": results}
 
 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--n", type=int, default=1000, help="light curves per noise level")
     ap.add_argument("--seed", type=int, default=20250405)
+    ap.add_argument("--batch", type=int, default=256, help="curves per batched search")
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         print("recovery: no GPU", file=sys.stderr)
         return 2
-    res = run(a.n, a.seed, log=lambda m: print(f"[recovery] {m}", flush=True))
+    res = run(a.n, a.seed, batch=a.batch, log=lambda m: print(f"[recovery] {m}", flush=True))
     text = json.dumps(res)
     print(text, flush=True)
     if a.out:

@@ -304,6 +304,28 @@ def batched_survey(n_curves: int, seed: int = 20250328, n_min: int = 5000, n_max
     return curves
 
 
+def survey_subset(n_curves: int, seed: int = 20250328, n_min: int = 5000, n_max: int = 120000,
+                  n_dur: int = 16, d_min_h: float = 0.5, d_max_h: float = 10.0, alpha: float = 0.389,
+                  p_min: float = 0.5, p_max: float = 40.0):
+    """A length-stratified stand-in for a large batched survey: curve k has
+    the k-th of n_curves equal-probability strata of the uniform length
+    distribution over [n_min, n_max] points (its stratum's midpoint), and its
+    own generator seeded with seed + k; everything else as batched_survey."""
+    durs = log_durations(d_min_h, d_max_h, n_dur)
+    curves = []
+    for k in range(n_curves):
+        rng = np.random.default_rng(seed + k)
+        n = int(round(n_min + (k + 0.5) / n_curves * (n_max - n_min)))
+        t, f, s, injs = survey_curve(rng, n, durations=durs, p_range=(p_min, p_max))
+        span = t[-1] - t[0]
+        hi = min(p_max, span / 2.0)
+        periods = duty_cycle_periods(p_min, hi, span, durs[0], alpha) if hi > p_min else np.zeros(0)
+        curves.append(Workload(name=f"survey-{k}", t=t, f=f, sigma=s, cadence=120.0 / DAY_S,
+                               durations=durs, periods=periods, dense=transit.dense_template(),
+                               injections=injs, seed=seed + k))
+    return curves
+
+
 def long_baseline(seed: int = 20250329) -> Workload:
     """Earth analogue: one 730.5-d light curve at 25-s cadence (2 524 608
     points, PLATO-like), white noise 200 ppm per point, no gaps.  One transit

@@ -89,9 +89,13 @@ def test_calls_reject_bad_arguments_without_a_gpu(lib):
 def test_tuning_roundtrip_and_validation(lib):
     import paper_2503_20875_amd as cm
     cm.reset_tuning()
-    assert cm.get_tuning() == dict(fold_period_block=8, fold_wgs_per_cu=8, fold_units_per_wg=4, fold_variant=2)
-    cm.set_tuning(4, 6, 2, 0)
-    assert cm.get_tuning() == dict(fold_period_block=4, fold_wgs_per_cu=6, fold_units_per_wg=2, fold_variant=0)
+    assert cm.get_tuning() == dict(fold_period_block=8, fold_wgs_per_cu=8, fold_units_per_wg=4, fold_variant=2,
+                                   linear_windows=4)
+    cm.set_tuning(4, 6, 2, 0, 2)
+    assert cm.get_tuning() == dict(fold_period_block=4, fold_wgs_per_cu=6, fold_units_per_wg=2, fold_variant=0,
+                                   linear_windows=2)
+    with pytest.raises(cm.CetraError, match="linear_windows"):
+        cm.set_tuning(4, 6, 2, 0, 3)
     with pytest.raises(cm.CetraError, match="fold_period_block"):
         cm.set_tuning(5, 6, 2)
     with pytest.raises(cm.CetraError, match="fold_variant"):
@@ -99,42 +103,6 @@ def test_tuning_roundtrip_and_validation(lib):
     assert cm.get_tuning()["fold_period_block"] == 4  # unchanged after a rejected call
     cm.reset_tuning()
     assert cm.get_tuning()["fold_period_block"] == 8
-
-
-def _survey_batch(cm, n, seed, n_min, n_max):
-    from synthlc import workloads as W
-    curves = W.batched_survey(n, seed=seed, n_min=n_min, n_max=n_max)
-    grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations) for c in curves]
-    oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
-    po = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
-    return curves, grids, oo, po
-
-
-def test_batch_plan_host_only(lib):
-    """Planning is host-only: workspace sized for the largest curve, order by
-    descending fold cost, argument checks."""
-    import paper_2503_20875_amd as cm
-    curves, grids, oo, po = _survey_batch(cm, 6, 3, 2000, 9000)
-    plan = cm.batch_plan(grids, oo, po)
-    info = plan.info
-    assert info["n_curves"] == 6 and info["total_periods"] == po[-1]
-    J = grids[0].n_dur
-    need = max(8 * J * g.n_t0 for g in grids) + 2 * 4 * max(g.n for g in grids)
-    assert need <= info["workspace_bytes"] <= need + 4 * 256 + max(
-        cm.periodic_workspace(g, int(po[c + 1] - po[c])) for c, g in enumerate(grids))
-    cost = [(po[c + 1] - po[c]) * J * g.n_t0 for c, g in enumerate(grids)]
-    order = plan.order()
-    assert sorted(order.tolist()) == list(range(6))
-    assert all(cost[a] >= cost[b] for a, b in zip(order, order[1:]))
-    # launches: status + per curve resample, J linear, fold (3) if periods, best
-    assert info["n_launches"] == 1 + sum(1 + J + (3 if po[c + 1] > po[c] else 0) + 1 for c in range(6))
-    other = cm.grid_plan(curves[0].t[0], curves[0].t[-1], curves[0].cadence, curves[0].durations * 1.01)
-    with pytest.raises(cm.CetraError, match="durations"):
-        cm.batch_plan([other] + grids[1:], oo, po)
-    with pytest.raises(cm.CetraError, match="offsets"):
-        cm.batch_plan(grids, oo[::-1].copy(), po)
-    with pytest.raises(ValueError):
-        cm.batch_plan(grids, oo[:-1], po)
 
 
 def test_noalloc_limit_and_range_error_without_a_gpu(lib):

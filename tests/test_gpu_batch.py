@@ -1,6 +1,13 @@
-"""Batched search: results bit-identical to single-curve calls, on a batch
-with edge cases (a two-point curve, a curve with every point missing, a
-curve without periods), and on every replay of a captured HIP graph."""
+"""Batched search (one persistent work-queue launch): results bit-identical
+to single-curve calls on a batch with edge cases (a two-point curve, a curve
+with every point missing, a curve without periods), whatever the queue order
+or period block, on every replay of a captured HIP graph, and after a
+cancelled search is resumed; per-curve parity with the FP64 oracle; host-set
+failure conditions (a workspace without the plan's tables, unsorted times)
+end in status bits, never in a hang."""
+
+import threading
+import time
 
 import numpy as np
 import pytest
@@ -68,9 +75,14 @@ def batch_results(cm, plan, curves, packed, model, **kw):
     return o
 
 
+def records(o):
+    return {k: v.cpu().numpy() for k, v in o.items() if k not in ("best", "status", "done")}
+
+
 def compare(cm, o, single, per_off):
-    h = {k: v.cpu().numpy() for k, v in o.items() if k not in ("best", "status")}
+    h = records(o)
     bests = cm.best_records(o["best"])
+    assert np.all(o["done"].cpu().numpy() == 1)
     for ci, r in enumerate(single):
         sl = slice(per_off[ci], per_off[ci + 1])
         if not r:
@@ -97,6 +109,19 @@ def test_batch_equals_single_bitwise(cm, setup):
     curves, model, packed, single = setup
     grids, obs_off, per_off = packed[:3]
     plan = cm.batch_plan(grids, obs_off, per_off)
+    assert plan.info["n_launches"] == 2
+    o = batch_results(cm, plan, curves, packed, model)
+    assert int(o["status"].item()) == 0
+    compare(cm, o, single, per_off)
+
+
+@pytest.mark.parametrize("shuffle,block", [(12345, 0), (0, 4), (777, 4)])
+def test_batch_order_and_block_do_not_change_results(cm, setup, shuffle, block):
+    """A seeded queue order or another period block interleaves the curves'
+    items differently; every record stays bit-identical."""
+    curves, model, packed, single = setup
+    grids, obs_off, per_off = packed[:3]
+    plan = cm.batch_plan(grids, obs_off, per_off, period_block=block, shuffle_seed=shuffle)
     o = batch_results(cm, plan, curves, packed, model)
     assert int(o["status"].item()) == 0
     compare(cm, o, single, per_off)
@@ -146,7 +171,7 @@ def test_batch_matches_oracle(cm, ora, setup):
     plan = cm.batch_plan(grids, obs_off, per_off)
     o = batch_results(cm, plan, curves, packed, model)
     assert int(o["status"].item()) == 0
-    h = {k: v.cpu().numpy() for k, v in o.items() if k not in ("best", "status")}
+    h = records(o)
     bests = cm.best_records(o["best"])
     for ci, c in enumerate(curves):
         print(f"[oracle] curve {ci}: n_obs={c.n_obs} K={len(c.periods)}", flush=True)
@@ -168,3 +193,128 @@ def test_batch_matches_oracle(cm, ora, setup):
             assert gap <= TOL, (ci, b["k"], ref["best"], gap)
         assert b["lr"] == pytest.approx(ref["periodic"]["lr"][b["k"]], rel=TOL)
         print(f"[oracle] curve {ci}: {res}", flush=True)
+
+
+def test_batch_cancel_then_resume(cm):
+    """The plan's pinned-host cancel flag: set before the search, nothing
+    runs; set by a host thread while it runs, the launch stops early with
+    some curves done; a resumed search then completes the rest, and every
+    record equals the uncancelled search's."""
+    import torch
+    curves = W.batched_survey(24, seed=31, n_min=20000, n_max=60000)
+    model = cm.template_resample(torch.as_tensor(curves[0].dense, device="cuda"), curves[0].n_model)
+    grids, obs_off, per_off, t, f, s, p = pack(cm, curves)
+    td, fd, sd, pd = (torch.as_tensor(x, device="cuda") for x in (t, f, s, p))
+    plan = cm.batch_plan(grids, obs_off, per_off)
+    work = cm.batch_workspace(plan)
+    flag = plan.cancel_flag()
+    flag[0] = 0
+    print("[cancel] reference search", flush=True)
+    t0 = time.perf_counter()
+    ref = cm.batch_search(plan, td, fd, sd, model, pd, work=work)
+    torch.cuda.synchronize()
+    ms_ref = (time.perf_counter() - t0) * 1e3
+    assert int(ref["status"].item()) == 0 and np.all(ref["done"].cpu().numpy() == 1)
+    want = records(ref)
+    want_best = ref["best"].cpu().numpy()
+    # cancelled before it starts: no curve is searched
+    flag[0] = 1
+    print("[cancel] pre-set flag", flush=True)
+    o = cm.batch_search(plan, td, fd, sd, model, pd, work=work)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) & cm._abi.BATCH_CANCELLED
+    assert np.all(o["done"].cpu().numpy() == 0)
+    # cancelled by a host thread part-way through
+    flag[0] = 0
+    timer = threading.Timer(max(ms_ref, 20.0) * 0.4e-3, lambda: flag.__setitem__(0, 1))
+    print(f"[cancel] flag set after {max(ms_ref, 20.0) * 0.4:.0f} ms of a {ms_ref:.0f} ms search", flush=True)
+    timer.start()
+    o = cm.batch_search(plan, td, fd, sd, model, pd, work=work)
+    torch.cuda.synchronize()
+    timer.join()
+    st, done = int(o["status"].item()), o["done"].cpu().numpy()
+    print(f"[cancel] status={st} done={int((done == 1).sum())}/{len(done)}", flush=True)
+    assert st in (0, cm._abi.BATCH_CANCELLED)
+    assert set(np.unique(done)) <= {0, 1}
+    # resume: the curves not done are searched, the done ones keep their records
+    flag[0] = 0
+    print("[cancel] resume", flush=True)
+    cm.batch_search(plan, td, fd, sd, model, pd, work=work, out=o, resume=True)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0 and np.all(o["done"].cpu().numpy() == 1)
+    got = records(o)
+    for k in want:
+        assert np.array_equal(got[k], want[k], equal_nan=True), k
+    assert np.array_equal(o["best"].cpu().numpy(), want_best)
+
+
+def test_batch_workspace_without_tables_sets_status(cm, setup):
+    """A workspace that does not hold the plan's tables: the persistent
+    kernel checks the tables' tag and plan id first and returns at once."""
+    import torch
+    curves, model, packed, _ = setup
+    grids, obs_off, per_off, t, f, s, p = packed
+    plan = cm.batch_plan(grids, obs_off, per_off)
+    other = cm.batch_plan(grids, obs_off, per_off)
+    work = cm.batch_workspace(other)  # tables of another plan
+    print("[tables] foreign tables", flush=True)
+    o = cm.batch_search(plan, t, f, s, model, p, work=work)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == cm._abi.BATCH_BAD_TABLES
+    assert np.all(o["done"].cpu().numpy() == 0)
+
+
+def test_batch_flags_unsorted_curve(cm, setup):
+    """A curve whose times are out of order is reported (done = -1 and the
+    status bit); the other curves are unaffected."""
+    import torch
+    curves, model, packed, single = setup
+    grids, obs_off, per_off, t, f, s, p = packed
+    t = t.copy()
+    a, b = int(obs_off[5]), int(obs_off[6])
+    t[a + 10], t[a + 11] = t[a + 11], t[a + 10]
+    plan = cm.batch_plan(grids, obs_off, per_off)
+    print("[unsorted] curve 5", flush=True)
+    o = cm.batch_search(plan, t, f, s, model, p)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == cm._abi.BATCH_UNSORTED
+    done = o["done"].cpu().numpy()
+    assert done[5] == -1 and np.all(np.delete(done, 5) == 1)
+    h = records(o)
+    for ci, r in enumerate(single):
+        if ci == 5 or not r:
+            continue
+        sl = slice(per_off[ci], per_off[ci + 1])
+        for k in ("lr", "epoch", "dur", "depth", "depth_var"):
+            assert np.array_equal(h[k][sl], r[k], equal_nan=True), (ci, k)
+
+
+def test_batch_duration_ranges_match_single_calls(cm, setup):
+    """Per-period duration ranges (the Keplerian filter's output form) in
+    the batch give the records of single-curve searches with the same
+    ranges."""
+    import torch
+    curves, model, packed, _ = setup
+    grids, obs_off, per_off, t, f, s, p = packed
+    J = grids[0].n_dur
+    rng = np.random.default_rng(17)
+    K = int(per_off[-1])
+    lo = rng.integers(0, J // 2, K)
+    jr = np.stack([lo, np.minimum(J - 1, lo + rng.integers(0, J, K))], axis=1).astype(np.int32)
+    plan = cm.batch_plan(grids, obs_off, per_off)
+    print("[jrange] batch", flush=True)
+    o = cm.batch_search(plan, t, f, s, model, p, jrange=jr)
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    h = records(o)
+    for ci, c in enumerate(curves):
+        if not len(c.periods):
+            continue
+        sl = slice(per_off[ci], per_off[ci + 1])
+        g = grids[ci]
+        flux, ivar, _ = cm.resample(g, c.t, c.f, c.sigma)
+        fold = cm.linear_search(g, flux, ivar, model)
+        ref = cm.periodic_search(g, fold, c.periods, jrange=jr[sl])
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            assert np.array_equal(h[k][sl], v.cpu().numpy(), equal_nan=True), (ci, k)

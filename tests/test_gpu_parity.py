@@ -116,11 +116,40 @@ def test_linear_long_windows_read_from_memory(cm, ora):
     wl = W.small_random(3, n_obs=30000, cadence_s=20.0, n_dur=2, n_per=6, p_range=(3.0, 5.0), dur_h=(2.0, 38.0))
     r, o, g = run_both(cm, ora, wl)
     og = o["grid"]
-    span_pairs = (255 * og.t0_step + wl.durations[-1]) / og.cadence
-    assert span_pairs * 8 + 4 * wl.n_model > 64 * 1024  # the longest duration takes the direct path
-    assert ((255 * og.t0_step + wl.durations[0]) / og.cadence) * 8 + 4 * wl.n_model < 64 * 1024  # staged
+    Wl = cm.get_tuning()["linear_windows"]
+    table = 8 * (wl.n_model + 4)
+    span_pairs = ((256 * Wl - 1) * og.t0_step + wl.durations[-1]) / og.cadence + 4
+    assert span_pairs * 8 + table > 64 * 1024  # the longest duration takes the direct path
+    assert (((256 * Wl - 1) * og.t0_step + wl.durations[0]) / og.cadence + 4) * 8 + table < 64 * 1024  # staged
     print("linear", check_linear(*lin_arrays(r), o["linear"]))
     print("periodic", check_periodic(g, o["periodic"], fold_at(ora, o), wl.periods))
+
+
+@pytest.mark.parametrize("name", ["tiny", "long_windows"])
+def test_linear_windows_per_lane_identical(cm, name):
+    """One, two or four windows per lane (tiles of 256 to 1 024 reference
+    times) give the same fold-ready pairs and public arrays, bit for bit:
+    FP32 partial sums cover aligned 32-point blocks whatever the tile, and
+    lanes with a null window walk each window alone in the same blocks."""
+    import torch
+    wl = W.tiny_single() if name == "tiny" else W.small_random(
+        3, n_obs=30000, cadence_s=20.0, n_dur=2, n_per=6, p_range=(3.0, 5.0), dur_h=(2.0, 38.0))
+    grid = cm.grid_plan(wl.t[0], wl.t[-1], wl.cadence, wl.durations, 0.0, wl.n_model)
+    model = cm.template_resample(torch.as_tensor(wl.dense, device="cuda"), wl.n_model)
+    flux, ivar, _ = cm.resample(grid, wl.t, wl.f, wl.sigma)
+    out = {}
+    try:
+        for Wl in (4, 2, 1):
+            print(f"[case] {name} linear_windows={Wl}", flush=True)
+            cm.set_tuning(linear_windows=Wl)
+            res = cm.linear_search(grid, flux, ivar, model, public=True)
+            torch.cuda.synchronize()
+            out[Wl] = [x.cpu().numpy() for x in res]
+    finally:
+        cm.reset_tuning()
+    for Wl in (2, 1):
+        for a, b in zip(out[Wl], out[4]):
+            assert np.array_equal(a, b, equal_nan=True), Wl
 
 
 def test_tiny_periodic_all_periods(ora, tiny_pair, tiny_wl):

@@ -65,3 +65,16 @@ def test_recovery_curves_match_oracle(cm, ora, row, level):
     assert b["lr"] == pytest.approx(alt[0], rel=TOL)
     assert alt[0] >= per["lr"].max() * (1 - TOL)
     print(f"recovered={R.recovered(b['period'], inj[0])} best={b['period']:.4f} snr={b['snr']:.2f}")
+    # recovery.run searches through the batched path: the same records
+    grid = cm.grid_plan(t[0], t[-1], R.CADENCE_S / 86400.0, durs, 0.0, 1024)
+    plan = cm.batch_plan([grid, grid], [0, len(t), 2 * len(t)], [0, K, 2 * K])
+    m = cm.template_resample(torch.as_tensor(dense, device="cuda"), 1024)
+    o = cm.batch_search(plan, np.tile(t, 2), np.tile(f, 2), np.tile(s, 2), m, np.tile(periods, 2),
+                        jrange=np.tile(jr, (2, 1)))
+    torch.cuda.synchronize()
+    assert int(o["status"].item()) == 0
+    for k in ("lr", "epoch", "dur", "depth", "depth_var"):
+        h = o[k].cpu().numpy()
+        assert np.array_equal(h[:K], g[k], equal_nan=True) and np.array_equal(h[K:], g[k], equal_nan=True), k
+    bb = cm.best_records(o["best"])
+    assert bb[0]["k"] == b["k"] == bb[1]["k"]
