@@ -102,7 +102,7 @@ def algorithmic_work(wl, grid):
                 linear_flop=4 * lin_points)
 
 
-def batched_block(n_curves: int = 64, seed: int = 20250328) -> dict:
+def batched_block(n_curves: int = 64, seed: int = 20250328, n_min: int = 5000, n_max: int = 120000) -> dict:
     """Batched survey: a length-stratified subset of the survey workload
     (curve k has the midpoint length of the k-th of n_curves strata of
     5 000-120 000 points at 2-min cadence; 16 durations 0.5-10 h; per-curve
@@ -114,7 +114,7 @@ def batched_block(n_curves: int = 64, seed: int = 20250328) -> dict:
     import torch
     import paper_2503_20875_amd as cm
     from synthlc import workloads as W
-    curves = W.survey_subset(n_curves, seed=seed)
+    curves = W.survey_subset(n_curves, seed=seed, n_min=n_min, n_max=n_max)
     log(f"batched survey: {n_curves} curves generated")
     grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations, 0.0, c.n_model) for c in curves]
     oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
@@ -180,7 +180,7 @@ def batched_block(n_curves: int = 64, seed: int = 20250328) -> dict:
     fold_bytes = float(sum(algorithmic_work(c, gr)["fold_bytes"] for c, gr in zip(curves, grids)))
     ms_eager, ms_graph, ms_single = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]), e[4].elapsed_time(e[5])
     sec = min(ms_eager, ms_graph) / 1e3
-    return {"workload": (f"{n_curves} length-stratified survey curves (5 000-120 000 points at 2 min), "
+    return {"workload": (f"{n_curves} length-stratified survey curves ({n_min}-{n_max} points at 2 min), "
                          f"{int(oo[-1])} observations, {int(po[-1])} trial periods in all"),
             "n_launches": plan.info["n_launches"], "n_items": plan.info["n_items"],
             "ms_eager": ms_eager, "ms_graph_replay": ms_graph, "ms_single_curve_calls": ms_single,
@@ -807,6 +807,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--batch-curves", type=int, default=64,
                     help="survey curves of the batched-search measurement (0: skip)")
+    ap.add_argument("--batch-points", default="5000,120000",
+                    help="length range (points) of the batched-search curves")
     ap.add_argument("--fold-tuning", default="",
                     help="period block, workgroups per CU, units per workgroup, variant (e.g. 4,8,4,0); "
                          "default: the library's")
@@ -837,8 +839,10 @@ def main():
     if args.mode == "net":
         print(json.dumps({"mode": "net", **net_block()}), flush=True)
         return
+    batch_pts = tuple(int(v) for v in args.batch_points.split(","))
     if args.mode == "batch":
-        print(json.dumps({"mode": "batch", **batched_block(args.batch_curves)}), flush=True)
+        print(json.dumps({"mode": "batch", **batched_block(args.batch_curves, n_min=batch_pts[0],
+                                                           n_max=batch_pts[1])}), flush=True)
         return
     if args.fold_tuning:
         cm.set_tuning(*(int(v) for v in args.fold_tuning.split(",")))
@@ -987,7 +991,9 @@ def main():
     out["roofline_net"] = net_block()
     if args.batch_curves > 0:
         log(f"batched survey ({args.batch_curves} curves)")
-        out["batched"] = batched_block(args.batch_curves)
+        out["batched"] = batched_block(args.batch_curves, n_min=batch_pts[0], n_max=batch_pts[1])
+        log("batched short curves (1 024 curves of 5 000-10 000 points)")
+        out["batched_short"] = batched_block(1024, seed=30250000, n_min=5000, n_max=10000)
     if args.learned_curves > 0:
         log(f"learned proposal ({args.learned_curves} held-out curves)")
         out["learned"] = learned_block(args.learned_curves)

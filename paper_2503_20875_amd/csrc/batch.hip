@@ -190,15 +190,26 @@ struct ItemRef {
     int64_t idx;
 };
 
-__device__ ItemRef locate(const Header *h, const Segment *segs, int64_t item) {
-    int64_t lo = 0, hi = h->n_segments - 1;  // last segment whose first <= item
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (segs[mid].first <= item)
-            lo = mid;
-        else
-            hi = mid - 1;
+// Segment of an item: the last segment whose first item is <= item.  A
+// workgroup pops items in increasing order, so the search starts from the
+// segment of its previous item (`hint`, updated): usually the same one or a
+// few later, which saves a chain of dependent loads per item.
+__device__ ItemRef locate(const Header *h, const Segment *segs, int64_t item, int64_t &hint) {
+    const int64_t last = h->n_segments - 1;
+    int64_t lo = hint;
+    if (lo < last && segs[lo + 1].first <= item) {
+        int64_t hi = last;
+        ++lo;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (segs[mid].first <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
     }
+    lo = uniform64(lo);
+    hint = lo;
     ItemRef r;
     r.curve = segs[lo].curve;
     r.stage = segs[lo].stage;
@@ -360,6 +371,13 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
     // loop that the wave's other lanes keep re-entering without lane 0: the
     // wave would then never leave it.)
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // the dependency this workgroup last saw complete: counters only grow and
+    // the acquire that saw it already made its data visible here, so later
+    // items with the same dependency skip the wait (and its cache
+    // invalidation, which would otherwise evict the fold's working set from
+    // L2 on every short item)
+    const uint32_t *seen_counter = nullptr;
+    int64_t seg_hint = 0;
     for (;;) {
         if (wave == 0) {
             long long it = -1;
@@ -374,7 +392,7 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
         __syncthreads();
         const int64_t item = uniform64(s_item);
         if (item < 0) break;
-        const ItemRef ir = locate(h, segs, item);
+        const ItemRef ir = locate(h, segs, item, seg_hint);
         const int32_t c = __builtin_amdgcn_readfirstlane(ir.curve);
         const int32_t stage = __builtin_amdgcn_readfirstlane(ir.stage);
         const int64_t idx = uniform64(ir.idx);
@@ -383,14 +401,21 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
         // RES the decode of the curve that used its slot before
         if (wave == 0) {
             const int32_t prev_curve = __builtin_amdgcn_readfirstlane(cd.prev_in_slot);
-            bool ok = true;
+            const uint32_t *counter = nullptr;
+            uint32_t need = 0;
             if (stage == kRes) {
-                if (prev_curve >= 0)
-                    ok = wait_for(a, &a.stage_done[(int64_t)prev_curve * kStages + kEpi],
-                                  __builtin_amdgcn_readfirstlane((uint32_t)curves[prev_curve].n_items[kEpi]));
+                if (prev_curve >= 0) {
+                    counter = &a.stage_done[(int64_t)prev_curve * kStages + kEpi];
+                    need = __builtin_amdgcn_readfirstlane((uint32_t)curves[prev_curve].n_items[kEpi]);
+                }
             } else {
-                ok = wait_for(a, &a.stage_done[(int64_t)c * kStages + stage - 1],
-                              __builtin_amdgcn_readfirstlane((uint32_t)cd.n_items[stage - 1]));
+                counter = &a.stage_done[(int64_t)c * kStages + stage - 1];
+                need = __builtin_amdgcn_readfirstlane((uint32_t)cd.n_items[stage - 1]);
+            }
+            bool ok = true;
+            if (counter && counter != seen_counter) {
+                ok = wait_for(a, counter, need);
+                if (ok) seen_counter = counter;
             }
             if (lane_zero()) s_go = ok ? 1 : 0;
         }
@@ -402,9 +427,14 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
         __syncthreads();  // every lane's stores of the item are complete
         if (wave == 0) {
             uint32_t prev = 0;
-            if (lane_zero())
-                prev = __hip_atomic_fetch_add(&a.stage_done[(int64_t)c * kStages + stage], 1u, __ATOMIC_ACQ_REL,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+            // release: the item's stores (and atomics) before the count; the
+            // decode stage also acquires, as its last item reads the others'
+            // records
+            if (lane_zero()) {
+                uint32_t *ctr = &a.stage_done[(int64_t)c * kStages + stage];
+                prev = stage == kEpi ? __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT)
+                                     : __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
             prev = __builtin_amdgcn_readfirstlane(prev);
             const uint32_t n_epi = __builtin_amdgcn_readfirstlane((uint32_t)cd.n_items[kEpi]);
             if (stage == kEpi && !skip && prev + 1 == n_epi && lane_zero()) finish_curve(a, cd, grids[c], c);

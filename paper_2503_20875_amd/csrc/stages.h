@@ -79,12 +79,13 @@ __host__ __device__ inline double linear_span(double t0_step, double duration, d
     return ((double)(kThreads * W - 1) * t0_step + duration) / cadence + 4.0;
 }
 
-// Template table entries in LDS: (m_k, m_k^2) for k < M, then copies of the
-// last sample.  The nearest-sample index of a point inside its window never
+// Template table entries in LDS: m_k for k < M, then copies of the last
+// sample (rounded up to an even count, so the data pairs after it stay 8-byte
+// aligned).  The nearest-sample index of a point inside its window never
 // exceeds M (the last point lies at most D after the window start), so the
 // copies stand in for the clamp to M - 1 of Sec. 2.1.2's table lookup.
 constexpr int kTemplatePad = 4;
-__host__ __device__ inline int template_table_entries(int n_model) { return n_model + kTemplatePad; }
+__host__ __device__ inline int template_table_entries(int n_model) { return (n_model + kTemplatePad + 1) & ~1; }
 
 __host__ __device__ inline LinearParams linear_params(const cetra_grid &g, int j) {
     LinearParams p;
@@ -128,13 +129,13 @@ __device__ __forceinline__ Window make_window(const LinearParams &p, int64_t i) 
 // depend on how many windows a lane computes or where they start.
 constexpr int kLinearBlockShift = 5;
 
-// One point of one window: template entry of 32.32 phase ph (integer part
+// One point of one window: template sample of 32.32 phase ph (integer part
 // <= M), (w f, w) of the point.
-__device__ __forceinline__ void linear_point(const float2 *__restrict__ tab, uint64_t &ph, uint64_t step,
-                                             float2 d, float &sfm, float &smm) {
-    const float2 mt = tab[(uint32_t)(ph >> 32)];
-    sfm = fmaf(d.x, mt.x, sfm);
-    smm = fmaf(d.y, mt.y, smm);
+__device__ __forceinline__ void linear_point(const float *__restrict__ tab, uint64_t &ph, uint64_t step, float2 d,
+                                             float &sfm, float &smm) {
+    const float mk = tab[(uint32_t)(ph >> 32)];
+    sfm = fmaf(d.x, mk, sfm);
+    smm = fmaf(d.y * mk, mk, smm);
     ph += step;
 }
 
@@ -152,7 +153,7 @@ __device__ __forceinline__ float2 linear_data(const float2 *__restrict__ s_data,
 // window ([lo[W-1], hi[0]]) read (w f, w) once for all W windows; the few
 // points near the ends test each window's range.
 template <int W, bool kStaged>
-__device__ __forceinline__ void linear_lane(const float2 *__restrict__ tab, const float2 *__restrict__ s_data,
+__device__ __forceinline__ void linear_lane(const float *__restrict__ tab, const float2 *__restrict__ s_data,
                                             int64_t base, const float *__restrict__ flux,
                                             const float *__restrict__ ivar, uint64_t step, const int64_t (&lo)[W],
                                             const int64_t (&hi)[W], uint64_t (&ph)[W], double (&dfm)[W],
@@ -207,7 +208,7 @@ __device__ __forceinline__ void linear_lane(const float2 *__restrict__ tab, cons
 }
 
 // One workgroup computes reference times i0 .. i0 + 256 W - 1 of one
-// duration, W adjacent ones per lane.  The template table (m, m^2) and, if
+// duration, W adjacent ones per lane.  The template table and, if
 // p.span_cap > 0, the light-curve span of the workgroup's windows as (w f, w)
 // pairs are staged in LDS.  Template indices advance in 32.32 fixed point;
 // per window S_fm = sum w f m and S_mm = sum w m^2 are FP32 over aligned
@@ -222,8 +223,8 @@ __device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, c
                                             float *__restrict__ var_row, float *__restrict__ lr_row, float *lds,
                                             int *s_bounds) {
     const int n_tab = template_table_entries(p.n_model);
-    float2 *s_tab = reinterpret_cast<float2 *>(lds);  // [n_tab]
-    float2 *s_data = s_tab + n_tab;                    // [span_cap]
+    float *s_tab = lds;                                              // [n_tab]
+    float2 *s_data = reinterpret_cast<float2 *>(lds + n_tab);        // [span_cap]
     const bool staged = p.span_cap > 0;
 
     const int64_t ib = i0 + (int64_t)threadIdx.x * W;
@@ -243,10 +244,7 @@ __device__ __forceinline__ void linear_tile(const LinearParams &p, int64_t i0, c
         any_ok = any_ok || ok[w];
     }
 
-    for (int k = threadIdx.x; k < n_tab; k += kThreads) {
-        const float m = model[min(k, p.n_model - 1)];
-        s_tab[k] = make_float2(m, m * m);
-    }
+    for (int k = threadIdx.x; k < n_tab; k += kThreads) s_tab[k] = model[min(k, p.n_model - 1)];
     int64_t base = 0;
     if (staged) {
         if (threadIdx.x == 0) {

@@ -36,7 +36,8 @@ def summary(r: dict) -> dict:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     here = os.path.dirname(os.path.abspath(__file__))
-    ap.add_argument("--weights", default=os.path.join(here, "weights", "proposal.npz"))
+    ap.add_argument("--weights", default=os.path.join(here, "weights", "proposal.npz"),
+                    help="weights file, or a comma-separated list evaluated on the same curves")
     ap.add_argument("--n", type=int, default=1000, help="held-out curves (half calibration, half test)")
     ap.add_argument("--target", type=float, default=0.99)
     ap.add_argument("--seed", type=int, default=20250410)
@@ -48,29 +49,41 @@ def main(argv=None) -> int:
         return 2
     from .learned import evaluate, fallback_threshold, k_for_recall, load_weights
     from .train_proposal import curve_source, make_pipeline
-    net, meta = load_weights(a.weights)
-    workload = meta.get("workload", "learned")
+    paths = [w for w in a.weights.split(",") if w]
+    nets = [load_weights(w) for w in paths]
+    workload = nets[0][1].get("workload", "learned")
     pipe = make_pipeline(workload=workload)
     n_cal = a.n // 2
     draw_cal, draw_test = curve_source(workload, a.seed), curve_source(workload, a.seed + 1)
-    cal = evaluate(pipe, net, [draw_cal() for _ in range(n_cal)], log=log)
-    k_target = k_for_recall(cal["ranks"], a.target, pipe.windows.n)
-    tau = fallback_threshold(cal["rows"], a.target)
-    log(f"calibration: {cal['n_detections']} detections, recall at K=64 {cal['recall']:.3f}; "
-        f"K for target {k_target}, fallback threshold {tau:.3f}")
+    cal_curves = [draw_cal() for _ in range(n_cal)]
     test_curves = [draw_test() for _ in range(a.n - n_cal)]
-    out = {"n_curves": a.n, "seed": a.seed, "workload": workload, "target_recall": a.target,
-           "calibration": {"k64": summary(cal), "k_for_target": k_target,
-                           "fallback_snr_for_target": tau if np.isfinite(tau) else None},
-           "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "batch", "lr", "seed")}}
-    test_k64 = evaluate(pipe, net, test_curves, top_k=64, log=log)
-    out["test_k64"] = summary(test_k64)
-    out["test_rank_recall"] = {K: float(np.mean(np.asarray(test_k64["ranks"]) < K))
-                               for K in (16, 32, 64, 96, 128, 192, 256, 384)}
-    plain = test_k64["plain"]  # the full searches of the test curves, run once
-    out["test_k_target"] = summary(evaluate(pipe, net, test_curves, top_k=k_target, log=log, plain=plain))
-    out["test_fallback"] = summary(evaluate(pipe, net, test_curves, top_k=64,
-                                            fallback_snr=tau if np.isfinite(tau) else None, log=log, plain=plain))
+    results = {}
+    plain_cal = plain_test = None  # the full searches run once, for the first network
+    for path, (net, meta) in zip(paths, nets):
+        log(f"network {path}")
+        cal = evaluate(pipe, net, cal_curves, log=log, plain=plain_cal)
+        plain_cal = cal["plain"]
+        k_target = k_for_recall(cal["ranks"], a.target, pipe.windows.n)
+        tau = fallback_threshold(cal["rows"], a.target)
+        log(f"calibration: {cal['n_detections']} detections, recall at K=64 {cal['recall']:.3f}; "
+            f"K for target {k_target}, fallback threshold {tau:.3f}")
+        out = {"calibration": {"k64": summary(cal), "k_for_target": k_target,
+                               "fallback_snr_for_target": tau if np.isfinite(tau) else None,
+                               "rank_recall": {K: float(np.mean(np.asarray(cal["ranks"]) < K))
+                                               for K in (16, 32, 64, 96, 128, 192, 256, 384)}},
+               "trained_on": {k: meta.get(k) for k in ("n_train", "epochs", "batch", "lr", "seed")}}
+        test_k64 = evaluate(pipe, net, test_curves, top_k=64, log=log, plain=plain_test)
+        plain_test = test_k64["plain"]
+        out["test_k64"] = summary(test_k64)
+        out["test_rank_recall"] = {K: float(np.mean(np.asarray(test_k64["ranks"]) < K))
+                                   for K in (16, 32, 64, 96, 128, 192, 256, 384)}
+        out["test_k_target"] = summary(evaluate(pipe, net, test_curves, top_k=k_target, log=log, plain=plain_test))
+        out["test_k96"] = summary(evaluate(pipe, net, test_curves, top_k=96, log=log, plain=plain_test))
+        out["test_fallback"] = summary(evaluate(pipe, net, test_curves, top_k=64,
+                                                fallback_snr=tau if np.isfinite(tau) else None, log=log,
+                                                plain=plain_test))
+        results[os.path.basename(path)] = out
+    out = {"n_curves": a.n, "seed": a.seed, "workload": workload, "target_recall": a.target, "networks": results}
     text = json.dumps(out)
     print(text, flush=True)
     if a.out:

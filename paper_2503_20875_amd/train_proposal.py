@@ -46,11 +46,15 @@ def make_pipeline(cfg=None, workload: str = "learned"):
                     cfg or LearnedConfig())
 
 
-def curve_source(workload: str, seed: int):
-    """A callable returning one (t, f, sigma, injections) curve per call."""
+def curve_source(workload: str, seed: int, device_gen: bool = True):
+    """A callable returning one (t, f, sigma, injections) curve per call:
+    generated on the device (LongCurves, LearnedCurves), or for the learned
+    workload with device_gen=False on the host (learned_curve)."""
     from synthlc import workloads as W
     if workload == "long":
         return W.LongCurves(seed).draw
+    if device_gen:
+        return W.LearnedCurves(seed).draw
     rng = np.random.default_rng(seed)
     return lambda: W.learned_curve(rng)
 

@@ -449,3 +449,65 @@ class LongCurves:
             off = off + depth * shape
             injs.append(inj)
         return self.t, off.to(torch.float32), self.sigma, injs
+
+
+class LearnedCurves:
+    """Light curves of the learned-proposal workload generated on a torch
+    device, with the recipe of learned_curve (80 000 points at 2 min, Poisson
+    (1.5) gaps of U(0.2, 2) d, per-point sigma log-normal around 800 ppm with
+    log-sd 0.25, half the curves with one planet: P log-uniform 1-100 d,
+    depth log-uniform 50-3000 ppm, b uniform 0-0.9 rounded to 0.01, the
+    duration of a circular orbit around a Sun-density star).  Points inside
+    gaps keep their times and get a NaN sigma, which the search treats as
+    missing.  The noise comes from a seeded device generator, the gap and
+    injection parameters from a seeded numpy generator.  draw() returns
+    device (t, f, sigma) and the injections."""
+
+    def __init__(self, seed: int, device="cuda", planet_frac: float = 0.5):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.n = LEARNED_N_POINTS
+        self.cadence = 120.0 / DAY_S
+        self.t = torch.arange(self.n, dtype=torch.float64, device=device) * self.cadence
+        self.span = float((self.n - 1) * self.cadence)
+        self.rng = np.random.default_rng(seed)
+        self.gen = torch.Generator(device=device)
+        self.gen.manual_seed(int(seed))
+        self.planet_frac = planet_frac
+        self.dense = {}
+
+    def _dense(self, b: float):
+        if b not in self.dense:
+            self.dense[b] = self.torch.as_tensor(transit.dense_template(b=b), device=self.device)
+        return self.dense[b]
+
+    def draw(self):
+        torch = self.torch
+        keep = torch.ones(self.n, dtype=torch.bool, device=self.device)
+        for _ in range(self.rng.poisson(1.5)):
+            glen = self.rng.uniform(0.2, 2.0)
+            g0 = self.rng.uniform(0.0, max(self.span - glen, 1e-9))
+            keep &= ~((self.t >= g0) & (self.t < g0 + glen))
+        sig = 800e-6 * torch.exp(0.25 * torch.randn(self.n, generator=self.gen, dtype=torch.float64,
+                                                       device=self.device))
+        off = -sig * torch.randn(self.n, generator=self.gen, dtype=torch.float64, device=self.device)
+        injs = []
+        if self.rng.uniform() < self.planet_frac:
+            P = float(np.exp(self.rng.uniform(np.log(LEARNED_P_RANGE[0]), np.log(LEARNED_P_RANGE[1]))))
+            b = round(round(float(self.rng.uniform(0.0, 0.9)) / 0.01) * 0.01, 6)
+            dur = transit.transit_duration_days(P, b)
+            depth = float(np.exp(self.rng.uniform(np.log(50e-6), np.log(3000e-6))))
+            inj = Injection(P, float(self.rng.uniform(0.0, P)), dur, depth, b)
+            dense = self._dense(b)
+            phase = torch.remainder(self.t - inj.epoch + 0.5 * P, P) - 0.5 * P
+            tau = phase / dur + 0.5
+            x = tau.clamp(0.0, 1.0) * (dense.shape[0] - 1)
+            i0 = x.floor().clamp(max=dense.shape[0] - 2).long()
+            w = x - i0
+            shape = dense[i0] * (1.0 - w) + dense[i0 + 1] * w
+            shape = torch.where((tau >= 0.0) & (tau <= 1.0), shape, torch.zeros_like(shape))
+            off = off + depth * shape
+            injs.append(inj)
+        sigma = torch.where(keep, sig, torch.full_like(sig, float("nan"))).to(torch.float32)
+        return self.t, off.to(torch.float32), sigma, injs

@@ -117,7 +117,7 @@ def test_linear_long_windows_read_from_memory(cm, ora):
     r, o, g = run_both(cm, ora, wl)
     og = o["grid"]
     Wl = cm.get_tuning()["linear_windows"]
-    table = 8 * (wl.n_model + 4)
+    table = 4 * ((wl.n_model + 5) & ~1)
     span_pairs = ((256 * Wl - 1) * og.t0_step + wl.durations[-1]) / og.cadence + 4
     assert span_pairs * 8 + table > 64 * 1024  # the longest duration takes the direct path
     assert (((256 * Wl - 1) * og.t0_step + wl.durations[0]) / og.cadence + 4) * 8 + table < 64 * 1024  # staged

@@ -70,3 +70,37 @@ def test_transit_duration_sun_like():
     """Earth around the Sun: ~13 h central transit."""
     d = transit.transit_duration_days(365.25, 0.0, p=0.009)
     assert 12.5 / 24 < d < 13.5 / 24
+
+
+def test_learned_curves_device_generator_recipe():
+    """The device generator of the learned workload (run here on the CPU
+    device) follows the recipe: 80 000 points at 2 min, gaps as NaN sigma,
+    log-normal sigma around 800 ppm, injections inside the stated ranges,
+    and the injected signal added with the template's shape."""
+    import numpy as np
+    import torch
+    from synthlc import workloads as W
+    gen = W.LearnedCurves(5, device="cpu")
+    n_planet = 0
+    for _ in range(12):
+        t, f, s, injs = gen.draw()
+        assert t.shape == f.shape == s.shape == (W.LEARNED_N_POINTS,)
+        assert f.dtype == torch.float32 and s.dtype == torch.float32 and t.dtype == torch.float64
+        assert abs(float(t[1] - t[0]) * 86400.0 - 120.0) < 1e-6
+        ok = torch.isfinite(s)
+        ls = torch.log(s[ok].double() / 800e-6)
+        assert abs(float(ls.mean())) < 0.01 and abs(float(ls.std()) - 0.25) < 0.01
+        gap_days = float((~ok).sum()) * 120.0 / 86400.0
+        assert gap_days < 20.0
+        for inj in injs:
+            n_planet += 1
+            assert 1.0 <= inj.period <= 100.0 and 50e-6 <= inj.depth <= 3000e-6 and 0.0 <= inj.b <= 0.9
+            assert inj.duration > 0
+            # the mean offset inside transits exceeds the mean outside by a
+            # fraction of the depth set by the limb-darkened shape
+            phase = np.mod(t.numpy() - inj.epoch + 0.5 * inj.period, inj.period) - 0.5 * inj.period
+            inside = np.abs(phase) < 0.25 * inj.duration
+            if inside.sum() > 200:
+                d = float(f.numpy()[inside].mean() - f.numpy()[~inside].mean())
+                assert 0.5 * inj.depth < d < 1.2 * inj.depth + 5 * 800e-6 / np.sqrt(inside.sum())
+    assert n_planet >= 3
