@@ -419,7 +419,10 @@ typedef struct cetra_batch_desc {
     int64_t shuffle_seed;          /* 0: curves queued by descending fold cost; else a
                                       permutation drawn from this seed (results do not
                                       depend on the order)                              */
-    int32_t reserved0;             /* must be 0                                      */
+    int32_t pop_items;             /* work items a workgroup takes per pop of the
+                                      queue, 1-64; 0 = chosen at launch (up to 8, fewer
+                                      when the batch is small).  Results do not depend
+                                      on it                                            */
     int32_t reserved1;
 } cetra_batch_desc;
 
@@ -453,9 +456,9 @@ typedef struct cetra_batch_plan cetra_batch_plan;
  * reference times, or a seeded shuffle), cuts every curve's stages into work
  * items (resampling, linear search, fold units, decode) and lays out the
  * queue so that each item's inputs come from items queued before it: curve
- * p+2's resampling and linear search and curve p-1's decode are queued
- * around curve p's fold.  Four device slots (resampled curve and fold-ready
- * array, sized for the longest curve) are reused in queue order.  The plan
+ * p+2's resampling and linear search and curve p-3's decode are queued
+ * around curve p's fold.  min(8, curves) device slots (resampled curve and
+ * fold-ready array, sized for the longest curve) are reused in queue order.  The plan
  * owns host memory only; free it with cetra_batch_plan_destroy. */
 int cetra_batch_plan_create(const cetra_batch_desc *desc, cetra_batch_plan **out);
 int cetra_batch_plan_destroy(cetra_batch_plan *plan);

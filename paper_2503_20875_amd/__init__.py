@@ -446,8 +446,11 @@ class BatchPlan:
                 pass
 
 
-def batch_plan(grids, obs_offsets, period_offsets, period_block: int = 0, shuffle_seed: int = 0) -> BatchPlan:
-    """Plan a batch from per-curve grid plans and CSR offsets (host arrays)."""
+def batch_plan(grids, obs_offsets, period_offsets, period_block: int = 0, shuffle_seed: int = 0,
+               pop_items: int = 0) -> BatchPlan:
+    """Plan a batch from per-curve grid plans and CSR offsets (host arrays).
+    pop_items: work items a workgroup takes per queue pop (0: chosen at
+    launch)."""
     n = len(grids)
     garr = (Grid * n)(*grids)
     oo = np.ascontiguousarray(obs_offsets, dtype=np.int64)
@@ -455,7 +458,7 @@ def batch_plan(grids, obs_offsets, period_offsets, period_block: int = 0, shuffl
     if oo.shape[0] != n + 1 or po.shape[0] != n + 1:
         raise ValueError("offsets must have n_curves + 1 entries")
     d = _abi.BatchDesc(n, int(period_block), ctypes.cast(garr, ctypes.c_void_p), oo.ctypes.data_as(ctypes.c_void_p),
-                       po.ctypes.data_as(ctypes.c_void_p), int(shuffle_seed), 0, 0)
+                       po.ctypes.data_as(ctypes.c_void_p), int(shuffle_seed), int(pop_items), 0)
     lib = _abi.load()
     h = ctypes.c_void_p()
     _abi.check(lib.cetra_batch_plan_create(ctypes.byref(d), ctypes.byref(h)))

@@ -98,7 +98,7 @@ class BatchDesc(ctypes.Structure):
         ("obs_offsets", ctypes.c_void_p),
         ("period_offsets", ctypes.c_void_p),
         ("shuffle_seed", ctypes.c_int64),
-        ("reserved0", ctypes.c_int32),
+        ("pop_items", ctypes.c_int32),
         ("reserved1", ctypes.c_int32),
     ]
 

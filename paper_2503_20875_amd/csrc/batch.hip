@@ -14,19 +14,22 @@
 //        a curve writes its best-period record and its done flag
 // The queue lists the items of curve p (queue position) in the order
 //   RES(0) LIN(0) RES(1) LIN(1), then for r = 0, 1, ...:
-//   FOLD(r) EPI(r-1) RES(r+2) LIN(r+2), and EPI(last) at the end,
-// so the linear search of curve r+2 and the decode of curve r-1 run while
+//   FOLD(r) EPI(r-3) RES(r+2) LIN(r+2), and the last three EPI at the end,
+// so the linear search of curve r+2 and the decode of curve r-3 run while
 // curve r folds.  A curve's resampled light curve and fold-ready array live
-// in one of four arena slots, slot p mod 4.
+// in one of S = min(8, curves) arena slots, slot p mod S.
 //
 // Dependencies.  An item may start only when the items it reads from are
 // complete: LIN(p) after every RES(p), FOLD(p) after every LIN(p), EPI(p)
-// after every FOLD(p), and RES(p) after every EPI(p-4), the last user of its
+// after every FOLD(p), and RES(p) after every EPI(p-8), the last user of its
 // slot.  Every such item sits earlier in the queue, and items are popped in
 // queue order by workgroups that keep running until they finish them, so
 // the earliest unfinished item never waits and the queue always drains.
+// The distances leave slack: a decode is queued three folds after its own
+// fold (whose last items may still be running when the next fold is taken),
+// and the resampling that reuses a slot three steps after that decode.
 // Completion is counted per (curve, stage): after an item the workgroup
-// synchronises and one lane adds 1 with release semantics at agent scope;
+// synchronises and one lane adds its count with release semantics at agent scope;
 // a waiting workgroup's first lane loads the counter with acquire semantics
 // (device-scope coherence across the XCDs' separate L2 caches), then the
 // workgroup synchronises.  Every wait is bounded: a host-set cancel flag,
@@ -55,9 +58,13 @@ enum Stage : int32_t { kRes = 0, kLin = 1, kFold = 2, kEpi = 3, kStages = 4 };
 constexpr int kResPoints = 2048;                 // grid points per RES item
 constexpr int kLinTiles = 4;                     // 256-reference-time tiles per LIN item
 constexpr int kEpiPeriods = kThreads;            // periods per EPI item
-constexpr int kMaxSlots = 4;                     // curves resident at once
+constexpr int kMaxSlots = 8;                     // curves resident at once
+constexpr int kLinAhead = 2;                     // RES/LIN of curve r+2 are queued with FOLD(r)
+constexpr int kEpiLag = 3;                       // EPI of curve r-3 is queued with FOLD(r)
 constexpr int kLdsCapBytes = 40 * 1024;          // dynamic LDS of the persistent kernel
 constexpr int64_t kFoldItemsTarget = 8192;       // fold items per curve to aim for (epoch chunks)
+constexpr int32_t kPopMax = 64;                  // largest run of items one queue pop may take
+constexpr int32_t kPopAuto = 8;                  // the automatic choice's largest run
 constexpr uint64_t kMagic = 0x31484354414254ull; // tables image tag
 
 struct Segment {
@@ -81,6 +88,8 @@ struct Header {
     int64_t slot_ivar, slot_fold;  // byte offsets inside a slot
     int32_t period_block, lds_bytes, lds_cap;
     int32_t linear_windows;  // W: reference times per lane of a LIN tile (256 W per tile)
+    int32_t pop_items;       // items a workgroup takes per queue pop; 0 = chosen at launch
+    int32_t reserved;
 };
 
 // Device status bits of cetra_batch_search.
@@ -118,6 +127,7 @@ struct BatchArgs {
     int64_t n_curves, n_items;
     uint64_t wait_ticks;    // wall-clock limit of one dependency wait
     int32_t resume;
+    int32_t pop;            // items taken per queue pop (>= 1)
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -349,6 +359,26 @@ __device__ void finish_curve(const BatchArgs &a, const CurveDesc &cd, const cetr
     a.done[c] = __hip_atomic_load(&a.bad[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? -1 : 1;
 }
 
+// Called by every lane of one wave: adds n finished items of (curve c, stage)
+// to the stage's counter; release orders the items' stores (and atomics)
+// before the count.  The decode stage also acquires, as the call that
+// completes a curve's decode writes its best-period record from the others'.
+__device__ void count_items(const BatchArgs &a, const CurveDesc *curves, const cetra_grid *grids, int32_t c,
+                            int32_t stage, uint32_t n, int32_t skipped) {
+    if (n == 0) return;
+    uint32_t prev = 0;
+    if (lane_zero()) {
+        uint32_t *ctr = &a.stage_done[(int64_t)c * kStages + stage];
+        prev = stage == kEpi ? __hip_atomic_fetch_add(ctr, n, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT)
+                             : __hip_atomic_fetch_add(ctr, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = __builtin_amdgcn_readfirstlane(prev);
+    if (stage == kEpi && !skipped) {
+        const uint32_t n_epi = __builtin_amdgcn_readfirstlane((uint32_t)curves[c].n_items[kEpi]);
+        if (prev + n == n_epi && lane_zero()) finish_curve(a, curves[c], grids[c], c);
+    }
+}
+
 template <int B, int W>
 __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
     extern __shared__ float lds[];
@@ -378,28 +408,46 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
     // L2 on every short item)
     const uint32_t *seen_counter = nullptr;
     int64_t seg_hint = 0;
+    // One pop takes a run of a.pop consecutive items, [next, end): the queue
+    // head and the per-stage counters are single words that every workgroup
+    // updates, and one update per item saturates them when items are short.
+    // Finished items of one (curve, stage) are counted together, before the
+    // workgroup moves to another (curve, stage), waits on a dependency, or
+    // pops again; so it never waits while holding uncounted items, and the
+    // earliest unfinished item still never waits.
+    int64_t next = 0, end = 0;
+    int32_t pend_c = 0, pend_stage = 0, pend_skip = 0;
+    uint32_t pend_n = 0;
     for (;;) {
-        if (wave == 0) {
-            long long it = -1;
-            if (!stop_requested(a)) {
-                unsigned long long v = 0;
-                if (lane_zero()) v = atomicAdd(&a.ctr->head, 1ull);
-                v = (unsigned long long)uniform64((int64_t)v);
-                if (v < (unsigned long long)a.n_items) it = (long long)v;
+        if (next >= end) {
+            if (wave == 0) {
+                count_items(a, curves, grids, pend_c, pend_stage, pend_n, pend_skip);
+                long long it = -1;
+                if (!stop_requested(a)) {
+                    unsigned long long v = 0;
+                    if (lane_zero()) v = atomicAdd(&a.ctr->head, (unsigned long long)a.pop);
+                    v = (unsigned long long)uniform64((int64_t)v);
+                    if (v < (unsigned long long)a.n_items) it = (long long)v;
+                }
+                if (lane_zero()) s_item = it;
             }
-            if (lane_zero()) s_item = it;
+            pend_n = 0;
+            __syncthreads();
+            next = uniform64(s_item);
+            if (next < 0) break;
+            end = min(next + (int64_t)a.pop, a.n_items);
         }
-        __syncthreads();
-        const int64_t item = uniform64(s_item);
-        if (item < 0) break;
+        const int64_t item = next++;
         const ItemRef ir = locate(h, segs, item, seg_hint);
         const int32_t c = __builtin_amdgcn_readfirstlane(ir.curve);
         const int32_t stage = __builtin_amdgcn_readfirstlane(ir.stage);
         const int64_t idx = uniform64(ir.idx);
         const CurveDesc &cd = curves[c];
+        const bool other_run = pend_n != 0 && (c != pend_c || stage != pend_stage);
         // dependency of the item: the previous stage of its curve, or for
         // RES the decode of the curve that used its slot before
         if (wave == 0) {
+            if (other_run) count_items(a, curves, grids, pend_c, pend_stage, pend_n, pend_skip);
             const int32_t prev_curve = __builtin_amdgcn_readfirstlane(cd.prev_in_slot);
             const uint32_t *counter = nullptr;
             uint32_t need = 0;
@@ -419,26 +467,17 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
             }
             if (lane_zero()) s_go = ok ? 1 : 0;
         }
+        if (other_run) pend_n = 0;
         __syncthreads();
         const int go = __builtin_amdgcn_readfirstlane(s_go);
         if (!go) break;
         const int skip = __builtin_amdgcn_readfirstlane(a.resume && a.done[c] != 0 ? 1 : 0);  // done earlier
         if (!skip) run_item<B, W>(a, h, cd, grids[c], c, stage, idx, lds, s_bounds);
-        __syncthreads();  // every lane's stores of the item are complete
-        if (wave == 0) {
-            uint32_t prev = 0;
-            // release: the item's stores (and atomics) before the count; the
-            // decode stage also acquires, as its last item reads the others'
-            // records
-            if (lane_zero()) {
-                uint32_t *ctr = &a.stage_done[(int64_t)c * kStages + stage];
-                prev = stage == kEpi ? __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT)
-                                     : __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            prev = __builtin_amdgcn_readfirstlane(prev);
-            const uint32_t n_epi = __builtin_amdgcn_readfirstlane((uint32_t)cd.n_items[kEpi]);
-            if (stage == kEpi && !skip && prev + 1 == n_epi && lane_zero()) finish_curve(a, cd, grids[c], c);
-        }
+        __syncthreads();  // every lane's stores of the item are complete before it is counted
+        pend_c = c;
+        pend_stage = stage;
+        pend_skip = skip;
+        ++pend_n;
     }
 }
 
@@ -489,7 +528,7 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     clear_error();
     CETRA_REQUIRE(d && out && d->grids && d->obs_offsets && d->period_offsets, "batch_plan: NULL pointer");
     CETRA_REQUIRE(d->n_curves >= 1, "batch_plan: n_curves must be >= 1");
-    CETRA_REQUIRE(d->reserved0 == 0, "batch_plan: reserved0 must be 0");
+    CETRA_REQUIRE(d->pop_items >= 0 && d->pop_items <= kPopMax, "batch_plan: pop_items must be 0-64");
     const int n = d->n_curves;
     const cetra_grid &g0 = d->grids[0];
     int rc;
@@ -581,17 +620,20 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
         segs.push_back(Segment{item, c, st});
         item += cds[c].n_items[st];
     };
-    emit(0, kRes);
-    emit(0, kLin);
-    emit(1, kRes);
-    emit(1, kLin);
+    // slot reuse needs RES(p), queued at step p - kLinAhead, after EPI(p - S),
+    // queued at step p - S + kEpiLag
+    static_assert(kMaxSlots > kLinAhead + kEpiLag, "a slot's next user would be queued before its last");
+    for (int p = 0; p < kLinAhead; ++p) {
+        emit(p, kRes);
+        emit(p, kLin);
+    }
     for (int r = 0; r < n; ++r) {
         emit(r, kFold);
-        emit(r - 1, kEpi);
-        emit(r + 2, kRes);
-        emit(r + 2, kLin);
+        emit(r - kEpiLag, kEpi);
+        emit(r + kLinAhead, kRes);
+        emit(r + kLinAhead, kLin);
     }
-    emit(n - 1, kEpi);
+    for (int p = std::max(0, n - kEpiLag); p < n; ++p) emit(p, kEpi);
 
     auto *plan = new (std::nothrow) cetra_batch_plan;
     if (!plan) return set_error(CETRA_ERR_INVALID, "batch_plan: out of host memory");
@@ -614,6 +656,7 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     h.slot_fold = (int64_t)slot_fold;
     h.period_block = B;
     h.linear_windows = W;
+    h.pop_items = d->pop_items;
     h.lds_bytes = lds_bytes;
     h.lds_cap = lds_cap;
     plan->h = h;
@@ -770,6 +813,11 @@ extern "C" int cetra_batch_search(const cetra_batch_plan *plan, void *stream, co
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, lds) != hipSuccess || occ <= 0) occ = 1;
     const int per_cu = std::max(1, std::min(current_tuning().fold_wgs_per_cu, occ));
     const int64_t wgs = std::min<int64_t>((int64_t)device_cu_count() * per_cu, std::max<int64_t>(plan->h.n_items, 1));
+    // runs of items per pop: up to kPopAuto, while every workgroup still
+    // takes at least 32 runs (a lone curve keeps every workgroup busy)
+    a.pop = plan->h.pop_items > 0
+                ? plan->h.pop_items
+                : (int32_t)std::max<int64_t>(1, std::min<int64_t>(kPopAuto, plan->h.n_items / (wgs * 32)));
     void *args[] = {(void *)&a};
     const hipError_t le = hipLaunchKernel(kern, dim3((unsigned)wgs), dim3(kThreads), args, lds, s);
     if (le != hipSuccess) return set_error(CETRA_ERR_HIP, "batch_search: %s", hipGetErrorString(le));

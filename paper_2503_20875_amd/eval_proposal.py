@@ -42,6 +42,10 @@ def main(argv=None) -> int:
     ap.add_argument("--target", type=float, default=0.99)
     ap.add_argument("--seed", type=int, default=20250410)
     ap.add_argument("--out", default="")
+    ap.add_argument("--quick", action="store_true",
+                    help="rank recall only: one K = 64 run per half, no operating-point runs")
+    ap.add_argument("--rows", action="store_true",
+                    help="also write every detection of the test half (rank, periods, SNR, truth)")
     a = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
@@ -77,6 +81,13 @@ def main(argv=None) -> int:
         out["test_k64"] = summary(test_k64)
         out["test_rank_recall"] = {K: float(np.mean(np.asarray(test_k64["ranks"]) < K))
                                    for K in (16, 32, 64, 96, 128, 192, 256, 384)}
+        if a.rows:
+            out["test_detections"] = [{k: r[k] for k in ("curve", "rank", "plain_period", "plain_snr",
+                                                         "true_detection", "injected")}
+                                      for r in test_k64["rows"] if r["detected"]]
+        if a.quick:
+            results[os.path.basename(path)] = out
+            continue
         out["test_k_target"] = summary(evaluate(pipe, net, test_curves, top_k=k_target, log=log, plain=plain_test))
         out["test_k96"] = summary(evaluate(pipe, net, test_curves, top_k=96, log=log, plain=plain_test))
         out["test_fallback"] = summary(evaluate(pipe, net, test_curves, top_k=64,

@@ -21,7 +21,8 @@ import pytest
 HEADER = np.dtype([("magic", "<u8"), ("plan_id", "<u8"), ("n_curves", "<i8"), ("n_segments", "<i8"),
                    ("n_items", "<i8"), ("off_curves", "<i8"), ("off_grids", "<i8"), ("off_segments", "<i8"),
                    ("tables_bytes", "<i8"), ("slot_ivar", "<i8"), ("slot_fold", "<i8"), ("period_block", "<i4"),
-                   ("lds_bytes", "<i4"), ("lds_cap", "<i4"), ("linear_windows", "<i4")])
+                   ("lds_bytes", "<i4"), ("lds_cap", "<i4"), ("linear_windows", "<i4"),
+                   ("pop_items", "<i4"), ("reserved", "<i4")])
 CURVE = np.dtype([("obs_off", "<i8"), ("n_obs", "<i8"), ("per_off", "<i8"), ("n_per", "<i8"), ("slot_off", "<i8"),
                   ("n_items", "<i8", (4,)), ("prev_in_slot", "<i4"), ("n_res", "<i4"), ("n_lin_per_dur", "<i4"),
                   ("n_pblk", "<i4"), ("n_chunks", "<i4"), ("n_tiles", "<i4")])
@@ -157,6 +158,69 @@ def simulate(cur, rng, n_items, workers, seed):
     return t
 
 
+def simulate_runs(cur, rng, n_items, workers, pop, seed):
+    """The kernel's queue protocol with runs: a workgroup pops `pop`
+    consecutive items, runs them in order, and adds its finished items of one
+    (curve, stage) to that stage's counter only before it moves to another
+    (curve, stage), waits, or pops again.  Dependency checks see counted items
+    only.  Raises on a deadlock, or if a workgroup would wait while holding
+    uncounted items; returns the finish time."""
+    r = np.random.default_rng(seed)
+    key_of = [None] * n_items
+    for k, (f, e) in rng.items():
+        for i in range(f, e):
+            key_of[i] = k
+    counted = {k: 0 for k in rng}
+    need = {k: e - f for k, (f, e) in rng.items()}
+    state = {"head": 0, "t": 0.0}
+    wgs = [dict(next=0, end=0, pend=None, n=0, mode="idle") for _ in range(workers)]
+    running = []
+
+    def flush(w):
+        if w["n"]:
+            counted[w["pend"]] += w["n"]
+            assert counted[w["pend"]] <= need[w["pend"]]
+            w["n"] = 0
+
+    def advance(i):
+        w = wgs[i]
+        if w["next"] >= w["end"]:
+            flush(w)
+            if state["head"] >= n_items:
+                w["mode"] = "exit"
+                return
+            w["next"], w["end"] = state["head"], min(state["head"] + pop, n_items)
+            state["head"] = w["end"]
+        k = key_of[w["next"]]
+        if w["n"] and k != w["pend"]:
+            flush(w)
+        dep = dependency(cur, *k)
+        if dep is None or dep not in rng or counted[dep] == need[dep]:
+            heapq.heappush(running, (state["t"] + r.uniform(0.5, 2.0), i))
+            w["mode"] = "run"
+        else:
+            assert w["n"] == 0, "waiting while holding uncounted items"
+            w["mode"] = "wait"
+
+    for i in range(workers):
+        advance(i)
+    finished = 0
+    while running:
+        state["t"], i = heapq.heappop(running)
+        w = wgs[i]
+        w["pend"], w["n"] = key_of[w["next"]], w["n"] + 1
+        w["next"] += 1
+        finished += 1
+        advance(i)
+        for j, v in enumerate(wgs):
+            if v["mode"] == "wait":
+                advance(j)
+    if finished < n_items or any(w["mode"] != "exit" for w in wgs):
+        raise AssertionError(f"deadlock: {finished} of {n_items} done")
+    assert counted == need
+    return state["t"]
+
+
 @pytest.fixture(scope="module")
 def cm():
     import paper_2503_20875_amd as cm
@@ -190,6 +254,8 @@ def test_plan_tables_queue_and_bounds(cm, n, seed, shuffle, block):
     assert plan.info["n_items"] == h["n_items"]
     for workers in (1, 3, 64):
         simulate(cur, rng, int(h["n_items"]), workers, seed)
+    for workers, pop in ((1, 8), (3, 2), (7, 64), (64, 3)):
+        simulate_runs(cur, rng, int(h["n_items"]), workers, pop, seed)
 
 
 def test_plan_order_is_by_fold_cost_or_seeded(cm):
@@ -218,6 +284,9 @@ def test_plan_ids_differ_and_validation(cm):
         cm.batch_plan(grids, oo[::-1].copy(), po)
     with pytest.raises(cm.CetraError, match="fold_period_block"):
         cm.batch_plan(grids, oo, po, period_block=16)
+    with pytest.raises(cm.CetraError, match="pop_items"):
+        cm.batch_plan(grids, oo, po, pop_items=65)
+    assert parse(make(cm, curves, pop_items=5)[3])[0]["pop_items"] == 5
     with pytest.raises(ValueError):
         cm.batch_plan(grids, oo[:-1], po)
 

@@ -115,13 +115,14 @@ def test_batch_equals_single_bitwise(cm, setup):
     compare(cm, o, single, per_off)
 
 
-@pytest.mark.parametrize("shuffle,block", [(12345, 0), (0, 4), (777, 4)])
-def test_batch_order_and_block_do_not_change_results(cm, setup, shuffle, block):
-    """A seeded queue order or another period block interleaves the curves'
-    items differently; every record stays bit-identical."""
+@pytest.mark.parametrize("shuffle,block,pop", [(12345, 0, 0), (0, 4, 1), (777, 4, 3), (0, 0, 64)])
+def test_batch_order_and_block_do_not_change_results(cm, setup, shuffle, block, pop):
+    """A seeded queue order, another period block or another run length per
+    queue pop interleaves the curves' items differently; every record stays
+    bit-identical."""
     curves, model, packed, single = setup
     grids, obs_off, per_off = packed[:3]
-    plan = cm.batch_plan(grids, obs_off, per_off, period_block=block, shuffle_seed=shuffle)
+    plan = cm.batch_plan(grids, obs_off, per_off, period_block=block, shuffle_seed=shuffle, pop_items=pop)
     o = batch_results(cm, plan, curves, packed, model)
     assert int(o["status"].item()) == 0
     compare(cm, o, single, per_off)
