@@ -15,7 +15,8 @@ Architecture (B examples, C_in input channels = durations, L bins):
   per window w, trial period T (bins) and phase phi:
         F = sum_k e_c[phi + round(k T)] / sqrt(#k)      fold pooling, the
         nearest-epoch rule of the periodic search at bin resolution
-        g[w, c] = max over the window's trials and phases of F
+        g[w, c] = F at the window's best (trial, phase), chosen on F in
+        FP32 (the kernel's precision; see score32)
   f[w] = [g[w, :], q_w]                  q_w = window position in [0, 1]
   z[w] = v . relu(U f[w] + u) + v0       shared head -> one logit per window
   loss = mean_{b,w} pos_w(y) * bce(z, y),  pos weight for the positives
@@ -92,16 +93,26 @@ def fold_step(T: float) -> int:
     return int(np.floor(4294967296.0 * float(T) + 0.5))
 
 
+def score32(s, n):
+    """The FP32 score on which fold pooling decides a window's winner:
+    fl32(fl32(s) * fl32(1 / sqrt(n))), the reciprocal square root rounded
+    once from FP64 (numpy's float32 arithmetic is IEEE, correctly rounded)."""
+    r = np.float32(1.0 / np.sqrt(np.float64(n)))
+    return np.asarray(s, dtype=np.float64).astype(np.float32) * r
+
+
 def fold_pool(e, trials, runner_up: bool = False):
     """Coarse fold of each event series at every trial period.  For trial T
     (bins) with fixed-point step R, phase phi in [0, min(L, ceil(R/2^32)))
     sums e over the transit positions phi + ((k R + 2^31) >> 32), k = 0, 1,
     ..., inside the series; the score is that sum over sqrt(number of
-    terms).  Per window: the maximum score over its trials and phases (ties:
-    the first trial, then the smallest phase).  Returns g [B][W][E] and the
-    winning (trial, phase) [B][W][E][2]; with runner_up, also the best
-    score of any other (trial, phase) [B][W][E] (to check that a test's
-    maxima are unambiguous)."""
+    terms).  Per window: the (trial, phase) of the maximum score (ties: the
+    first trial, then the smallest phase), the decision taken on the FP32
+    score of score32 (the kernel's precision); the feature is that winner's
+    score in FP64.  Returns g [B][W][E] and the winning (trial, phase)
+    [B][W][E][2]; with runner_up, also the best FP64 score of any other
+    (trial, phase) [B][W][E] (to check that a test's maxima are
+    unambiguous)."""
     B, E, L = e.shape
     W, S = trials.shape
     g = np.zeros((B, W, E))
@@ -109,6 +120,7 @@ def fold_pool(e, trials, runner_up: bool = False):
     arg = np.zeros((B, W, E, 2), dtype=np.int64)
     for w in range(W):
         best = np.full((B, E), -np.inf)
+        best32 = np.full((B, E), -np.inf, dtype=np.float32)
         sec = np.full((B, E), -np.inf)
         for s_ in range(S):
             if not (1.0 <= trials[w, s_] < 1e9):
@@ -127,10 +139,13 @@ def fold_pool(e, trials, runner_up: bool = False):
             for ph in range(n_ph):
                 pos = ph + o
                 pos = pos[pos < L]
-                sc = e[:, :, pos].sum(axis=2) / np.sqrt(len(pos))
-                better = sc > best
+                tot = e[:, :, pos].sum(axis=2)
+                sc = tot / np.sqrt(len(pos))
+                sc32 = score32(tot, len(pos))
+                better = sc32 > best32
                 sec = np.where(better, best, np.maximum(sec, sc))
                 best = np.where(better, sc, best)
+                best32 = np.where(better, sc32, best32)
                 arg[:, w, :, 0] = np.where(better, s_, arg[:, w, :, 0])
                 arg[:, w, :, 1] = np.where(better, ph, arg[:, w, :, 1])
         g[:, w, :] = np.where(np.isfinite(best), best, 0.0)

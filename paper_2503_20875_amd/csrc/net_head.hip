@@ -96,91 +96,174 @@ __global__ void __launch_bounds__(kT) project_bwd_dp_kernel(const __bf16 *__rest
 // Coarse fold of each event series at every window's trial periods.  Trial
 // T (bins) has the 32.32 step R = floor(2^32 T + 1/2); phase phi in
 // [0, min(L, ceil(R / 2^32))) sums e over the positions phi + ((k R + 2^31)
-// >> 32) inside the series, and scores sum / sqrt(count).  Per (example,
-// window, channel) the maximum score over trials and phases is the feature
-// (ties: first trial, then smallest phase); arg keeps trial * 65536 + phase.
-// One workgroup per (channel, example) with the series staged in LDS; the
-// (trial, phase) items of a window are spread over the lanes.  Sums are FP32
-// (exact for the integer-valued inputs of the tests), scores FP64.
+// >> 32) inside the series; its count n is the number of those positions.
+// Per (example, window, channel) the feature is the best score over the
+// window's trials and phases, the decision taken on the FP32 score
+// fl(S * r(n)), r(n) = fl(1 / sqrt(n)) rounded from FP64 (ties: first trial,
+// then smallest phase); f holds that FP32 score and arg keeps
+// trial * 65536 + phase.  One workgroup per (channel, example, window group)
+// with the series staged in LDS; each wave takes whole windows.  Sums are
+// FP32 (exact for the integer-valued inputs of the tests).
 // 0 for a trial that is not finite or shorter than one bin (such a trial is
 // skipped: its offsets would not advance)
 __device__ __forceinline__ uint64_t trial_step(double T) {
     return (T >= 1.0 && T < 1.0e9) ? (uint64_t)floor(4294967296.0 * T + 0.5) : 0ull;
 }
 
-// Sums of s_e over the transit positions ph + ((k R + 2^31) >> 32) < L for
-// the 64 consecutive phases ph = ph0 + lane of a wave, and their counts.  The
-// offset of transit k does not depend on the phase, so it is stepped once per
-// wave (32.32 fixed point in scalar registers); a lane only tests its bound,
-// reads and adds.  Four partial sums (element k into sum k mod 4, FP32).
-__device__ __forceinline__ float fold_sum_wave(const float *s_e, int32_t L, uint64_t R, int32_t ph0, int lane,
-                                               int32_t &n) {
-    float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    int32_t cnt = 0;
-    const uint32_t Rh = __builtin_amdgcn_readfirstlane((uint32_t)(R >> 32));
-    const uint32_t Rl = __builtin_amdgcn_readfirstlane((uint32_t)R);
-    const uint64_t step = ((uint64_t)Rh << 32) | Rl;
-    uint64_t o = 2147483648ull;  // + 1/2: round half up
-    const uint32_t uL = (uint32_t)L;
-    const uint32_t ph = (uint32_t)(ph0 + lane);
-    const uint32_t lim0 = uL - (uint32_t)ph0;  // ph0 < L: lane 0 is in range at transit 0
-    // groups of four transits, branch-free inside: out-of-range elements read
-    // a clamped index and add zero, so the four LDS reads are in flight
-    // together; full groups while lane 0's fourth transit is inside the
-    // series, then at most three single transits into the same partial sums
-    // (transit k always goes to a[k % 4], so the sums do not depend on how
-    // the loop is split)
-    while ((uint32_t)((o + 3 * step) >> 32) < lim0) {
-        uint32_t x[4];
+__device__ __forceinline__ float inv_sqrt_count(int32_t n) {
+    return n > 0 ? (float)(1.0 / sqrt((double)n)) : 0.0f;
+}
+
+// Sums over the transit positions of the 64 P phases ph = ph0 + lane + 64 v
+// (v < P) of one wave, and the counts of positions in the series.  The
+// offset of transit k, ((k R + 2^31) >> 32), is the same for every phase:
+// it is stepped once per wave in scalar registers.  While the group's last
+// phase is still inside the series at transit k ("full" transits, the bulk)
+// every lane reads without a bounds test, eight transits at a time; transit
+// k always adds into partial sum k mod 4.  The few transits after that
+// ("tail", while the group's first phase is inside) count each phase's
+// positions in the series; their reads past the series land in the zero
+// padding after it (kFoldPad >= 64 P - 1 floats).  The count of a lane's
+// phase is n_full + tail[v].  Lanes past the trial's phases still read
+// inside the staged array; the caller ignores them.
+constexpr int kFoldPad = 128;
+
+template <int P>
+__device__ __forceinline__ void fold_sum_group(const float *s_e, uint32_t uL, uint64_t step, uint32_t ph0, int lane,
+                                               float (&sum)[P], int32_t (&cnt)[P]) {
+    static_assert(64 * P - 1 <= kFoldPad, "tail reads must stay inside the padding");
+    float a[P][4], t[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+        a[v][0] = a[v][1] = a[v][2] = a[v][3] = 0.0f;
+        t[v] = 0.0f;
+        cnt[v] = 0;
+    }
+    const uint32_t base = ph0 + (uint32_t)lane;
+    // full transits: offset < uL - (ph0 + 64 P - 1)
+    const uint32_t last = ph0 + 64u * P - 1u;
+    const uint32_t lim_full = uL > last ? uL - last : 0u;
+    uint64_t o = 2147483648ull;
+    uint32_t n_full = 0;
+    // (a step of 2^45 or more, a trial of at least kMaxL bins, has one
+    // transit in the series; the guard also keeps 7 steps from overflowing).
+    // The offsets of a block of eight are o + u step with the multiples
+    // precomputed: two scalar adds per transit.
+    if (step < (1ull << 45)) {
+        uint64_t m[8];
+        m[0] = 0;
+#pragma unroll
+        for (int u = 1; u < 8; ++u) m[u] = m[u - 1] + step;
+        const uint64_t m8 = m[7] + step;
+        while ((uint32_t)((o + m[7]) >> 32) < lim_full) {
+            uint32_t ou[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ou[u] = (uint32_t)((o + m[u]) >> 32);
+            float val[P][8];
+#pragma unroll
+            for (int v = 0; v < P; ++v)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) val[v][u] = s_e[base + 64u * v + ou[u]];
+#pragma unroll
+            for (int v = 0; v < P; ++v)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[v][u & 3] += val[v][u];
+            o += m8;
+            n_full += 8;
+        }
+    }
+    if ((uint32_t)((o + 3 * step) >> 32) < lim_full) {
+        uint32_t ou[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            x[u] = ph + (uint32_t)(o >> 32);
+            ou[u] = (uint32_t)(o >> 32);
             o += step;
         }
-        float val[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) val[u] = s_e[x[u] < uL ? x[u] : uL - 1];
+        for (int v = 0; v < P; ++v)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool in = x[u] < uL;
-            a[u] += in ? val[u] : 0.0f;
-            cnt += in ? 1 : 0;
-        }
+            for (int u = 0; u < 4; ++u) a[v][u] += s_e[base + 64u * v + ou[u]];
+        n_full += 4;
     }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-        if ((uint32_t)(o >> 32) >= lim0) break;  // wave-uniform
-        const uint32_t x = ph + (uint32_t)(o >> 32);
+        if ((uint32_t)(o >> 32) >= lim_full) break;  // wave-uniform
+        const uint32_t ou = (uint32_t)(o >> 32);
+#pragma unroll
+        for (int v = 0; v < P; ++v) a[v][u] += s_e[base + 64u * v + ou];
         o += step;
-        const bool in = x < uL;
-        const float val = s_e[in ? x : uL - 1];
-        a[u] += in ? val : 0.0f;
-        cnt += in ? 1 : 0;
+        ++n_full;
     }
-    n = cnt;
-    return (a[0] + a[1]) + (a[2] + a[3]);
+    // tail: transits while the group's first phase is in the series
+    const uint32_t lim0 = uL - ph0;  // ph0 < L
+    while ((uint32_t)(o >> 32) < lim0) {
+        const uint32_t ou = (uint32_t)(o >> 32);
+#pragma unroll
+        for (int v = 0; v < P; ++v) {
+            const uint32_t x = base + 64u * v + ou;  // < L + 64 P - 1
+            t[v] += s_e[x];                          // 0 past the series
+            cnt[v] += x < uL ? 1 : 0;
+        }
+        o += step;
+    }
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+        sum[v] = ((a[v][0] + a[v][1]) + (a[v][2] + a[v][3])) + t[v];
+        cnt[v] += (int32_t)n_full;
+    }
+}
+
+// One trial's phases of a wave, P per lane: scores, and the lane's best
+// (score, index) updated in increasing index order (so a strict comparison
+// keeps the first of equal scores).  Every phase's count is n0 or n0 - 1,
+// n0 the count of phase 0: the phases span fewer bins than the gap between
+// two transits, so at most one transit position leaves the series across
+// them.  r0, r1 are computed once, after the first group, where lane 0 holds
+// phase 0.
+template <int P>
+__device__ __forceinline__ void fold_trial(const float *s_e, uint32_t uL, uint64_t step, int32_t n_ph, int32_t q,
+                                           int32_t n_ph_max, int lane, float &best, int32_t &bj) {
+    int32_t n0 = 0;
+    float r0 = 0.0f, r1 = 0.0f;
+    for (int32_t ph0 = 0; ph0 < n_ph; ph0 += 64 * P) {
+        float sum[P];
+        int32_t cnt[P];
+        fold_sum_group<P>(s_e, uL, step, (uint32_t)ph0, lane, sum, cnt);
+        if (ph0 == 0) {
+            n0 = __builtin_amdgcn_readfirstlane(cnt[0]);
+            r0 = inv_sqrt_count(n0);
+            r1 = inv_sqrt_count(n0 - 1);
+        }
+#pragma unroll
+        for (int v = 0; v < P; ++v) {
+            const int32_t ph = ph0 + lane + 64 * v;
+            const float sc = sum[v] * (cnt[v] == n0 ? r0 : r1);
+            if (ph < n_ph && sc > best) {
+                best = sc;
+                bj = q * n_ph_max + ph;
+            }
+        }
+    }
 }
 
 // Grid (channel, example, window group); each workgroup stages its event
 // series in LDS, and each wave takes whole windows (wave index = group * 4
-// + wave, striding by 4 n_groups), so a window's maximum is a wave reduction.
-// Lane candidates are (trial q, phase ph), numbered jj = q n_ph_max + ph; a
-// phase is scored exactly, (double) sum / sqrt(n), only if its FP32 score
-// sum * rsqrt(n), within a few 1e-7 of the exact one, does not fall below
-// the lane's best by more than 1e-5 of it -- a phase rejected that way cannot
-// win or tie, so the maxima are those of exact scoring.
+// + wave, striding by 4 n_groups), so a window's maximum is a wave
+// reduction.  Trials with more than 64 phases take two phases per lane, so
+// each scalar offset step serves 128 phases.
 __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
                                                           const double *__restrict__ trials, int32_t W, int32_t S,
                                                           const float *__restrict__ win_q, float *__restrict__ f,
                                                           int32_t *__restrict__ arg) {
-    __shared__ float s_e[kMaxL];
+    __shared__ float s_e[kMaxL + kFoldPad];
     const int32_t c = blockIdx.x;
     const int64_t b = blockIdx.y;
     const int32_t nf = E + 1;
     const int lane = threadIdx.x & 63;
     const int32_t wave_id = blockIdx.z * (kT / 64) + (threadIdx.x >> 6);
     const int32_t n_waves = gridDim.z * (kT / 64);
-    for (int t = threadIdx.x; t < L; t += kT) s_e[t] = e[(b * L + t) * E + c];
+    const uint32_t uL = (uint32_t)L;
+    for (int t = threadIdx.x; t < L + kFoldPad; t += kT) s_e[t] = t < L ? e[(b * L + t) * E + c] : 0.0f;
     __syncthreads();
     for (int32_t w = wave_id; w < W; w += n_waves) {
         int32_t n_ph_max = 0;
@@ -188,38 +271,22 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
             const uint64_t R = trial_step(trials[w * S + q]);
             n_ph_max = max(n_ph_max, (int32_t)min<uint64_t>((uint64_t)L, (R + 4294967295ull) >> 32));
         }
-        if (n_ph_max == 0) {  // no valid trial: zero feature, no argmax
-            if (lane == 0) {
-                f[(b * W + w) * nf + c] = 0.0f;
-                arg[(b * W + w) * E + c] = -1;
-                if (c == 0) f[(b * W + w) * nf + E] = win_q[w];
-            }
-            continue;
-        }
-        double best = -INFINITY;
-        float cut = -INFINITY;
+        float best = -INFINITY;
         int32_t bj = INT_MAX;
         for (int32_t q = 0; q < S; ++q) {
             const uint64_t R = trial_step(trials[w * S + q]);
-            if (R == 0) continue;
-            const int32_t n_ph = (int32_t)min<uint64_t>((uint64_t)L, (R + 4294967295ull) >> 32);
-            for (int32_t ph0 = 0; ph0 < n_ph; ph0 += 64) {
-                const int32_t ph = ph0 + lane;
-                int32_t n = 0;
-                const float acc = fold_sum_wave(s_e, L, R, ph0, lane, n);
-                if (ph >= n_ph || acc * rsqrtf((float)n) < cut) continue;
-                const double sc = (double)acc / sqrt((double)n);
-                const int32_t jj = q * n_ph_max + ph;
-                if (sc > best || (sc == best && jj < bj)) {
-                    best = sc;
-                    bj = jj;
-                    const float fb = (float)sc;
-                    cut = fb - 1e-5f * fabsf(fb) - 1e-30f;
-                }
-            }
+            const uint32_t Rh = __builtin_amdgcn_readfirstlane((uint32_t)(R >> 32));
+            const uint32_t Rl = __builtin_amdgcn_readfirstlane((uint32_t)R);
+            const uint64_t step = ((uint64_t)Rh << 32) | Rl;
+            if (step == 0) continue;
+            const int32_t n_ph = (int32_t)min<uint64_t>((uint64_t)L, (step + 4294967295ull) >> 32);
+            if (n_ph > 64)
+                fold_trial<2>(s_e, uL, step, n_ph, q, n_ph_max, lane, best, bj);
+            else
+                fold_trial<1>(s_e, uL, step, n_ph, q, n_ph_max, lane, best, bj);
         }
         for (int off = 32; off > 0; off >>= 1) {
-            const double ov = __shfl_xor(best, off, 64);
+            const float ov = __shfl_xor(best, off, 64);
             const int32_t oj = __shfl_xor(bj, off, 64);
             if (ov > best || (ov == best && oj < bj)) {
                 best = ov;
@@ -227,9 +294,9 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
             }
         }
         if (lane == 0) {
-            const int32_t q = bj / n_ph_max, ph = bj % n_ph_max;
-            f[(b * W + w) * nf + c] = (float)best;
-            arg[(b * W + w) * E + c] = q * 65536 + ph;
+            const bool none = bj == INT_MAX;  // no valid trial, or no finite score
+            f[(b * W + w) * nf + c] = none ? 0.0f : best;
+            arg[(b * W + w) * E + c] = none ? -1 : (bj / n_ph_max) * 65536 + bj % n_ph_max;
             if (c == 0) f[(b * W + w) * nf + E] = win_q[w];
         }
     }

@@ -169,35 +169,75 @@ def test_network_forward_backward(torch, pn, seed):
         float(np.max(np.abs(gx - g_ref["x"]) / (mag + 1e-30)))
 
 
-def test_fold_pool_kernels(torch, pn):
-    """Fold pooling alone on integer-valued events (sums exact in FP32 and
-    FP64, so every argmax decision is the oracle's): features and argmax
-    bit for bit, the backward to FP32 summation order; trials shorter than
-    one bin are skipped and a window without a valid trial gives zero."""
-    rng = np.random.default_rng(21)
-    B, E, L, W, S = 2, 3, 300, 6, 3
-    e = rng.integers(-3, 4, (B, E, L)).astype(np.float64)
-    trials = np.array([[5.3, 5.6, 5.9], [17.2, 17.9, 18.3], [40.0, 41.5, 43.0], [0.5, 60.2, 61.7],
-                       [149.5, 151.0, 152.5], [0.2, 0.6, 0.9]])
-    q = np.linspace(0.05, 0.95, W).astype(np.float32)
+def _winner_score32(e, trials, arg_ref, b, w, c):
+    """FP32 score of the oracle's winning (trial, phase): the exact sum of
+    the integer-valued events at its transit positions, and its count."""
+    s_, ph = arg_ref[b, w, c]
+    L = e.shape[2]
+    R = onet.fold_step(trials[w, s_])
+    pos = []
+    k = 0
+    while ph + ((k * R + 2 ** 31) >> 32) < L:
+        pos.append(ph + ((k * R + 2 ** 31) >> 32))
+        k += 1
+    return onet.score32(e[b, c, pos].sum(), len(pos))
+
+
+def _check_fold_pool(torch, pn, e, trials, q):
+    B, E, L = e.shape
+    W, S = trials.shape
     g_ref, arg_ref = onet.fold_pool(e, trials)
     win = pn.Windows(q, np.arange(W + 1, dtype=np.float64) + 1.0, 1.0)
-    win._trials3 = torch.as_tensor(trials, device="cuda")
+    setattr(win, f"_trials{S}", torch.as_tensor(trials, device="cuda"))
     model_e = torch.as_tensor(e.transpose(0, 2, 1).copy(), dtype=torch.float32, device="cuda")
+    print(f"[foldpool] B={B} E={E} L={L} W={W} S={S}", flush=True)
     f, arg = pn.foldpool_fwd(model_e, win, S)
     f, arg = f.cpu().numpy(), arg.cpu().numpy()
     for b in range(B):
         for w in range(W):
             for c in range(E):
                 s_, ph = arg_ref[b, w, c]
-                assert arg[b, w, c] == (-1 if s_ < 0 else s_ * 65536 + ph), (b, w, c)
-                assert f[b, w, c] == np.float32(g_ref[b, w, c])
+                assert arg[b, w, c] == (-1 if s_ < 0 else s_ * 65536 + ph), (b, w, c, arg[b, w, c], s_, ph)
+                want = np.float32(0.0) if s_ < 0 else _winner_score32(e, trials, arg_ref, b, w, c)
+                assert f[b, w, c] == want, (b, w, c, f[b, w, c], want)
+                assert abs(f[b, w, c] - g_ref[b, w, c]) <= 2.0 ** -22 * abs(g_ref[b, w, c])
             assert f[b, w, E] == q[w]
+    return f, arg, arg_ref, win
+
+
+def test_fold_pool_kernels(torch, pn):
+    """Fold pooling alone on integer-valued events (sums exact in FP32 and
+    FP64, so every argmax decision is the oracle's): argmax bit for bit and
+    the feature equal to the FP32 score of the oracle's winner, the backward
+    to FP32 summation order; trials shorter than one bin are skipped and a
+    window without a valid trial gives zero.  Trials of more than 64 phases
+    take two phases per lane, with full and tail transits."""
+    rng = np.random.default_rng(21)
+    B, E, L, W, S = 2, 3, 300, 6, 3
+    e = rng.integers(-3, 4, (B, E, L)).astype(np.float64)
+    trials = np.array([[5.3, 5.6, 5.9], [17.2, 17.9, 18.3], [40.0, 41.5, 43.0], [0.5, 60.2, 61.7],
+                       [149.5, 151.0, 152.5], [0.2, 0.6, 0.9]])
+    q = np.linspace(0.05, 0.95, W).astype(np.float32)
+    f, arg, arg_ref, win = _check_fold_pool(torch, pn, e, trials, q)
     assert np.all(f[:, 5, :E] == 0) and np.all(arg[:, 5] == -1)
     gg = rng.normal(size=(B, W, E + 1)).astype(np.float32)
     ge = pn.foldpool_bwd(torch.as_tensor(gg, device="cuda"), torch.as_tensor(arg, device="cuda"), win, E, L, S)
     ref = onet.fold_pool_backward(gg[:, :, :E].astype(np.float64), arg_ref, trials, L)
     assert np.allclose(ge.cpu().numpy().transpose(0, 2, 1), ref, rtol=1e-5, atol=1e-6)
+
+
+def test_fold_pool_full_length(torch, pn):
+    """The network's series length, 8 192 bins: trials from one bin to past
+    the series (one transit per phase) and a huge trial (the fixed-point
+    step near its 2^62 limit), each window's groups of 64 or 128 phases
+    with their full and tail transits, bit for bit against the oracle."""
+    rng = np.random.default_rng(22)
+    B, E, L = 1, 2, 8192
+    e = rng.integers(-4, 5, (B, E, L)).astype(np.float64)
+    trials = np.array([[1.0, 1.37, 2.9], [7.49, 63.5, 64.2], [127.9, 128.0, 129.3], [700.6, 1023.7, 2049.1],
+                       [4095.5, 5000.25, 8191.6], [8192.0, 9000.0, 5.0e8]])
+    q = np.linspace(0.1, 0.9, trials.shape[0]).astype(np.float32)
+    _check_fold_pool(torch, pn, e, trials, q)
 
 
 def test_adam_step(torch, pn):

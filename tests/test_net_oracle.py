@@ -97,6 +97,23 @@ def test_fold_pool_brute_force():
             assert second[0, w, c] == pytest.approx(sorted(t[0] for t in scores)[-2], abs=1e-12)
 
 
+def test_fold_pool_decides_in_fp32():
+    """Two phases whose scores differ below FP32 resolution tie, and the tie
+    goes to the first phase; a difference FP32 resolves decides.  The
+    feature is the FP64 score of the winner."""
+    e = np.zeros((1, 1, 4))
+    e[0, 0, 0] = 1.0
+    e[0, 0, 2] = 1.0 + 1e-12         # later phase, FP64-larger, FP32-equal
+    trials = np.array([[4.0]])          # one transit per phase, n = 1
+    g, arg = net.fold_pool(e, trials)
+    assert arg[0, 0, 0].tolist() == [0, 0] and g[0, 0, 0] == 1.0
+    e[0, 0, 2] = 1.0 + 2.0 ** -20       # resolved in FP32
+    g, arg = net.fold_pool(e, trials)
+    assert arg[0, 0, 0].tolist() == [0, 2] and g[0, 0, 0] == 1.0 + 2.0 ** -20
+    # the FP32 score rounds the reciprocal square root once from FP64
+    assert net.score32(3.0, 7) == np.float32(3.0) * np.float32(1.0 / np.sqrt(7.0))
+
+
 def test_fold_offsets_are_nearest_multiples():
     """The fixed-point transit offsets equal round-half-up of k T, exactly
     (Fraction arithmetic on the FP64 trial)."""
