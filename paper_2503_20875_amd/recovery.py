@@ -160,13 +160,16 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, default=1000, help="light curves per noise level")
     ap.add_argument("--seed", type=int, default=20250405)
     ap.add_argument("--batch", type=int, default=256, help="curves per batched search")
+    ap.add_argument("--levels", default="",
+                    help="comma-separated noise levels in ppm per hour (default: the paper's three)")
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
+    levels = tuple(float(v) for v in a.levels.split(",")) if a.levels else NOISE_LEVELS
     import torch
     if not torch.cuda.is_available():
         print("recovery: no GPU", file=sys.stderr)
         return 2
-    res = run(a.n, a.seed, batch=a.batch, log=lambda m: print(f"[recovery] {m}", flush=True))
+    res = run(a.n, a.seed, levels=levels, batch=a.batch, log=lambda m: print(f"[recovery] {m}", flush=True))
     text = json.dumps(res)
     print(text, flush=True)
     if a.out:
