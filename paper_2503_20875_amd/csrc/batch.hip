@@ -7,7 +7,9 @@
 // of allowed durations times reference times), or by a seeded permutation.
 // Each curve has four stages, cut into work items:
 //   RES  resampling of 2048 grid points; also clears a share of the curve's
-//        argmax keys and checks a share of its times for order
+//        argmax keys, computes the same share of its periods' fold steps,
+//        epoch counts and duration ranges (for the fold and decode items),
+//        and checks a share of its times for order
 //   LIN  linear search of 4 tiles of 256 W reference times of one duration
 //   FOLD one fold unit: a block of B periods, one duration, one epoch chunk
 //   EPI  decode of 256 periods' winners (FP64 recompute); the last EPI item of
@@ -86,6 +88,7 @@ struct Header {
     int64_t n_curves, n_segments, n_items;
     int64_t off_curves, off_grids, off_segments, tables_bytes;
     int64_t slot_ivar, slot_fold;  // byte offsets inside a slot
+    int64_t slot_ptab;             // the curve's per-period steps, epoch counts, duration ranges
     int32_t period_block, lds_bytes, lds_cap;
     int32_t linear_windows;  // W: reference times per lane of a LIN tile (256 W per tile)
     int32_t pop_items;       // items a workgroup takes per queue pop; 0 = chosen at launch
@@ -234,6 +237,7 @@ __device__ void run_item(const BatchArgs &a, const Header *h, const CurveDesc &c
     float *flux = reinterpret_cast<float *>(slot);
     float *ivar = reinterpret_cast<float *>(slot + h->slot_ivar);
     float2 *fold = reinterpret_cast<float2 *>(slot + h->slot_fold);
+    cetra::dev::PeriodInfo *ptab = reinterpret_cast<cetra::dev::PeriodInfo *>(slot + h->slot_ptab);
     const int64_t I = g.n_t0;
     if (stage == kRes) {
         const int64_t q0 = idx * kResPoints;
@@ -244,7 +248,13 @@ __device__ void run_item(const BatchArgs &a, const Header *h, const CurveDesc &c
         // a share of the argmax keys, and of the order check of the times
         const int64_t nres = cd.n_res;
         const int64_t k0 = cd.n_per * idx / nres, k1 = cd.n_per * (idx + 1) / nres;
-        for (int64_t k = k0 + threadIdx.x; k < k1; k += kThreads) a.keys[cd.per_off + k] = 0ull;
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += kThreads) {
+            const int64_t o = cd.per_off + k;
+            a.keys[o] = 0ull;
+            ptab[k] = cetra::dev::period_info(a.periods[o], g.t0_step, I, g.n_dur, g.durations,
+                                              a.jrange ? a.jrange[2 * o] : 0,
+                                              a.jrange ? a.jrange[2 * o + 1] : g.n_dur - 1);
+        }
         const int64_t o0 = cd.n_obs * idx / nres, o1 = cd.n_obs * (idx + 1) / nres;
         const double *t = a.t + cd.obs_off;
         bool bad = false;
@@ -286,10 +296,7 @@ __device__ void run_item(const BatchArgs &a, const Header *h, const CurveDesc &c
             R[b] = 0;
             ipb[b] = 0;
             if (k < cd.n_per) {
-                const int64_t o = cd.per_off + k;
-                const cetra::dev::PeriodInfo pi = cetra::dev::period_info(
-                    a.periods[o], g.t0_step, I, g.n_dur, g.durations, a.jrange ? a.jrange[2 * o] : 0,
-                    a.jrange ? a.jrange[2 * o + 1] : g.n_dur - 1);
+                const cetra::dev::PeriodInfo pi = ptab[k];  // written by the curve's RES items
                 if (j >= pi.jlo && j <= pi.jhi) {
                     R[b] = pi.step;
                     ipb[b] = pi.n_ep;
@@ -314,8 +321,7 @@ __device__ void run_item(const BatchArgs &a, const Header *h, const CurveDesc &c
         uint64_t bk = 0;
         if (k < cd.n_per) {
             const int64_t o = cd.per_off + k;
-            const cetra::dev::PeriodInfo pi =
-                cetra::dev::period_info(a.periods[o], g.t0_step, I, g.n_dur, g.durations, 0, g.n_dur - 1);
+            const cetra::dev::PeriodInfo pi = ptab[k];  // the step does not depend on the duration range
             const uint64_t key = __hip_atomic_load(&a.keys[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const float l = cetra::dev::fold_decode(fold, I, g.n_dur, pi.step, key, a.lr + o, a.epoch + o,
                                                     a.dur + o, a.depth + o, a.depth_var + o);
@@ -543,7 +549,7 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     CETRA_REQUIRE(d->obs_offsets[0] == 0 && d->period_offsets[0] == 0, "batch_plan: offsets must start at 0");
     std::vector<CurveDesc> cds(n);
     std::vector<double> cost(n);
-    size_t max_n = 1, max_fold = 8;
+    size_t max_n = 1, max_fold = 8, max_per = 1;
     const int64_t tab_bytes = (int64_t)dev::template_table_entries(g0.n_model) * 8;
     const int32_t lds_cap = (int32_t)std::max<int64_t>(kLdsCapBytes, tab_bytes);
     int32_t lds_bytes = (int32_t)tab_bytes;
@@ -579,6 +585,7 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
                 return set_error(CETRA_ERR_RANGE, "batch_plan: curve %d has too many work items", c);
         max_n = std::max(max_n, (size_t)g.n);
         max_fold = std::max(max_fold, (size_t)8 * (size_t)g.n_dur * (size_t)g.n_t0);
+        max_per = std::max(max_per, (size_t)cd.n_per);
         cost[c] = (double)cd.n_per * g.n_dur * (double)g.n_t0;
         for (int j = 0; j < g.n_dur; ++j) {
             int32_t span_cap = 0;
@@ -604,7 +611,8 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     const int n_slots = std::min(kMaxSlots, n);
     const size_t slot_ivar = align256(4 * max_n);
     const size_t slot_fold = slot_ivar + align256(4 * max_n);
-    const size_t slot_bytes = slot_fold + align256(max_fold);
+    const size_t slot_ptab = slot_fold + align256(max_fold);
+    const size_t slot_bytes = slot_ptab + align256(sizeof(dev::PeriodInfo) * max_per);
     for (int p = 0; p < n; ++p) {
         CurveDesc &cd = cds[order[p]];
         cd.slot_off = (int64_t)((size_t)(p % n_slots) * slot_bytes);
@@ -654,6 +662,7 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     h.tables_bytes = (int64_t)off;
     h.slot_ivar = (int64_t)slot_ivar;
     h.slot_fold = (int64_t)slot_fold;
+    h.slot_ptab = (int64_t)slot_ptab;
     h.period_block = B;
     h.linear_windows = W;
     h.pop_items = d->pop_items;

@@ -20,7 +20,8 @@ import pytest
 
 HEADER = np.dtype([("magic", "<u8"), ("plan_id", "<u8"), ("n_curves", "<i8"), ("n_segments", "<i8"),
                    ("n_items", "<i8"), ("off_curves", "<i8"), ("off_grids", "<i8"), ("off_segments", "<i8"),
-                   ("tables_bytes", "<i8"), ("slot_ivar", "<i8"), ("slot_fold", "<i8"), ("period_block", "<i4"),
+                   ("tables_bytes", "<i8"), ("slot_ivar", "<i8"), ("slot_fold", "<i8"), ("slot_ptab", "<i8"),
+                   ("period_block", "<i4"),
                    ("lds_bytes", "<i4"), ("lds_cap", "<i4"), ("linear_windows", "<i4"),
                    ("pop_items", "<i4"), ("reserved", "<i4")])
 CURVE = np.dtype([("obs_off", "<i8"), ("n_obs", "<i8"), ("per_off", "<i8"), ("n_per", "<i8"), ("slot_off", "<i8"),
@@ -29,6 +30,7 @@ CURVE = np.dtype([("obs_off", "<i8"), ("n_obs", "<i8"), ("per_off", "<i8"), ("n_
 SEGMENT = np.dtype([("first", "<i8"), ("curve", "<i4"), ("stage", "<i4")])
 RES, LIN, FOLD, EPI = range(4)
 RES_POINTS, LIN_TILES, THREADS, EPI_PERIODS = 2048, 4, 256, 256
+PERIOD_INFO_BYTES = 24  # u64 step, i32 epochs, i32 jlo, i32 jhi, padded to 8
 
 
 def parse(plan):
@@ -112,9 +114,10 @@ def check_plan(cm, curves, grids, oo, po, plan):
         if p < n_slots:
             assert d["slot_off"] == p * (cur[order[1]]["slot_off"] if n_slots > 1 else 0)
         assert h["slot_ivar"] >= 4 * g.n and h["slot_fold"] - h["slot_ivar"] >= 4 * g.n
+        assert h["slot_ptab"] - h["slot_fold"] >= 8 * g.n_dur * g.n_t0
         if n_slots > 1:
             slot_bytes = int(cur[order[1]]["slot_off"])
-            assert slot_bytes - h["slot_fold"] >= 8 * g.n_dur * g.n_t0
+            assert slot_bytes - h["slot_ptab"] >= PERIOD_INFO_BYTES * d["n_per"]
         assert g.n_t0 < 1 << 28
     assert plan.info["workspace_bytes"] >= h["tables_bytes"] + n_slots * (slot_bytes or h["slot_fold"])
     assert 0 < h["lds_bytes"] <= h["lds_cap"]
