@@ -433,7 +433,7 @@ typedef struct cetra_batch_info {
     int64_t total_periods;
     int64_t n_launches;      /* kernel launches per cetra_batch_search (2)         */
     int64_t n_items;         /* work-queue items of one search                     */
-    int32_t n_slots;         /* curves whose device data are resident at once      */
+    int32_t n_slots;         /* curves whose device slots are live at once          */
     int32_t period_block;
     int32_t lds_bytes;       /* dynamic LDS per workgroup of the persistent kernel */
     int32_t reserved;
@@ -454,11 +454,13 @@ typedef struct cetra_batch_plan cetra_batch_plan;
 /* Plan a batch (host only): validates the grids and offsets, orders the
  * curves (descending fold cost = sum over periods of allowed durations times
  * reference times, or a seeded shuffle), cuts every curve's stages into work
- * items (resampling, linear search, fold units, decode) and lays out the
- * queue so that each item's inputs come from items queued before it: curve
- * p+2's resampling and linear search and curve p-3's decode are queued
- * around curve p's fold.  min(8, curves) device slots (resampled curve and
- * fold-ready array, sized for the longest curve) are reused in queue order.  The plan
+ * items (resampling, linear search, fold units, decode), groups consecutive
+ * curves until a group's fold has enough items (a long curve is a group of
+ * one), and lays out the queue so that each item's inputs come from items
+ * queued before it: group g+2's resampling and linear search and group g-3's
+ * decode are queued around group g's fold.  Each curve has a device slot
+ * (resampled curve, fold-ready array, per-period table); min(8, groups) slot
+ * sets are reused in queue order.  The plan
  * owns host memory only; free it with cetra_batch_plan_destroy. */
 int cetra_batch_plan_create(const cetra_batch_desc *desc, cetra_batch_plan **out);
 int cetra_batch_plan_destroy(cetra_batch_plan *plan);
@@ -549,6 +551,14 @@ int cetra_net_mfma_probe(void *stream, const void *a, const void *b, float *c);
  * bins split the reference times evenly (bin b covers i in
  * [b n_t0 / n_bins, (b+1) n_t0 / n_bins)).  x is [n_bins][n_dur]. */
 int cetra_net_downsample(void *stream, const float *fold, int32_t n_dur, int64_t n_t0, int32_t n_bins, void *x);
+
+/* The signed form of the same input: x[bin][j] (bf16) = clamp(z, -30, 30) / 8
+ * with z the largest S_fm / sqrt(S_mm) over the bin's reference times (the
+ * single-event depth over its error, Sec. 2.2, keeping its sign: a dimming is
+ * positive); a bin whose elements are all null gives 0.  Same layout, bins and
+ * errors as cetra_net_downsample. */
+int cetra_net_downsample_signed(void *stream, const float *fold, int32_t n_dur, int64_t n_t0, int32_t n_bins,
+                                void *x);
 
 /* y = relu(conv(x, w) + bias): x [batch][L][cin] bf16 (cin 16 or 64),
  * w packed bf16, bias[64] FP32, y [batch][L][64] bf16.  MFMA implicit GEMM. */

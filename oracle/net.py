@@ -212,6 +212,26 @@ def downsample(fold, n_bins: int):
     return np.minimum(out, 30.0) / 8.0
 
 
+def downsample_signed(fold, n_bins: int):
+    """The signed form of the network input: per duration and bin, the
+    largest S_fm / sqrt(S_mm) over the bin (the single-event depth over its
+    error, keeping the sign, so that a dimming is positive), clipped to
+    [-30, 30] and divided by 8; a bin whose elements are all null gives 0.
+    Same bins and layout as downsample; FP64."""
+    fold = np.asarray(fold, dtype=np.float64)
+    J, I = fold.shape[0], fold.shape[1]
+    out = np.zeros((n_bins, J))
+    for b in range(n_bins):
+        i0, i1 = b * I // n_bins, (b + 1) * I // n_bins
+        for j in range(J):
+            a = fold[j, i0:i1, 0]
+            s = fold[j, i0:i1, 1]
+            ok = s > 0
+            if np.any(ok):
+                out[b, j] = np.max(a[ok] / np.sqrt(s[ok]))
+    return np.clip(out, -30.0, 30.0) / 8.0
+
+
 def bf16(x):
     """Round to the nearest bfloat16 (ties to even), returned as float64."""
     a = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)

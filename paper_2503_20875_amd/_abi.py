@@ -182,6 +182,7 @@ SIGNATURES = {
                                           _P, _P, _P]),
     "cetra_net_mfma_probe": (ctypes.c_int, [_P, _P, _P, _P]),
     "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
+    "cetra_net_downsample_signed": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),
     "cetra_conv1d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _P, _i32, _P, _P, _P, _P, _P]),
     "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _P]),

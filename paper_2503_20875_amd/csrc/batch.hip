@@ -14,27 +14,32 @@
 //   FOLD one fold unit: a block of B periods, one duration, one epoch chunk
 //   EPI  decode of 256 periods' winners (FP64 recompute); the last EPI item of
 //        a curve writes its best-period record and its done flag
-// The queue lists the items of curve p (queue position) in the order
+// Consecutive curves in queue order form groups: a group closes once its
+// fold has enough items (long curves are groups of one).  Dependencies and
+// completion counts are per (group, stage), so a workgroup waits on, and
+// acquires, one counter per group and stage rather than per curve.  The
+// queue lists the items of group r in the order
 //   RES(0) LIN(0) RES(1) LIN(1), then for r = 0, 1, ...:
 //   FOLD(r) EPI(r-3) RES(r+2) LIN(r+2), and the last three EPI at the end,
-// so the linear search of curve r+2 and the decode of curve r-3 run while
-// curve r folds.  A curve's resampled light curve and fold-ready array live
-// in one of S = min(8, curves) arena slots, slot p mod S.
+// so the linear search of group r+2 and the decode of group r-3 run while
+// group r folds.  Each curve's resampled light curve, fold-ready array and
+// per-period table live in its own slot of slot set r mod S, S =
+// min(8, groups); a set is sized for the largest group it serves.
 //
 // Dependencies.  An item may start only when the items it reads from are
-// complete: LIN(p) after every RES(p), FOLD(p) after every LIN(p), EPI(p)
-// after every FOLD(p), and RES(p) after every EPI(p-8), the last user of its
-// slot.  Every such item sits earlier in the queue, and items are popped in
-// queue order by workgroups that keep running until they finish them, so
-// the earliest unfinished item never waits and the queue always drains.
-// The distances leave slack: a decode is queued three folds after its own
-// fold (whose last items may still be running when the next fold is taken),
-// and the resampling that reuses a slot three steps after that decode.
-// Completion is counted per (curve, stage): after an item the workgroup
-// synchronises and one lane adds its count with release semantics at agent scope;
-// a waiting workgroup's first lane loads the counter with acquire semantics
-// (device-scope coherence across the XCDs' separate L2 caches), then the
-// workgroup synchronises.  Every wait is bounded: a host-set cancel flag,
+// complete: LIN after every RES of its group, FOLD after every LIN of its
+// group, EPI after every FOLD of its group, and RES after every EPI of the
+// group that used the slot set before (group r-8).  Every such item sits
+// earlier in the queue, and items are popped in queue order by workgroups
+// that keep running until they finish them, so the earliest unfinished item
+// never waits and the queue always drains.  The distances leave slack: a
+// decode is queued three folds after its own fold, and the resampling that
+// reuses a slot set three steps after that decode.
+// Completion is counted per (group, stage): after a run of items the
+// workgroup synchronises and one lane adds the run's count with release
+// semantics at agent scope; a waiting workgroup's first wave polls the
+// counter and acquires once it is complete (device-scope coherence across
+// the XCDs' separate L2 caches), then the workgroup synchronises.  Every wait is bounded: a host-set cancel flag,
 // another workgroup's abort, or a wall-clock limit ends it, and the limit
 // marks the status so no result is trusted.
 //
@@ -60,9 +65,11 @@ enum Stage : int32_t { kRes = 0, kLin = 1, kFold = 2, kEpi = 3, kStages = 4 };
 constexpr int kResPoints = 2048;                 // grid points per RES item
 constexpr int kLinTiles = 4;                     // 256-reference-time tiles per LIN item
 constexpr int kEpiPeriods = kThreads;            // periods per EPI item
-constexpr int kMaxSlots = 8;                     // curves resident at once
-constexpr int kLinAhead = 2;                     // RES/LIN of curve r+2 are queued with FOLD(r)
-constexpr int kEpiLag = 3;                       // EPI of curve r-3 is queued with FOLD(r)
+constexpr int kMaxSlots = 8;                     // groups of curves resident at once
+constexpr int kLinAhead = 2;                     // RES/LIN of group r+2 are queued with FOLD(r)
+constexpr int kEpiLag = 3;                       // EPI of group r-3 is queued with FOLD(r)
+constexpr int kMaxGroup = 16;                    // curves per group at most
+constexpr int64_t kGroupFoldItems = 49152;       // a group closes once its fold has this many items
 constexpr int kLdsCapBytes = 40 * 1024;          // dynamic LDS of the persistent kernel
 constexpr int64_t kFoldItemsTarget = 8192;       // fold items per curve to aim for (epoch chunks)
 constexpr int32_t kPopMax = 64;                  // largest run of items one queue pop may take
@@ -77,18 +84,26 @@ struct Segment {
 
 struct CurveDesc {
     int64_t obs_off, n_obs, per_off, n_per;
-    int64_t slot_off;            // byte offset of the curve's slot in the arena
+    int64_t slot_off;                      // byte offset of the curve's slot in the arena
+    int64_t ivar_off, fold_off, ptab_off;  // inside the slot: flux at 0, then ivar, the
+                                           // fold-ready array, the per-period steps, epoch
+                                           // counts and duration ranges
     int64_t n_items[kStages];
-    int32_t prev_in_slot;        // curve whose EPI must finish before RES, or -1
+    int32_t group;                         // the curve's group (consecutive in queue order)
     int32_t n_res, n_lin_per_dur, n_pblk, n_chunks, n_tiles;
+};
+
+struct GroupDesc {
+    int64_t n_items[kStages];  // items of the group's curves per stage (what a dependency waits for)
+    int32_t prev_group;        // group that used the same slots before, whose decode must finish
+                               // before this group resamples; -1 if none
+    int32_t n_curves;
 };
 
 struct Header {
     uint64_t magic, plan_id;
-    int64_t n_curves, n_segments, n_items;
-    int64_t off_curves, off_grids, off_segments, tables_bytes;
-    int64_t slot_ivar, slot_fold;  // byte offsets inside a slot
-    int64_t slot_ptab;             // the curve's per-period steps, epoch counts, duration ranges
+    int64_t n_curves, n_groups, n_segments, n_items;
+    int64_t off_curves, off_groups, off_grids, off_segments, tables_bytes;
     int32_t period_block, lds_bytes, lds_cap;
     int32_t linear_windows;  // W: reference times per lane of a LIN tile (256 W per tile)
     int32_t pop_items;       // items a workgroup takes per queue pop; 0 = chosen at launch
@@ -105,14 +120,14 @@ struct Counters {  // cleared by batch_init_kernel at every call
     unsigned long long head;
     uint32_t abort_flag;
     uint32_t pad;
-    // then uint32_t done_ctr[n_curves][kStages], uint32_t bad[n_curves]
 };
 
 struct BatchArgs {
     const char *tables;
     uint64_t plan_id;
     Counters *ctr;
-    uint32_t *stage_done;  // [n_curves][kStages]
+    uint32_t *group_done;  // [n_groups][kStages]: finished items per group and stage
+    uint32_t *curve_epi;   // [n_curves]: finished decode items per curve
     uint32_t *bad;         // [n_curves]
     uint64_t *best_keys;   // [n_curves]
     uint64_t *keys;        // [total periods]
@@ -127,7 +142,7 @@ struct BatchArgs {
     cetra_best_record *best;
     int32_t *done;          // [n_curves]
     int32_t *status;
-    int64_t n_curves, n_items;
+    int64_t n_curves, n_groups, n_items;
     uint64_t wait_ticks;    // wall-clock limit of one dependency wait
     int32_t resume;
     int32_t pop;            // items taken per queue pop (>= 1)
@@ -146,8 +161,9 @@ __global__ void batch_init_kernel(BatchArgs a) {
         a.ctr->abort_flag = 0u;
         a.status[0] = 0;
     }
-    for (int64_t i = tid; i < a.n_curves * kStages; i += stride) a.stage_done[i] = 0u;
+    for (int64_t i = tid; i < a.n_groups * kStages; i += stride) a.group_done[i] = 0u;
     for (int64_t c = tid; c < a.n_curves; c += stride) {
+        a.curve_epi[c] = 0u;
         a.bad[c] = 0u;
         a.best_keys[c] = 0ull;
         if (!a.resume) a.done[c] = 0;
@@ -179,13 +195,19 @@ __device__ __forceinline__ bool stop_requested(const BatchArgs &a) {
 
 // Called by every lane of one wave: wait until *counter >= need (acquire);
 // false when the batch is being stopped or the wait exceeded its limit.  The
-// loop's exit conditions are wave-uniform.
+// loop's exit conditions are wave-uniform.  The counter is polled with
+// relaxed loads and the acquire is one fence after the load that sees the
+// count complete (an acquire load per poll would invalidate the XCD's L2 on
+// every iteration of a spinning workgroup).
 __device__ bool wait_for(const BatchArgs &a, const uint32_t *counter, uint32_t need) {
     if (need == 0) return true;
     const uint64_t t0 = wall_clock64();
     for (;;) {
-        const uint32_t v = __hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (__builtin_amdgcn_readfirstlane(v) >= need) return true;
+        const uint32_t v = __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readfirstlane(v) >= need) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
         if (stop_requested(a)) return false;
         if (wall_clock64() - t0 > a.wait_ticks) {
             if (lane_zero()) {
@@ -235,9 +257,9 @@ __device__ void run_item(const BatchArgs &a, const Header *h, const CurveDesc &c
                          int32_t stage, int64_t idx, float *lds, int *s_bounds) {
     char *slot = a.arena + cd.slot_off;
     float *flux = reinterpret_cast<float *>(slot);
-    float *ivar = reinterpret_cast<float *>(slot + h->slot_ivar);
-    float2 *fold = reinterpret_cast<float2 *>(slot + h->slot_fold);
-    cetra::dev::PeriodInfo *ptab = reinterpret_cast<cetra::dev::PeriodInfo *>(slot + h->slot_ptab);
+    float *ivar = reinterpret_cast<float *>(slot + cd.ivar_off);
+    float2 *fold = reinterpret_cast<float2 *>(slot + cd.fold_off);
+    cetra::dev::PeriodInfo *ptab = reinterpret_cast<cetra::dev::PeriodInfo *>(slot + cd.ptab_off);
     const int64_t I = g.n_t0;
     if (stage == kRes) {
         const int64_t q0 = idx * kResPoints;
@@ -365,28 +387,30 @@ __device__ void finish_curve(const BatchArgs &a, const CurveDesc &cd, const cetr
     a.done[c] = __hip_atomic_load(&a.bad[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? -1 : 1;
 }
 
-// Called by every lane of one wave: adds n finished items of (curve c, stage)
-// to the stage's counter; release orders the items' stores (and atomics)
-// before the count.  The decode stage also acquires, as the call that
-// completes a curve's decode writes its best-period record from the others'.
+// Called by every lane of one wave: adds n finished items of (curve c,
+// stage) to the stage's counter of the curve's group; release orders the
+// items' stores (and atomics) before the count.  Decode items also count per
+// curve, with acquire and release: the call that completes a curve's decode
+// writes its best-period record from the other items' records, before the
+// group count.
 __device__ void count_items(const BatchArgs &a, const CurveDesc *curves, const cetra_grid *grids, int32_t c,
                             int32_t stage, uint32_t n, int32_t skipped) {
     if (n == 0) return;
-    uint32_t prev = 0;
-    if (lane_zero()) {
-        uint32_t *ctr = &a.stage_done[(int64_t)c * kStages + stage];
-        prev = stage == kEpi ? __hip_atomic_fetch_add(ctr, n, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT)
-                             : __hip_atomic_fetch_add(ctr, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    prev = __builtin_amdgcn_readfirstlane(prev);
-    if (stage == kEpi && !skipped) {
+    const int32_t g = __builtin_amdgcn_readfirstlane(curves[c].group);
+    if (stage == kEpi) {
+        uint32_t prev = 0;
+        if (lane_zero()) prev = __hip_atomic_fetch_add(&a.curve_epi[c], n, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        prev = __builtin_amdgcn_readfirstlane(prev);
         const uint32_t n_epi = __builtin_amdgcn_readfirstlane((uint32_t)curves[c].n_items[kEpi]);
-        if (prev + n == n_epi && lane_zero()) finish_curve(a, curves[c], grids[c], c);
+        if (!skipped && prev + n == n_epi && lane_zero()) finish_curve(a, curves[c], grids[c], c);
     }
+    if (lane_zero())
+        (void)__hip_atomic_fetch_add(&a.group_done[(int64_t)g * kStages + stage], n, __ATOMIC_RELEASE,
+                                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int B, int W>
-__global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(kThreads, 3) batch_kernel(BatchArgs a) {
     extern __shared__ float lds[];
     __shared__ int s_bounds[2];
     __shared__ long long s_item;
@@ -397,6 +421,7 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
         return;
     }
     const CurveDesc *curves = reinterpret_cast<const CurveDesc *>(a.tables + h->off_curves);
+    const GroupDesc *groups = reinterpret_cast<const GroupDesc *>(a.tables + h->off_groups);
     const cetra_grid *grids = reinterpret_cast<const cetra_grid *>(a.tables + h->off_grids);
     const Segment *segs = reinterpret_cast<const Segment *>(a.tables + h->off_segments);
     // The first wave takes items, waits on dependencies and counts
@@ -450,21 +475,22 @@ __global__ void __launch_bounds__(kThreads) batch_kernel(BatchArgs a) {
         const int64_t idx = uniform64(ir.idx);
         const CurveDesc &cd = curves[c];
         const bool other_run = pend_n != 0 && (c != pend_c || stage != pend_stage);
-        // dependency of the item: the previous stage of its curve, or for
-        // RES the decode of the curve that used its slot before
+        // dependency of the item: the previous stage of its curve's group,
+        // or for RES the decode of the group that used its slots before
         if (wave == 0) {
             if (other_run) count_items(a, curves, grids, pend_c, pend_stage, pend_n, pend_skip);
-            const int32_t prev_curve = __builtin_amdgcn_readfirstlane(cd.prev_in_slot);
+            const int32_t g = __builtin_amdgcn_readfirstlane(cd.group);
             const uint32_t *counter = nullptr;
             uint32_t need = 0;
             if (stage == kRes) {
-                if (prev_curve >= 0) {
-                    counter = &a.stage_done[(int64_t)prev_curve * kStages + kEpi];
-                    need = __builtin_amdgcn_readfirstlane((uint32_t)curves[prev_curve].n_items[kEpi]);
+                const int32_t pg = __builtin_amdgcn_readfirstlane(groups[g].prev_group);
+                if (pg >= 0) {
+                    counter = &a.group_done[(int64_t)pg * kStages + kEpi];
+                    need = __builtin_amdgcn_readfirstlane((uint32_t)groups[pg].n_items[kEpi]);
                 }
             } else {
-                counter = &a.stage_done[(int64_t)c * kStages + stage - 1];
-                need = __builtin_amdgcn_readfirstlane((uint32_t)cd.n_items[stage - 1]);
+                counter = &a.group_done[(int64_t)g * kStages + stage - 1];
+                need = __builtin_amdgcn_readfirstlane((uint32_t)groups[g].n_items[stage - 1]);
             }
             bool ok = true;
             if (counter && counter != seen_counter) {
@@ -522,9 +548,10 @@ struct cetra_batch_plan {
     Header h;
     std::vector<int32_t> order;
     int64_t n_curves, total_periods;
-    size_t off_counters, off_stage_done, off_bad, off_best_keys, off_keys, off_arena, slot_bytes;
+    size_t off_counters, off_group_done, off_curve_epi, off_bad, off_best_keys, off_keys, off_arena, arena_bytes;
     size_t workspace_bytes;
-    int32_t n_slots;
+    int32_t n_slots;   // curves whose slots are live at once
+    int32_t n_groups;
     int32_t *cancel_host;  // pinned flag of cetra_batch_cancel_flag, or NULL
 };
 
@@ -549,7 +576,6 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     CETRA_REQUIRE(d->obs_offsets[0] == 0 && d->period_offsets[0] == 0, "batch_plan: offsets must start at 0");
     std::vector<CurveDesc> cds(n);
     std::vector<double> cost(n);
-    size_t max_n = 1, max_fold = 8, max_per = 1;
     const int64_t tab_bytes = (int64_t)dev::template_table_entries(g0.n_model) * 8;
     const int32_t lds_cap = (int32_t)std::max<int64_t>(kLdsCapBytes, tab_bytes);
     int32_t lds_bytes = (int32_t)tab_bytes;
@@ -583,9 +609,6 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
         for (int s = 0; s < kStages; ++s)
             if (cd.n_items[s] >= (int64_t)UINT32_MAX)
                 return set_error(CETRA_ERR_RANGE, "batch_plan: curve %d has too many work items", c);
-        max_n = std::max(max_n, (size_t)g.n);
-        max_fold = std::max(max_fold, (size_t)8 * (size_t)g.n_dur * (size_t)g.n_t0);
-        max_per = std::max(max_per, (size_t)cd.n_per);
         cost[c] = (double)cd.n_per * g.n_dur * (double)g.n_t0;
         for (int j = 0; j < g.n_dur; ++j) {
             int32_t span_cap = 0;
@@ -608,40 +631,94 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     } else {
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     }
-    const int n_slots = std::min(kMaxSlots, n);
-    const size_t slot_ivar = align256(4 * max_n);
-    const size_t slot_fold = slot_ivar + align256(4 * max_n);
-    const size_t slot_ptab = slot_fold + align256(max_fold);
-    const size_t slot_bytes = slot_ptab + align256(sizeof(dev::PeriodInfo) * max_per);
+    // groups: consecutive curves in queue order, closed once their fold has
+    // kGroupFoldItems items (long curves form groups of one); dependencies
+    // and counters are per group, so a workgroup acquires once per group and
+    // stage rather than per curve
+    std::vector<int32_t> gfirst, gcount;
+    {
+        int64_t acc = 0;
+        for (int p = 0; p < n; ++p) {
+            if (gfirst.empty() || gcount.back() == kMaxGroup || acc >= kGroupFoldItems) {
+                gfirst.push_back(p);
+                gcount.push_back(0);
+                acc = 0;
+            }
+            cds[order[p]].group = (int32_t)(gfirst.size() - 1);
+            ++gcount.back();
+            acc += cds[order[p]].n_items[kFold];
+        }
+    }
+    const int n_groups = (int)gfirst.size();
+    std::vector<GroupDesc> grp(n_groups);
+    // slot sets: group gi uses set gi mod S, with one slot per curve sized
+    // for that curve; a set holds the largest of the groups it serves
+    const int n_sets = std::min(kMaxSlots, n_groups);
+    std::vector<size_t> set_bytes(n_sets, 0), grp_bytes(n_groups, 0);
+    for (int gi = 0; gi < n_groups; ++gi) {
+        GroupDesc &gd = grp[gi];
+        std::memset(&gd, 0, sizeof gd);
+        gd.prev_group = gi >= n_sets ? gi - n_sets : -1;
+        gd.n_curves = gcount[gi];
+        size_t off_in_group = 0;
+        for (int p = gfirst[gi]; p < gfirst[gi] + gcount[gi]; ++p) {
+            CurveDesc &cd = cds[order[p]];
+            const cetra_grid &g = d->grids[order[p]];
+            cd.ivar_off = (int64_t)align256(4 * (size_t)g.n);
+            cd.fold_off = cd.ivar_off + (int64_t)align256(4 * (size_t)g.n);
+            cd.ptab_off = cd.fold_off + (int64_t)align256((size_t)8 * g.n_dur * (size_t)g.n_t0);
+            cd.slot_off = (int64_t)off_in_group;  // relative to the set for now
+            off_in_group += (size_t)cd.ptab_off + align256(sizeof(dev::PeriodInfo) * (size_t)std::max<int64_t>(cd.n_per, 1));
+            for (int st = 0; st < kStages; ++st) gd.n_items[st] += cd.n_items[st];
+        }
+        for (int st = 0; st < kStages; ++st)
+            if (gd.n_items[st] >= (int64_t)UINT32_MAX)
+                return set_error(CETRA_ERR_RANGE, "batch_plan: group %d has too many work items", gi);
+        grp_bytes[gi] = off_in_group;
+        set_bytes[gi % n_sets] = std::max(set_bytes[gi % n_sets], off_in_group);
+    }
+    std::vector<size_t> set_off(n_sets, 0);
+    size_t arena_bytes = 0;
+    for (int si = 0; si < n_sets; ++si) {
+        set_off[si] = arena_bytes;
+        arena_bytes += set_bytes[si];
+    }
+    int32_t resident = 0;  // curves whose slots are live at once: the largest group of each set
+    {
+        std::vector<int32_t> set_max(n_sets, 0);
+        for (int gi = 0; gi < n_groups; ++gi) set_max[gi % n_sets] = std::max(set_max[gi % n_sets], gcount[gi]);
+        for (int si = 0; si < n_sets; ++si) resident += set_max[si];
+    }
     for (int p = 0; p < n; ++p) {
         CurveDesc &cd = cds[order[p]];
-        cd.slot_off = (int64_t)((size_t)(p % n_slots) * slot_bytes);
-        cd.prev_in_slot = p >= n_slots ? order[p - n_slots] : -1;
+        cd.slot_off += (int64_t)set_off[cd.group % n_sets];
     }
     // items in queue order
     std::vector<Segment> segs;
     int64_t item = 0;
-    auto emit = [&](int p, int st) {
-        if (p < 0 || p >= n) return;
-        const int c = order[p];
-        if (cds[c].n_items[st] == 0) return;
-        segs.push_back(Segment{item, c, st});
-        item += cds[c].n_items[st];
+    auto emit_group = [&](int gi, int st) {
+        if (gi < 0 || gi >= n_groups) return;
+        for (int p = gfirst[gi]; p < gfirst[gi] + gcount[gi]; ++p) {
+            const int c = order[p];
+            if (cds[c].n_items[st] == 0) continue;
+            segs.push_back(Segment{item, c, st});
+            item += cds[c].n_items[st];
+        }
     };
-    // slot reuse needs RES(p), queued at step p - kLinAhead, after EPI(p - S),
-    // queued at step p - S + kEpiLag
+    // slot reuse needs RES(group gi), queued at step gi - kLinAhead, after
+    // EPI(group gi - S), queued at step gi - S + kEpiLag
     static_assert(kMaxSlots > kLinAhead + kEpiLag, "a slot's next user would be queued before its last");
-    for (int p = 0; p < kLinAhead; ++p) {
-        emit(p, kRes);
-        emit(p, kLin);
+    for (int gi = 0; gi < kLinAhead; ++gi) {
+        emit_group(gi, kRes);
+        emit_group(gi, kLin);
     }
-    for (int r = 0; r < n; ++r) {
-        emit(r, kFold);
-        emit(r - kEpiLag, kEpi);
-        emit(r + kLinAhead, kRes);
-        emit(r + kLinAhead, kLin);
+    for (int r = 0; r < n_groups; ++r) {
+        emit_group(r, kFold);
+        emit_group(r - kEpiLag, kEpi);
+        emit_group(r + kLinAhead, kRes);
+        emit_group(r + kLinAhead, kLin);
     }
-    for (int p = std::max(0, n - kEpiLag); p < n; ++p) emit(p, kEpi);
+    for (int gi = std::max(0, n_groups - kEpiLag); gi < n_groups; ++gi) emit_group(gi, kEpi);
 
     auto *plan = new (std::nothrow) cetra_batch_plan;
     if (!plan) return set_error(CETRA_ERR_INVALID, "batch_plan: out of host memory");
@@ -650,19 +727,19 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     h.magic = kMagic;
     h.plan_id = next_plan_id();
     h.n_curves = n;
+    h.n_groups = n_groups;
     h.n_segments = (int64_t)segs.size();
     h.n_items = item;
     size_t off = align256(sizeof(Header));
     h.off_curves = (int64_t)off;
     off += align256(sizeof(CurveDesc) * n);
+    h.off_groups = (int64_t)off;
+    off += align256(sizeof(GroupDesc) * n_groups);
     h.off_grids = (int64_t)off;
     off += align256(sizeof(cetra_grid) * n);
     h.off_segments = (int64_t)off;
     off += align256(sizeof(Segment) * std::max<size_t>(segs.size(), 1));
     h.tables_bytes = (int64_t)off;
-    h.slot_ivar = (int64_t)slot_ivar;
-    h.slot_fold = (int64_t)slot_fold;
-    h.slot_ptab = (int64_t)slot_ptab;
     h.period_block = B;
     h.linear_windows = W;
     h.pop_items = d->pop_items;
@@ -672,17 +749,22 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     plan->tables.assign(off, 0);
     std::memcpy(plan->tables.data(), &h, sizeof h);
     std::memcpy(plan->tables.data() + h.off_curves, cds.data(), sizeof(CurveDesc) * n);
+    std::memcpy(plan->tables.data() + h.off_groups, grp.data(), sizeof(GroupDesc) * n_groups);
     std::memcpy(plan->tables.data() + h.off_grids, d->grids, sizeof(cetra_grid) * n);
     if (!segs.empty()) std::memcpy(plan->tables.data() + h.off_segments, segs.data(), sizeof(Segment) * segs.size());
     plan->order = order;
     plan->n_curves = n;
+    plan->n_groups = n_groups;
     plan->total_periods = d->period_offsets[n];
-    // workspace: tables | counters | per-curve stage counters | bad flags | best keys | keys | slots
+    // workspace: tables | counters | group stage counters | curve decode
+    // counters | bad flags | best keys | keys | slots
     size_t w = off;
     plan->off_counters = w;
     w += align256(sizeof(Counters));
-    plan->off_stage_done = w;
-    w += align256(sizeof(uint32_t) * kStages * (size_t)n);
+    plan->off_group_done = w;
+    w += align256(sizeof(uint32_t) * kStages * (size_t)n_groups);
+    plan->off_curve_epi = w;
+    w += align256(sizeof(uint32_t) * (size_t)n);
     plan->off_bad = w;
     w += align256(sizeof(uint32_t) * (size_t)n);
     plan->off_best_keys = w;
@@ -690,10 +772,10 @@ extern "C" int cetra_batch_plan_create(const cetra_batch_desc *d, cetra_batch_pl
     plan->off_keys = w;
     w += align256(sizeof(uint64_t) * (size_t)std::max<int64_t>(plan->total_periods, 1));
     plan->off_arena = w;
-    w += slot_bytes * (size_t)n_slots;
-    plan->slot_bytes = slot_bytes;
+    w += arena_bytes;
+    plan->arena_bytes = arena_bytes;
     plan->workspace_bytes = w;
-    plan->n_slots = n_slots;
+    plan->n_slots = resident;
     plan->cancel_host = nullptr;
     *out = plan;
     return CETRA_OK;
@@ -782,7 +864,8 @@ extern "C" int cetra_batch_search(const cetra_batch_plan *plan, void *stream, co
     a.tables = w;
     a.plan_id = plan->h.plan_id;
     a.ctr = reinterpret_cast<Counters *>(w + plan->off_counters);
-    a.stage_done = reinterpret_cast<uint32_t *>(w + plan->off_stage_done);
+    a.group_done = reinterpret_cast<uint32_t *>(w + plan->off_group_done);
+    a.curve_epi = reinterpret_cast<uint32_t *>(w + plan->off_curve_epi);
     a.bad = reinterpret_cast<uint32_t *>(w + plan->off_bad);
     a.best_keys = reinterpret_cast<uint64_t *>(w + plan->off_best_keys);
     a.keys = reinterpret_cast<uint64_t *>(w + plan->off_keys);
@@ -803,6 +886,7 @@ extern "C" int cetra_batch_search(const cetra_batch_plan *plan, void *stream, co
     a.done = done;
     a.status = status;
     a.n_curves = plan->n_curves;
+    a.n_groups = plan->n_groups;
     a.n_items = plan->h.n_items;
     a.resume = (flags & CETRA_BATCH_RESUME) ? 1 : 0;
     a.wait_ticks = (uint64_t)(wall_clock_hz() * 30.0);  // 30 s: far beyond any item's run time

@@ -74,6 +74,23 @@ __global__ void downsample_kernel(const float2 *__restrict__ fold, int32_t J, in
     x[id] = (__bf16)(fminf(sqrtf(best), 30.0f) * 0.125f);
 }
 
+// x[b][bin][j] = clamp(z, -30, 30) / 8 with z = max over the reference times
+// of the bin of S_fm / sqrt(S_mm) (signed single-event SNR, max-pooled: a
+// dimming gives S_fm > 0); a bin with only null elements gives 0.
+__global__ void downsample_signed_kernel(const float2 *__restrict__ fold, int32_t J, int64_t I, int32_t L,
+                                         __bf16 *__restrict__ x) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)J * L) return;
+    const int32_t bin = (int32_t)(id / J), j = (int32_t)(id % J);
+    const int64_t i0 = (int64_t)bin * I / L, i1 = (int64_t)(bin + 1) * I / L;
+    float best = -INFINITY;
+    for (int64_t i = i0; i < i1; ++i) {
+        const float2 v = fold[(int64_t)j * I + i];
+        if (v.y > 0.0f) best = fmaxf(best, v.x / sqrtf(v.y));
+    }
+    x[id] = (__bf16)(best == -INFINITY ? 0.0f : fminf(fmaxf(best, -30.0f), 30.0f) * 0.125f);
+}
+
 // ------------------------------------------------------------ conv forward
 // Implicit GEMM with a 64 x 64 register tile per wave.  Workgroup: 512
 // positions x 64 output channels of one example (8 waves); wave w owns
@@ -458,6 +475,17 @@ extern "C" int cetra_net_downsample(void *stream, const float *fold, int32_t n_d
     hipLaunchKernelGGL(downsample_kernel, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, as_stream(stream),
                        reinterpret_cast<const float2 *>(fold), n_dur, n_t0, n_bins, (__bf16 *)x);
     return check_launch("net_downsample");
+}
+
+extern "C" int cetra_net_downsample_signed(void *stream, const float *fold, int32_t n_dur, int64_t n_t0,
+                                           int32_t n_bins, void *x) {
+    clear_error();
+    CETRA_REQUIRE(fold && x, "net_downsample_signed: NULL pointer");
+    CETRA_REQUIRE(n_dur >= 1 && n_t0 >= 1 && n_bins >= 1 && n_bins <= n_t0, "net_downsample_signed: bad sizes");
+    const int64_t n = (int64_t)n_dur * n_bins;
+    hipLaunchKernelGGL(downsample_signed_kernel, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, as_stream(stream),
+                       reinterpret_cast<const float2 *>(fold), n_dur, n_t0, n_bins, (__bf16 *)x);
+    return check_launch("net_downsample_signed");
 }
 
 static int conv_args_ok(int32_t cin, int32_t L, int32_t batch, int32_t k32) {

@@ -62,16 +62,20 @@ class Pipeline:
 
     # ------------------------------------------------------------ features
     def linear(self, t, f, sigma):
-        """Resample + linear search: fold-ready [J][I][2] (device)."""
+        """Resample + linear search: fold-ready [J][I][2] (device).  The
+        times must be finite and ascending: this path skips resample's order
+        check (status=False) so that it stays free of host synchronisation;
+        resample(status=True) or the batched search report unsorted input."""
         flux, ivar, _ = resample(self.grid, t, f, sigma, status=False)
         return linear_search(self.grid, flux, ivar, self.model)
 
-    def features(self, fold, out=None):
+    def features(self, fold, out=None, signed: bool = False):
         """bf16 [n_bins][16] network input from a fold-ready array (its
-        feature rows only, when the grid has more durations)."""
+        feature rows only, when the grid has more durations): the binned
+        |SNR|, or the signed SNR for a network trained on it."""
         if self.rows is not None:
             fold = fold.index_select(0, self.rows)
-        return downsample(fold, self.cfg.n_bins, out=out)
+        return downsample(fold, self.cfg.n_bins, out=out, signed=signed)
 
     # -------------------------------------------------------------- search
     def plain(self, fold):
@@ -102,7 +106,7 @@ class Pipeline:
         result is returned instead.  Returns (host best record, restricted
         SNR (-inf when nothing was folded), fell back, periods folded).  The
         window scores [1][W] stay in `last_scores`."""
-        x = self.features(fold)
+        x = self.features(fold, signed=net.signed_input)
         z = net.forward(x.unsqueeze(0), self.windows)
         self.last_scores = z
         sel = topk_windows(z, int(top_k or self.cfg.top_k))
@@ -122,7 +126,7 @@ class Pipeline:
         from .proposal import C_IN
         x = torch.empty((len(folds), self.cfg.n_bins, C_IN), dtype=torch.bfloat16, device="cuda")
         for b, fold in enumerate(folds):
-            self.features(fold, out=x[b])
+            self.features(fold, out=x[b], signed=net.signed_input)
         z = net.forward(x, self.windows)
         self.last_scores = z
         sel = topk_windows(z, int(top_k or self.cfg.top_k))
@@ -171,6 +175,7 @@ def load_weights(path: str) -> tuple:
         if meta.get("pool", "fold") != "fold":
             raise ValueError(f"{path}: weights of an unsupported pooling ({meta.get('pool')})")
         net = ProposalNet(n_event=meta["n_event"], hidden=meta["hidden"], n_trial=meta.get("n_trial", 4))
+        net.signed_input = meta.get("input", "abs") == "signed"
         import torch
         for name in net.offsets:
             net.view(name).copy_(torch.as_tensor(z[name]))

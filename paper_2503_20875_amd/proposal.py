@@ -105,6 +105,7 @@ class ProposalNet:
         if not (1 <= self.E <= 16 and 1 <= self.H <= 128 and 1 <= n_trial <= 32):
             raise ValueError("proposal net: need 1 <= n_event <= 16, 1 <= hidden <= 128, 1 <= n_trial <= 32")
         self.S = int(n_trial)
+        self.signed_input = False  # input features: |SNR| (False) or signed SNR (True)
         self.nf = self.E + 1
         shapes = []
         cin = C_IN
@@ -332,13 +333,16 @@ def conv1d_bwd(dy, y, x, w_packed, stream=None):
     return dx, dw, db
 
 
-def downsample(fold, n_bins: int, out=None, stream=None):
-    """fold-ready FP32 [J][I][2] -> bf16 [n_bins][J] single-event features."""
+def downsample(fold, n_bins: int, out=None, signed: bool = False, stream=None):
+    """fold-ready FP32 [J][I][2] -> bf16 [n_bins][J] single-event features:
+    the bin's largest |SNR| (cetra_net_downsample), or with signed=True its
+    largest signed SNR (cetra_net_downsample_signed)."""
     import torch
     J, I = int(fold.shape[0]), int(fold.shape[1])
     if out is None:
         out = torch.empty((n_bins, J), dtype=torch.bfloat16, device="cuda")
-    _abi.check(_lib().cetra_net_downsample(_stream(stream), _ptr(fold), J, I, int(n_bins), _ptr(out)))
+    fn = _lib().cetra_net_downsample_signed if signed else _lib().cetra_net_downsample
+    _abi.check(fn(_stream(stream), _ptr(fold), J, I, int(n_bins), _ptr(out)))
     return out
 
 

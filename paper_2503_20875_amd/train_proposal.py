@@ -80,7 +80,7 @@ def labels_for(pipe, injections) -> np.ndarray:
 
 
 def build_dataset(pipe, n: int, seed: int, workload: str = "learned", plain_labels: bool = False,
-                  snr_min: float = 7.0):
+                  snr_min: float = 7.0, signed: bool = False):
     """Device features [n][n_bins][16] (bf16) and labels [n][W], plus the
     injections of every curve.  With plain_labels the full periodic search
     also runs on every curve and its best period's window is marked when its
@@ -98,7 +98,7 @@ def build_dataset(pipe, n: int, seed: int, workload: str = "learned", plain_labe
         t, f, s, inj = draw()
         fold = pipe.linear(torch.as_tensor(t, device="cuda"), torch.as_tensor(f, device="cuda"),
                            torch.as_tensor(s, device="cuda"))
-        pipe.features(fold, out=x[i])
+        pipe.features(fold, out=x[i], signed=signed)
         y[i] = labels_for(pipe, inj)
         if plain_labels:
             rec = pipe.plain(fold)
@@ -125,6 +125,8 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="learned", choices=["learned", "long"])
     ap.add_argument("--plain-labels", action="store_true",
                     help="also label each curve's full-search best window when its SNR is at least 7")
+    ap.add_argument("--signed-input", action="store_true",
+                    help="network input: the binned signed single-event SNR instead of its absolute value")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
 
@@ -137,12 +139,14 @@ def main(argv=None) -> int:
     pipe = make_pipeline(workload=a.workload)
     log(f"grid I={pipe.grid.n_t0} J={pipe.grid.n_dur} K={pipe.K} windows={pipe.windows.n} "
         f"bin {pipe.windows.bin_days:.5f} d")
-    x, y, _ = build_dataset(pipe, a.n_train, a.seed, a.workload, plain_labels=a.plain_labels)
+    x, y, _ = build_dataset(pipe, a.n_train, a.seed, a.workload, plain_labels=a.plain_labels,
+                            signed=a.signed_input)
     log(f"labelled windows per curve {float(y.sum()) / a.n_train:.3f}")
     net = ProposalNet(n_event=pipe.cfg.n_event, hidden=pipe.cfg.hidden, seed=a.seed, n_trial=a.n_trial)
+    net.signed_input = bool(a.signed_input)
     losses = train(net, x, y, pipe.windows, a.epochs, a.batch, a.lr, a.pos_weight, seed=a.seed, log=log)
     meta = dict(n_event=net.E, hidden=net.H, pool="fold", n_trial=net.S, workload=a.workload,
-                plain_labels=bool(a.plain_labels),
+                plain_labels=bool(a.plain_labels), input="signed" if a.signed_input else "abs",
                 feature_rows=list(pipe.cfg.feature_rows), n_train=a.n_train, epochs=a.epochs,
                 batch=a.batch, lr=a.lr,
                 pos_weight=a.pos_weight, seed=a.seed, losses=losses, n_bins=pipe.cfg.n_bins,

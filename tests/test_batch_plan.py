@@ -18,27 +18,30 @@ import heapq
 import numpy as np
 import pytest
 
-HEADER = np.dtype([("magic", "<u8"), ("plan_id", "<u8"), ("n_curves", "<i8"), ("n_segments", "<i8"),
-                   ("n_items", "<i8"), ("off_curves", "<i8"), ("off_grids", "<i8"), ("off_segments", "<i8"),
-                   ("tables_bytes", "<i8"), ("slot_ivar", "<i8"), ("slot_fold", "<i8"), ("slot_ptab", "<i8"),
-                   ("period_block", "<i4"),
-                   ("lds_bytes", "<i4"), ("lds_cap", "<i4"), ("linear_windows", "<i4"),
+HEADER = np.dtype([("magic", "<u8"), ("plan_id", "<u8"), ("n_curves", "<i8"), ("n_groups", "<i8"),
+                   ("n_segments", "<i8"), ("n_items", "<i8"), ("off_curves", "<i8"), ("off_groups", "<i8"),
+                   ("off_grids", "<i8"), ("off_segments", "<i8"), ("tables_bytes", "<i8"),
+                   ("period_block", "<i4"), ("lds_bytes", "<i4"), ("lds_cap", "<i4"), ("linear_windows", "<i4"),
                    ("pop_items", "<i4"), ("reserved", "<i4")])
 CURVE = np.dtype([("obs_off", "<i8"), ("n_obs", "<i8"), ("per_off", "<i8"), ("n_per", "<i8"), ("slot_off", "<i8"),
-                  ("n_items", "<i8", (4,)), ("prev_in_slot", "<i4"), ("n_res", "<i4"), ("n_lin_per_dur", "<i4"),
-                  ("n_pblk", "<i4"), ("n_chunks", "<i4"), ("n_tiles", "<i4")])
+                  ("ivar_off", "<i8"), ("fold_off", "<i8"), ("ptab_off", "<i8"), ("n_items", "<i8", (4,)),
+                  ("group", "<i4"), ("n_res", "<i4"), ("n_lin_per_dur", "<i4"), ("n_pblk", "<i4"),
+                  ("n_chunks", "<i4"), ("n_tiles", "<i4")])
+GROUP = np.dtype([("n_items", "<i8", (4,)), ("prev_group", "<i4"), ("n_curves", "<i4")])
 SEGMENT = np.dtype([("first", "<i8"), ("curve", "<i4"), ("stage", "<i4")])
 RES, LIN, FOLD, EPI = range(4)
 RES_POINTS, LIN_TILES, THREADS, EPI_PERIODS = 2048, 4, 256, 256
 PERIOD_INFO_BYTES = 24  # u64 step, i32 epochs, i32 jlo, i32 jhi, padded to 8
+MAX_SETS, MAX_GROUP, GROUP_FOLD_ITEMS = 8, 16, 49152
 
 
 def parse(plan):
     raw = plan.tables()
     h = np.frombuffer(raw, HEADER, count=1)[0]
     cur = np.frombuffer(raw, CURVE, count=int(h["n_curves"]), offset=int(h["off_curves"]))
+    grp = np.frombuffer(raw, GROUP, count=int(h["n_groups"]), offset=int(h["off_groups"]))
     seg = np.frombuffer(raw, SEGMENT, count=int(h["n_segments"]), offset=int(h["off_segments"]))
-    return h, cur, seg
+    return h, cur, grp, seg
 
 
 def make(cm, curves, **kw):
@@ -57,18 +60,26 @@ def segments_of(h, seg):
     return out
 
 
-def dependency(cur, c, stage):
-    """(curve, stage) whose items must all be complete first, or None."""
+def dependency(cur, grp, c, stage):
+    """The (curve, stage) keys whose items must all be complete first: the
+    previous stage of every curve of c's group, or for RES the decode of
+    every curve of the group that used the slot set before."""
+    g = int(cur[c]["group"])
+    members = lambda gi: [k for k in range(len(cur)) if int(cur[k]["group"]) == gi]
     if stage == RES:
-        p = int(cur[c]["prev_in_slot"])
-        return None if p < 0 else (p, EPI)
-    return (c, stage - 1)
+        pg = int(grp[g]["prev_group"])
+        return [] if pg < 0 else [(k, EPI) for k in members(pg)]
+    return [(k, stage - 1) for k in members(g)]
+
+
+def slot_size(cur, c):
+    return int(cur[c]["ptab_off"]) + PERIOD_INFO_BYTES * max(int(cur[c]["n_per"]), 1)
 
 
 def check_plan(cm, curves, grids, oo, po, plan):
-    h, cur, seg = parse(plan)
+    h, cur, grp, seg = parse(plan)
     n = len(curves)
-    assert h["n_curves"] == n and h["n_segments"] == len(seg)
+    assert h["n_curves"] == n and h["n_segments"] == len(seg) and h["n_groups"] == len(grp)
     B = int(h["period_block"])
     Wl = int(h["linear_windows"])
     assert Wl in (1, 2)
@@ -85,22 +96,31 @@ def check_plan(cm, curves, grids, oo, po, plan):
                 f, e = rng[(c, st)]
                 assert e - f == cnt, (c, st)
     assert sum(int(x) for x in cur["n_items"].sum(axis=1)) == h["n_items"]
+    # groups: consecutive in queue order, closed by size or fold items, with
+    # per-stage sums and the previous user of their slot set
+    order = plan.order()
+    G = len(grp)
+    S = min(MAX_SETS, G)
+    gseq = [int(cur[c]["group"]) for c in order]
+    assert gseq[0] == 0 and all(b - a in (0, 1) for a, b in zip(gseq, gseq[1:])) and gseq[-1] == G - 1
+    for gi in range(G):
+        mem = [c for c in order if int(cur[c]["group"]) == gi]
+        assert int(grp[gi]["n_curves"]) == len(mem) <= MAX_GROUP
+        assert np.array_equal(grp[gi]["n_items"], cur[mem]["n_items"].sum(axis=0))
+        assert int(grp[gi]["prev_group"]) == (gi - S if gi >= S else -1)
+        fold_before_last = int(cur[mem[:-1]]["n_items"][:, FOLD].sum()) if len(mem) > 1 else 0
+        assert fold_before_last < GROUP_FOLD_ITEMS  # a group closes only once it has enough fold items
     # dependencies sit earlier in the queue
     for (c, st), (f, e) in rng.items():
-        dep = dependency(cur, c, st)
-        if dep is None or dep not in rng:
-            continue
-        assert rng[dep][1] <= f, ((c, st), dep, rng[dep], (f, e))
+        for dep in dependency(cur, grp, c, st):
+            if dep in rng:
+                assert rng[dep][1] <= f, ((c, st), dep, rng[dep], (f, e))
     # bounds of what items index
-    order = plan.order()
-    n_slots = plan.info["n_slots"]
-    slot_bytes = None
     for p, c in enumerate(order):
         g = grids[c]
         d = cur[c]
         assert d["obs_off"] == oo[c] and d["n_obs"] == oo[c + 1] - oo[c]
         assert d["per_off"] == po[c] and d["n_per"] == po[c + 1] - po[c]
-        assert d["prev_in_slot"] == (order[p - n_slots] if p >= n_slots else -1)
         assert d["n_res"] * RES_POINTS >= g.n > (d["n_res"] - 1) * RES_POINTS
         assert d["n_tiles"] * THREADS * Wl >= g.n_t0 > (d["n_tiles"] - 1) * THREADS * Wl
         assert d["n_lin_per_dur"] * LIN_TILES >= d["n_tiles"]
@@ -109,22 +129,25 @@ def check_plan(cm, curves, grids, oo, po, plan):
         assert d["n_items"][FOLD] == g.n_dur * d["n_pblk"] * d["n_chunks"]
         assert 1 <= d["n_chunks"] <= 64
         assert d["n_items"][EPI] == max(1, -(-int(d["n_per"]) // EPI_PERIODS))
-        # slot p mod n_slots; flux, ivar and the fold-ready array fit the slot
-        assert d["slot_off"] % 256 == 0
-        if p < n_slots:
-            assert d["slot_off"] == p * (cur[order[1]]["slot_off"] if n_slots > 1 else 0)
-        assert h["slot_ivar"] >= 4 * g.n and h["slot_fold"] - h["slot_ivar"] >= 4 * g.n
-        assert h["slot_ptab"] - h["slot_fold"] >= 8 * g.n_dur * g.n_t0
-        if n_slots > 1:
-            slot_bytes = int(cur[order[1]]["slot_off"])
-            assert slot_bytes - h["slot_ptab"] >= PERIOD_INFO_BYTES * d["n_per"]
+        # the slot: flux, ivar, the fold-ready array and the period table fit
+        assert d["slot_off"] % 256 == 0 and d["ivar_off"] >= 4 * g.n and d["fold_off"] - d["ivar_off"] >= 4 * g.n
+        assert d["ptab_off"] - d["fold_off"] >= 8 * g.n_dur * g.n_t0
+        assert slot_size(cur, c) + d["slot_off"] <= plan.info["workspace_bytes"]
         assert g.n_t0 < 1 << 28
-    assert plan.info["workspace_bytes"] >= h["tables_bytes"] + n_slots * (slot_bytes or h["slot_fold"])
+    # slots of curves that can be live together do not overlap: curves of one
+    # group, and of groups in different slot sets
+    spans = [(int(cur[c]["slot_off"]), int(cur[c]["slot_off"]) + slot_size(cur, c), int(cur[c]["group"]))
+             for c in range(n)]
+    for i in range(n):
+        for k in range(i + 1, n):
+            a, b = spans[i], spans[k]
+            if a[2] == b[2] or a[2] % S != b[2] % S:
+                assert a[1] <= b[0] or b[1] <= a[0], (i, k, a, b)
     assert 0 < h["lds_bytes"] <= h["lds_cap"]
-    return h, cur, seg, rng
+    return h, cur, grp, seg, rng
 
 
-def simulate(cur, rng, n_items, workers, seed):
+def simulate(cur, grp, rng, n_items, workers, seed):
     """Workgroups pop items in queue order; an item whose dependency is not
     complete waits (holding its workgroup) until it is.  Returns the finish
     time; raises if the queue stops with items outstanding (a deadlock)."""
@@ -135,6 +158,7 @@ def simulate(cur, rng, n_items, workers, seed):
     owner.sort()
     done = {k: 0 for k in rng}
     need = {k: e - f for k, (f, e) in rng.items()}
+    deps = {k: [d for d in dependency(cur, grp, *k) if d in rng] for k in rng}
     head, t, running, waiting = 0, 0.0, [], []
     free = workers
     finished = 0
@@ -146,8 +170,7 @@ def simulate(cur, rng, n_items, workers, seed):
             waiting.append((c, st))
         still = []
         for c, st in waiting:
-            dep = dependency(cur, c, st)
-            if dep is None or dep not in rng or done[dep] == need[dep]:
+            if all(done[d] == need[d] for d in deps[(c, st)]):
                 heapq.heappush(running, (t + r.uniform(0.5, 2.0), c, st))
             else:
                 still.append((c, st))
@@ -161,7 +184,7 @@ def simulate(cur, rng, n_items, workers, seed):
     return t
 
 
-def simulate_runs(cur, rng, n_items, workers, pop, seed):
+def simulate_runs(cur, grp, rng, n_items, workers, pop, seed):
     """The kernel's queue protocol with runs: a workgroup pops `pop`
     consecutive items, runs them in order, and adds its finished items of one
     (curve, stage) to that stage's counter only before it moves to another
@@ -175,6 +198,7 @@ def simulate_runs(cur, rng, n_items, workers, pop, seed):
             key_of[i] = k
     counted = {k: 0 for k in rng}
     need = {k: e - f for k, (f, e) in rng.items()}
+    deps = {k: [d for d in dependency(cur, grp, *k) if d in rng] for k in rng}
     state = {"head": 0, "t": 0.0}
     wgs = [dict(next=0, end=0, pend=None, n=0, mode="idle") for _ in range(workers)]
     running = []
@@ -197,8 +221,7 @@ def simulate_runs(cur, rng, n_items, workers, pop, seed):
         k = key_of[w["next"]]
         if w["n"] and k != w["pend"]:
             flush(w)
-        dep = dependency(cur, *k)
-        if dep is None or dep not in rng or counted[dep] == need[dep]:
+        if all(counted[d] == need[d] for d in deps[k]):
             heapq.heappush(running, (state["t"] + r.uniform(0.5, 2.0), i))
             w["mode"] = "run"
         else:
@@ -252,13 +275,27 @@ def _batch(n, seed, n_min=2000, n_max=15000, thin=25, edges=True):
 def test_plan_tables_queue_and_bounds(cm, n, seed, shuffle, block):
     curves = _batch(n, seed)
     grids, oo, po, plan = make(cm, curves, period_block=block, shuffle_seed=shuffle)
-    h, cur, seg, rng = check_plan(cm, curves, grids, oo, po, plan)
+    h, cur, grp, seg, rng = check_plan(cm, curves, grids, oo, po, plan)
     assert plan.info["n_launches"] == 2
     assert plan.info["n_items"] == h["n_items"]
     for workers in (1, 3, 64):
-        simulate(cur, rng, int(h["n_items"]), workers, seed)
+        simulate(cur, grp, rng, int(h["n_items"]), workers, seed)
     for workers, pop in ((1, 8), (3, 2), (7, 64), (64, 3)):
-        simulate_runs(cur, rng, int(h["n_items"]), workers, pop, seed)
+        simulate_runs(cur, grp, rng, int(h["n_items"]), workers, pop, seed)
+
+
+def test_plan_groups_reuse_slot_sets(cm):
+    """Many small curves: groups of up to 16 curves, more groups than slot
+    sets, so every set is reused; the tables, slot spans and queue checks
+    hold, and the queue drains under both protocols."""
+    curves = _batch(160, 13, n_min=2000, n_max=6000, thin=2000, edges=False)
+    grids, oo, po, plan = make(cm, curves)
+    h, cur, grp, seg, rng = check_plan(cm, curves, grids, oo, po, plan)
+    assert len(grp) > MAX_SETS and int(grp["n_curves"].max()) > 1
+    assert np.any(grp["prev_group"] >= 0)
+    for workers in (1, 16):
+        simulate(cur, grp, rng, int(h["n_items"]), workers, 3)
+    simulate_runs(cur, grp, rng, int(h["n_items"]), 16, 8, 3)
 
 
 def test_plan_order_is_by_fold_cost_or_seeded(cm):

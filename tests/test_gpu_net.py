@@ -326,6 +326,8 @@ def test_downsample(torch, pn):
         fold[:, ::7, 1] = 0.0  # null elements
         fold[min(3, J - 1), :, 0] = 1e4  # saturates at 30
         fold[0, : I // nb + 1, 1] = 0.0  # the first bin of duration 0 is all null
+        jn = 1 % J
+        fold[jn, : 2 * (I // nb) + 2, 0] = -np.abs(fold[jn, : 2 * (I // nb) + 2, 0]) - 0.25  # brightenings only
         print(f"[case] downsample J={J} I={I} bins={nb}", flush=True)
         out = pn.downsample(torch.as_tensor(fold, device="cuda"), nb).float().cpu().numpy()
         ref = onet.downsample(fold, nb)
@@ -333,3 +335,8 @@ def test_downsample(torch, pn):
         assert np.all(np.abs(out - ref) <= 2.0 ** -8 * ref + 1e-6), np.max(np.abs(out - ref) - 2.0 ** -8 * ref)
         sat = ref[:, min(3, J - 1)] == 3.75
         assert sat.sum() > nb // 2 and np.all(out[:, min(3, J - 1)][sat] == 3.75) and out[0, 0] == 0.0
+        # the signed form: largest S_fm / sqrt(S_mm), clipped to [-30, 30]
+        out_s = pn.downsample(torch.as_tensor(fold, device="cuda"), nb, signed=True).float().cpu().numpy()
+        ref_s = onet.downsample_signed(fold, nb)
+        assert np.all(np.abs(out_s - ref_s) <= 2.0 ** -8 * np.abs(ref_s) + 1e-6)
+        assert out_s[0, 0] == 0.0 and (J == 1 or (ref_s[1, jn] < 0 and out_s[1, jn] < 0))

@@ -114,6 +114,21 @@ def test_fold_pool_decides_in_fp32():
     assert net.score32(3.0, 7) == np.float32(3.0) * np.float32(1.0 / np.sqrt(7.0))
 
 
+def test_downsample_signed_keeps_the_sign():
+    """Signed input on hand-made pairs: per bin the largest S_fm/sqrt(S_mm)
+    with its sign, null elements skipped, an all-null bin 0, clipping at
+    +-30 before the division by 8; the |SNR| input of the same pairs is the
+    bin's largest absolute value."""
+    fold = np.zeros((1, 6, 2))
+    fold[0, :, 0] = [-2.0, -8.0, 3.0, 1.0, 0.0, -1e4]
+    fold[0, :, 1] = [4.0, 16.0, 9.0, 0.0, 0.0, 1.0]
+    x = net.downsample_signed(fold, 3)       # bins {0,1}, {2,3}, {4,5}
+    assert x[:, 0].tolist() == [-1.0 / 8.0, 1.0 / 8.0, -30.0 / 8.0]
+    fold[0, 4:, 1] = 0.0                     # the last bin all null
+    assert net.downsample_signed(fold, 3)[2, 0] == 0.0
+    assert net.downsample(fold, 3)[:, 0].tolist() == [2.0 / 8.0, 1.0 / 8.0, 0.0]
+
+
 def test_fold_offsets_are_nearest_multiples():
     """The fixed-point transit offsets equal round-half-up of k T, exactly
     (Fraction arithmetic on the FP64 trial)."""
