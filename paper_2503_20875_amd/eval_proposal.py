@@ -44,6 +44,8 @@ def main(argv=None) -> int:
     ap.add_argument("--out", default="")
     ap.add_argument("--quick", action="store_true",
                     help="rank recall only: one K = 64 run per half, no operating-point runs")
+    ap.add_argument("--store-calibration", action="store_true",
+                    help="write the calibration half's operating points into the (single) weights file")
     ap.add_argument("--rows", action="store_true",
                     help="also write every detection of the test half (rank, periods, SNR, truth)")
     a = ap.parse_args(argv)
@@ -94,6 +96,11 @@ def main(argv=None) -> int:
                                                 fallback_snr=tau if np.isfinite(tau) else None, log=log,
                                                 plain=plain_test))
         results[os.path.basename(path)] = out
+        if a.store_calibration:
+            from .learned import store_calibration
+            store_calibration(path, k_target, tau if np.isfinite(tau) else None,
+                              f"eval_proposal --n {a.n} --seed {a.seed}: calibration half of {n_cal} curves, "
+                              f"{cal['n_detections']} plain detections above SNR 7, target {a.target}")
     out = {"n_curves": a.n, "seed": a.seed, "workload": workload, "target_recall": a.target, "networks": results}
     text = json.dumps(out)
     print(text, flush=True)

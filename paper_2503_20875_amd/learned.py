@@ -169,6 +169,20 @@ def save_weights(net: ProposalNet, path: str, meta: dict) -> None:
         np.savez(fh, **arrays)
 
 
+def store_calibration(path: str, k: int, fallback_snr, note: str) -> None:
+    """Record calibrated operating points in a weights archive's metadata:
+    the K whose top-K windows held the target share of a calibration set's
+    plain detections, and the full-fold fallback threshold at K = 64."""
+    with np.load(path, allow_pickle=False) as z:
+        arrays = {name: z[name] for name in z.files if name != "__meta__"}
+        meta = json.loads(bytes(z["__meta__"]).decode())
+    meta.update(calibrated_k=int(k), calibrated_fallback_snr=None if fallback_snr is None else float(fallback_snr),
+                calibration=note)
+    arrays["__meta__"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
+    with open(path, "wb") as fh:
+        np.savez(fh, **arrays)
+
+
 def load_weights(path: str) -> tuple:
     with np.load(path, allow_pickle=False) as z:
         meta = json.loads(bytes(z["__meta__"]).decode())
