@@ -317,8 +317,7 @@ conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L, const __bf16 *__restr
 // and db[co] += sum over t of G[t][co]: a GEMM whose reduction runs over
 // positions, so both operands are staged in LDS position-fastest (one chunk
 // of 256 positions at a time; X with a 4-position halo on each side).
-// Workgroup: up to kChunksPerWg consecutive chunks of one example (fewer
-// when that leaves fewer than two workgroups per CU); wave w owns output channels
+// Workgroup: kChunksPerWg chunks of one example; wave w owns output channels
 // [16 w, 16 w + 16) and every (ci tile, tap) column tile, 9 cin / 16 tiles
 // of FP32 accumulators.  Per 32-position step a lane reads its G fragment
 // (8 positions) and, per ci tile, 16 consecutive positions of X (two aligned
@@ -351,8 +350,8 @@ __device__ __forceinline__ bf16x8 window8(const u32x4 &lo, const u32x4 &hi) {
 
 template <int CT>
 __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
-                                                        int32_t L, int32_t k32, int32_t chunks_per_wg,
-                                                        float *__restrict__ dw, float *__restrict__ db) {
+                                                        int32_t L, int32_t k32, float *__restrict__ dw,
+                                                        float *__restrict__ db) {
     constexpr int cin = 16 * CT;
     // rows of 264 elements (528 bytes, 16 bytes past a multiple of 256): the
     // 16 rows one MFMA fragment read touches start on distinct bank groups
@@ -374,8 +373,8 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) co
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
     const int co = 16 * wave + (l % 16);
-    for (int32_t ch = 0; ch < chunks_per_wg; ++ch) {
-        const int32_t p0 = (blockIdx.x * chunks_per_wg + ch) * kPosChunk;
+    for (int32_t ch = 0; ch < kChunksPerWg; ++ch) {
+        const int32_t p0 = (blockIdx.x * kChunksPerWg + ch) * kPosChunk;
         if (p0 >= L) break;  // uniform over the workgroup
         __syncthreads();     // the previous chunk's reads are done
         // transposing copies in 8 x 8 blocks: a thread loads 8 consecutive
@@ -528,18 +527,13 @@ extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, co
         hipLaunchKernelGGL(relu_mask_kernel, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, dy, (const __bf16 *)y,
                            n, (__bf16 *)g_scratch);
     if ((rc = check_launch("conv1d_bwd/mask"))) return rc;
-    // chunks per workgroup: up to kChunksPerWg (fewer FP32 atomics per
-    // position), but no fewer than two workgroups per CU over the batch
-    const int64_t n_chunks = ceil_div((int64_t)L, (int64_t)kPosChunk);
-    const int32_t cpw = (int32_t)std::max<int64_t>(
-        1, std::min<int64_t>(kChunksPerWg, (n_chunks * batch) / (2 * (int64_t)device_cu_count())));
-    const dim3 gw((unsigned)ceil_div(n_chunks, (int64_t)cpw), (unsigned)batch);
+    const dim3 gw((unsigned)ceil_div(L, kPosChunk * kChunksPerWg), (unsigned)batch);
     if (cin == 16)
         hipLaunchKernelGGL(conv_bwd_w_kernel<1>, gw, dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
-                           k32, cpw, dw, db);
+                           k32, dw, db);
     else
         hipLaunchKernelGGL(conv_bwd_w_kernel<4>, gw, dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
-                           k32, cpw, dw, db);
+                           k32, dw, db);
     if ((rc = check_launch("conv1d_bwd/w"))) return rc;
     if (!dx) return CETRA_OK;
     hipLaunchKernelGGL(conv_transpose_w_kernel, dim3((unsigned)ceil_div(kWidth * kTaps * cin, kT)), dim3(kT), 0, s,
