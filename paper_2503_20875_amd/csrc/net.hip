@@ -317,18 +317,21 @@ conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L, const __bf16 *__restr
 // and db[co] += sum over t of G[t][co]: a GEMM whose reduction runs over
 // positions, so both operands are staged in LDS position-fastest (one chunk
 // of 256 positions at a time; X with a 4-position halo on each side).
-// Workgroup: kChunksPerWg chunks of one example; wave w owns output channels
-// [16 w, 16 w + 16) and every (ci tile, tap) column tile, 9 cin / 16 tiles
-// of FP32 accumulators.  Per 32-position step a lane reads its G fragment
-// (8 positions) and, per ci tile, 16 consecutive positions of X (two aligned
-// 16-byte reads); the nine taps' fragments are the 8-position windows of
-// those 16 values starting at the tap (a register selection for even taps,
-// one byte-align per dword for odd taps).  The bias gradient is one more
-// MFMA against a fragment of ones.  The workgroup's sums go to dW and db by
-// FP32 atomics.
+// Workgroup: kChunksPerWg chunks of one example, eight waves; wave w owns
+// output channels [16 (w mod 4), +16) and half of the (ci tile, tap) column
+// tiles (w < 4 the first half), so a CU keeps twice as many MFMA streams
+// busy as with one wave per channel tile, for the same FP32 atomics.  Per
+// 32-position step a lane reads its G fragment (8 positions) and, per ci
+// tile, 16 consecutive positions of X (two aligned 16-byte reads); the nine
+// taps' fragments are the 8-position windows of those 16 values starting at
+// the tap (a register selection for even taps, one byte-align per dword for
+// odd taps).  The bias gradient is one more MFMA against a fragment of ones.
+// The workgroup's sums go to dW and db by FP32 atomics.
 constexpr int kPosChunk = 256;
 constexpr int kChunksPerWg = 8;
 constexpr int kHalo = 4;
+constexpr int kBwdWaves = 8;
+constexpr int kBwdThreads = 64 * kBwdWaves;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -348,31 +351,75 @@ __device__ __forceinline__ bf16x8 window8(const u32x4 &lo, const u32x4 &hi) {
     return __builtin_bit_cast(bf16x8, w);
 }
 
+// The same for a tap known after unrolling (the switch folds away).
+__device__ __forceinline__ bf16x8 window8_at(int s, const u32x4 &lo, const u32x4 &hi) {
+    switch (s) {
+    case 0: return window8<0>(lo, hi);
+    case 1: return window8<1>(lo, hi);
+    case 2: return window8<2>(lo, hi);
+    case 3: return window8<3>(lo, hi);
+    case 4: return window8<4>(lo, hi);
+    case 5: return window8<5>(lo, hi);
+    case 6: return window8<6>(lo, hi);
+    case 7: return window8<7>(lo, hi);
+    default: return window8<8>(lo, hi);
+    }
+}
+
+// (ci tile, tap) column tiles p = 9 c + tap of half H: [H NH, min(NP, (H + 1) NH)).
 template <int CT>
-__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
+struct BwdPairs {
+    static constexpr int NP = CT * kTaps;
+    static constexpr int NH = (NP + 1) / 2;
+};
+
+// One 32-position step of half H: the G fragment against every column tile
+// of the half (and the bias for half 0).
+template <int CT, int H, int kRow>
+__device__ __forceinline__ void bwd_w_step(const bf16x8 &afrag, const __bf16 (*s_x)[kRow], int q, int l,
+                                           f32x4 (&acc)[BwdPairs<CT>::NH]) {
+    constexpr int NP = BwdPairs<CT>::NP, NH = BwdPairs<CT>::NH;
+    constexpr int P0 = H * NH, P1 = (P0 + NH < NP) ? P0 + NH : NP;
+    constexpr int C0 = P0 / kTaps, C1 = (P1 - 1) / kTaps;
+    u32x4 lo[C1 - C0 + 1], hi[C1 - C0 + 1];
+#pragma unroll
+    for (int c = C0; c <= C1; ++c) {
+        // X[p0 + q + tap - 4 + i] = s_x[ci][q + tap + i], i < 8, tap < 9
+        const __bf16 *row = &s_x[16 * c + (l % 16)][q];
+        lo[c - C0] = *reinterpret_cast<const u32x4 *>(row);
+        hi[c - C0] = *reinterpret_cast<const u32x4 *>(row + 8);
+    }
+#pragma unroll
+    for (int p = P0; p < P1; ++p)
+        acc[p - P0] = mfma16(afrag, window8_at(p % kTaps, lo[p / kTaps - C0], hi[p / kTaps - C0]), acc[p - P0]);
+}
+
+template <int CT>
+__global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(2))) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
                                                         int32_t L, int32_t k32, float *__restrict__ dw,
                                                         float *__restrict__ db) {
     constexpr int cin = 16 * CT;
+    constexpr int NH = BwdPairs<CT>::NH, NP = BwdPairs<CT>::NP;
     // rows of 264 elements (528 bytes, 16 bytes past a multiple of 256): the
     // 16 rows one MFMA fragment read touches start on distinct bank groups
     constexpr int kRow = kPosChunk + 2 * kHalo;
     static_assert(kRow % 8 == 0 && kPosChunk % 8 == 0, "8-position blocks");
     __shared__ __attribute__((aligned(16))) __bf16 s_g[kWidth][kRow];  // 33 KB
     __shared__ __attribute__((aligned(16))) __bf16 s_x[cin][kRow];     // <= 33 KB
-    const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int half = wave >> 2;  // wave-uniform
     const int64_t b = blockIdx.y;
     const __bf16 *gb = g + b * (int64_t)L * kWidth;
     const __bf16 *xb = x + b * (int64_t)L * cin;
-    f32x4 acc[CT][kTaps];
+    f32x4 acc[NH];
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-#pragma unroll
-        for (int tap = 0; tap < kTaps; ++tap) acc[c][tap] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < NH; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc_b = {0.0f, 0.0f, 0.0f, 0.0f};
     bf16x8 ones;
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
-    const int co = 16 * wave + (l % 16);
+    const int co = 16 * (wave & 3) + (l % 16);
     for (int32_t ch = 0; ch < kChunksPerWg; ++ch) {
         const int32_t p0 = (blockIdx.x * kChunksPerWg + ch) * kPosChunk;
         if (p0 >= L) break;  // uniform over the workgroup
@@ -382,7 +429,7 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) co
         // always valid positions, zeroed afterwards when outside [0, L)),
         // transposes them in registers and writes 8 channel rows of 8
         // positions with 16-byte LDS stores
-        for (int i = threadIdx.x; i < (kWidth / 8) * (kPosChunk / 8); i += kT) {
+        for (int i = threadIdx.x; i < (kWidth / 8) * (kPosChunk / 8); i += kBwdThreads) {
             const int c8 = 8 * (i / (kPosChunk / 8)), pg = 8 * (i % (kPosChunk / 8));
             bf16x8 v[8];
 #pragma unroll
@@ -399,7 +446,7 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) co
             }
         }
         // s_x[ci][pp] = X[p0 + pp - kHalo], pp < kRow (= 33 blocks of 8)
-        for (int i = threadIdx.x; i < (cin / 8) * (kRow / 8); i += kT) {
+        for (int i = threadIdx.x; i < (cin / 8) * (kRow / 8); i += kBwdThreads) {
             const int c8 = 8 * (i / (kRow / 8)), pg = 8 * (i % (kRow / 8));
             bf16x8 v[8];
 #pragma unroll
@@ -422,35 +469,25 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(2))) co
         for (int32_t q0 = 0; q0 < kPosChunk; q0 += 32) {
             const int q = q0 + 8 * (l / 16);  // this lane's 8 positions
             const bf16x8 afrag = *reinterpret_cast<const bf16x8 *>(&s_g[co][q]);
-            acc_b = mfma16(afrag, ones, acc_b);
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                // X[p0 + q + tap - 4 + i] = s_x[ci][q + tap + i], i < 8, tap < 9
-                const __bf16 *row = &s_x[16 * c + (l % 16)][q];
-                const u32x4 lo = *reinterpret_cast<const u32x4 *>(row);
-                const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 8);
-                acc[c][0] = mfma16(afrag, window8<0>(lo, hi), acc[c][0]);
-                acc[c][1] = mfma16(afrag, window8<1>(lo, hi), acc[c][1]);
-                acc[c][2] = mfma16(afrag, window8<2>(lo, hi), acc[c][2]);
-                acc[c][3] = mfma16(afrag, window8<3>(lo, hi), acc[c][3]);
-                acc[c][4] = mfma16(afrag, window8<4>(lo, hi), acc[c][4]);
-                acc[c][5] = mfma16(afrag, window8<5>(lo, hi), acc[c][5]);
-                acc[c][6] = mfma16(afrag, window8<6>(lo, hi), acc[c][6]);
-                acc[c][7] = mfma16(afrag, window8<7>(lo, hi), acc[c][7]);
-                acc[c][8] = mfma16(afrag, window8<8>(lo, hi), acc[c][8]);
+            if (half == 0) {
+                acc_b = mfma16(afrag, ones, acc_b);
+                bwd_w_step<CT, 0, kRow>(afrag, s_x, q, l, acc);
+            } else {
+                bwd_w_step<CT, 1, kRow>(afrag, s_x, q, l, acc);
             }
         }
     }
     // C layout: lane holds rows 4 (l / 16) + r of the tile, column l % 16
+    const int p_base = half * NH;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int row = 16 * wave + 4 * (l / 16) + r;
-        if (l % 16 == 0) atomicAdd(&db[row], acc_b[r]);
+        const int row = 16 * (wave & 3) + 4 * (l / 16) + r;
+        if (half == 0 && l % 16 == 0) atomicAdd(&db[row], acc_b[r]);
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-#pragma unroll
-            for (int tap = 0; tap < kTaps; ++tap)
-                atomicAdd(&dw[row * k32 + tap * cin + 16 * c + (l % 16)], acc[c][tap][r]);
+        for (int k = 0; k < NH; ++k) {
+            const int p = p_base + k;
+            if (p < NP) atomicAdd(&dw[row * k32 + (p % kTaps) * cin + 16 * (p / kTaps) + (l % 16)], acc[k][r]);
+        }
     }
 }
 
@@ -529,10 +566,10 @@ extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, co
     if ((rc = check_launch("conv1d_bwd/mask"))) return rc;
     const dim3 gw((unsigned)ceil_div(L, kPosChunk * kChunksPerWg), (unsigned)batch);
     if (cin == 16)
-        hipLaunchKernelGGL(conv_bwd_w_kernel<1>, gw, dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
+        hipLaunchKernelGGL(conv_bwd_w_kernel<1>, gw, dim3(kBwdThreads), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
                            k32, dw, db);
     else
-        hipLaunchKernelGGL(conv_bwd_w_kernel<4>, gw, dim3(kT), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
+        hipLaunchKernelGGL(conv_bwd_w_kernel<4>, gw, dim3(kBwdThreads), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
                            k32, dw, db);
     if ((rc = check_launch("conv1d_bwd/w"))) return rc;
     if (!dx) return CETRA_OK;
