@@ -78,14 +78,16 @@ def fold_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_work(wl, grid):
+def algorithmic_work(wl, grid, linear: bool = True):
     """Element visits of the fold (sum over periods of allowed durations x I),
-    fold bytes (8 B per visit + 20 B per period record) and linear FLOP
-    (4 per window-point visit: two FMAs)."""
+    fold bytes (8 B per visit + 20 B per period record) and, unless
+    linear=False, linear FLOP (4 per window-point visit: two FMAs)."""
     durs = np.asarray(wl.durations)
-    J_k = np.array([np.count_nonzero(durs < P) for P in wl.periods], dtype=np.int64)
+    J_k = np.searchsorted(np.sort(durs), np.asarray(wl.periods), side="left")  # durations below each P
     visits = int(J_k.sum()) * int(grid.n_t0)
     fold_bytes = 8 * visits + 20 * len(wl.periods)
+    if not linear:
+        return dict(fold_visits=visits, fold_bytes=fold_bytes)
     c, dt = grid.cadence, grid.t0_step
     # points per window: floor(te/c) - ceil(ts/c) + 1 ~ D/c (exact count summed below)
     lin_points = 0
@@ -102,7 +104,8 @@ def algorithmic_work(wl, grid):
                 linear_flop=4 * lin_points)
 
 
-def batched_block(n_curves: int = 64, seed: int = 20250328, n_min: int = 5000, n_max: int = 120000) -> dict:
+def batched_block(n_curves: int = 64, seed: int = 20250328, n_min: int = 5000, n_max: int = 120000,
+                  compare: bool = True, workers: int = 1) -> dict:
     """Batched survey: a length-stratified subset of the survey workload
     (curve k has the midpoint length of the k-th of n_curves strata of
     5 000-120 000 points at 2-min cadence; 16 durations 0.5-10 h; per-curve
@@ -110,12 +113,19 @@ def batched_block(n_curves: int = 64, seed: int = 20250328, n_min: int = 5000, n
     persistent work-queue launch, eagerly and as a replayed HIP graph, both
     timed with HIP events; then the same curves as back-to-back single-curve
     searches (resample, linear search, periodic search, best per curve) for
-    comparison.  Throughput is sum over curves of N_obs x K_c per second."""
+    comparison.  Throughput is sum over curves of N_obs x K_c per second.
+    compare=False times one eager batch only (no warm-up call, graph replay
+    or single-curve calls), for surveys that take minutes; while it runs the
+    per-curve done flags are read on a side stream every 15 s and logged.
+    workers > 1 generates the curves in a forked process pool, so it must
+    run before anything initialises the GPU."""
     import torch
     import paper_2503_20875_amd as cm
     from synthlc import workloads as W
-    curves = W.survey_subset(n_curves, seed=seed, n_min=n_min, n_max=n_max)
+    curves = W.survey_subset(n_curves, seed=seed, n_min=n_min, n_max=n_max, workers=workers,
+                             progress=lambda k: log(f"batched survey: {k}/{n_curves} curves generated"))
     log(f"batched survey: {n_curves} curves generated")
+    torch.cuda.init()
     grids = [cm.grid_plan(c.t[0], c.t[-1], c.cadence, c.durations, 0.0, c.n_model) for c in curves]
     oo = np.concatenate([[0], np.cumsum([c.n_obs for c in curves])])
     po = np.concatenate([[0], np.cumsum([len(c.periods) for c in curves])])
@@ -127,6 +137,33 @@ def batched_block(n_curves: int = 64, seed: int = 20250328, n_min: int = 5000, n
     model = cm.template_resample(torch.as_tensor(curves[0].dense, device=dev), curves[0].n_model)
     plan = cm.batch_plan(grids, oo, po)
     work = cm.batch_workspace(plan)
+    log(f"batched survey: inputs resident, plan and workspace made ({plan.info['n_items']} queue items)")
+    work_units = float(sum(c.n_obs * len(c.periods) for c in curves))
+    fold_bytes = float(sum(algorithmic_work(c, gr, linear=False)["fold_bytes"] for c, gr in zip(curves, grids)))
+    workload = (f"{n_curves} length-stratified survey curves ({n_min}-{n_max} points at 2 min), "
+                f"{int(oo[-1])} observations, {int(po[-1])} trial periods in all")
+    if not compare:
+        torch.cuda.synchronize()
+        log("batched survey: one timed batch")
+        side = torch.cuda.Stream()
+        done_host = torch.empty(n_curves, dtype=torch.int32, pin_memory=True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        out = cm.batch_search(plan, t, f, s_, model, p, work=work)
+        e[1].record()
+        while not e[1].query():
+            time.sleep(15.0)
+            with torch.cuda.stream(side):
+                done_host.copy_(out["done"], non_blocking=True)
+            side.synchronize()
+            log(f"batched survey: {int((done_host == 1).sum())}/{n_curves} curves done")
+        torch.cuda.synchronize()
+        sec = e[0].elapsed_time(e[1]) / 1e3
+        return {"workload": workload, "n_launches": plan.info["n_launches"], "n_items": plan.info["n_items"],
+                "workspace_bytes": plan.info["workspace_bytes"], "ms_eager": sec * 1e3,
+                "value": work_units / sec, "unit": "LC points x trial periods / s",
+                "fold_algorithmic_bytes": fold_bytes, "fold_algorithmic_GBps": fold_bytes / sec / 1e9,
+                "status": int(out["status"].item()), "curves_done": int((out["done"] == 1).sum().item())}
     out = cm.batch_search(plan, t, f, s_, model, p, work=work)
     torch.cuda.synchronize()
     log(f"batched survey: first search done, status {int(out['status'].item())}")
@@ -176,12 +213,9 @@ def batched_block(n_curves: int = 64, seed: int = 20250328, n_min: int = 5000, n
                for i, (c, b) in enumerate(zip(curves, bufs)) if len(c.periods))
     del bufs
     torch.cuda.empty_cache()
-    work_units = float(sum(c.n_obs * len(c.periods) for c in curves))
-    fold_bytes = float(sum(algorithmic_work(c, gr)["fold_bytes"] for c, gr in zip(curves, grids)))
     ms_eager, ms_graph, ms_single = e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]), e[4].elapsed_time(e[5])
     sec = min(ms_eager, ms_graph) / 1e3
-    return {"workload": (f"{n_curves} length-stratified survey curves ({n_min}-{n_max} points at 2 min), "
-                         f"{int(oo[-1])} observations, {int(po[-1])} trial periods in all"),
+    return {"workload": workload,
             "n_launches": plan.info["n_launches"], "n_items": plan.info["n_items"],
             "ms_eager": ms_eager, "ms_graph_replay": ms_graph, "ms_single_curve_calls": ms_single,
             "speedup_over_single_curve_calls": ms_single / min(ms_eager, ms_graph),
@@ -823,6 +857,9 @@ def main():
                     help="survey curves of the batched-search measurement (0: skip)")
     ap.add_argument("--batch-points", default="5000,120000",
                     help="length range (points) of the batched-search curves")
+    ap.add_argument("--batch-compare", type=int, default=1,
+                    help="with --mode batch: 0 times one eager batch only (no graph replay or single-curve "
+                         "calls), with progress lines, and generates the curves with 8 processes")
     ap.add_argument("--fold-tuning", default="",
                     help="period block, workgroups per CU, units per workgroup, variant (e.g. 4,8,4,0); "
                          "default: the library's")
@@ -838,6 +875,13 @@ def main():
     import paper_2503_20875_amd as cm
     from synthlc import workloads as W
 
+    batch_pts = tuple(int(v) for v in args.batch_points.split(","))
+    if args.mode == "batch":  # before any GPU call: its curve generator may fork
+        print(json.dumps({"mode": "batch", **batched_block(args.batch_curves, n_min=batch_pts[0],
+                                                           n_max=batch_pts[1], compare=bool(args.batch_compare),
+                                                           workers=1 if args.batch_compare else 8)}),
+              flush=True)
+        return
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.mode == "copy":
@@ -852,11 +896,6 @@ def main():
         return
     if args.mode == "net":
         print(json.dumps({"mode": "net", **net_block()}), flush=True)
-        return
-    batch_pts = tuple(int(v) for v in args.batch_points.split(","))
-    if args.mode == "batch":
-        print(json.dumps({"mode": "batch", **batched_block(args.batch_curves, n_min=batch_pts[0],
-                                                           n_max=batch_pts[1])}), flush=True)
         return
     if args.fold_tuning:
         cm.set_tuning(*(int(v) for v in args.fold_tuning.split(",")))

@@ -304,25 +304,45 @@ def batched_survey(n_curves: int, seed: int = 20250328, n_min: int = 5000, n_max
     return curves
 
 
+def _survey_member(args) -> Workload:
+    """Curve k of a survey_subset (module level so a process pool can run it)."""
+    k, n_curves, seed, n_min, n_max, durs, alpha, p_min, p_max = args
+    rng = np.random.default_rng(seed + k)
+    n = int(round(n_min + (k + 0.5) / n_curves * (n_max - n_min)))
+    t, f, s, injs = survey_curve(rng, n, durations=durs, p_range=(p_min, p_max))
+    span = t[-1] - t[0]
+    hi = min(p_max, span / 2.0)
+    periods = duty_cycle_periods(p_min, hi, span, durs[0], alpha) if hi > p_min else np.zeros(0)
+    return Workload(name=f"survey-{k}", t=t, f=f, sigma=s, cadence=120.0 / DAY_S,
+                    durations=durs, periods=periods, dense=transit.dense_template(),
+                    injections=injs, seed=seed + k)
+
+
 def survey_subset(n_curves: int, seed: int = 20250328, n_min: int = 5000, n_max: int = 120000,
                   n_dur: int = 16, d_min_h: float = 0.5, d_max_h: float = 10.0, alpha: float = 0.389,
-                  p_min: float = 0.5, p_max: float = 40.0):
+                  p_min: float = 0.5, p_max: float = 40.0, workers: int = 1, progress=None):
     """A length-stratified stand-in for a large batched survey: curve k has
     the k-th of n_curves equal-probability strata of the uniform length
     distribution over [n_min, n_max] points (its stratum's midpoint), and its
-    own generator seeded with seed + k; everything else as batched_survey."""
+    own generator seeded with seed + k; everything else as batched_survey.
+    workers > 1 generates in a forked process pool (same curves: each has its
+    own seed); progress(k_done) is called after every 256 curves."""
     durs = log_durations(d_min_h, d_max_h, n_dur)
+    jobs = [(k, n_curves, seed, n_min, n_max, durs, alpha, p_min, p_max) for k in range(n_curves)]
     curves = []
-    for k in range(n_curves):
-        rng = np.random.default_rng(seed + k)
-        n = int(round(n_min + (k + 0.5) / n_curves * (n_max - n_min)))
-        t, f, s, injs = survey_curve(rng, n, durations=durs, p_range=(p_min, p_max))
-        span = t[-1] - t[0]
-        hi = min(p_max, span / 2.0)
-        periods = duty_cycle_periods(p_min, hi, span, durs[0], alpha) if hi > p_min else np.zeros(0)
-        curves.append(Workload(name=f"survey-{k}", t=t, f=f, sigma=s, cadence=120.0 / DAY_S,
-                               durations=durs, periods=periods, dense=transit.dense_template(),
-                               injections=injs, seed=seed + k))
+
+    def take(it):
+        for c in it:
+            curves.append(c)
+            if progress is not None and len(curves) % 256 == 0:
+                progress(len(curves))
+
+    if workers > 1:
+        import multiprocessing
+        with multiprocessing.get_context("fork").Pool(workers) as pool:
+            take(pool.imap(_survey_member, jobs, chunksize=16))
+    else:
+        take(map(_survey_member, jobs))
     return curves
 
 
