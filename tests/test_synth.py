@@ -104,3 +104,17 @@ def test_learned_curves_device_generator_recipe():
                 d = float(f.numpy()[inside].mean() - f.numpy()[~inside].mean())
                 assert 0.5 * inj.depth < d < 1.2 * inj.depth + 5 * 800e-6 / np.sqrt(inside.sum())
     assert n_planet >= 3
+
+
+def test_survey_subset_process_pool_gives_the_same_curves():
+    """Each survey curve has its own seed, so generating them in a forked
+    pool returns the serial curves, in order."""
+    serial = W.survey_subset(24, n_min=5000, n_max=9000)
+    seen = []
+    pooled = W.survey_subset(24, n_min=5000, n_max=9000, workers=3, progress=seen.append)
+    assert seen == []  # progress is reported every 256 curves
+    assert [c.name for c in pooled] == [c.name for c in serial]
+    for a, b in zip(serial, pooled):
+        for x, y in ((a.t, b.t), (a.f, b.f), (a.sigma, b.sigma), (a.periods, b.periods)):
+            assert np.array_equal(x, y)
+        assert a.injections == b.injections
