@@ -568,10 +568,20 @@ int cetra_conv1d_fwd(void *stream, const void *x, int32_t cin, int32_t L, int32_
 /* Backward of cetra_conv1d_fwd given dy [batch][L][64] FP32 (gradient of the
  * post-ReLU output y): dw [64][k32] FP32 and db[64] accumulate; dx
  * [batch][L][cin] FP32 is overwritten (dx = NULL skips it).  Scratch:
- * g_scratch batch*L*64 bf16, wt_scratch 64*9*cin bf16 (device). */
+ * g_scratch batch*L*64 bf16, wt_scratch 64*9*cin bf16 (device).
+ * dw_partial (device FP32, 16-byte aligned, dw_partial_floats >=
+ * cetra_conv1d_bwd_partial_floats(cin, L, batch), else CETRA_ERR_INVALID):
+ * each weight-gradient workgroup stores its sums there and a second kernel
+ * adds them into dw and db in a fixed order, so the gradients do not depend
+ * on timing.  dw_partial = NULL adds them with FP32 atomics instead (no
+ * workspace; the order of the additions, and so the rounding, may vary). */
 int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, const void *x, int32_t cin, int32_t L,
-                     int32_t batch, const void *w, int32_t k32, void *g_scratch, void *wt_scratch, float *dx,
-                     float *dw, float *db);
+                     int32_t batch, const void *w, int32_t k32, void *g_scratch, void *wt_scratch,
+                     float *dw_partial, int64_t dw_partial_floats, float *dx, float *dw, float *db);
+
+/* Floats of the dw_partial workspace of cetra_conv1d_bwd for these sizes
+ * (-1 for sizes it rejects).  Host only. */
+int64_t cetra_conv1d_bwd_partial_floats(int32_t cin, int32_t L, int32_t batch);
 
 /* e[pos][c] = P[c][:] . h[pos][:] + p[c] over n_pos = batch*L positions;
  * P [E][64], p[E] FP32. */

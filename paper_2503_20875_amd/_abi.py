@@ -184,7 +184,8 @@ SIGNATURES = {
     "cetra_net_downsample": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_net_downsample_signed": (ctypes.c_int, [_P, _P, _i32, _i64, _i32, _P]),
     "cetra_conv1d_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _P, _P]),
-    "cetra_conv1d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _P, _i32, _P, _P, _P, _P, _P]),
+    "cetra_conv1d_bwd": (ctypes.c_int, [_P, _P, _P, _P, _i32, _i32, _i32, _P, _i32, _P, _P, _P, _i64, _P, _P, _P]),
+    "cetra_conv1d_bwd_partial_floats": (ctypes.c_int64, [_i32, _i32, _i32]),
     "cetra_net_project_fwd": (ctypes.c_int, [_P, _P, _i64, _P, _P, _i32, _P]),
     "cetra_net_project_bwd": (ctypes.c_int, [_P, _P, _P, _i64, _P, _i32, _P, _P, _P]),
     "cetra_net_foldpool_fwd": (ctypes.c_int, [_P, _P, _i32, _i32, _i32, _P, _i32, _i32, _P, _P, _P]),

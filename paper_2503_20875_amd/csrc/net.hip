@@ -326,7 +326,10 @@ conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L, const __bf16 *__restr
 // taps' fragments are the 8-position windows of those 16 values starting at
 // the tap (a register selection for even taps, one byte-align per dword for
 // odd taps).  The bias gradient is one more MFMA against a fragment of ones.
-// The workgroup's sums go to dW and db by FP32 atomics.
+// The workgroup's sums go to dW and db by FP32 atomics (kPartial = false),
+// or (kPartial = true) to the workgroup's own slab of a partial-sum array,
+// [workgroup][64 k32 + 64] FP32, by plain stores; conv_bwd_w_reduce_kernel
+// then adds the slabs into dW and db in workgroup order.
 constexpr int kPosChunk = 256;
 constexpr int kChunksPerWg = 8;
 constexpr int kHalo = 4;
@@ -394,10 +397,10 @@ __device__ __forceinline__ void bwd_w_step(const bf16x8 &afrag, const __bf16 (*s
         acc[p - P0] = mfma16(afrag, window8_at(p % kTaps, lo[p / kTaps - C0], hi[p / kTaps - C0]), acc[p - P0]);
 }
 
-template <int CT>
-__global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(2))) conv_bwd_w_kernel(const __bf16 *__restrict__ g, const __bf16 *__restrict__ x,
-                                                        int32_t L, int32_t k32, float *__restrict__ dw,
-                                                        float *__restrict__ db) {
+template <int CT, bool kPartial>
+__global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_eu(2))) conv_bwd_w_kernel(
+    const __bf16 *__restrict__ g, const __bf16 *__restrict__ x, int32_t L, int32_t k32, int32_t chunks_per_wg,
+    float *__restrict__ dw, float *__restrict__ db, float *__restrict__ part) {
     constexpr int cin = 16 * CT;
     constexpr int NH = BwdPairs<CT>::NH, NP = BwdPairs<CT>::NP;
     // rows of 264 elements (528 bytes, 16 bytes past a multiple of 256): the
@@ -420,8 +423,8 @@ __global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_e
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
     const int co = 16 * (wave & 3) + (l % 16);
-    for (int32_t ch = 0; ch < kChunksPerWg; ++ch) {
-        const int32_t p0 = (blockIdx.x * kChunksPerWg + ch) * kPosChunk;
+    for (int32_t ch = 0; ch < chunks_per_wg; ++ch) {
+        const int32_t p0 = (blockIdx.x * chunks_per_wg + ch) * kPosChunk;
         if (p0 >= L) break;  // uniform over the workgroup
         __syncthreads();     // the previous chunk's reads are done
         // transposing copies in 8 x 8 blocks: a thread loads 8 consecutive
@@ -479,16 +482,91 @@ __global__ void __launch_bounds__(kBwdThreads) __attribute__((amdgpu_waves_per_e
     }
     // C layout: lane holds rows 4 (l / 16) + r of the tile, column l % 16
     const int p_base = half * NH;
+    float *slab = kPartial ? part + (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * (kWidth * k32 + kWidth)
+                           : nullptr;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = 16 * (wave & 3) + 4 * (l / 16) + r;
-        if (half == 0 && l % 16 == 0) atomicAdd(&db[row], acc_b[r]);
+        if (half == 0 && l % 16 == 0) {
+            if (kPartial)
+                slab[kWidth * k32 + row] = acc_b[r];
+            else
+                atomicAdd(&db[row], acc_b[r]);
+        }
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
             const int p = p_base + k;
-            if (p < NP) atomicAdd(&dw[row * k32 + (p % kTaps) * cin + 16 * (p / kTaps) + (l % 16)], acc[k][r]);
+            if (p >= NP) continue;
+            const int32_t o = row * k32 + (p % kTaps) * cin + 16 * (p / kTaps) + (l % 16);
+            if (kPartial)
+                slab[o] = acc[k][r];
+            else
+                atomicAdd(&dw[o], acc[k][r]);
         }
     }
+}
+
+// dW[o] += sum over slabs of part[s][o] for the columns below n_col = 9 cin
+// (a slab's padding columns are never written) and db[co] += sum of
+// part[s][64 k32 + co].  A workgroup takes 256 consecutive outputs, four per
+// lane (16-byte loads); wave w sums slabs w, w + 8, w + 16, ... in order and
+// wave 0 adds the eight wave sums in order, so the result does not depend
+// on timing.
+constexpr int kRedWaves = 8;
+
+__global__ void __launch_bounds__(64 * kRedWaves) conv_bwd_w_reduce_kernel(const float *__restrict__ part,
+                                                                            int32_t n_slabs, int32_t k32,
+                                                                            int32_t n_col, float *__restrict__ dw,
+                                                                            float *__restrict__ db) {
+    __shared__ float s_sum[kRedWaves][4][64];
+    const int32_t slab = kWidth * k32 + kWidth;  // a multiple of 4
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t o4 = (blockIdx.x * 64 + lane) * 4;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    if (o4 < slab) {
+#pragma unroll 8
+        for (int32_t i = wave; i < n_slabs; i += kRedWaves) {
+            const float4 v = *reinterpret_cast<const float4 *>(part + (int64_t)i * slab + o4);
+            a0 += v.x;
+            a1 += v.y;
+            a2 += v.z;
+            a3 += v.w;
+        }
+    }
+    s_sum[wave][0][lane] = a0;
+    s_sum[wave][1][lane] = a1;
+    s_sum[wave][2][lane] = a2;
+    s_sum[wave][3][lane] = a3;
+    __syncthreads();
+    if (wave != 0 || o4 >= slab) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float t = s_sum[0][j][lane];
+#pragma unroll
+        for (int w = 1; w < kRedWaves; ++w) t += s_sum[w][j][lane];
+        const int32_t o = o4 + j;
+        if (o < kWidth * k32) {
+            if (o % k32 < n_col) dw[o] += t;
+        } else {
+            db[o - kWidth * k32] += t;
+        }
+    }
+}
+
+// Chunks of 256 positions per weight-gradient workgroup.  With partial
+// slabs: the most (8, 4, 2 or 1) that still give one workgroup per CU of
+// the 256; with atomics: 8 (each workgroup adds its sums once).
+int bwd_chunks_per_wg(int32_t L, int32_t batch, bool partial) {
+    if (!partial) return kChunksPerWg;
+    for (int c = kChunksPerWg; c > 1; c /= 2)
+        if (cetra::ceil_div(L, kPosChunk * c) * (int64_t)batch >= 256) return c;
+    return 1;
+}
+
+int64_t bwd_partial_floats(int32_t cin, int32_t L, int32_t batch) {
+    const int64_t k32 = ((kTaps * cin + 31) / 32) * 32;
+    const int64_t n_wg = cetra::ceil_div(L, kPosChunk * bwd_chunks_per_wg(L, batch, true)) * (int64_t)batch;
+    return n_wg * (kWidth * k32 + kWidth);
 }
 
 }  // namespace
@@ -548,13 +626,22 @@ extern "C" int cetra_conv1d_fwd(void *stream, const void *x, int32_t cin, int32_
     return check_launch("conv1d_fwd");
 }
 
+extern "C" int64_t cetra_conv1d_bwd_partial_floats(int32_t cin, int32_t L, int32_t batch) {
+    clear_error();
+    if ((cin != 16 && cin != 64) || L < 1 || batch < 1) return -1;
+    return bwd_partial_floats(cin, L, batch);
+}
+
 extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, const void *x, int32_t cin, int32_t L,
                                 int32_t batch, const void *w, int32_t k32, void *g_scratch, void *wt_scratch,
-                                float *dx, float *dw, float *db) {
+                                float *dw_partial, int64_t dw_partial_floats, float *dx, float *dw, float *db) {
     clear_error();
     CETRA_REQUIRE(dy && y && x && w && g_scratch && wt_scratch && dw && db, "conv1d_bwd: NULL pointer");
     int rc = conv_args_ok(cin, L, batch, k32);
     if (rc) return rc;
+    CETRA_REQUIRE(((uintptr_t)dw_partial & 15) == 0, "conv1d_bwd: dw_partial must be 16-byte aligned");
+    CETRA_REQUIRE(!dw_partial || dw_partial_floats >= bwd_partial_floats(cin, L, batch),
+                  "conv1d_bwd: dw_partial smaller than cetra_conv1d_bwd_partial_floats");
     hipStream_t s = as_stream(stream);
     const int64_t n = (int64_t)batch * L * kWidth;  // a multiple of 64
     if ((((uintptr_t)dy & 31) | ((uintptr_t)y & 15) | ((uintptr_t)g_scratch & 15)) == 0)
@@ -564,14 +651,29 @@ extern "C" int cetra_conv1d_bwd(void *stream, const float *dy, const void *y, co
         hipLaunchKernelGGL(relu_mask_kernel, dim3((unsigned)ceil_div(n, kT)), dim3(kT), 0, s, dy, (const __bf16 *)y,
                            n, (__bf16 *)g_scratch);
     if ((rc = check_launch("conv1d_bwd/mask"))) return rc;
-    const dim3 gw((unsigned)ceil_div(L, kPosChunk * kChunksPerWg), (unsigned)batch);
-    if (cin == 16)
-        hipLaunchKernelGGL(conv_bwd_w_kernel<1>, gw, dim3(kBwdThreads), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
-                           k32, dw, db);
+    const bool partial = dw_partial != nullptr;
+    const int cpw = bwd_chunks_per_wg(L, batch, partial);
+    const dim3 gw((unsigned)ceil_div(L, kPosChunk * cpw), (unsigned)batch);
+    const __bf16 *gs = (const __bf16 *)g_scratch, *xs = (const __bf16 *)x;
+    if (cin == 16 && partial)
+        hipLaunchKernelGGL((conv_bwd_w_kernel<1, true>), gw, dim3(kBwdThreads), 0, s, gs, xs, L, k32, cpw, dw, db,
+                           dw_partial);
+    else if (cin == 16)
+        hipLaunchKernelGGL((conv_bwd_w_kernel<1, false>), gw, dim3(kBwdThreads), 0, s, gs, xs, L, k32, cpw, dw, db,
+                           nullptr);
+    else if (partial)
+        hipLaunchKernelGGL((conv_bwd_w_kernel<4, true>), gw, dim3(kBwdThreads), 0, s, gs, xs, L, k32, cpw, dw, db,
+                           dw_partial);
     else
-        hipLaunchKernelGGL(conv_bwd_w_kernel<4>, gw, dim3(kBwdThreads), 0, s, (const __bf16 *)g_scratch, (const __bf16 *)x, L,
-                           k32, dw, db);
+        hipLaunchKernelGGL((conv_bwd_w_kernel<4, false>), gw, dim3(kBwdThreads), 0, s, gs, xs, L, k32, cpw, dw, db,
+                           nullptr);
     if ((rc = check_launch("conv1d_bwd/w"))) return rc;
+    if (partial) {
+        const int32_t slab = kWidth * k32 + kWidth;
+        hipLaunchKernelGGL(conv_bwd_w_reduce_kernel, dim3((unsigned)ceil_div(slab, 256)), dim3(64 * kRedWaves), 0, s,
+                           dw_partial, (int32_t)(gw.x * gw.y), k32, kTaps * cin, dw, db);
+        if ((rc = check_launch("conv1d_bwd/w_reduce"))) return rc;
+    }
     if (!dx) return CETRA_OK;
     hipLaunchKernelGGL(conv_transpose_w_kernel, dim3((unsigned)ceil_div(kWidth * kTaps * cin, kT)), dim3(kT), 0, s,
                        (const __bf16 *)w, cin, k32, (__bf16 *)wt_scratch);

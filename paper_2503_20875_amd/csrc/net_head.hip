@@ -19,6 +19,7 @@ constexpr int kT = 256;
 constexpr int kWidth = 64;
 constexpr int kMaxE = 16;
 constexpr int kMaxL = 8192;  // bins of an event series (staged in LDS)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -60,36 +61,113 @@ __global__ void __launch_bounds__(kT) project_bwd_dh_kernel(const float *__restr
 }
 
 // dP[c][ci] += sum_pos ge[pos][c] h[pos][ci] and dp[c] += sum_pos ge[pos][c]
-// over a chunk of positions per workgroup: lane t accumulates the (c, ci)
-// pairs t, t + 256, ... in registers and adds them once (one atomic per pair
-// and workgroup).
-constexpr int kProjChunk = 256;
+// over kProjChunk positions per workgroup: wave w takes a quarter of them in
+// order, lane ci holds the E sums of its channel, lanes c < E the bias
+// sums.  The four waves' sums meet in LDS and wave 0 adds them with one
+// atomic per (c, ci) and workgroup.  (Any E up to kMaxE; E = 8 has its own
+// kernel below.)
+constexpr int kProjChunk = 1024;
 __global__ void __launch_bounds__(kT) project_bwd_dp_kernel(const __bf16 *__restrict__ h,
                                                             const float *__restrict__ ge, int64_t n_pos, int32_t E,
                                                             float *__restrict__ dP, float *__restrict__ dp) {
-    constexpr int kPairs = kMaxE * kWidth / kT;  // pairs per lane at most (4)
-    const int64_t p0 = (int64_t)blockIdx.x * kProjChunk;
-    const int64_t p1 = min(p0 + kProjChunk, n_pos);
-    const int32_t n_pairs = E * kWidth;
-    float acc[kPairs] = {0.0f, 0.0f, 0.0f, 0.0f};
-    float accb = 0.0f;
-    for (int64_t pos = p0; pos < p1; ++pos) {
+    constexpr int kWaves = kT / 64;
+    __shared__ float s_acc[kWaves][kMaxE][kWidth];
+    __shared__ float s_b[kWaves][kMaxE];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t q0 = (int64_t)blockIdx.x * kProjChunk + (int64_t)wave * (kProjChunk / kWaves);
+    const int64_t q1 = min(q0 + kProjChunk / kWaves, n_pos);
+    float acc[kMaxE];
 #pragma unroll
-        for (int k = 0; k < kPairs; ++k) {
-            const int32_t pr = threadIdx.x + k * kT;
-            if (pr < n_pairs) {
-                const int32_t c = pr / kWidth, ci = pr % kWidth;
-                acc[k] = fmaf(ge[pos * E + c], (float)h[pos * kWidth + ci], acc[k]);
+    for (int c = 0; c < kMaxE; ++c) acc[c] = 0.0f;
+    float accb = 0.0f;
+    for (int64_t pos = q0; pos < q1; ++pos) {
+        const float hv = (float)h[pos * kWidth + lane];
+        const float *gp = ge + pos * E;
+#pragma unroll
+        for (int c = 0; c < kMaxE; ++c)
+            if (c < E) acc[c] = fmaf(gp[c], hv, acc[c]);
+        if (lane < E) accb += gp[lane];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxE; ++c) s_acc[wave][c][lane] = acc[c];
+    if (lane < kMaxE) s_b[wave][lane] = accb;
+    __syncthreads();
+    if (wave != 0) return;
+    for (int c = 0; c < E; ++c) {
+        float t = s_acc[0][c][lane];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t += s_acc[w][c][lane];
+        atomicAdd(&dP[c * kWidth + lane], t);
+    }
+    if (lane < E) {
+        float t = s_b[0][lane];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t += s_b[w][lane];
+        atomicAdd(&dp[lane], t);
+    }
+}
+
+// The same for E = 8 with wide reads: lane (j, g) = (lane / 8, lane % 8)
+// takes channels 8 g .. 8 g + 7 of every eighth position (16 bytes of h, so
+// a wave reads eight whole 128-byte rows at once, and the position's 32
+// bytes of ge) and keeps 8 x 8 sums plus the 8 bias sums.  The 32 (wave, j)
+// partial sums of each output meet in LDS and are added in a fixed order,
+// then one atomic per output and workgroup.
+constexpr int kProj8Chunk = 1024;
+__global__ void __launch_bounds__(kT) project_bwd_dp8_kernel(const __bf16 *__restrict__ h,
+                                                             const float *__restrict__ ge, int64_t n_pos,
+                                                             float *__restrict__ dP, float *__restrict__ dp) {
+    constexpr int kE = 8;
+    constexpr int kWaves = kT / 64;
+    __shared__ float s_acc[kWaves * 8][kE][kWidth];  // [wave * 8 + j][c][ci]: 64 KB
+    __shared__ float s_b[kWaves * 8][kE];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int j = lane >> 3, g8 = 8 * (lane & 7);
+    const int64_t q0 = (int64_t)blockIdx.x * kProj8Chunk + (int64_t)wave * (kProj8Chunk / kWaves);
+    float acc[kE][8], accb[kE];
+#pragma unroll
+    for (int c = 0; c < kE; ++c) {
+        accb[c] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[c][k] = 0.0f;
+    }
+#pragma unroll 2
+    for (int it = 0; it < kProj8Chunk / kWaves / 8; ++it) {
+        const int64_t pos = q0 + 8 * it + j;
+        if (pos < n_pos) {
+            const bf16x8 hv8 = *reinterpret_cast<const bf16x8 *>(h + pos * kWidth + g8);
+            const float4 ga = *reinterpret_cast<const float4 *>(ge + pos * kE);
+            const float4 gb = *reinterpret_cast<const float4 *>(ge + pos * kE + 4);
+            const float gv[kE] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+#pragma unroll
+            for (int c = 0; c < kE; ++c) {
+                accb[c] += gv[c];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc[c][k] = fmaf(gv[c], (float)hv8[k], acc[c][k]);
             }
         }
-        if (threadIdx.x < E) accb += ge[pos * E + threadIdx.x];
     }
+    const int row = wave * 8 + j;
 #pragma unroll
-    for (int k = 0; k < kPairs; ++k) {
-        const int32_t pr = threadIdx.x + k * kT;
-        if (pr < n_pairs) atomicAdd(&dP[pr], acc[k]);
+    for (int c = 0; c < kE; ++c) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s_acc[row][c][g8 + k] = acc[c][k];
+        if (g8 == 0) s_b[row][c] = accb[c];
     }
-    if (threadIdx.x < E) atomicAdd(&dp[threadIdx.x], accb);
+    __syncthreads();
+    for (int o = threadIdx.x; o < kE * kWidth; o += kT) {
+        const int c = o / kWidth, ci = o % kWidth;
+        float t = 0.0f;
+        for (int r = 0; r < kWaves * 8; ++r) t += s_acc[r][c][ci];
+        atomicAdd(&dP[o], t);
+    }
+    if (threadIdx.x < kE) {
+        float t = 0.0f;
+        for (int r = 0; r < kWaves * 8; ++r) t += s_b[r][threadIdx.x];
+        atomicAdd(&dp[threadIdx.x], t);
+    }
 }
 
 // ---------------------------------------------------------- fold pooling
@@ -115,36 +193,32 @@ __device__ __forceinline__ float inv_sqrt_count(int32_t n) {
 }
 
 // Sums over the transit positions of the 64 P phases ph = ph0 + lane + 64 v
-// (v < P) of one wave, and the counts of positions in the series.  The
-// offset of transit k, ((k R + 2^31) >> 32), is the same for every phase:
-// it is stepped once per wave in scalar registers.  While the group's last
-// phase is still inside the series at transit k ("full" transits, the bulk)
-// every lane reads without a bounds test, eight transits at a time; transit
-// k always adds into partial sum k mod 4.  The few transits after that
-// ("tail", while the group's first phase is inside) count each phase's
-// positions in the series; their reads past the series land in the zero
-// padding after it (kFoldPad >= 64 P - 1 floats).  The count of a lane's
-// phase is n_full + tail[v].  Lanes past the trial's phases still read
+// (v < P) of one wave.  The offset of transit k, ((k R + 2^31) >> 32), is the
+// same for every phase: it is stepped once per wave in scalar registers.
+// While the group's last phase is still inside the series at transit k
+// ("full" transits, the bulk) every lane reads without a bounds test, eight
+// transits at a time; transit k always adds into partial sum k mod 4.  The
+// few transits after that ("tail", while the group's first phase is inside)
+// read past the series into the zero padding after it (kFoldPad >= 64 P - 1
+// floats), which adds nothing.  Lanes past the trial's phases still read
 // inside the staged array; the caller ignores them.
 constexpr int kFoldPad = 128;
 
 template <int P>
 __device__ __forceinline__ void fold_sum_group(const float *s_e, uint32_t uL, uint64_t step, uint32_t ph0, int lane,
-                                               float (&sum)[P], int32_t (&cnt)[P]) {
+                                               float (&sum)[P]) {
     static_assert(64 * P - 1 <= kFoldPad, "tail reads must stay inside the padding");
     float a[P][4], t[P];
 #pragma unroll
     for (int v = 0; v < P; ++v) {
         a[v][0] = a[v][1] = a[v][2] = a[v][3] = 0.0f;
         t[v] = 0.0f;
-        cnt[v] = 0;
     }
     const uint32_t base = ph0 + (uint32_t)lane;
     // full transits: offset < uL - (ph0 + 64 P - 1)
     const uint32_t last = ph0 + 64u * P - 1u;
     const uint32_t lim_full = uL > last ? uL - last : 0u;
     uint64_t o = 2147483648ull;
-    uint32_t n_full = 0;
     // (a step of 2^45 or more, a trial of at least kMaxL bins, has one
     // transit in the series; the guard also keeps 7 steps from overflowing).
     // The offsets of a block of eight are o + u step with the multiples
@@ -169,7 +243,6 @@ __device__ __forceinline__ void fold_sum_group(const float *s_e, uint32_t uL, ui
 #pragma unroll
                 for (int u = 0; u < 8; ++u) a[v][u & 3] += val[v][u];
             o += m8;
-            n_full += 8;
         }
     }
     if ((uint32_t)((o + 3 * step) >> 32) < lim_full) {
@@ -183,7 +256,6 @@ __device__ __forceinline__ void fold_sum_group(const float *s_e, uint32_t uL, ui
         for (int v = 0; v < P; ++v)
 #pragma unroll
             for (int u = 0; u < 4; ++u) a[v][u] += s_e[base + 64u * v + ou[u]];
-        n_full += 4;
     }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
@@ -192,52 +264,79 @@ __device__ __forceinline__ void fold_sum_group(const float *s_e, uint32_t uL, ui
 #pragma unroll
         for (int v = 0; v < P; ++v) a[v][u] += s_e[base + 64u * v + ou];
         o += step;
-        ++n_full;
     }
     // tail: transits while the group's first phase is in the series
     const uint32_t lim0 = uL - ph0;  // ph0 < L
     while ((uint32_t)(o >> 32) < lim0) {
         const uint32_t ou = (uint32_t)(o >> 32);
 #pragma unroll
-        for (int v = 0; v < P; ++v) {
-            const uint32_t x = base + 64u * v + ou;  // < L + 64 P - 1
-            t[v] += s_e[x];                          // 0 past the series
-            cnt[v] += x < uL ? 1 : 0;
-        }
+        for (int v = 0; v < P; ++v) t[v] += s_e[base + 64u * v + ou];  // < L + 64 P - 1; 0 past the series
         o += step;
     }
 #pragma unroll
-    for (int v = 0; v < P; ++v) {
-        sum[v] = ((a[v][0] + a[v][1]) + (a[v][2] + a[v][3])) + t[v];
-        cnt[v] += (int32_t)n_full;
+    for (int v = 0; v < P; ++v) sum[v] = ((a[v][0] + a[v][1]) + (a[v][2] + a[v][3])) + t[v];
+}
+
+// The same sums for a trial of few transits per phase (at most about eight):
+// one accumulator per phase, every transit while the group's first phase is
+// inside the series, four at a time, reads past the series landing in the
+// zero padding.
+template <int P>
+__device__ __forceinline__ void fold_sum_group_sparse(const float *s_e, uint32_t uL, uint64_t step, uint32_t ph0,
+                                                      int lane, float (&sum)[P]) {
+    static_assert(64 * P - 1 <= kFoldPad, "reads past the series must stay inside the padding");
+#pragma unroll
+    for (int v = 0; v < P; ++v) sum[v] = 0.0f;
+    const uint32_t base = ph0 + (uint32_t)lane;
+    const uint32_t lim0 = uL - ph0;  // ph0 < L
+    uint64_t o = 2147483648ull;
+    while ((uint32_t)((o + 3 * step) >> 32) < lim0) {
+        uint32_t ou[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ou[u] = (uint32_t)((o + u * step) >> 32);
+        float val[P][4];
+#pragma unroll
+        for (int v = 0; v < P; ++v)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) val[v][u] = s_e[base + 64u * v + ou[u]];
+#pragma unroll
+        for (int v = 0; v < P; ++v) sum[v] += (val[v][0] + val[v][1]) + (val[v][2] + val[v][3]);
+        o += 4 * step;
+    }
+    while ((uint32_t)(o >> 32) < lim0) {
+        const uint32_t ou = (uint32_t)(o >> 32);
+#pragma unroll
+        for (int v = 0; v < P; ++v) sum[v] += s_e[base + 64u * v + ou];
+        o += step;
     }
 }
 
 // One trial's phases of a wave, P per lane: scores, and the lane's best
 // (score, index) updated in increasing index order (so a strict comparison
-// keeps the first of equal scores).  Every phase's count is n0 or n0 - 1,
-// n0 the count of phase 0: the phases span fewer bins than the gap between
-// two transits, so at most one transit position leaves the series across
-// them.  r0, r1 are computed once, after the first group, where lane 0 holds
-// phase 0.
+// keeps the first of equal scores).  Phase 0 has n0 = ceil((2^32 L - 2^31)
+// / R) transit positions in the series, the number of k with
+// (k R + 2^31) >> 32 < L.  The phases span fewer bins than the gap between
+// two transits, so only transit n0 - 1 can leave the series across them: a
+// phase has n0 positions below ph_split = L - ((( n0 - 1) R + 2^31) >> 32)
+// and n0 - 1 from there on.
 template <int P>
 __device__ __forceinline__ void fold_trial(const float *s_e, uint32_t uL, uint64_t step, int32_t n_ph, int32_t q,
                                            int32_t n_ph_max, int lane, float &best, int32_t &bj) {
-    int32_t n0 = 0;
-    float r0 = 0.0f, r1 = 0.0f;
+    const uint64_t num = ((uint64_t)uL << 32) - 2147483649ull;  // 2^32 L - 2^31 - 1 >= 2^31 - 1
+    const int32_t n0 = (int32_t)(num / step) + 1;
+    const int32_t ph_split = (int32_t)uL - (int32_t)(((uint64_t)(n0 - 1) * step + 2147483648ull) >> 32);
+    const float r0 = inv_sqrt_count(n0), r1 = inv_sqrt_count(n0 - 1);
+    const bool sparse = step >= ((uint64_t)uL << 29);  // at most about 8 transits per phase
     for (int32_t ph0 = 0; ph0 < n_ph; ph0 += 64 * P) {
         float sum[P];
-        int32_t cnt[P];
-        fold_sum_group<P>(s_e, uL, step, (uint32_t)ph0, lane, sum, cnt);
-        if (ph0 == 0) {
-            n0 = __builtin_amdgcn_readfirstlane(cnt[0]);
-            r0 = inv_sqrt_count(n0);
-            r1 = inv_sqrt_count(n0 - 1);
-        }
+        if (sparse)
+            fold_sum_group_sparse<P>(s_e, uL, step, (uint32_t)ph0, lane, sum);
+        else
+            fold_sum_group<P>(s_e, uL, step, (uint32_t)ph0, lane, sum);
 #pragma unroll
         for (int v = 0; v < P; ++v) {
             const int32_t ph = ph0 + lane + 64 * v;
-            const float sc = sum[v] * (cnt[v] == n0 ? r0 : r1);
+            const float sc = sum[v] * (ph < ph_split ? r0 : r1);
             if (ph < n_ph && sc > best) {
                 best = sc;
                 bj = q * n_ph_max + ph;
@@ -246,12 +345,15 @@ __device__ __forceinline__ void fold_trial(const float *s_e, uint32_t uL, uint64
     }
 }
 
-// Grid (channel, example, window group); each workgroup stages its event
-// series in LDS, and each wave takes whole windows (wave index = group * 4
-// + wave, striding by 4 n_groups), so a window's maximum is a wave
-// reduction.  Trials with more than 64 phases take two phases per lane, so
-// each scalar offset step serves 128 phases.
-__global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
+// Grid (channel, example, window group); each workgroup of eight waves
+// stages its event series in LDS (33 KB, so four workgroups, eight waves per
+// SIMD, share a CU and hide each other's LDS and scalar latencies), and each
+// wave takes whole windows (wave index = group * 8 + wave, striding by
+// 8 n_groups), so a window's maximum is a wave reduction.  Trials with more
+// than 64 phases take two phases per lane, so each scalar offset step serves
+// 128 phases.
+constexpr int kFoldThreads = 512;
+__global__ void __launch_bounds__(kFoldThreads) foldpool_fwd_kernel(const float *__restrict__ e, int32_t L, int32_t E,
                                                           const double *__restrict__ trials, int32_t W, int32_t S,
                                                           const float *__restrict__ win_q, float *__restrict__ f,
                                                           int32_t *__restrict__ arg) {
@@ -260,10 +362,10 @@ __global__ void __launch_bounds__(kT) foldpool_fwd_kernel(const float *__restric
     const int64_t b = blockIdx.y;
     const int32_t nf = E + 1;
     const int lane = threadIdx.x & 63;
-    const int32_t wave_id = blockIdx.z * (kT / 64) + (threadIdx.x >> 6);
-    const int32_t n_waves = gridDim.z * (kT / 64);
+    const int32_t wave_id = blockIdx.z * (kFoldThreads / 64) + (threadIdx.x >> 6);
+    const int32_t n_waves = gridDim.z * (kFoldThreads / 64);
     const uint32_t uL = (uint32_t)L;
-    for (int t = threadIdx.x; t < L + kFoldPad; t += kT) s_e[t] = t < L ? e[(b * L + t) * E + c] : 0.0f;
+    for (int t = threadIdx.x; t < L + kFoldPad; t += kFoldThreads) s_e[t] = t < L ? e[(b * L + t) * E + c] : 0.0f;
     __syncthreads();
     for (int32_t w = wave_id; w < W; w += n_waves) {
         int32_t n_ph_max = 0;
@@ -559,8 +661,13 @@ extern "C" int cetra_net_project_bwd(void *stream, const void *h, const float *g
                        dim3(kT), 0, st, ge, n_pos, P, E, dh);
     int rc = check_launch("net_project_bwd/dh");
     if (rc) return rc;
-    hipLaunchKernelGGL(project_bwd_dp_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kProjChunk)),
-                       dim3(kT), 0, st, (const __bf16 *)h, ge, n_pos, E, dP, dp);
+    const bool wide = E == 8 && (((uintptr_t)h | (uintptr_t)ge) & 15) == 0;
+    if (wide)
+        hipLaunchKernelGGL(project_bwd_dp8_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kProj8Chunk)),
+                           dim3(kT), 0, st, (const __bf16 *)h, ge, n_pos, dP, dp);
+    else
+        hipLaunchKernelGGL(project_bwd_dp_kernel, dim3((unsigned)ceil_div(std::max<int64_t>(n_pos, 1), kProjChunk)),
+                           dim3(kT), 0, st, (const __bf16 *)h, ge, n_pos, E, dP, dp);
     return check_launch("net_project_bwd");
 }
 
@@ -581,8 +688,8 @@ extern "C" int cetra_net_foldpool_fwd(void *stream, const float *e, int32_t B, i
     // window groups: enough workgroups to fill the chip even for one example
     const int64_t want = (int64_t)4 * device_cu_count();
     const int32_t groups = (int32_t)std::max<int64_t>(
-        1, std::min<int64_t>(ceil_div(W, kT / 64), ceil_div(want, (int64_t)E * B)));
-    hipLaunchKernelGGL(foldpool_fwd_kernel, dim3((unsigned)E, (unsigned)B, (unsigned)groups), dim3(kT), 0,
+        1, std::min<int64_t>(ceil_div(W, kFoldThreads / 64), ceil_div(want, (int64_t)E * B)));
+    hipLaunchKernelGGL(foldpool_fwd_kernel, dim3((unsigned)E, (unsigned)B, (unsigned)groups), dim3(kFoldThreads), 0,
                        as_stream(stream), e, L, E, trials, W, S, win_q, f, arg);
     return check_launch("net_foldpool_fwd");
 }

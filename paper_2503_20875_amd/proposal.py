@@ -217,6 +217,8 @@ class ProposalNet:
             dh=[torch.empty((B, L, WIDTH), dtype=f32, device=dev) for _ in range(2)],
             g_scratch=torch.empty((B, L, WIDTH), dtype=bf, device=dev),
             wt_scratch=torch.empty((WIDTH * TAPS * WIDTH,), dtype=bf, device=dev),
+            w_partial=torch.empty((max(bwd_partial_floats(C_IN, L, B), bwd_partial_floats(WIDTH, L, B)),),
+                                  dtype=f32, device=dev),
             loss=torch.zeros(1, dtype=f32, device=dev),
         )
         self._bufs = {key: b}  # keep one shape's buffers
@@ -286,7 +288,8 @@ class ProposalNet:
                 out = dh_out
             _abi.check(lib.cetra_conv1d_bwd(s, _ptr(dh_in), _ptr(bufs["h"][l + 1]), _ptr(bufs["h"][l]), cin, L, B,
                                             _ptr(self.packed[l]), _k32(cin), _ptr(bufs["g_scratch"]),
-                                            _ptr(bufs["wt_scratch"]), _ptr(out) if out is not None else None,
+                                            _ptr(bufs["wt_scratch"]), _ptr(bufs["w_partial"]),
+                                            bufs["w_partial"].numel(), _ptr(out) if out is not None else None,
                                             _ptr(self.view(f"W{l}", self.grad)), _ptr(self.view(f"b{l}", self.grad))))
             dh_in, dh_out = dh_out, dh_in
         return (bufs["loss"], dx) if want_dx else bufs["loss"]
@@ -318,18 +321,30 @@ def conv1d_fwd(x, w_packed, bias, stream=None):
     return y
 
 
-def conv1d_bwd(dy, y, x, w_packed, stream=None):
-    """Returns dx [B][L][cin] FP32, dw [64][k32] FP32, db [64] FP32."""
+def bwd_partial_floats(cin: int, L: int, B: int) -> int:
+    """Floats of the weight-gradient partial-sum workspace (cetra_conv1d_bwd)."""
+    n = int(_lib().cetra_conv1d_bwd_partial_floats(int(cin), int(L), int(B)))
+    if n < 0:
+        raise ValueError(f"conv1d_bwd: no workspace size for cin={cin}, L={L}, B={B}")
+    return n
+
+
+def conv1d_bwd(dy, y, x, w_packed, stream=None, partial: bool = True, dx_out: bool = True):
+    """Returns dx [B][L][cin] FP32 (None with dx_out=False), dw [64][k32]
+    FP32, db [64] FP32.  partial=False adds the weight gradient with
+    atomics instead of the partial-sum workspace."""
     import torch
     B, L, cin = (int(v) for v in x.shape)
     k32 = int(w_packed.shape[1])
-    dx = torch.empty((B, L, cin), dtype=torch.float32, device="cuda")
+    dx = torch.empty((B, L, cin), dtype=torch.float32, device="cuda") if dx_out else None
     dw = torch.zeros((WIDTH, k32), dtype=torch.float32, device="cuda")
     db = torch.zeros(WIDTH, dtype=torch.float32, device="cuda")
     g = torch.empty((B, L, WIDTH), dtype=torch.bfloat16, device="cuda")
     wt = torch.empty(WIDTH * TAPS * cin, dtype=torch.bfloat16, device="cuda")
+    part = torch.empty(bwd_partial_floats(cin, L, B), dtype=torch.float32, device="cuda") if partial else None
     _abi.check(_lib().cetra_conv1d_bwd(_stream(stream), _ptr(dy), _ptr(y), _ptr(x), cin, L, B, _ptr(w_packed), k32,
-                                       _ptr(g), _ptr(wt), _ptr(dx), _ptr(dw), _ptr(db)))
+                                       _ptr(g), _ptr(wt), _ptr(part), part.numel() if partial else 0,
+                                       _ptr(dx) if dx_out else None, _ptr(dw), _ptr(db)))
     return dx, dw, db
 
 

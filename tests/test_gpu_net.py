@@ -114,6 +114,50 @@ def test_conv_backward(torch, pn, cin, L, B):
         assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-5 * scale)
 
 
+def test_conv_backward_partial_sums_at_training_size(torch, pn):
+    """The weight gradient through the partial-sum workspace, where several
+    256-position chunks share a workgroup (cin 16, 32 x 4 096 positions: two
+    chunks per workgroup), against the oracle and against the atomic path;
+    two calls give the same bits."""
+    cin, L, B = 16, 4096, 32
+    assert pn.bwd_partial_floats(cin, L, B) == (L // 512) * B * (64 * 160 + 64)
+    rng = np.random.default_rng(4096)
+    x = bf16_exact(rng, (B, cin, L), 0.0, 1.0)
+    W = onet.bf16(rng.normal(0, np.sqrt(2.0 / (9 * cin)), (64, cin, 9)))
+    y = onet.bf16(np.maximum(onet.conv1d(x, W, rng.normal(0, 0.1, 64)), 0.0))
+    dy = bf16_exact(rng, (B, 64, L))
+    _, gW, gb = onet.conv1d_backward(x, W, dy * (y > 0))
+    print(f"[net] conv bwd partial sums cin={cin} L={L} B={B}", flush=True)
+    args = (to_dev(torch, dy.transpose(0, 2, 1), torch.float32), to_dev(torch, y.transpose(0, 2, 1), torch.bfloat16),
+            to_dev(torch, x.transpose(0, 2, 1), torch.bfloat16), to_dev(torch, packed_w(W), torch.bfloat16))
+    _, dw1, db1 = pn.conv1d_bwd(*args, dx_out=False)
+    _, dw2, db2 = pn.conv1d_bwd(*args, dx_out=False)
+    _, dwa, dba = pn.conv1d_bwd(*args, partial=False, dx_out=False)
+    torch.cuda.synchronize()
+    assert torch.equal(dw1, dw2) and torch.equal(db1, db2)
+    got_w = dw1.cpu().numpy().astype(np.float64)
+    assert np.all(got_w[:, 9 * cin:] == 0.0)
+    got_w = got_w[:, :9 * cin].reshape(64, 9, cin).transpose(0, 2, 1)
+    got_a = dwa.cpu().numpy().astype(np.float64)[:, :9 * cin].reshape(64, 9, cin).transpose(0, 2, 1)
+    for got, ref in ((got_w, gW), (got_a, gW), (db1.cpu().numpy(), gb), (dba.cpu().numpy(), gb)):
+        scale = max(np.abs(ref).max(), 1e-30)
+        assert np.all(np.abs(got - ref) <= 1e-5 * np.abs(ref) + 1e-5 * scale)
+
+
+def test_conv_backward_rejects_a_short_workspace(torch, pn):
+    from paper_2503_20875_amd import _abi
+    cin, L, B = 64, 512, 2
+    need = pn.bwd_partial_floats(cin, L, B)
+    t = lambda *shape, dt=torch.bfloat16: torch.zeros(shape, dtype=dt, device="cuda")  # noqa: E731
+    dy, y, x, w = t(B, L, 64, dt=torch.float32), t(B, L, 64), t(B, L, cin), t(64, 576)
+    g, wt, part = t(B, L, 64), t(64 * 9 * cin), t(need - 4, dt=torch.float32)
+    dw, db = t(64, 576, dt=torch.float32), t(64, dt=torch.float32)
+    rc = _abi.load().cetra_conv1d_bwd(None, dy.data_ptr(), y.data_ptr(), x.data_ptr(), cin, L, B, w.data_ptr(), 576,
+                                      g.data_ptr(), wt.data_ptr(), part.data_ptr(), need - 4, None, dw.data_ptr(),
+                                      db.data_ptr())
+    assert rc != 0
+
+
 def net_case(seed=0, B=2, L=700, n_win=16):
     """Parameters (FP32-exact), a bfloat16-exact input, log windows over
     0.1-5 d on 0.02-d bins and one positive window per example."""
@@ -340,3 +384,34 @@ def test_downsample(torch, pn):
         ref_s = onet.downsample_signed(fold, nb)
         assert np.all(np.abs(out_s - ref_s) <= 2.0 ** -8 * np.abs(ref_s) + 1e-6)
         assert out_s[0, 0] == 0.0 and (J == 1 or (ref_s[1, jn] < 0 and out_s[1, jn] < 0))
+
+
+@pytest.mark.parametrize("E,n_pos", [(8, 3000), (5, 2049), (16, 700), (8, 0)])
+def test_project_backward_against_the_plain_sums(torch, pn, E, n_pos):
+    """dh = ge P, dP += ge^T h, dp += column sums of ge, with a ragged last
+    workgroup and the compile-time (E = 8) and run-time channel counts."""
+    from paper_2503_20875_amd import _abi
+    rng = np.random.default_rng(100 + E + n_pos)
+    h = onet.bf16(rng.normal(0, 1, (n_pos, 64)))
+    ge = rng.normal(0, 1, (n_pos, E)).astype(np.float32).astype(np.float64)
+    P = rng.normal(0, 0.1, (E, 64)).astype(np.float32).astype(np.float64)
+    dP0 = rng.normal(0, 1, (E, 64)).astype(np.float32).astype(np.float64)
+    dp0 = rng.normal(0, 1, E).astype(np.float32).astype(np.float64)
+    print(f"[net] project bwd E={E} n_pos={n_pos}", flush=True)
+    h_d = to_dev(torch, h.reshape(max(n_pos, 1), 64) if n_pos else np.zeros((1, 64)), torch.bfloat16)
+    ge_d = to_dev(torch, ge if n_pos else np.zeros((1, E)), torch.float32)
+    P_d = to_dev(torch, P, torch.float32)
+    dh = torch.zeros((max(n_pos, 1), 64), dtype=torch.float32, device="cuda")
+    dP = to_dev(torch, dP0, torch.float32)
+    dp = to_dev(torch, dp0, torch.float32)
+    _abi.check(_abi.load().cetra_net_project_bwd(None, h_d.data_ptr(), ge_d.data_ptr(), n_pos, P_d.data_ptr(), E,
+                                                 dh.data_ptr(), dP.data_ptr(), dp.data_ptr()))
+    torch.cuda.synchronize()
+    ref_P = dP0 + ge.T @ h
+    ref_p = dp0 + ge.sum(axis=0)
+    for got, ref, absref in ((dP, ref_P, np.abs(dP0) + np.abs(ge).T @ np.abs(h)),
+                             (dp, ref_p, np.abs(dp0) + np.abs(ge).sum(axis=0))):
+        assert np.all(np.abs(got.cpu().numpy() - ref) <= 1e-5 * absref + 1e-30)
+    if n_pos:
+        ref_h = ge @ P
+        assert np.all(np.abs(dh.cpu().numpy() - ref_h) <= 1e-5 * (np.abs(ge) @ np.abs(P)) + 1e-30)
