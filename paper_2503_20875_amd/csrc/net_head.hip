@@ -472,39 +472,70 @@ __global__ void bce_kernel(const float *__restrict__ z, const float *__restrict_
 // Head backward: the window-feature gradients gf[b][w][k] per row, and the
 // parameter gradients summed over the workgroup's kHeadRows rows in LDS
 // (per-row terms staged there; one thread per parameter sums them), so each
-// workgroup adds one FP32 atomic per parameter.
+// workgroup adds one FP32 atomic per parameter.  The rows' features are
+// staged in LDS first; then wave q takes hidden units q, q + 4, ... of every
+// row (lane = row), so the weights it reads are wave-uniform, and the four
+// waves' partial feature gradients are added in order.  Loops over the
+// features are unrolled to their maximum with a guard, which keeps the
+// per-row arrays in registers.
 constexpr int kHeadRows = 64;
+constexpr int kHeadMaxF = 2 * kMaxE + 1;
 __global__ void __launch_bounds__(kT) head_bwd_kernel(const float *__restrict__ f, int64_t n_bw, int32_t nf,
                                                       const float *__restrict__ U, const float *__restrict__ u,
                                                       const float *__restrict__ v, int32_t H,
                                                       const float *__restrict__ gz, float *__restrict__ gU,
                                                       float *__restrict__ gu, float *__restrict__ gv,
                                                       float *__restrict__ gv0, float *__restrict__ gf) {
+    constexpr int kWaves = kT / 64;
+    static_assert(kHeadRows == 64, "one lane per row");
     __shared__ float s_gp[kHeadRows][kMaxHidden + 1];   // dL/d(pre-activation) of the hidden units
     __shared__ float s_grr[kHeadRows][kMaxHidden + 1];  // gz times the hidden activation
-    __shared__ float s_f[kHeadRows][2 * kMaxE + 1];
+    __shared__ float s_f[kHeadRows][kHeadMaxF];
+    __shared__ float s_gfp[kWaves][kHeadRows][kHeadMaxF];  // partial feature gradients per wave
     __shared__ float s_g[kHeadRows];
     const int64_t row0 = (int64_t)blockIdx.x * kHeadRows;
-    for (int r = threadIdx.x; r < kHeadRows; r += blockDim.x) {
-        const int64_t bw = row0 + r;
-        const bool ok = bw < n_bw;
-        const float g = ok ? gz[bw] : 0.0f;
-        float fv[2 * kMaxE + 1];
-        for (int k = 0; k < nf; ++k) fv[k] = ok ? f[bw * nf + k] : 0.0f;
-        float gfv[2 * kMaxE + 1];
-        for (int k = 0; k < nf; ++k) gfv[k] = 0.0f;
-        for (int hh = 0; hh < H; ++hh) {
+    const int64_t n_rows = min((int64_t)kHeadRows, n_bw - row0);
+    for (int i = threadIdx.x; i < kHeadRows * nf; i += kT) {
+        const int r = i / nf, k = i % nf;
+        s_f[r][k] = r < n_rows ? f[(row0 + r) * nf + k] : 0.0f;
+    }
+    for (int r = threadIdx.x; r < kHeadRows; r += kT) s_g[r] = r < n_rows ? gz[row0 + r] : 0.0f;
+    __syncthreads();
+    {
+        const int r = threadIdx.x & 63;
+        const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const float g = s_g[r];
+        float fv[kHeadMaxF], gfv[kHeadMaxF];
+#pragma unroll
+        for (int k = 0; k < kHeadMaxF; ++k) {
+            fv[k] = k < nf ? s_f[r][k] : 0.0f;
+            gfv[k] = 0.0f;
+        }
+        for (int hh = q; hh < H; hh += kWaves) {
+            const float *Uh = U + hh * nf;
             float pre = u[hh];
-            for (int k = 0; k < nf; ++k) pre = fmaf(U[hh * nf + k], fv[k], pre);
+#pragma unroll
+            for (int k = 0; k < kHeadMaxF; ++k)
+                if (k < nf) pre = fmaf(Uh[k], fv[k], pre);
             const float gp = pre > 0.0f ? g * v[hh] : 0.0f;
             s_gp[r][hh] = gp;
             s_grr[r][hh] = g * fmaxf(pre, 0.0f);
-            for (int k = 0; k < nf; ++k) gfv[k] = fmaf(U[hh * nf + k], gp, gfv[k]);
+#pragma unroll
+            for (int k = 0; k < kHeadMaxF; ++k)
+                if (k < nf) gfv[k] = fmaf(Uh[k], gp, gfv[k]);
         }
-        for (int k = 0; k < nf; ++k) s_f[r][k] = fv[k];
-        s_g[r] = g;
-        if (ok)
-            for (int k = 0; k < nf; ++k) gf[bw * nf + k] = gfv[k];
+#pragma unroll
+        for (int k = 0; k < kHeadMaxF; ++k)
+            if (k < nf) s_gfp[q][r][k] = gfv[k];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHeadRows * nf; i += kT) {
+        const int r = i / nf, k = i % nf;
+        if (r >= n_rows) continue;
+        float t = s_gfp[0][r][k];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t += s_gfp[w][r][k];
+        gf[(row0 + r) * nf + k] = t;
     }
     __syncthreads();
     // parameters: gU[hh][k] (H nf), gu[hh] (H), gv[hh] (H), gv0 (1)
