@@ -121,3 +121,23 @@ def test_noalloc_limit_and_range_error_without_a_gpu(lib):
                                            None, None, None, None, None)
     assert rc == -1
     assert _abi.SIGNATURES["cetra_periodic_search_noalloc"][0] is ctypes.c_int
+
+
+def test_conv_backward_workspace_size(lib):
+    """cetra_conv1d_bwd_partial_floats (host only): one slab of 64 k32 + 64
+    floats per weight-gradient workgroup, with the most 256-position chunks
+    per workgroup (8, 4, 2 or 1) that still give 256 workgroups."""
+    def expected(cin, L, B):
+        k32 = (9 * cin + 31) // 32 * 32
+        cpw = 1
+        for c in (8, 4, 2):
+            if -(-L // (256 * c)) * B >= 256:
+                cpw = c
+                break
+        return -(-L // (256 * cpw)) * B * (64 * k32 + 64)
+    for cin, L, B in ((64, 8192, 32), (16, 8192, 32), (16, 4096, 32), (64, 8192, 256), (64, 300, 2), (16, 1, 1),
+                      (64, 8192, 1), (64, 65536, 4)):
+        assert lib.cetra_conv1d_bwd_partial_floats(cin, L, B) == expected(cin, L, B), (cin, L, B)
+    assert lib.cetra_conv1d_bwd_partial_floats(64, 8192, 32) == 256 * (64 * 576 + 64)
+    for bad in ((32, 100, 1), (64, 0, 1), (64, 100, 0)):
+        assert lib.cetra_conv1d_bwd_partial_floats(*bad) == -1
