@@ -235,3 +235,33 @@ def test_downsample_saturation_and_nulls():
     out = net.downsample(fold, 2)
     assert np.array_equal(out[:, 0], [3.75, 3.75])
     assert out[0, 1] == 0.0 and out[1, 1] == pytest.approx(3.0 / 8.0)
+
+
+def test_fold_phase_counts_follow_the_split_rule():
+    """The rule the fold-pooling kernel applies instead of counting: with
+    step R, phase 0 has n0 = (2^32 L - 2^31 - 1) // R + 1 positions inside a
+    series of L bins, and every phase below n_ph = min(L, ceil(R / 2^32))
+    has n0 of them below ph_split = L - (((n0 - 1) R + 2^31) >> 32) and
+    n0 - 1 from there on.  Checked against counting every phase's positions
+    (offsets by their definition), for random and edge-case trials."""
+    rng = np.random.default_rng(11)
+    cases = [(int(L), float(T)) for L, T in zip(rng.integers(1, 8193, 60), rng.uniform(1.0, 400.0, 60))]
+    cases += [(int(L), float(L) * f) for L, f in zip(rng.integers(1, 8193, 30), rng.uniform(0.05, 3.0, 30))]
+    cases += [(8192, 1.0), (8192, 1.5), (8192, 64.0), (8192, 1024.0), (8192, 8191.5), (8192, 8192.0), (8192, 1e9 - 1),
+              (1, 1.0), (1, 7.3), (2, 1.0), (100, 99.9999), (100, 100.0), (100, 33.3333333)]
+    for L, T in cases:
+        R = net.fold_step(T)
+        n_ph = min(L, -(-R // 2 ** 32))
+        offs = []
+        k = 0
+        while (k * R + 2 ** 31) >> 32 < L:
+            offs.append((k * R + 2 ** 31) >> 32)
+            k += 1
+        offs = np.array(offs, dtype=np.int64)
+        counts = np.searchsorted(offs, L - np.arange(n_ph), side="left")  # positions ph + o < L
+        n0 = (2 ** 32 * L - 2 ** 31 - 1) // R + 1
+        ph_split = L - (((n0 - 1) * R + 2 ** 31) >> 32)
+        assert n0 == len(offs) == counts[0], (L, T)
+        want = np.where(np.arange(n_ph) < ph_split, n0, n0 - 1)
+        assert np.array_equal(counts, want), (L, T)
+        assert counts.min() >= 1
