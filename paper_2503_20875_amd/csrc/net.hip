@@ -317,7 +317,8 @@ conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L, const __bf16 *__restr
 // and db[co] += sum over t of G[t][co]: a GEMM whose reduction runs over
 // positions, so both operands are staged in LDS position-fastest (one chunk
 // of 256 positions at a time; X with a 4-position halo on each side).
-// Workgroup: kChunksPerWg chunks of one example, eight waves; wave w owns
+// Workgroup: chunks_per_wg chunks of one example (8 with atomics, fewer with
+// partial sums so that every CU gets a workgroup), eight waves; wave w owns
 // output channels [16 (w mod 4), +16) and half of the (ci tile, tap) column
 // tiles (w < 4 the first half), so a CU keeps twice as many MFMA streams
 // busy as with one wave per channel tile, for the same FP32 atomics.  Per
@@ -329,7 +330,7 @@ conv_bwd_x_kernel(const __bf16 *__restrict__ g, int32_t L, const __bf16 *__restr
 // The workgroup's sums go to dW and db by FP32 atomics (kPartial = false),
 // or (kPartial = true) to the workgroup's own slab of a partial-sum array,
 // [workgroup][64 k32 + 64] FP32, by plain stores; conv_bwd_w_reduce_kernel
-// then adds the slabs into dW and db in workgroup order.
+// then adds the slabs into dW and db in a fixed order.
 constexpr int kPosChunk = 256;
 constexpr int kChunksPerWg = 8;
 constexpr int kHalo = 4;
