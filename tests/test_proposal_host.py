@@ -63,3 +63,36 @@ def test_fallback_threshold():
     assert fallback_threshold([row(False, False, 3.0)], 0.99) == float("-inf")
     # a curve where nothing was folded has a restricted SNR of -inf and always falls back
     assert fallback_threshold([row(True, False, float("-inf"))] + [row(True, True, 9.0)] * 3, 1.0) > float("-inf")
+
+
+def test_store_calibration_keeps_the_arrays(tmp_path):
+    """Calibrated operating points go into the archive's metadata; every
+    array and the other metadata stay as they were."""
+    import json
+    from paper_2503_20875_amd.learned import store_calibration
+    path = str(tmp_path / "w.npz")
+    meta = {"n_event": 8, "hidden": 64, "input": "signed"}
+    a = np.arange(12, dtype=np.float32).reshape(3, 4)
+    np.savez(path, W0=a, __meta__=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+    store_calibration(path, 89, 6.25, "calibration half of 1000 curves")
+    store_calibration(path, 90, None, "again")
+    with np.load(path, allow_pickle=False) as z:
+        assert np.array_equal(z["W0"], a) and z["W0"].dtype == np.float32
+        got = json.loads(bytes(z["__meta__"]).decode())
+    assert got == dict(meta, calibrated_k=90, calibrated_fallback_snr=None, calibration="again")
+
+
+def test_committed_weights_carry_their_operating_points():
+    """The default network's archive says which input it was trained on and
+    the operating points calibrated for it (read without executing anything
+    from the file)."""
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with np.load(os.path.join(root, "paper_2503_20875_amd", "weights", "proposal.npz"), allow_pickle=False) as z:
+        meta = json.loads(bytes(z["__meta__"]).decode())
+    assert meta["input"] == "signed"
+    assert meta["calibrated_k"] == 89
+    assert 5.0 < meta["calibrated_fallback_snr"] < 8.0
+    with np.load(os.path.join(root, "paper_2503_20875_amd", "weights", "proposal_long.npz"), allow_pickle=False) as z:
+        assert json.loads(bytes(z["__meta__"]).decode()).get("input", "abs") in ("abs", "signed")
